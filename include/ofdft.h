@@ -1,0 +1,230 @@
+/*
+ * ofdft.h -- C ABI of the MI355X (gfx950) library for the hot path of periodic
+ * real-space orbital-free DFT with higher-order finite differences
+ * (Ghosh & Suryanarayana, arXiv:1412.8250).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid: uniform, periodic, n_x x n_y x n_z points with spacings h_x, h_y, h_z
+ *   (Section 4: L_a = n_a h).  Arrays are stored [nz][ny][nx], x fastest,
+ *   contiguous.  Complex arrays interleave (re, im); complex128 is two doubles
+ *   per point, complex64 two floats.
+ * Pointers: every array pointer is a DEVICE pointer owned by the caller; the
+ *   library never frees or keeps a caller pointer beyond the call, except where
+ *   a create call says so.  Scalars and descriptors live in host memory.
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *   Work is enqueued on it; calls that must read convergence scalars back
+ *   synchronise that stream only.
+ * Errors: every call returns an int status (OFDFT_OK = 0).  Negative values are
+ *   errors, 1 means "finished without meeting the tolerance" (results written).
+ *   ofdft_last_error() gives a thread-local message for the last failure.
+ *   No C++ exception crosses this boundary.
+ * Allocation: device workspaces are allocated by the *_create calls only;
+ *   solve/apply/mix/step calls do not allocate.
+ */
+#ifndef OFDFT_H
+#define OFDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OFDFT_OK             0
+#define OFDFT_NOT_CONVERGED  1
+#define OFDFT_INVALID_ARG   (-1)
+#define OFDFT_NONFINITE     (-2)
+#define OFDFT_BREAKDOWN     (-3)
+#define OFDFT_HIP_ERROR     (-4)
+#define OFDFT_NO_MEMORY     (-5)
+
+typedef enum { OFDFT_F64 = 0, OFDFT_F32 = 1, OFDFT_C128 = 2, OFDFT_C64 = 3 } ofdft_dtype;
+
+/* Solver forms for the Poisson solve. */
+typedef enum {
+    OFDFT_PLAIN_F64 = 0,       /* CG in FP64 throughout                                   */
+    OFDFT_REFINED_F32 = 1,     /* FP32 stencil + FP32 CG inside FP64 residual refinement  */
+    OFDFT_LEARNED = 2,         /* network initial guess + flexible CG with the network as
+                                  preconditioner, FP64 vectors; plain CG as fallback      */
+} ofdft_mode;
+
+typedef struct {
+    int nx, ny, nz;            /* points per axis, >= 1                                   */
+    double hx, hy, hz;         /* spacings (bohr), > 0                                    */
+} ofdft_grid;
+
+typedef struct {
+    int iters;                 /* Krylov iterations (inner iterations for refined form)  */
+    int outer_iters;           /* refinement steps (refined form), else 0                */
+    int nn_applies;            /* network applications (learned form)                    */
+    int fell_back;             /* 1 if the learned form fell back to plain CG            */
+    int status;                /* OFDFT_* status of this solve                            */
+    double rel_res;            /* final true relative residual, recomputed in FP64       */
+    double removed_mean;       /* mean removed from the Poisson right-hand side          */
+    double seconds;            /* wall time of the call, measured with HIP events        */
+} ofdft_solve_stats;
+
+/* Thread-local message of the last failing call; returns its length. */
+int ofdft_last_error(char *buf, size_t len);
+
+/* Library version string (static storage). */
+const char *ofdft_version(void);
+
+/* ------------------------------------------------------------------------
+ * fd_laplacian_apply -- y = alpha * L_h x + beta * y
+ *
+ * L_h is the order-2N central-difference Laplacian of Section 4 (FD Laplacian
+ * equation): sum over p = 0..N of w_p times the six values at offsets +-p along
+ * the axes, w_0 = -(1/h^2) sum_{q<=N} 1/q^2 and
+ * w_p = 2(-1)^{p+1} (N!)^2 / (h^2 p^2 (N-p)!(N+p)!), per axis with that axis'
+ * spacing; indices outside the grid map to their periodic images (applied
+ * repeatedly when the grid is shorter than the stencil).
+ *   grid    grid descriptor (host)
+ *   radius  N in 1..6 (6 = 12th order)
+ *   dtype   element type of x and y; alpha/beta are real
+ *   x, y    device arrays of nx*ny*nz elements; must not overlap
+ *   beta == 0 means y is write-only (its old contents are not read).
+ * Errors: INVALID_ARG for bad sizes/radius/dtype or null pointers.
+ * ------------------------------------------------------------------------ */
+int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
+                       const void *x, void *y, double alpha, double beta, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Periodic Poisson solve (Section 3.3, Poisson equation; Section 4 solver
+ * notes): finds phi with -L_h phi = P g and sum(phi) = 0, where
+ * P = I - (1/n) 1 1^T removes the mean of the right-hand side.  The paper
+ * solves the continuum problem -(1/4 pi) Lap phi = rho + b, so callers pass
+ * g = 4 pi (rho + b).  A non-neutral g is not an error: its mean is removed
+ * and reported in stats->removed_mean.
+ *
+ * ofdft_poisson_create allocates the workspace for one grid and one mode.
+ *   mode  OFDFT_PLAIN_F64 or OFDFT_REFINED_F32 (OFDFT_LEARNED needs a network,
+ *         see ofdft_poisson_set_network)
+ * cg_poisson_solve:
+ *   rhs      device FP64 array g (not modified)
+ *   x        device FP64 array: initial guess on entry (warm start), solution on
+ *            exit, shifted to zero mean
+ *   rel_tol  stop when ||P g + L_h x||_2 <= rel_tol ||P g||_2, with the residual
+ *            recomputed in FP64 at the end
+ *   max_iter maximum Krylov iterations in total
+ *   stats    optional (may be NULL)
+ * Returns OK, NOT_CONVERGED (x still written), BREAKDOWN (p^T A p <= 0),
+ * NONFINITE (NaN/Inf met), INVALID_ARG, HIP_ERROR.
+ * ------------------------------------------------------------------------ */
+typedef struct ofdft_poisson ofdft_poisson;
+int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode, ofdft_poisson **out);
+int ofdft_poisson_destroy(ofdft_poisson *s);
+int cg_poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol,
+                     int max_iter, ofdft_solve_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched complex shifted solves (Section 3.1, Helmholtz equations):
+ *   (-L_h + kappa_j) u_j = f_j,  j = 0..nsys-1,
+ * the paper's  -(2kF)^-2 Lap V + Q V = P f  multiplied by (2kF)^2
+ * (kappa = (2kF)^2 Q).  Each system may live on its own grid.  The matrix is
+ * complex symmetric; the solver is COCG (conjugate gradients with the
+ * unconjugated bilinear form).  All systems run in one persistent launch.
+ *
+ * ofdft_batch_create: nsys systems, grids[j] (host array), one radius, dtype
+ *   OFDFT_C128 or OFDFT_C64 (C64 runs COCG in complex64 inside complex128
+ *   residual refinement).  Allocates all workspaces.
+ * cg_helmholtz_solve_batched:
+ *   kappa    host array of 2*nsys doubles (re, im) per system; kappa != 0
+ *   rhs      host array of nsys device pointers to complex128 arrays f_j
+ *   x        host array of nsys device pointers to complex128 arrays:
+ *            initial guess on entry, solution on exit
+ *   rel_tol  per-system relative residual target (true residual, complex128)
+ *   stats    optional host array of nsys records
+ * Returns OK, NOT_CONVERGED if any system missed the tolerance, BREAKDOWN,
+ * NONFINITE, INVALID_ARG, HIP_ERROR.
+ * ------------------------------------------------------------------------ */
+typedef struct ofdft_batch ofdft_batch;
+int ofdft_batch_create(int nsys, const ofdft_grid *grids, int radius, ofdft_dtype dtype,
+                       ofdft_batch **out);
+int ofdft_batch_destroy(ofdft_batch *b);
+int cg_helmholtz_solve_batched(ofdft_batch *b, const double *kappa, const void *const *rhs,
+                               void *const *x, double rel_tol, int max_iter,
+                               ofdft_solve_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Anderson mixing (Appendix D):
+ *   v_{k+1} = v_k + zeta f_k - (S_k + zeta Y_k)(Y_k^T Y_k)^{-1} Y_k^T f_k,
+ * S_k, Y_k the last m differences of iterates and of residuals f = vhat - v.
+ * The first call (no history) returns v + zeta f.  If Y^T Y is numerically
+ * singular (condition estimate >= 1e12) the oldest columns are dropped.
+ * ofdft_anderson_create: n grid values per vector, history m in 0..16, zeta.
+ *   The context keeps S, Y (m columns each) and the previous v, f in device
+ *   memory.
+ * anderson_mix: v, f, v_next are device FP64 arrays of n values; v_next may
+ *   alias v.
+ * ------------------------------------------------------------------------ */
+typedef struct ofdft_anderson ofdft_anderson;
+int ofdft_anderson_create(int64_t n, int m, double zeta, ofdft_anderson **out);
+int ofdft_anderson_destroy(ofdft_anderson *a);
+int ofdft_anderson_reset(ofdft_anderson *a);
+int anderson_mix(ofdft_anderson *a, const double *v, const double *f, double *v_next,
+                 void *stream);
+
+/* ------------------------------------------------------------------------
+ * Fixed-point (SCF-type) iteration, Section 3.3 and its flowchart.
+ * The mixing variable is v = phi + mu V_LR.  One step:
+ *   u      = U(v)  -- minimiser of the local functional
+ *            h^3 sum [C_F rho^{5/3} + eps_xc(rho) rho + v rho] - (lambda/2) h^3 sum u L_h u
+ *            subject to h^3 sum u^2 = N_e (Appendix C, Algorithm 1: Polak-Ribiere
+ *            non-linear CG with restarts, Brent line search, renormalisation)
+ *   phi    = Poisson(4 pi (u^2 + b))                               (warm start)
+ *   V_LR   = C_F sum_r [alpha rho^{alpha-1} V_{beta,r} + beta rho^{beta-1} V_{alpha,r}]
+ *            from the 8 shifted solves of the K_00 term, kappa_r = (2kF)^2 Q_00r,
+ *            right-hand sides P_00r (-L_h rho^beta) and P_00r (-L_h rho^alpha)
+ *            (Section 3.1 with m = n = 0; Appendix A table)      (mu = 1 only)
+ *   vhat   = phi + mu V_LR,  f = vhat - v,  v <- Anderson(v, f)
+ * and reports ||f|| / ||v||.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    ofdft_grid grid;
+    int radius;                /* FD order / 2, 1..6                                     */
+    double lambda;             /* von Weizsacker weight (TFW: 0.2)                      */
+    int mu;                    /* 0: TFW, 1: add the K_00 linear-response kernel term     */
+    double n_electrons;        /* N_e                                                     */
+    int history;               /* Anderson history m                                      */
+    double zeta;               /* Anderson mixing parameter                               */
+    double u_tol;              /* stop U when ||H u - eta u|| / ||u|| <= u_tol            */
+    int n_restart;             /* Polak-Ribiere restart period                            */
+    int u_max_iter;
+    double poisson_tol;        /* relative residual of the Poisson solve                  */
+    int poisson_mode;          /* OFDFT_PLAIN_F64 or OFDFT_REFINED_F32                    */
+    double helmholtz_tol;      /* relative residual of each shifted solve                 */
+    ofdft_dtype helmholtz_dtype; /* OFDFT_C128 or OFDFT_C64                               */
+    int max_iter;              /* Krylov iteration cap per solve                          */
+} ofdft_scf_params;
+
+typedef struct ofdft_scf ofdft_scf;
+/* b: device FP64 nuclear charge density; u0: device FP64 initial sqrt-density.
+ * Both are copied.  Computes v_0 = phi[u0] + mu V_LR[u0]. */
+int ofdft_scf_create(const ofdft_scf_params *p, const double *b, const double *u0,
+                     ofdft_scf **out, void *stream);
+int ofdft_scf_destroy(ofdft_scf *s);
+int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream);
+
+/* State access for checkpointing and inspection.  which: 0 = v, 1 = u, 2 = phi,
+ * 3 = V_LR.  dst/src are device FP64 arrays of nx*ny*nz values. */
+int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream);
+int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
+/* Statistics of the last step: [0] U iterations, [1] Poisson iterations,
+ * [2] total shifted-solve iterations, [3] U residual, [4] Poisson residual,
+ * [5] worst shifted-solve residual, [6] eta. */
+int ofdft_scf_stats(ofdft_scf *s, double *out7);
+
+/* The density update U(v) alone (Algorithm 1), using the context's parameters:
+ * v, u device FP64; u holds the starting guess on entry and U(v) on exit.
+ * iters/residual/eta (host, optional) receive the iteration count, the final
+ * ||H u - eta u|| / ||u|| and eta. */
+int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
+                         double *residual, double *eta, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFDFT_H */

@@ -1,0 +1,43 @@
+// Poisson solver context shared by the plain, refined and learned forms.
+#pragma once
+
+#include "cg.hpp"
+
+struct ofdft_nn;
+
+struct ofdft_poisson {
+    ofdft_grid g{};
+    int radius = 6;
+    int mode = OFDFT_PLAIN_F64;
+    ofdft::Coef<double> coef{};
+    ofdft::Coef<float> coef32{};
+    double *gp = nullptr, *r = nullptr, *pA = nullptr, *pB = nullptr, *Ap = nullptr;
+    float *r32 = nullptr, *d32 = nullptr, *qA = nullptr, *qB = nullptr, *Aq = nullptr;
+    ofdft::CgState *st = nullptr, *st_host = nullptr;
+    double *totals = nullptr, *totals_host = nullptr;
+    ofdft::RedBuf rb{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // learned form
+    ofdft_nn *net = nullptr;
+    double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
+};
+
+namespace ofdft {
+
+template <typename T>
+int cg_k1(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *r, const T *p_old,
+          T *p_new, T *Ap, CgState *st, const RedBuf &rb, hipStream_t s);
+template <typename T>
+int residual_pass(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *x,
+                  const double *gp, T *r, double *totals, const RedBuf &rb, hipStream_t s);
+template <typename T>
+int cg_iterate(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r, T *pA, T *pB,
+               T *Ap, CgState *st, CgState *st_host, const RedBuf &rb, hipStream_t s, int &iters,
+               int &done);
+int status_from_done(int done);
+int poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol, int max_iter,
+                  ofdft_solve_stats &stats, hipStream_t st);
+int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                          ofdft_solve_stats &stats, hipStream_t st);
+
+}  // namespace ofdft

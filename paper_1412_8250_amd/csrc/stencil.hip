@@ -1,0 +1,58 @@
+// fd_laplacian_apply: y = alpha L_h x + beta y for f64 / f32 / c128 / c64.
+#include "stencil_core.hpp"
+#include "tuning.hpp"
+
+namespace ofdft {
+
+template <typename T, int TX, int TYT, int RY>
+static int apply_cfg(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x, void *y,
+                     double alpha, double beta, hipStream_t s, int zlen) {
+    using S = typename VT<T>::S;
+    TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
+    LoadPlain<T> ld{(const T *)x};
+    EpiAxpby<T> ep{(T *)y, (S)alpha, (S)beta};
+    hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T>>), dim3(tg.nblocks),
+                       dim3(TX, TYT), 0, s, tg, c, ld, ep);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+template <typename T>
+static int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x, void *y,
+                   double alpha, double beta, hipStream_t s) {
+    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
+    switch (cfg.shape) {
+        case SHAPE_64x4x4: return apply_cfg<T, 64, 4, 4>(g, c, x, y, alpha, beta, s, cfg.zlen);
+        case SHAPE_64x4x2: return apply_cfg<T, 64, 4, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
+        case SHAPE_32x8x2: return apply_cfg<T, 32, 8, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
+        default: return apply_cfg<T, 64, 4, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
+    }
+}
+
+}  // namespace ofdft
+
+using namespace ofdft;
+
+extern "C" int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
+                                  const void *x, void *y, double alpha, double beta, void *stream) {
+    OFDFT_TRY(check_grid(grid, radius));
+    if (!x || !y) {
+        set_error("fd_laplacian_apply: NULL array pointer");
+        return OFDFT_INVALID_ARG;
+    }
+    if (x == y) {
+        set_error("fd_laplacian_apply: x and y must not overlap");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const Coef<double> c = make_coef(*grid, radius);
+    switch (dtype) {
+        case OFDFT_F64: return apply_t<double>(*grid, c, x, y, alpha, beta, s);
+        case OFDFT_F32: return apply_t<float>(*grid, to_float(c), x, y, alpha, beta, s);
+        case OFDFT_C128: return apply_t<double2>(*grid, c, x, y, alpha, beta, s);
+        case OFDFT_C64: return apply_t<float2>(*grid, to_float(c), x, y, alpha, beta, s);
+        default:
+            set_error("fd_laplacian_apply: unknown dtype %d", (int)dtype);
+            return OFDFT_INVALID_ARG;
+    }
+}

@@ -1,0 +1,59 @@
+// Stencil launch-shape table and heuristics.
+#include <mutex>
+#include <map>
+#include <tuple>
+
+#include "tuning.hpp"
+
+namespace ofdft {
+
+namespace {
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int>, StencilCfg> g_table;   // (nx, ny, nz, bytes)
+}
+
+int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks) {
+    int tx, ty;
+    shape_extent(shape, tx, ty);
+    const int64_t tiles = (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    int64_t chunks = (target_blocks + tiles - 1) / tiles;
+    // keep chunks long enough that the 12-plane queue warm-up stays small
+    const int64_t max_chunks = g.nz / 24 > 0 ? g.nz / 24 : 1;
+    if (chunks > max_chunks) chunks = max_chunks;
+    if (chunks < 1) chunks = 1;
+    if (tiles * chunks > 8192) chunks = 8192 / tiles > 0 ? 8192 / tiles : 1;
+    return (int)((g.nz + chunks - 1) / chunks);
+}
+
+StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_table.find(std::make_tuple(g.nx, g.ny, g.nz, elem_bytes));
+        if (it != g_table.end()) return it->second;
+    }
+    StencilCfg c;
+    if (elem_bytes >= 16) c.shape = SHAPE_64x4x2;        // complex128: 2 rows keep the queue in registers
+    else if (g.nx <= 40) c.shape = SHAPE_32x8x2;
+    else c.shape = SHAPE_64x4x4;
+    c.zlen = zlen_for_blocks(g, c.shape, 1024);
+    return c;
+}
+
+}  // namespace ofdft
+
+// Record a launch shape for one (grid, element size); shape < 0 removes it.
+extern "C" int ofdft_stencil_set_config(int nx, int ny, int nz, int elem_bytes, int shape, int zlen) {
+    using namespace ofdft;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(nx, ny, nz, elem_bytes);
+    if (shape < 0) {
+        g_table.erase(key);
+        return OFDFT_OK;
+    }
+    if (shape >= SHAPE_COUNT || zlen < 0) {
+        set_error("ofdft_stencil_set_config: bad shape %d / zlen %d", shape, zlen);
+        return OFDFT_INVALID_ARG;
+    }
+    g_table[key] = StencilCfg{shape, zlen};
+    return OFDFT_OK;
+}

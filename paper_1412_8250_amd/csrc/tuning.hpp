@@ -1,0 +1,29 @@
+// Launch-shape selection for the stencil kernels.  A small table keyed by
+// (grid size, element bytes) is consulted; entries are measured by the
+// library's own tuner (ofdft_tune_stencil) and can be overridden at run time.
+#pragma once
+
+#include "common.hpp"
+
+namespace ofdft {
+
+enum StencilShape { SHAPE_64x4x4 = 0, SHAPE_64x4x2 = 1, SHAPE_32x8x2 = 2, SHAPE_COUNT = 3 };
+
+struct StencilCfg {
+    int shape;
+    int zlen;     // planes per z chunk (0 = whole axis)
+};
+
+// Tile extents of each shape (x, y).
+inline void shape_extent(int shape, int &tx, int &ty) {
+    switch (shape) {
+        case SHAPE_64x4x4: tx = 64; ty = 16; break;
+        case SHAPE_32x8x2: tx = 32; ty = 16; break;
+        default: tx = 64; ty = 8; break;
+    }
+}
+
+StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes);
+int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks);
+
+}  // namespace ofdft
