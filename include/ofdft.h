@@ -224,6 +224,30 @@ int ofdft_scf_stats(ofdft_scf *s, double *out7);
 int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
                          double *residual, double *eta, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Launch configuration and accounting (not part of the method; used by the
+ * tuner, the benchmark and the tests).
+ *
+ * ofdft_stencil_set_config: fix the stencil launch shape for one grid and
+ *   element size (elem_bytes 4, 8 or 16): shape 0 = 64x16 tile (4 rows per
+ *   thread), 1 = 64x8 tile, 2 = 32x16 tile; zlen = planes per z chunk (0 =
+ *   automatic).  shape < 0 removes the entry.  INVALID_ARG for unknown shapes.
+ * ofdft_batch_set_config: launch shape and workgroups per system (1..16) of
+ *   the persistent shifted-system kernel; shape < 0 / group 0 = automatic.
+ * ofdft_profile_reset: clear the per-class launch counters; classes whose bit
+ *   is set in timed_mask are timed with HIP events on their launch stream.
+ *   Classes: 0 apply, 1 CG stencil pass, 2 CG vector update, 3 true-residual
+ *   passes, 4 persistent COCG, 5 density-update stencil passes, 6 density-update
+ *   vector passes, 7 Anderson, 8 other vector passes.
+ * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
+ *   each result written once), timed launches and their summed milliseconds
+ *   for one class since the last reset (synchronises on pending events).
+ * ------------------------------------------------------------------------ */
+int ofdft_stencil_set_config(int nx, int ny, int nz, int elem_bytes, int shape, int zlen);
+int ofdft_batch_set_config(ofdft_batch *b, int shape, int group);
+int ofdft_profile_reset(unsigned timed_mask);
+int ofdft_profile_read(int cls, int64_t *launches, double *bytes, int64_t *timed, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

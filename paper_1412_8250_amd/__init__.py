@@ -84,6 +84,10 @@ def _declare(l):
         "ofdft_density_update": (_I, [_V, _V, _V, ctypes.POINTER(_I), ctypes.POINTER(_D),
                                       ctypes.POINTER(_D), _V]),
         "ofdft_stencil_set_config": (_I, [_I, _I, _I, _I, _I, _I]),
+        "ofdft_batch_set_config": (_I, [_V, _I, _I]),
+        "ofdft_profile_reset": (_I, [ctypes.c_uint]),
+        "ofdft_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
     }
     for name, (res, args) in sig.items():
         if not hasattr(l, name):
@@ -159,6 +163,30 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
     return y
 
 
+KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
+                  "anderson", "pointwise")
+
+
+def profile_reset(timed=()):
+    """Clear the launch counters; launches of the named classes get HIP-event timing."""
+    mask = 0
+    for name in timed:
+        mask |= 1 << KERNEL_CLASSES.index(name)
+    _check(lib().ofdft_profile_reset(mask))
+
+
+def profile_read() -> dict:
+    """{class: {launches, bytes, timed, ms}} accumulated since the last reset."""
+    out = {}
+    for k, name in enumerate(KERNEL_CLASSES):
+        la, tm = ctypes.c_int64(), ctypes.c_int64()
+        by, ms = ctypes.c_double(), ctypes.c_double()
+        _check(lib().ofdft_profile_read(k, ctypes.byref(la), ctypes.byref(by), ctypes.byref(tm),
+                                        ctypes.byref(ms)))
+        out[name] = {"launches": la.value, "bytes": by.value, "timed": tm.value, "ms": ms.value}
+    return out
+
+
 def set_stencil_config(shape_zyx, elem_bytes: int, shape_id: int, zlen: int = 0):
     nz, ny, nx = shape_zyx
     _check(lib().ofdft_stencil_set_config(nx, ny, nz, elem_bytes, shape_id, zlen))
@@ -189,6 +217,141 @@ class PoissonSolver:
     def close(self):
         if self._h:
             lib().ofdft_poisson_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HelmholtzBatch:
+    """Workspace for many complex shifted systems (-L_h + kappa_j) u_j = f_j."""
+
+    def __init__(self, shapes_zyx, hs_xyz, radius: int = 6, dtype: int = C128):
+        self.shapes = [tuple(s) for s in shapes_zyx]
+        self.n = len(self.shapes)
+        grids = (Grid * self.n)(*[grid_of(s, h) for s, h in zip(self.shapes, hs_xyz)])
+        self._grids = grids
+        self._h = ctypes.c_void_p()
+        _check(lib().ofdft_batch_create(self.n, grids, int(radius), int(dtype), ctypes.byref(self._h)))
+
+    def set_config(self, shape_id: int, group: int):
+        _check(lib().ofdft_batch_set_config(self._h, int(shape_id), int(group)))
+
+    def solve(self, kappas, rhs, xs, rel_tol: float = 1e-8, max_iter: int = 100000, stream=None,
+              allow_not_converged: bool = False):
+        """kappas: sequence of complex; rhs, xs: complex128 CUDA tensors (x = guess in, solution out)."""
+        if len(kappas) != self.n or len(rhs) != self.n or len(xs) != self.n:
+            raise ValueError("one kappa, rhs and x per system")
+        k = (ctypes.c_double * (2 * self.n))()
+        for j, kj in enumerate(kappas):
+            k[2 * j], k[2 * j + 1] = float(complex(kj).real), float(complex(kj).imag)
+        for t, s in zip(list(rhs) + list(xs), self.shapes * 2):
+            if str(t.dtype) != "torch.complex128":
+                raise TypeError("shifted systems take complex128 arrays")
+            _dev(t, s)
+        fp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in rhs])
+        xp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in xs])
+        st = (SolveStats * self.n)()
+        status = lib().cg_helmholtz_solve_batched(self._h, k, fp, xp, float(rel_tol), int(max_iter),
+                                                  st, _stream(stream))
+        ok = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        _check(status, ok)
+        return status, [s.as_dict() for s in st]
+
+    def close(self):
+        if self._h:
+            lib().ofdft_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Anderson:
+    """Anderson mixing state (history m, parameter zeta) for vectors of n values."""
+
+    def __init__(self, n: int, m: int, zeta: float):
+        self._h = ctypes.c_void_p()
+        _check(lib().ofdft_anderson_create(int(n), int(m), float(zeta), ctypes.byref(self._h)))
+
+    def mix(self, v, f, out=None, stream=None):
+        out = v if out is None else out
+        _check(lib().anderson_mix(self._h, _dev(v), _dev(f), _dev(out), _stream(stream)))
+        return out
+
+    def reset(self):
+        _check(lib().ofdft_anderson_reset(self._h))
+
+    def close(self):
+        if self._h:
+            lib().ofdft_anderson_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SCF:
+    """Fixed-point iteration context (mixing variable v = phi + mu V_LR)."""
+
+    V, U, PHI, VLR = 0, 1, 2, 3
+
+    def __init__(self, shape_zyx, h_xyz, b, u0, n_electrons: float, lam: float = 0.2, mu: int = 0,
+                 history: int = 7, zeta: float = 0.3, u_tol: float = 1e-10, n_restart: int = 50,
+                 u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
+                 helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
+                 radius: int = 6, stream=None):
+        self.shape = tuple(shape_zyx)
+        p = ScfParams()
+        p.grid = grid_of(shape_zyx, h_xyz)
+        p.radius, p.lam, p.mu, p.n_electrons = int(radius), float(lam), int(mu), float(n_electrons)
+        p.history, p.zeta, p.u_tol, p.n_restart = int(history), float(zeta), float(u_tol), int(n_restart)
+        p.u_max_iter, p.poisson_tol, p.poisson_mode = int(u_max_iter), float(poisson_tol), int(poisson_mode)
+        p.helmholtz_tol, p.helmholtz_dtype, p.max_iter = float(helmholtz_tol), int(helmholtz_dtype), int(max_iter)
+        self.params = p
+        self._h = ctypes.c_void_p()
+        _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),
+                                      ctypes.byref(self._h), _stream(stream)))
+
+    def step(self, stream=None) -> float:
+        res = ctypes.c_double()
+        _check(lib().ofdft_scf_step(self._h, ctypes.byref(res), _stream(stream)))
+        return res.value
+
+    def get(self, which: int, out, stream=None):
+        _check(lib().ofdft_scf_get(self._h, int(which), _dev(out, self.shape), _stream(stream)))
+        return out
+
+    def set(self, which: int, src, stream=None):
+        _check(lib().ofdft_scf_set(self._h, int(which), _dev(src, self.shape), _stream(stream)))
+
+    def stats(self) -> dict:
+        out = (ctypes.c_double * 7)()
+        _check(lib().ofdft_scf_stats(self._h, out))
+        keys = ("u_iters", "poisson_iters", "helmholtz_iters", "u_res", "poisson_res",
+                "helmholtz_res", "eta")
+        return dict(zip(keys, list(out)))
+
+    def density_update(self, v, u, stream=None, allow_not_converged=False):
+        it, res, eta = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        st = lib().ofdft_density_update(self._h, _dev(v, self.shape), _dev(u, self.shape),
+                                        ctypes.byref(it), ctypes.byref(res), ctypes.byref(eta),
+                                        _stream(stream))
+        _check(st, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        return it.value, res.value, eta.value
+
+    def close(self):
+        if self._h:
+            lib().ofdft_scf_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

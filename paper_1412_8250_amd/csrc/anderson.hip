@@ -232,6 +232,7 @@ struct ofdft_anderson {
     AndState *st = nullptr;
     double *partials = nullptr;
     unsigned int *counter = nullptr;
+    int calls = 0;          // host-side count of mixes since the last reset (accounting only)
 };
 
 namespace {
@@ -239,11 +240,16 @@ namespace {
 template <int M>
 int and_run(ofdft_anderson *a, const double *v, const double *f, double *v_next, hipStream_t s) {
     const int blocks = std::min(kAndBlocks, vec_blocks(a->n));
+    const int have = a->calls > 0 ? 1 : 0;
+    const int cols = std::min(a->calls, a->m);
+    a->calls += 1;
+    ProfScope ps1(K_ANDERSON, (double)a->n * 8.0 * (4 + 2 * (have && a->m > 0) + 2 + cols), s);
     hipLaunchKernelGGL((and_push_gram<M>), dim3(blocks), dim3(kVecThreads), 0, s, a->n, v, f,
                        a->v_prev, a->f_prev, a->S, a->Y, a->st, a->partials, a->counter);
     OFDFT_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL((and_solve<M>), dim3(1), dim3(64), 0, s, a->st, 1e12);
     OFDFT_CHECK_HIP(hipGetLastError());
+    ProfScope ps2(K_ANDERSON, (double)a->n * 8.0 * (3 + 2 * cols), s);
     hipLaunchKernelGGL((and_update<M>), dim3(vec_blocks(a->n)), dim3(kVecThreads), 0, s, a->n, v,
                        f, a->S, a->Y, v_next, a->st, a->zeta);
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -294,6 +300,7 @@ extern "C" int ofdft_anderson_reset(ofdft_anderson *a) {
     if (!a) return OFDFT_INVALID_ARG;
     AndState h{};
     h.m = a->m;
+    a->calls = 0;
     OFDFT_CHECK_HIP(hipMemcpy(a->st, &h, sizeof(AndState), hipMemcpyHostToDevice));
     return OFDFT_OK;
 }

@@ -76,6 +76,8 @@ struct EpiCgAp {
 
 template <typename T>
 struct CgUpdate {     // K2 body
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 6 * sizeof(T);
     T *__restrict__ x;
     T *__restrict__ r;
     const T *__restrict__ p;

@@ -1,0 +1,335 @@
+// The density update U(v) (Appendix C, Algorithm 1; Section 3.3 fixed-point map):
+// minimise  h^3 sum [C_F rho^{5/3} + eps_xc(rho) rho + v rho] - (lambda/2) h^3 sum u L_h u
+// over u with h^3 sum u^2 = N_e, by Polak-Ribiere non-linear CG with restarts,
+// a line search and renormalisation.  Gradient: 2 H u with
+//   H u = -(lambda/2) L_h u + (V_TF + V_xc + v) u.
+//
+// GPU work per iteration (FP64):
+//   Ka  stencil pass on u: L u and H u; totals <u,Hu>, <u,Lu>, <u,u>; eta on device
+//   Kb  r = -2 (H u - eta u); totals <r,r>, <r,r_prev>
+//   Kd  stencil pass on the new direction d = r + xi d_prev (formed while loading);
+//       stores d and L d; totals <u,d>, <d,d>, <u,Ld>, <d,Ld>
+//   Ke  (per line-search probe) sum of (V_TF+V_xc+v)(rho_s) w (d - t w), w = u + s d
+//   Kf  u <- sqrt(N_e) (u + s d) / ||u + s d||
+// The line search finds the root of dE/ds with Brent's method; the von
+// Weizsacker part of dE/ds is a quadratic in s built from the Kd/Ka totals, so
+// each probe reads only u, d and v.
+#include <algorithm>
+#include <cmath>
+
+#include "physics.hpp"
+#include "scf.hpp"
+
+namespace ofdft {
+
+namespace {
+
+// device scalar slots
+enum {
+    S_UHU = 0, S_ULU, S_UU, S_ETA, S_RR, S_RRP, S_UD, S_DD, S_ULD, S_DLD, S_EVAL, S_COUNT
+};
+
+struct EpiHu {
+    const double *__restrict__ v;
+    double *__restrict__ Hu;
+    double *__restrict__ Lu;
+    double *dsc;
+    double *partials;
+    unsigned int *counter;
+    double half_lam, inv_ne_dv;
+    double a0, a1, a2;
+    __device__ bool skip() const { return false; }
+    __device__ void point(int64_t i, double c, double s) {
+        const double rho = c * c;
+        const double vl = rho > 0.0 ? v_local(rho) : 0.0;
+        const double hu = ::fma(-half_lam, s, (vl + v[i]) * c);
+        Lu[i] = s;
+        Hu[i] = hu;
+        a0 = ::fma(c, hu, a0);
+        a1 = ::fma(c, s, a1);
+        a2 = ::fma(c, c, a2);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[3] = {a0, a1, a2};
+        block_sum<3>(x, scratch);
+        if (publish_partial<3>(x, partials, nblocks, block, counter)) {
+            double t[3];
+            sum_partials<3>(partials, nblocks, t);
+            dsc[S_UHU] = t[0];
+            dsc[S_ULU] = t[1];
+            dsc[S_UU] = t[2];
+            dsc[S_ETA] = t[0] * inv_ne_dv;          // eta = h^3 <u,Hu> / N_e
+        }
+    }
+};
+
+struct ResidOp {        // r = -2 (Hu - eta u); totals {<r,r>, <r,r_prev>}
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 32;
+    const double *Hu, *u, *r_prev;
+    double *r;
+    const double *dsc;
+    int have_prev;
+    double eta;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() { eta = dsc[S_ETA]; }
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double ri = -2.0 * (Hu[i] - eta * u[i]);
+        r[i] = ri;
+        acc[0] = ::fma(ri, ri, acc[0]);
+        if (have_prev) acc[1] = ::fma(ri, r_prev[i], acc[1]);
+    }
+};
+
+struct LoadDir {        // d = r + xi d_prev (xi = 0: steepest descent)
+    const double *__restrict__ r;
+    const double *__restrict__ d_prev;
+    double xi;
+    __device__ void prepare() {}
+    __device__ double operator()(int64_t i) const { return xi != 0.0 ? ::fma(xi, d_prev[i], r[i]) : r[i]; }
+};
+
+struct EpiLd {
+    const double *__restrict__ u;
+    double *__restrict__ d;
+    double *__restrict__ Ld;
+    double *totals;
+    double *partials;
+    unsigned int *counter;
+    double a0, a1, a2, a3;
+    __device__ bool skip() const { return false; }
+    __device__ void point(int64_t i, double c, double s) {
+        const double ui = u[i];
+        d[i] = c;
+        Ld[i] = s;
+        a0 = ::fma(ui, c, a0);
+        a1 = ::fma(c, c, a1);
+        a2 = ::fma(ui, s, a2);
+        a3 = ::fma(c, s, a3);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[4] = {a0, a1, a2, a3};
+        block_sum<4>(x, scratch);
+        if (publish_partial<4>(x, partials, nblocks, block, counter)) {
+            double t[4];
+            sum_partials<4>(partials, nblocks, t);
+            for (int k = 0; k < 4; ++k) totals[k] = t[k];
+        }
+    }
+};
+
+struct EvalOp {         // sum (V_loc(rho_s) + v) w (d - t w),  w = u + s d,  rho_s = c2 w^2
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 24;
+    const double *u, *d, *v;
+    double s, c2, t;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double w = ::fma(s, d[i], u[i]);
+        const double rho = c2 * w * w;
+        const double vl = rho > 0.0 ? v_local(rho) : 0.0;
+        acc[0] = ::fma((vl + v[i]) * w, ::fma(-t, w, d[i]), acc[0]);
+    }
+};
+
+struct StepOp {         // u <- c (u + s d)
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 24;
+    double *u;
+    const double *d;
+    double s, c;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { u[i] = c * ::fma(s, d[i], u[i]); }
+};
+
+template <class Load, class Epi>
+int stencil_pass(const ofdft_grid &g, const Coef<double> &c, const Load &ld, const Epi &ep, hipStream_t s,
+                 int bytes_per_point) {
+    const StencilCfg cfg = pick_stencil_cfg(g, 8);
+    ProfScope ps(K_U_STENCIL, (double)npoints(g) * bytes_per_point, s);
+    switch (cfg.shape) {
+        case SHAPE_64x4x4: {
+            TileGeom tg = make_tile_geom<64, 4, 4>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 4, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
+            break;
+        }
+        case SHAPE_32x8x2: {
+            TileGeom tg = make_tile_geom<32, 8, 2>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 32, 8, 2, Load, Epi>), dim3(tg.nblocks), dim3(32, 8), 0, s, tg, c, ld, ep);
+            break;
+        }
+        default: {
+            TileGeom tg = make_tile_geom<64, 4, 2>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 2, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
+            break;
+        }
+    }
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+int fetch(ofdft_scf *s, int first, int count, hipStream_t st) {
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + first, s->dsc + first, sizeof(double) * count,
+                                   hipMemcpyDeviceToHost, st));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+    return OFDFT_OK;
+}
+
+// Brent's method for a root of f on [a, b] with f(a) f(b) <= 0 (Brent 1973:
+// bisection safeguarding secant / inverse quadratic interpolation steps).
+template <class F>
+int brent_root(F &&f, double a, double b, double fa, double fb, double tol, int maxit, double &root) {
+    double c = a, fc = fa, d = b - a, e = d;
+    for (int it = 0; it < maxit; ++it) {
+        if ((fb > 0) == (fc > 0)) {
+            c = a;
+            fc = fa;
+            d = e = b - a;
+        }
+        if (std::fabs(fc) < std::fabs(fb)) {
+            a = b; b = c; c = a;
+            fa = fb; fb = fc; fc = fa;
+        }
+        const double tol1 = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 0.5 * tol;
+        const double xm = 0.5 * (c - b);
+        if (std::fabs(xm) <= tol1 || fb == 0.0) {
+            root = b;
+            return OFDFT_OK;
+        }
+        if (std::fabs(e) >= tol1 && std::fabs(fa) > std::fabs(fb)) {
+            double p, q, r;
+            const double sr = fb / fa;
+            if (a == c) {
+                p = 2.0 * xm * sr;
+                q = 1.0 - sr;
+            } else {
+                q = fa / fc;
+                r = fb / fc;
+                p = sr * (2.0 * xm * q * (q - r) - (b - a) * (r - 1.0));
+                q = (q - 1.0) * (r - 1.0) * (sr - 1.0);
+            }
+            if (p > 0) q = -q;
+            p = std::fabs(p);
+            if (2.0 * p < std::min(3.0 * xm * q - std::fabs(tol1 * q), std::fabs(e * q))) {
+                e = d;
+                d = p / q;
+            } else {
+                d = xm;
+                e = d;
+            }
+        } else {
+            d = xm;
+            e = d;
+        }
+        a = b;
+        fa = fb;
+        b += std::fabs(d) > tol1 ? d : (xm > 0 ? tol1 : -tol1);
+        int st = f(b, fb);
+        if (st != OFDFT_OK) return st;
+    }
+    root = b;
+    return OFDFT_OK;
+}
+
+}  // namespace
+
+int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
+                   hipStream_t st) {
+    const ofdft_grid &g = s->g;
+    const int64_t n = s->n;
+    const double ne = s->p.n_electrons, dv = s->dv, lam = s->p.lambda;
+    const double sqn = std::sqrt(ne);
+    double *r_cur = s->rA, *r_prev = s->rB, *d_cur = s->dA, *d_prev = s->dB;
+    double *tot = s->dsc + 16;          // Kd totals
+    int q = 0;
+    double rr_prev = 0.0;
+    res = INFINITY;
+    eta = 0.0;
+    double s_prev = s->s_prev;
+    const int maxit = s->p.u_max_iter > 0 ? s->p.u_max_iter : 20000;
+    const int nres = s->p.n_restart > 0 ? s->p.n_restart : 50;
+    for (;;) {
+        // Ka: H u
+        OFDFT_TRY(stencil_pass(g, s->coef, LoadPlain<double>{u},
+                               EpiHu{v, s->Hu, s->Lu, s->dsc, s->rb.partials, s->rb.counter, 0.5 * lam,
+                                     dv / ne, 0, 0, 0},
+                               st, 32));
+        // Kb: r
+        ResidOp ro{s->Hu, u, r_prev, r_cur, s->dsc, q > 0, 0.0};
+        OFDFT_TRY((launch_reduce<2>(n, ro, StoreTotals<2>{s->dsc + S_RR}, s->rb, st)));
+        OFDFT_TRY(fetch(s, 0, S_COUNT, st));
+        const double *h = s->hsc;
+        eta = h[S_ETA];
+        const double rr = h[S_RR], uu = h[S_UU];
+        res = 0.5 * std::sqrt(rr / uu);
+        if (!std::isfinite(res)) return OFDFT_NONFINITE;
+        if (res <= s->p.u_tol || q >= maxit) break;
+        double xi = 0.0;
+        if (q > 0) xi = (rr - h[S_RRP]) / rr_prev;    // <r - r_prev, r> / <r_prev, r_prev>
+        if (q % nres == 0 || !(xi > 0.0)) xi = 0.0;
+        // Kd: d = r + xi d_prev, L d
+        auto make_dir = [&](double xiv) -> int {
+            OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{r_cur, d_prev, xiv},
+                                   EpiLd{u, d_cur, s->Ld, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0}, st, 40));
+            OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 16, tot, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+            OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+            return OFDFT_OK;
+        };
+        OFDFT_TRY(make_dir(xi));
+        double ud = s->hsc[16], dd = s->hsc[17], uLd = s->hsc[18], dLd = s->hsc[19];
+        const double uLu = h[S_ULU];
+        if (!(dd > 0.0)) break;
+        // dE/ds (up to the positive factor 2 h^3)
+        auto slope = [&](double sv, double &out) -> int {
+            const double ww = uu + sv * (2.0 * ud + sv * dd);
+            const double t = (ud + sv * dd) / ww;
+            const double c2 = ne / (dv * ww);
+            EvalOp ev{u, d_cur, v, sv, c2, t};
+            OFDFT_TRY((launch_reduce<1>(n, ev, StoreTotals<1>{s->dsc + S_EVAL}, s->rb, st)));
+            OFDFT_TRY(fetch(s, S_EVAL, 1, st));
+            const double vw = uLd + sv * dLd - t * (uLu + sv * (2.0 * uLd + sv * dLd));
+            out = c2 * (s->hsc[S_EVAL] - 0.5 * lam * vw);
+            return OFDFT_OK;
+        };
+        double f0;
+        OFDFT_TRY(slope(0.0, f0));
+        if (!(f0 < 0.0) && xi != 0.0) {          // not a descent direction: restart along r
+            xi = 0.0;
+            OFDFT_TRY(make_dir(0.0));
+            ud = s->hsc[16]; dd = s->hsc[17]; uLd = s->hsc[18]; dLd = s->hsc[19];
+            OFDFT_TRY(slope(0.0, f0));
+        }
+        if (!(f0 < 0.0)) break;                  // no descent possible at this precision
+        double lo = 0.0, flo = f0;
+        double hi = s_prev > 0 ? s_prev : 1.0 / std::sqrt(std::max(dd * dv / ne, 1e-300));
+        double fhi;
+        OFDFT_TRY(slope(hi, fhi));
+        int grow = 0;
+        while (fhi < 0.0 && grow < 80) {
+            lo = hi;
+            flo = fhi;
+            hi *= 2.0;
+            OFDFT_TRY(slope(hi, fhi));
+            ++grow;
+        }
+        if (!std::isfinite(fhi)) return OFDFT_NONFINITE;
+        double sstar = hi;
+        OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, 1e-15 * hi, 200, sstar));
+        const double ww = uu + sstar * (2.0 * ud + sstar * dd);
+        const double c = sqn / std::sqrt(dv * ww);
+        StepOp so{u, d_cur, sstar, c};
+        OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+        s_prev = std::fabs(sstar);
+        rr_prev = rr;
+        std::swap(r_cur, r_prev);
+        std::swap(d_cur, d_prev);
+        ++q;
+    }
+    s->s_prev = s_prev;
+    iters = q;
+    return OFDFT_OK;
+}
+
+}  // namespace ofdft

@@ -363,6 +363,8 @@ struct EpiHRes {         // r = f - A x in complex128; totals {|r|^2, |f|^2}
 };
 
 struct CastC64 {         // f32 = r / ||r||, x32 = 0
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 32;
     const double2 *r;
     float2 *f32;
     float2 *x32;
@@ -378,6 +380,8 @@ struct CastC64 {         // f32 = r / ||r||, x32 = 0
 };
 
 struct AddC64 {          // x += ||r|| x32
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 40;
     double2 *x;
     const float2 *x32;
     const double *totals;
@@ -458,6 +462,7 @@ int launch_persistent(ofdft_batch *b, int P, int nsys_run, double tol, hipStream
     int *abort_flag = b->d_abort;
     void *args[] = {(void *)&sys, (void *)&st, (void *)&order, (void *)&nsys_run, (void *)&ctl,
                     (void *)&P, (void *)&queue, (void *)&abort_flag, (void *)&tol};
+    ProfScope ps(K_COCG, 0.0, s);     // bytes are added after the run from the iteration counts
     OFDFT_CHECK_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(blocks), dim3(TX, TYT), args,
                                                0, s));
     return OFDFT_OK;
@@ -465,10 +470,12 @@ int launch_persistent(ofdft_batch *b, int P, int nsys_run, double tol, hipStream
 
 template <typename T>
 int run_persistent(ofdft_batch *b, int shape, int P, int nsys_run, double tol, hipStream_t s) {
+    if constexpr (sizeof(T) == 8) {      // complex64 can afford four rows per thread
+        if (shape == SHAPE_64x4x4) return launch_persistent<T, 64, 4, 4>(b, P, nsys_run, tol, s);
+    }
     switch (shape) {
-        case SHAPE_64x4x2: return launch_persistent<T, 64, 4, 2>(b, P, nsys_run, tol, s);
-        case SHAPE_64x4x4: return launch_persistent<T, 64, 4, 4>(b, P, nsys_run, tol, s);
-        default: return launch_persistent<T, 32, 8, 2>(b, P, nsys_run, tol, s);
+        case SHAPE_32x8x2: return launch_persistent<T, 32, 8, 2>(b, P, nsys_run, tol, s);
+        default: return launch_persistent<T, 64, 4, 2>(b, P, nsys_run, tol, s);
     }
 }
 
@@ -479,6 +486,7 @@ int residual_c128(ofdft_batch *b, int j, const double2 *f, const double2 *x, dou
     TileGeom tg = make_tile_geom<64, 4, 2>(g, zlen_for_blocks(g, SHAPE_64x4x2, 512));
     LoadPlain<double2> ld{x};
     EpiHRes<double2> ep{f, r, make_double2(kre, kim), totals, b->rb.partials, b->rb.counter, 0.0, 0.0};
+    ProfScope ps(K_RESIDUAL, (double)npoints(g) * (r ? 48 : 32), s);
     hipLaunchKernelGGL((stencil_kernel<double2, 64, 4, 2, LoadPlain<double2>, EpiHRes<double2>>),
                        dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -520,10 +528,11 @@ int upload_systems(ofdft_batch *b, const double *kappa, const std::vector<const 
         int tx, ty;
         shape_extent(shape, tx, ty);
         const int zl = zlen_for_units(g, shape);
-        switch (shape) {
-            case SHAPE_64x4x2: h.tg = make_tile_geom<64, 4, 2>(g, zl); break;
+        const int eff = (shape == SHAPE_64x4x4 && !c64) ? SHAPE_64x4x2 : shape;
+        switch (eff) {
             case SHAPE_64x4x4: h.tg = make_tile_geom<64, 4, 4>(g, zl); break;
-            default: h.tg = make_tile_geom<32, 8, 2>(g, zl); break;
+            case SHAPE_32x8x2: h.tg = make_tile_geom<32, 8, 2>(g, zl); break;
+            default: h.tg = make_tile_geom<64, 4, 2>(g, zl); break;
         }
         h.nunits = h.tg.nblocks;
         h.n = npoints(g);
@@ -673,10 +682,16 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
             set_error("cg_helmholtz_solve_batched: persistent kernel aborted (barrier wait expired)");
             return OFDFT_HIP_ERROR;
         }
+        double bytes = 0.0;
+        const double e = c64 ? 8.0 : 16.0;
         for (int j : which) {
             iters[j] += hst[j].iter;
             done[j] = hst[j].done;
+            // init: read x, f, write r; per iteration: read r, p_old, write p, Ap;
+            // read x, p, r, Ap, write x, r
+            bytes += (double)npoints(b->grids[j]) * e * (3.0 + 10.0 * hst[j].iter);
         }
+        prof_add(K_COCG, bytes, 0);
         return OFDFT_OK;
     };
 

@@ -24,6 +24,7 @@ int launch_k1(const ofdft_grid &g, int zlen, const Coef<typename VT<T>::S> &c, c
     TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
     LoadCgP<T> ld{r, p_old, st, 0, 0};
     EpiCgAp<T> ep{p_new, Ap, st, rb.partials, rb.counter, 0.0};
+    ProfScope ps(K_CG_STENCIL, (double)npoints(g) * sizeof(T) * 4, s);
     hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadCgP<T>, EpiCgAp<T>>), dim3(tg.nblocks),
                        dim3(TX, TYT), 0, s, tg, c, ld, ep);
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -36,6 +37,7 @@ int launch_residual(const ofdft_grid &g, int zlen, const Coef<typename VT<T>::S>
     TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
     LoadPlain<T> ld{x};
     EpiResidual<T> ep{gp, r, totals, rb.partials, rb.counter, 0.0, 0.0};
+    ProfScope ps(K_RESIDUAL, (double)npoints(g) * (2 * sizeof(T) + 8), s);
     hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiResidual<T>>),
                        dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -75,6 +77,8 @@ template int residual_pass<double>(const ofdft_grid &, const Coef<double> &, con
 
 // ---- small vector kernels --------------------------------------------------
 struct SumOp {           // totals {sum a, sum a^2}
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 8;
     const double *a;
     __device__ bool skip() const { return false; }
     __device__ void prepare() {}
@@ -86,6 +90,8 @@ struct SumOp {           // totals {sum a, sum a^2}
 };
 
 struct ShiftOp {         // out = a - mean (mean = totals[0] / n), totals' {., sum out^2}
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
     const double *a;
     double *out;
     const double *totals;
@@ -101,6 +107,8 @@ struct ShiftOp {         // out = a - mean (mean = totals[0] / n), totals' {., s
 };
 
 struct CastScaleOp {     // r32 = (r - mean) * inv_norm, d32 = 0, totals {., sum r32^2}
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
     const double *r;
     float *r32;
     float *d32;
@@ -122,6 +130,8 @@ struct CastScaleOp {     // r32 = (r - mean) * inv_norm, d32 = 0, totals {., sum
 };
 
 struct AddScaledOp {     // x += ||r|| d32   (||r|| from the residual totals)
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 20;
     double *x;
     const float *d32;
     const double *totals;

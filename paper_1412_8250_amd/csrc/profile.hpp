@@ -1,0 +1,52 @@
+// Launch accounting: every kernel launch adds its algorithmic HBM bytes (the
+// bytes the method must move: each operand read once, each result written
+// once) to a per-class counter; classes selected with ofdft_profile_reset()
+// are also timed with HIP events recorded on the launch stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ofdft {
+
+enum KClass {
+    K_APPLY = 0,       // fd_laplacian_apply
+    K_CG_STENCIL,      // CG: p update + stencil + p.Ap
+    K_CG_UPDATE,       // CG: x, r update + r.r
+    K_RESIDUAL,        // true-residual stencil passes
+    K_COCG,            // persistent batched COCG
+    K_U_STENCIL,       // density update: H u and L d passes
+    K_U_VECTOR,        // density update: residual, line-search probes, step
+    K_ANDERSON,
+    K_POINTWISE,       // other vector passes (projections, casts, assembly)
+    K_CLASSES
+};
+
+void prof_add(int cls, double bytes, int64_t launches = 1);
+bool prof_timed(int cls);
+void prof_record(int cls, hipEvent_t a, hipEvent_t b);
+hipEvent_t prof_event();
+
+// RAII helper around one launch.
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int c, double bytes, hipStream_t st) : cls(c), s(st) {
+        prof_add(c, bytes);
+        if (prof_timed(c)) {
+            a = prof_event();
+            b = prof_event();
+            if (a && b) (void)hipEventRecord(a, s);
+        }
+    }
+    ~ProfScope() {
+        if (a && b) {
+            (void)hipEventRecord(b, s);
+            prof_record(cls, a, b);
+        }
+    }
+};
+
+}  // namespace ofdft

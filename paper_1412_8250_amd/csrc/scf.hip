@@ -1,0 +1,361 @@
+// ofdft_scf_step: one step of the fixed-point iteration (Section 3.3 and its
+// flowchart; Appendix D), with mixing variable v = phi + mu V_LR:
+//   u = U(v); phi = Poisson(4 pi (u^2 + b)); V_LR from the 8 K_00 shifted solves
+//   (mu = 1); vhat = phi + mu V_LR; f = vhat - v; v <- Anderson(v, f).
+// Kernel-term constants: K_00 row of the Appendix A table (r = 1, 3 printed;
+// r = 2, 4 their complex conjugates), alpha = 5/6 + sqrt(5)/6,
+// beta = 5/6 - sqrt(5)/6 (Section 5), kF = (3 pi^2 N_e / |Omega|)^{1/3}.
+// With m = n = 0 the right-hand side of each shifted equation is
+// P_r (-L_h rho^p) after multiplying through by (2 kF)^2, and
+// kappa_r = (2 kF)^2 Q_r.  V_{beta,r} (solution for rho^beta) multiplies
+// alpha rho^{alpha-1} in V_LR and V_{alpha,r} multiplies beta rho^{beta-1}.
+#include <cmath>
+#include <new>
+
+#include "physics.hpp"
+#include "scf.hpp"
+
+namespace ofdft {
+
+namespace {
+
+const double kAlpha = 5.0 / 6.0 + 0.37267799624996495;   // sqrt(5)/6
+const double kBeta = 5.0 / 6.0 - 0.37267799624996495;
+const double kP00[4][2] = {{0.108403, 0.079657}, {0.108403, -0.079657},
+                           {-0.908403, 0.439708}, {-0.908403, -0.439708}};
+const double kQ00[4][2] = {{-0.470923, -0.465392}, {-0.470923, 0.465392},
+                           {0.066051, -0.259678}, {0.066051, 0.259678}};
+
+struct PoissonRhsOp {   // g = 4 pi (u^2 + b)
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *u, *b;
+    double *g;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double ui = u[i];
+        g[i] = 4.0 * kPi * ::fma(ui, ui, b[i]);
+    }
+};
+
+struct PowersOp {       // rho^alpha, rho^beta
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *u;
+    double *ra, *rb;
+    double a, bb;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double rho = u[i] * u[i];
+        ra[i] = rho > 0.0 ? pow(rho, a) : 0.0;
+        rb[i] = rho > 0.0 ? pow(rho, bb) : 0.0;
+    }
+};
+
+struct ShiftRhsOp {     // F_j = P_j f_beta (j < 4), P_{j-4} f_alpha (j >= 4)
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 144;
+    const double *fa, *fb;
+    double2 *F0, *F1, *F2, *F3, *F4, *F5, *F6, *F7;
+    double pr[4], pi[4];
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double b_ = fb[i], a_ = fa[i];
+        F0[i] = make_double2(pr[0] * b_, pi[0] * b_);
+        F1[i] = make_double2(pr[1] * b_, pi[1] * b_);
+        F2[i] = make_double2(pr[2] * b_, pi[2] * b_);
+        F3[i] = make_double2(pr[3] * b_, pi[3] * b_);
+        F4[i] = make_double2(pr[0] * a_, pi[0] * a_);
+        F5[i] = make_double2(pr[1] * a_, pi[1] * a_);
+        F6[i] = make_double2(pr[2] * a_, pi[2] * a_);
+        F7[i] = make_double2(pr[3] * a_, pi[3] * a_);
+    }
+};
+
+struct VlrOp {          // V_LR = C_F Re sum [alpha rho^(alpha-1) V_beta,r + beta rho^(beta-1) V_alpha,r]
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 144;
+    const double *u;
+    const double2 *V0, *V1, *V2, *V3, *V4, *V5, *V6, *V7;
+    double *vlr;
+    double floor_rho, a, bb;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double rho = fmax(u[i] * u[i], floor_rho);
+        const double vb = V0[i].x + V1[i].x + V2[i].x + V3[i].x;
+        const double va = V4[i].x + V5[i].x + V6[i].x + V7[i].x;
+        vlr[i] = kCF * (a * pow(rho, a - 1.0) * vb + bb * pow(rho, bb - 1.0) * va);
+    }
+};
+
+struct MixResidOp {     // vhat = phi + mu vlr; f = vhat - v; totals {|f|^2, |v|^2}
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 32;
+    const double *phi, *vlr, *v;
+    double *f;
+    double mu;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double vh = mu != 0.0 ? ::fma(mu, vlr[i], phi[i]) : phi[i];
+        const double vi = v[i];
+        const double fi = vh - vi;
+        f[i] = fi;
+        acc[0] = ::fma(fi, fi, acc[0]);
+        acc[1] = ::fma(vi, vi, acc[1]);
+    }
+};
+
+struct CopyOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
+    const double *a;
+    double *b;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { b[i] = a[i]; }
+};
+
+template <typename P_>
+int salloc(ofdft_scf *s, P_ **p, size_t bytes) {
+    void *q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+        set_error("ofdft_scf: out of device memory (%zu bytes)", bytes);
+        return OFDFT_NO_MEMORY;
+    }
+    s->allocs.push_back(q);
+    *p = (P_ *)q;
+    return OFDFT_OK;
+}
+
+void scf_free(ofdft_scf *s) {
+    if (s->pois) ofdft_poisson_destroy(s->pois);
+    if (s->batch) ofdft_batch_destroy(s->batch);
+    if (s->mix) ofdft_anderson_destroy(s->mix);
+    for (void *p : s->allocs)
+        if (p) (void)hipFree(p);
+    s->allocs.clear();
+    if (s->hsc) (void)hipHostFree(s->hsc);
+    redbuf_free(s->rb);
+}
+
+// vhat -> s->fres (phi and the shifted solutions are updated as warm starts)
+int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, int &helm_it,
+                  double &helm_res) {
+    const int64_t n = s->n;
+    OFDFT_TRY((launch_reduce<1>(n, PoissonRhsOp{s->u, s->b, s->g4}, NoFin{}, s->rb, st)));
+    ofdft_solve_stats ps{};
+    int pst = poisson_solve(s->pois, s->g4, s->phi, s->p.poisson_tol, s->p.max_iter, ps, st);
+    if (pst < 0) return pst;
+    pois_res = ps.rel_res;
+    pois_it = ps.iters;
+    helm_it = 0;
+    helm_res = 0.0;
+    if (s->p.mu) {
+        OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
+        OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
+        OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
+        ShiftRhsOp sr{s->f_a, s->f_b, s->Fr[0], s->Fr[1], s->Fr[2], s->Fr[3], s->Fr[4], s->Fr[5],
+                      s->Fr[6], s->Fr[7], {}, {}};
+        for (int r = 0; r < 4; ++r) {
+            sr.pr[r] = kP00[r][0];
+            sr.pi[r] = kP00[r][1];
+        }
+        OFDFT_TRY((launch_reduce<1>(n, sr, NoFin{}, s->rb, st)));
+        const void *rhs[8];
+        void *xs[8];
+        for (int j = 0; j < 8; ++j) {
+            rhs[j] = s->Fr[j];
+            xs[j] = s->Vr[j];
+        }
+        ofdft_solve_stats hs[8];
+        int hst = cg_helmholtz_solve_batched(s->batch, s->kappa, rhs, xs, s->p.helmholtz_tol,
+                                             s->p.max_iter, hs, st);
+        if (hst < 0) return hst;
+        for (int j = 0; j < 8; ++j) {
+            helm_it += hs[j].iters;
+            helm_res = std::max(helm_res, hs[j].rel_res);
+        }
+        const double rho_bar = s->p.n_electrons / ((double)n * s->dv);
+        VlrOp vo{s->u, s->Vr[0], s->Vr[1], s->Vr[2], s->Vr[3], s->Vr[4], s->Vr[5], s->Vr[6], s->Vr[7],
+                 s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
+        OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+    }
+    return OFDFT_OK;
+}
+
+}  // namespace
+
+}  // namespace ofdft
+
+using namespace ofdft;
+
+extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, const double *u0,
+                                ofdft_scf **out, void *stream) {
+    if (!p || !b || !u0 || !out) {
+        set_error("ofdft_scf_create: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_TRY(check_grid(&p->grid, p->radius));
+    if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
+        !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0))) {
+        set_error("ofdft_scf_create: invalid parameters");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    ofdft_scf *s = new (std::nothrow) ofdft_scf();
+    if (!s) return OFDFT_NO_MEMORY;
+    s->p = *p;
+    if (s->p.max_iter <= 0) s->p.max_iter = 100000;
+    s->g = p->grid;
+    s->n = npoints(p->grid);
+    s->dv = p->grid.hx * p->grid.hy * p->grid.hz;
+    s->coef = make_coef(p->grid, p->radius);
+    auto fail = [&](int code) {
+        scf_free(s);
+        delete s;
+        return code;
+    };
+    const size_t b8 = sizeof(double) * s->n;
+    int rc = OFDFT_OK;
+    double **vecs[] = {&s->b, &s->u, &s->v, &s->phi, &s->vlr, &s->fres, &s->g4, &s->Hu, &s->Lu,
+                       &s->rA, &s->rB, &s->dA, &s->dB, &s->Ld};
+    for (double **q : vecs)
+        if ((rc = salloc(s, q, b8))) return fail(rc);
+    if ((rc = salloc(s, &s->dsc, sizeof(double) * 64))) return fail(rc);
+    if (hipHostMalloc(&s->hsc, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) return fail(OFDFT_NO_MEMORY);
+    if ((rc = redbuf_alloc(s->rb))) return fail(rc);
+    if (p->mu) {
+        if ((rc = salloc(s, &s->rho_a, b8)) || (rc = salloc(s, &s->rho_b, b8)) ||
+            (rc = salloc(s, &s->f_a, b8)) || (rc = salloc(s, &s->f_b, b8)))
+            return fail(rc);
+        for (int j = 0; j < 8; ++j)
+            if ((rc = salloc(s, &s->Fr[j], 2 * b8)) || (rc = salloc(s, &s->Vr[j], 2 * b8))) return fail(rc);
+        const double volume = (double)s->n * s->dv;
+        const double kf = std::cbrt(3.0 * kPi * kPi * p->n_electrons / volume);
+        const double k2 = 4.0 * kf * kf;
+        for (int j = 0; j < 8; ++j) {
+            s->kappa[2 * j] = k2 * kQ00[j % 4][0];
+            s->kappa[2 * j + 1] = k2 * kQ00[j % 4][1];
+        }
+        ofdft_grid grids[8];
+        for (int j = 0; j < 8; ++j) grids[j] = p->grid;
+        if ((rc = ofdft_batch_create(8, grids, p->radius,
+                                     p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
+            return fail(rc);
+        for (int j = 0; j < 8; ++j)
+            if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
+    }
+    const int pmode = p->poisson_mode == OFDFT_REFINED_F32 ? OFDFT_REFINED_F32 : OFDFT_PLAIN_F64;
+    if ((rc = ofdft_poisson_create(&p->grid, p->radius, pmode, &s->pois))) return fail(rc);
+    if ((rc = ofdft_anderson_create(s->n, p->history, p->zeta, &s->mix))) return fail(rc);
+    if (hipMemcpyAsync(s->b, b, b8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(s->u, u0, b8, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        hipMemsetAsync(s->phi, 0, b8, st) != hipSuccess || hipMemsetAsync(s->vlr, 0, b8, st) != hipSuccess ||
+        hipMemsetAsync(s->v, 0, b8, st) != hipSuccess)
+        return fail(OFDFT_HIP_ERROR);
+    // v_0 = phi[u_0] + mu V_LR[u_0]
+    double pr, hr;
+    int pit, hit;
+    if ((rc = potential_map(s, st, pr, pit, hit, hr)) < 0) return fail(rc);
+    if ((rc = launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)p->mu},
+                               NoFin{}, s->rb, st)) < 0)
+        return fail(rc);
+    // v = 0 + f  (MixResidOp wrote f = vhat - 0)
+    if ((rc = launch_reduce<1>(s->n, CopyOp{s->fres, s->v}, NoFin{}, s->rb, st)) < 0) return fail(rc);
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
+    *out = s;
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_scf_destroy(ofdft_scf *s) {
+    if (!s) return OFDFT_OK;
+    scf_free(s);
+    delete s;
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
+    if (!s) {
+        set_error("ofdft_scf_step: NULL context");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int uit = 0;
+    double ures = 0, eta = 0;
+    OFDFT_TRY(density_update(s, s->v, s->u, uit, ures, eta, st));
+    double pr = 0, hr = 0;
+    int pit = 0, hit = 0;
+    OFDFT_TRY(potential_map(s, st, pr, pit, hit, hr));
+    OFDFT_TRY((launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)s->p.mu},
+                                StoreTotals<2>{s->dsc + 40}, s->rb, st)));
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 40, s->dsc + 40, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    OFDFT_TRY(anderson_mix(s->mix, s->v, s->fres, s->v, st));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+    const double f2 = s->hsc[40], v2 = s->hsc[41];
+    const double res = v2 > 0 ? std::sqrt(f2 / v2) : std::sqrt(f2);
+    if (fp_residual) *fp_residual = res;
+    s->last[0] = uit;
+    s->last[1] = pit;
+    s->last[2] = hit;
+    s->last[3] = ures;
+    s->last[4] = pr;
+    s->last[5] = hr;
+    s->last[6] = eta;
+    return std::isfinite(res) ? OFDFT_OK : OFDFT_NONFINITE;
+}
+
+static double *state_ptr(ofdft_scf *s, int which) {
+    switch (which) {
+        case 0: return s->v;
+        case 1: return s->u;
+        case 2: return s->phi;
+        case 3: return s->vlr;
+        default: return nullptr;
+    }
+}
+
+extern "C" int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream) {
+    double *p = s ? state_ptr(s, which) : nullptr;
+    if (!p || !dst) {
+        set_error("ofdft_scf_get: bad context, index or destination");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipMemcpyAsync(dst, p, sizeof(double) * s->n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream) {
+    double *p = s ? state_ptr(s, which) : nullptr;
+    if (!p || !src) {
+        set_error("ofdft_scf_set: bad context, index or source");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipMemcpyAsync(p, src, sizeof(double) * s->n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_scf_stats(ofdft_scf *s, double *out7) {
+    if (!s || !out7) return OFDFT_INVALID_ARG;
+    for (int k = 0; k < 7; ++k) out7[k] = s->last[k];
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
+                                    double *residual, double *eta, void *stream) {
+    if (!s || !v || !u) {
+        set_error("ofdft_density_update: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    int it = 0;
+    double res = 0, e = 0;
+    OFDFT_TRY(density_update(s, v, u, it, res, e, (hipStream_t)stream));
+    if (iters) *iters = it;
+    if (residual) *residual = res;
+    if (eta) *eta = e;
+    return res <= s->p.u_tol ? OFDFT_OK : OFDFT_NOT_CONVERGED;
+}

@@ -1,0 +1,43 @@
+// Fixed-point (SCF-type) context: state vectors, solver contexts and the
+// density-update workspace.
+#pragma once
+
+#include "poisson.hpp"
+
+struct ofdft_batch;
+struct ofdft_anderson;
+
+struct ofdft_scf {
+    ofdft_scf_params p{};
+    ofdft_grid g{};
+    int64_t n = 0;
+    double dv = 0;                       // h_x h_y h_z (quadrature weight, Section 4)
+    ofdft::Coef<double> coef{};
+    // state
+    double *b = nullptr, *u = nullptr, *v = nullptr, *phi = nullptr, *vlr = nullptr;
+    double *fres = nullptr, *g4 = nullptr;
+    // kernel-term work (mu = 1)
+    double *rho_a = nullptr, *rho_b = nullptr, *f_a = nullptr, *f_b = nullptr;
+    double2 *Fr[8] = {}, *Vr[8] = {};
+    double kappa[16] = {};
+    // density update workspace
+    double *Hu = nullptr, *Lu = nullptr, *rA = nullptr, *rB = nullptr, *dA = nullptr, *dB = nullptr,
+           *Ld = nullptr;
+    double s_prev = 0;
+    // solver contexts
+    ofdft_poisson *pois = nullptr;
+    ofdft_batch *batch = nullptr;
+    ofdft_anderson *mix = nullptr;
+    ofdft::RedBuf rb{};
+    double *dsc = nullptr, *hsc = nullptr;   // device / pinned host scalars
+    double last[8] = {};                     // statistics of the last step
+    std::vector<void *> allocs;
+};
+
+namespace ofdft {
+
+// U(v): Algorithm 1 from the current s->u; v is a device array.
+int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
+                   hipStream_t st);
+
+}  // namespace ofdft

@@ -11,6 +11,7 @@ static int apply_cfg(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, cons
     TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
     LoadPlain<T> ld{(const T *)x};
     EpiAxpby<T> ep{(T *)y, (S)alpha, (S)beta};
+    ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
     hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T>>), dim3(tg.nblocks),
                        dim3(TX, TYT), 0, s, tg, c, ld, ep);
     OFDFT_CHECK_HIP(hipGetLastError());

@@ -21,6 +21,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace ofdft {
 

@@ -1,7 +1,10 @@
 // Grid-stride elementwise kernels with fused deterministic reductions.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
+#include "profile.hpp"
 
 namespace ofdft {
 
@@ -45,12 +48,26 @@ struct RedBuf {
 constexpr int kRedSlots = 8192;
 constexpr int kRedMaxK = 8;
 
+// Accounting class and algorithmic bytes per element of an elementwise op
+// (ops without kBytes count as pointwise work with no bytes recorded).
+template <class F, class = void>
+struct OpInfo {
+    static constexpr int cls = K_POINTWISE;
+    static constexpr int bytes = 0;
+};
+template <class F>
+struct OpInfo<F, std::void_t<decltype(F::kBytes)>> {
+    static constexpr int cls = F::kClass;
+    static constexpr int bytes = F::kBytes;
+};
+
 template <int K, class F, class Fin>
 inline int launch_reduce(int64_t n, const F &f, const Fin &fin, const RedBuf &rb, hipStream_t s,
                          int blocks = 0) {
     static_assert(K <= kRedMaxK, "too many reduction values");
     if (blocks <= 0) blocks = vec_blocks(n);
     if (blocks > kRedSlots) blocks = kRedSlots;
+    ProfScope ps(OpInfo<F>::cls, (double)OpInfo<F>::bytes * (double)n, s);
     hipLaunchKernelGGL((reduce_kernel<K, F, Fin>), dim3(blocks), dim3(kVecThreads), 0, s, n, f, fin,
                        rb.partials, rb.counter);
     OFDFT_CHECK_HIP(hipGetLastError());
