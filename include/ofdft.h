@@ -209,9 +209,14 @@ int ofdft_scf_destroy(ofdft_scf *s);
 int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream);
 
 /* State access for checkpointing and inspection.  which: 0 = v, 1 = u, 2 = phi,
- * 3 = V_LR.  dst/src are device FP64 arrays of nx*ny*nz values. */
+ * 3 = V_LR (device FP64 arrays of nx*ny*nz values); 4..11 = the solution of
+ * shifted system which-4, kept as its next warm start (device complex128
+ * arrays, 2*nx*ny*nz doubles; mu = 1 only).  INVALID_ARG for other values. */
 int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream);
 int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
+/* Forget the Anderson history and the line-search step memory, so that the
+ * next step behaves like the first step from the current state. */
+int ofdft_scf_reset_history(ofdft_scf *s);
 /* Statistics of the last step: [0] U iterations, [1] Poisson iterations,
  * [2] total shifted-solve iterations, [3] U residual, [4] Poisson residual,
  * [5] worst shifted-solve residual, [6] eta. */

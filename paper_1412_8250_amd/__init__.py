@@ -81,6 +81,7 @@ def _declare(l):
         "ofdft_scf_get": (_I, [_V, _I, _V, _V]),
         "ofdft_scf_set": (_I, [_V, _I, _V, _V]),
         "ofdft_scf_stats": (_I, [_V, ctypes.POINTER(_D)]),
+        "ofdft_scf_reset_history": (_I, [_V]),
         "ofdft_density_update": (_I, [_V, _V, _V, ctypes.POINTER(_I), ctypes.POINTER(_D),
                                       ctypes.POINTER(_D), _V]),
         "ofdft_stencil_set_config": (_I, [_I, _I, _I, _I, _I, _I]),
@@ -328,11 +329,31 @@ class SCF:
         return res.value
 
     def get(self, which: int, out, stream=None):
+        """Copy state vector `which` into `out` (float64 for 0..3, complex128 for 4..11)."""
         _check(lib().ofdft_scf_get(self._h, int(which), _dev(out, self.shape), _stream(stream)))
         return out
 
     def set(self, which: int, src, stream=None):
         _check(lib().ofdft_scf_set(self._h, int(which), _dev(src, self.shape), _stream(stream)))
+
+    def reset_history(self):
+        _check(lib().ofdft_scf_reset_history(self._h))
+
+    def snapshot(self):
+        """Device copies of every state vector (restorable with restore())."""
+        import torch
+        snap = {}
+        for which in range(12 if self.params.mu else 4):
+            dt = torch.float64 if which < 4 else torch.complex128
+            t = torch.empty(self.shape, dtype=dt, device="cuda")
+            self.get(which, t)
+            snap[which] = t
+        return snap
+
+    def restore(self, snap):
+        for which, t in snap.items():
+            self.set(which, t)
+        self.reset_history()
 
     def stats(self) -> dict:
         out = (ctypes.c_double * 7)()

@@ -28,20 +28,20 @@ struct CgState {
 };
 
 template <typename T>
-struct LoadCgP {      // operand of K1: r + beta p_old (beta = 0 on the first iteration)
+struct LoadCgP {      // operand of K1: r + beta p_old (first iteration: p_old := r, beta := 0)
     const T *__restrict__ r;
     const T *__restrict__ p_old;
     const CgState *st;
     typename VT<T>::S beta;
-    int first;
     __device__ void prepare() {
-        first = st->first;
-        beta = (typename VT<T>::S)st->beta;
+        if (st->first) {
+            p_old = r;
+            beta = 0;
+        } else {
+            beta = (typename VT<T>::S)st->beta;
+        }
     }
-    __device__ T operator()(int64_t i) const {
-        if (first) return r[i];
-        return VT<T>::fma(beta, p_old[i], r[i]);
-    }
+    __device__ T operator()(int64_t i) const { return VT<T>::fma(beta, p_old[i], r[i]); }
 };
 
 template <typename T>
@@ -53,7 +53,8 @@ struct EpiCgAp {
     unsigned int *counter;
     double acc;
     __device__ bool skip() const { return st->done != CG_RUNNING; }
-    __device__ void point(int64_t i, T c, T s) {
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, T c, T s) {
         const T a = VT<T>::mul(typename VT<T>::S(-1), s);
         p_out[i] = c;
         Ap[i] = a;
@@ -117,9 +118,11 @@ struct EpiResidual {
     double *partials;
     unsigned int *counter;
     double acc0, acc1;
+    double gv[4];
     __device__ bool skip() const { return false; }
-    __device__ void point(int64_t i, T, T s) {
-        const double v = g[i] + (double)s;
+    __device__ void pre(int q, int64_t i) { gv[q] = g[i]; }
+    __device__ void point(int q, int64_t i, T, T s) {
+        const double v = gv[q] + (double)s;
         r[i] = (T)v;
         acc0 += v;
         acc1 = ::fma(v, v, acc1);

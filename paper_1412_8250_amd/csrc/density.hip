@@ -38,11 +38,13 @@ struct EpiHu {
     unsigned int *counter;
     double half_lam, inv_ne_dv;
     double a0, a1, a2;
+    double vv[4];
     __device__ bool skip() const { return false; }
-    __device__ void point(int64_t i, double c, double s) {
+    __device__ void pre(int q, int64_t i) { vv[q] = v[i]; }
+    __device__ void point(int q, int64_t i, double c, double s) {
         const double rho = c * c;
         const double vl = rho > 0.0 ? v_local(rho) : 0.0;
-        const double hu = ::fma(-half_lam, s, (vl + v[i]) * c);
+        const double hu = ::fma(-half_lam, s, (vl + vv[q]) * c);
         Lu[i] = s;
         Hu[i] = hu;
         a0 = ::fma(c, hu, a0);
@@ -81,12 +83,14 @@ struct ResidOp {        // r = -2 (Hu - eta u); totals {<r,r>, <r,r_prev>}
     }
 };
 
-struct LoadDir {        // d = r + xi d_prev (xi = 0: steepest descent)
+struct LoadDir {        // d = r + xi d_prev (xi = 0: steepest descent, with d_prev := r)
     const double *__restrict__ r;
     const double *__restrict__ d_prev;
     double xi;
-    __device__ void prepare() {}
-    __device__ double operator()(int64_t i) const { return xi != 0.0 ? ::fma(xi, d_prev[i], r[i]) : r[i]; }
+    __device__ void prepare() {
+        if (xi == 0.0) d_prev = r;
+    }
+    __device__ double operator()(int64_t i) const { return ::fma(xi, d_prev[i], r[i]); }
 };
 
 struct EpiLd {
@@ -97,9 +101,11 @@ struct EpiLd {
     double *partials;
     unsigned int *counter;
     double a0, a1, a2, a3;
+    double uv[4];
     __device__ bool skip() const { return false; }
-    __device__ void point(int64_t i, double c, double s) {
-        const double ui = u[i];
+    __device__ void pre(int q, int64_t i) { uv[q] = u[i]; }
+    __device__ void point(int q, int64_t i, double c, double s) {
+        const double ui = uv[q];
         d[i] = c;
         Ld[i] = s;
         a0 = ::fma(ui, c, a0);

@@ -31,7 +31,7 @@
 
 namespace ofdft {
 
-constexpr int kMaxGroupP = 16;
+constexpr int kMaxGroupP = 1024;
 constexpr long kSpinLimit = 1L << 22;
 
 enum HDone { H_RUNNING = 0, H_CONVERGED = 1, H_BREAKDOWN = 2, H_NONFINITE = 3, H_MAXIT = 4 };
@@ -56,8 +56,6 @@ struct HState {
 struct GroupCtl {
     unsigned int count, gen;
     int sys, pad;
-    double partA[kMaxGroupP][4];
-    double partB[kMaxGroupP][4];
 };
 
 template <typename T> struct CX;
@@ -122,16 +120,12 @@ struct LoadX {
 };
 
 template <typename T>
-struct LoadCocgP {       // r + beta p_old (complex beta), or r on the first iteration
+struct LoadCocgP {       // r + beta p_old (complex beta); first iteration: p_old = r, beta = 0
     const T *__restrict__ r;
     const T *__restrict__ p_old;
     T beta;
-    int first;
     __device__ void prepare() {}
-    __device__ T operator()(int64_t i) const {
-        if (first) return r[i];
-        return cfma(beta, p_old[i], r[i]);
-    }
+    __device__ T operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
 };
 
 template <typename T>
@@ -140,9 +134,11 @@ struct EpiInitRes {      // r = f - (-L x + kappa x); acc {r.r re, r.r im, |r|^2
     T *__restrict__ r;
     T kappa;
     double acc[4];
-    __device__ void point(int64_t i, T c, T s) {
+    T fv[4];
+    __device__ void pre(int q, int64_t i) { fv[q] = f[i]; }
+    __device__ void point(int q, int64_t i, T c, T s) {
         T ax = cfma(kappa, c, T{-s.x, -s.y});
-        const T fi = f[i];
+        const T fi = fv[q];
         T rv{fi.x - ax.x, fi.y - ax.y};
         r[i] = rv;
         const double a = rv.x, b = rv.y;
@@ -159,7 +155,8 @@ struct EpiCocgAp {       // p_new = centre, Ap = -L p + kappa p; acc {p.Ap re, i
     T *__restrict__ Ap;
     T kappa;
     double acc[4];
-    __device__ void point(int64_t i, T c, T s) {
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, T c, T s) {
         T a = cfma(kappa, c, T{-s.x, -s.y});
         p_out[i] = c;
         Ap[i] = a;
@@ -168,12 +165,19 @@ struct EpiCocgAp {       // p_new = centre, Ap = -L p + kappa p; acc {p.Ap re, i
     }
 };
 
-// Sum the P partial rows (fixed order) into out[0..3]; leader thread only.
+// Sum the P partial rows of a group into out[0..3], by the first wave: lane q
+// accumulates rows q, q+64, ... then a fixed shuffle tree combines the lanes,
+// so the result does not depend on timing.
 __device__ inline void combine(const double (*part)[4], int P, double *out) {
+    const int lane = threadIdx.x + threadIdx.y * blockDim.x;
+    if (lane >= 64) return;
+    double a[4] = {0, 0, 0, 0};
+    for (int q = lane; q < P; q += 64)
+        for (int k = 0; k < 4; ++k)
+            a[k] += __hip_atomic_load(&part[q][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int k = 0; k < 4; ++k) {
-        double s = 0.0;
-        for (int q = 0; q < P; ++q) s += __hip_atomic_load(&part[q][k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        out[k] = s;
+        const double t = wave_sum(a[k]);
+        if (lane == 0) out[k] = t;
     }
 }
 
@@ -204,9 +208,9 @@ __device__ inline void publish4(double (&acc)[4], double (*part)[4], int rank, d
 }
 
 template <typename T, int TX, int TYT, int RY>
-__device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, int P, int rank, T *lds,
-                               double *scratch, double *bcast, int *abort_flag, int *s_flag,
-                               double tol) {
+__device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, double (*partA)[4],
+                               double (*partB)[4], int P, int rank, T *lds, double *scratch,
+                               double *bcast, int *abort_flag, int *s_flag, double tol) {
     using CT = CX<T>;
     const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
     const int tid = threadIdx.y * TX + threadIdx.x;
@@ -222,10 +226,10 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, int P, in
         LoadX<T> ld{x};
         EpiInitRes<T> ep{f, r, kappa, {0, 0, 0, 0}};
         stencil_units<T, TX, TYT, RY>(s, w, ld, ep, rank, P, lds);
-        publish4(ep.acc, c->partB, rank, scratch);
+        publish4(ep.acc, partB, rank, scratch);
     }
     if (!group_barrier(c, P, abort_flag, s_flag)) return;
-    if (leader) combine(c->partB, P, bcast);
+    combine(partB, P, bcast);
     __syncthreads();
     double rr_re = bcast[0], rr_im = bcast[1], rn2 = bcast[2];
     const double fn2 = bcast[3];
@@ -240,13 +244,13 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, int P, in
     while (done == H_RUNNING) {
         // Phase A: p = r + beta p_old; Ap = (-L + kappa) p; p.Ap
         {
-            LoadCocgP<T> ld{r, p_old, CT::mk(be_re, be_im), iter == 0};
+            LoadCocgP<T> ld{r, iter == 0 ? r : p_old, CT::mk(iter == 0 ? 0.0 : be_re, iter == 0 ? 0.0 : be_im)};
             EpiCocgAp<T> ep{p_new, Ap, kappa, {0, 0, 0, 0}};
             stencil_units<T, TX, TYT, RY>(s, w, ld, ep, rank, P, lds);
-            publish4(ep.acc, c->partA, rank, scratch);
+            publish4(ep.acc, partA, rank, scratch);
         }
         if (!group_barrier(c, P, abort_flag, s_flag)) return;
-        if (leader) combine(c->partA, P, bcast);
+        combine(partA, P, bcast);
         __syncthreads();
         const double pa_re = bcast[0], pa_im = bcast[1];
         const double den = pa_re * pa_re + pa_im * pa_im;
@@ -270,10 +274,10 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, int P, in
                 acc[1] += 2.0 * a * b;
                 acc[2] += a * a + b * b;
             }
-            publish4(acc, c->partB, rank, scratch);
+            publish4(acc, partB, rank, scratch);
         }
         if (!group_barrier(c, P, abort_flag, s_flag)) return;
-        if (leader) combine(c->partB, P, bcast);
+        combine(partB, P, bcast);
         __syncthreads();
         const double nr_re = bcast[0], nr_im = bcast[1];
         rn2 = bcast[2];
@@ -303,15 +307,18 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, int P, in
 
 template <typename T, int TX, int TYT, int RY>
 __global__ void __launch_bounds__(TX * TYT)
-cocg_persistent(const HSys *sys, HState *st, const int *order, int nsys, GroupCtl *ctl, int P,
-                unsigned int *queue, int *abort_flag, double tol) {
+cocg_persistent(const HSys *sys, HState *st, const int *order, int nsys, GroupCtl *ctl,
+                double (*part)[4], int P, unsigned int *queue, int *abort_flag, double tol) {
     using TS = TileShape<TX, TYT, RY>;
-    __shared__ T lds[TS::W * TS::H];
+    __shared__ T lds[2 * (TS::W * TS::H + 1)];
     __shared__ double scratch[4 * (TX * TYT / 64)];
     __shared__ double bcast[4];
     __shared__ int s_flag, s_sys;
     const int group = blockIdx.x / P, rank = blockIdx.x % P;
     GroupCtl *c = ctl + group;
+    // partial-sum rows of this group: [A: gridDim rows][B: gridDim rows]
+    double(*partA)[4] = part + (size_t)group * P;
+    double(*partB)[4] = part + gridDim.x + (size_t)group * P;
     const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
     for (;;) {
         if (rank == 0 && leader) {
@@ -325,8 +332,8 @@ cocg_persistent(const HSys *sys, HState *st, const int *order, int nsys, GroupCt
         const int sidx = s_sys;
         __syncthreads();
         if (sidx < 0) return;
-        cocg_solve_one<T, TX, TYT, RY>(sys[sidx], st + sidx, c, P, rank, lds, scratch, bcast,
-                                       abort_flag, &s_flag, tol);
+        cocg_solve_one<T, TX, TYT, RY>(sys[sidx], st + sidx, c, partA, partB, P, rank, lds, scratch,
+                                       bcast, abort_flag, &s_flag, tol);
         if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     }
 }
@@ -341,10 +348,12 @@ struct EpiHRes {         // r = f - A x in complex128; totals {|r|^2, |f|^2}
     double *partials;
     unsigned int *counter;
     double acc0, acc1;
+    double2 fv[4];
     __device__ bool skip() const { return false; }
-    __device__ void point(int64_t i, double2 c, double2 s) {
+    __device__ void pre(int q, int64_t i) { fv[q] = f[i]; }
+    __device__ void point(int q, int64_t i, double2 c, double2 s) {
         double2 ax = cfma(kappa, c, double2{-s.x, -s.y});
-        const double2 fi = f[i];
+        const double2 fi = fv[q];
         double2 rv{fi.x - ax.x, fi.y - ax.y};
         if (r) r[i] = rv;
         acc0 += rv.x * rv.x + rv.y * rv.y;
@@ -409,6 +418,7 @@ struct ofdft_batch {
     HState *d_st = nullptr;
     int *d_order = nullptr;
     GroupCtl *d_ctl = nullptr;
+    double (*d_part)[4] = nullptr;    // 2 * groups_cap rows of 4 partial sums
     unsigned int *d_queue = nullptr;
     int *d_abort = nullptr;
     double *d_totals = nullptr;   // 2 per system
@@ -446,10 +456,15 @@ int launch_persistent(ofdft_batch *b, int P, int nsys_run, double tol, hipStream
         set_error("persistent COCG kernel cannot be made resident (occupancy %d, coop %d)", per_cu, coop);
         return OFDFT_HIP_ERROR;
     }
-    int resident = per_cu * cus;
+    const int resident = std::min(per_cu * cus, b->groups_cap);
+    if (P <= 0) {
+        // few systems: spread the whole GPU over them; many: one or two workgroups each
+        P = std::max(1, resident / std::max(1, nsys_run));
+        if (nsys_run >= resident / 2) P = std::max(1, resident / nsys_run);
+    }
+    P = std::min(P, resident);
     int groups = resident / P;
     groups = std::min(groups, std::max(1, nsys_run));
-    groups = std::min(groups, b->groups_cap);
     const int blocks = groups * P;
     OFDFT_CHECK_HIP(hipMemsetAsync(b->d_ctl, 0, sizeof(GroupCtl) * groups, s));
     OFDFT_CHECK_HIP(hipMemsetAsync(b->d_queue, 0, sizeof(unsigned int), s));
@@ -458,10 +473,11 @@ int launch_persistent(ofdft_batch *b, int P, int nsys_run, double tol, hipStream
     HState *st = b->d_st;
     const int *order = b->d_order;
     GroupCtl *ctl = b->d_ctl;
+    double(*part)[4] = b->d_part;
     unsigned int *queue = b->d_queue;
     int *abort_flag = b->d_abort;
     void *args[] = {(void *)&sys, (void *)&st, (void *)&order, (void *)&nsys_run, (void *)&ctl,
-                    (void *)&P, (void *)&queue, (void *)&abort_flag, (void *)&tol};
+                    (void *)&part, (void *)&P, (void *)&queue, (void *)&abort_flag, (void *)&tol};
     ProfScope ps(K_COCG, 0.0, s);     // bytes are added after the run from the iteration counts
     OFDFT_CHECK_HIP(hipLaunchCooperativeKernel((const void *)kern, dim3(blocks), dim3(TX, TYT), args,
                                                0, s));
@@ -617,6 +633,7 @@ extern "C" int ofdft_batch_create(int nsys, const ofdft_grid *grids, int radius,
         (st = dalloc(b, &b->d_st, sizeof(HState) * nsys)) ||
         (st = dalloc(b, &b->d_order, sizeof(int) * nsys)) ||
         (st = dalloc(b, &b->d_ctl, sizeof(GroupCtl) * b->groups_cap)) ||
+        (st = dalloc(b, &b->d_part, sizeof(double) * 4 * 2 * b->groups_cap)) ||
         (st = dalloc(b, &b->d_queue, 256)) || (st = dalloc(b, &b->d_abort, 256)) ||
         (st = dalloc(b, &b->d_totals, sizeof(double) * 2 * nsys)))
         return fail(st);
@@ -650,8 +667,7 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
     const int nsys = b->nsys;
     const bool c64 = b->dtype == OFDFT_C64;
     const int shape = b->shape >= 0 ? b->shape : default_shape(b);
-    int P = b->P;
-    if (P <= 0) P = 2;
+    const int P = b->P;      // 0: chosen per launch from the residency and the system count
     // LPT order: longest estimated solve first
     std::vector<double> cost(nsys);
     for (int j = 0; j < nsys; ++j) cost[j] = est_cost(b->grids[j], kappa[2 * j], kappa[2 * j + 1]);

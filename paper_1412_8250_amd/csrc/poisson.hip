@@ -22,7 +22,7 @@ template <typename T, int TX, int TYT, int RY>
 int launch_k1(const ofdft_grid &g, int zlen, const Coef<typename VT<T>::S> &c, const T *r,
               const T *p_old, T *p_new, T *Ap, CgState *st, const RedBuf &rb, hipStream_t s) {
     TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
-    LoadCgP<T> ld{r, p_old, st, 0, 0};
+    LoadCgP<T> ld{r, p_old, st, 0};
     EpiCgAp<T> ep{p_new, Ap, st, rb.partials, rb.counter, 0.0};
     ProfScope ps(K_CG_STENCIL, (double)npoints(g) * sizeof(T) * 4, s);
     hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadCgP<T>, EpiCgAp<T>>), dim3(tg.nblocks),
@@ -288,7 +288,10 @@ static int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter
 static int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
                          ofdft_solve_stats &stats, hipStream_t st) {
     const int64_t n = npoints(s->g);
-    const double inner_tol = 1e-4;
+    // Each FP32 inner solve targets the reduction still needed (with margin),
+    // bounded below by what FP32 CG reliably reaches and above so that every
+    // outer step makes real progress.
+    const double inner_min = 1e-5, inner_max = 1e-2;
     const int max_outer = 12;
     int total = 0, outer = 0, status = OFDFT_NOT_CONVERGED;
     for (; outer <= max_outer; ++outer) {
@@ -308,6 +311,8 @@ static int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_it
             break;
         }
         if (outer == max_outer || total >= max_iter) break;
+        const double rel = g2 > 0 ? std::sqrt(rn2 / g2) : 0.0;
+        const double inner_tol = std::min(inner_max, std::max(inner_min, 0.3 * rel_tol / rel));
         // r_hat = (r - mean) / ||r - mean|| in FP32, d = 0
         CastScaleOp cs{s->r, s->r32, s->d32, s->totals + 4, 1.0 / (double)n, 0, 0};
         OFDFT_TRY((launch_reduce<2>(n, cs, InitCgFin{s->st, inner_tol * inner_tol, max_iter - total},

@@ -309,34 +309,53 @@ extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
     return std::isfinite(res) ? OFDFT_OK : OFDFT_NONFINITE;
 }
 
-static double *state_ptr(ofdft_scf *s, int which) {
+// State vectors: 0 v, 1 u, 2 phi, 3 V_LR (n doubles); 4..11 the shifted-solve
+// solutions V_j, j = which - 4 (complex128, 2n doubles; mu = 1 only).
+static double *state_ptr(ofdft_scf *s, int which, size_t &count) {
+    count = (size_t)s->n;
     switch (which) {
         case 0: return s->v;
         case 1: return s->u;
         case 2: return s->phi;
         case 3: return s->vlr;
-        default: return nullptr;
+        default:
+            if (which >= 4 && which < 12 && s->Vr[which - 4]) {
+                count = 2 * (size_t)s->n;
+                return (double *)s->Vr[which - 4];
+            }
+            return nullptr;
     }
 }
 
 extern "C" int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream) {
-    double *p = s ? state_ptr(s, which) : nullptr;
+    size_t count = 0;
+    double *p = s ? state_ptr(s, which, count) : nullptr;
     if (!p || !dst) {
         set_error("ofdft_scf_get: bad context, index or destination");
         return OFDFT_INVALID_ARG;
     }
-    OFDFT_CHECK_HIP(hipMemcpyAsync(dst, p, sizeof(double) * s->n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    OFDFT_CHECK_HIP(hipMemcpyAsync(dst, p, sizeof(double) * count, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return OFDFT_OK;
 }
 
 extern "C" int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream) {
-    double *p = s ? state_ptr(s, which) : nullptr;
+    size_t count = 0;
+    double *p = s ? state_ptr(s, which, count) : nullptr;
     if (!p || !src) {
         set_error("ofdft_scf_set: bad context, index or source");
         return OFDFT_INVALID_ARG;
     }
-    OFDFT_CHECK_HIP(hipMemcpyAsync(p, src, sizeof(double) * s->n, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    OFDFT_CHECK_HIP(hipMemcpyAsync(p, src, sizeof(double) * count, hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return OFDFT_OK;
+}
+
+extern "C" int ofdft_scf_reset_history(ofdft_scf *s) {
+    if (!s) {
+        set_error("ofdft_scf_reset_history: NULL context");
+        return OFDFT_INVALID_ARG;
+    }
+    s->s_prev = 0.0;
+    return ofdft_anderson_reset(s->mix);
 }
 
 extern "C" int ofdft_scf_stats(ofdft_scf *s, double *out7) {

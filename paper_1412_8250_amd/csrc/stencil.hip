@@ -10,10 +10,16 @@ static int apply_cfg(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, cons
     using S = typename VT<T>::S;
     TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
     LoadPlain<T> ld{(const T *)x};
-    EpiAxpby<T> ep{(T *)y, (S)alpha, (S)beta};
     ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
-    hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T>>), dim3(tg.nblocks),
-                       dim3(TX, TYT), 0, s, tg, c, ld, ep);
+    if (beta != 0.0) {
+        EpiAxpby<T, true> ep{(T *)y, (S)alpha, (S)beta, {}};
+        hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T, true>>),
+                           dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
+    } else {
+        EpiAxpby<T, false> ep{(T *)y, (S)alpha, (S)beta, {}};
+        hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T, false>>),
+                           dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
+    }
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }

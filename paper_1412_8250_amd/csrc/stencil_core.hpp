@@ -63,9 +63,12 @@ __device__ inline int wrapi(int i, int n) {
     return r < 0 ? r + n : r;
 }
 
-// Loader: T operator()(int64_t idx) const -- value of the operand at idx.
-// Epilogue: void point(int64_t idx, T centre, T lap) for every owned output
-//   point (only valid points are passed), then finish(block, scratch) once.
+// Loader: T operator()(int64_t idx) const -- value of the operand at idx
+//   (branch-free, so that the prefetched loads stay in flight).
+// Epilogue: pre(r, idx) loads the per-point operands of owned row r of the
+//   current plane (issued before the prefetches, so waiting for them does not
+//   drain the pipeline); point(r, idx, centre, lap) for every valid owned
+//   point; finish(block, nblocks, scratch) once per workgroup.
 template <typename T, int TX, int TYT, int RY, class Load, class Epi>
 __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>::S> &w,
                                     const Load &ld, Epi &ep, int logical_block, T *lds) {
@@ -120,9 +123,9 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
             }
             ring_lds[i] = ly * W + lx;
             ring_glb[i] = wrapi(y0 - R + ly, g.ny) * g.nx + wrapi(x0 - R + lx, g.nx);
-        } else {
-            ring_lds[i] = -1;
-            ring_glb[i] = 0;
+        } else {                                  // spare slot: harmless load, dummy LDS cell
+            ring_lds[i] = W * H;
+            ring_glb[i] = own[0];
         }
     }
 
@@ -134,46 +137,77 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[j][r] = ld(pb + own[r]);
     }
+    // Software pipeline: the halo ring is fetched two planes ahead and the
+    // queue front (plane k + R + 1) two planes ahead of its use, so each
+    // plane's global loads overlap two planes of compute.
+    T ringA[TS::RING_PER_T], ringB[TS::RING_PER_T];
+    {
+        const int64_t p0 = (int64_t)zb * nxy, p1 = (int64_t)wrapi(zb + 1, g.nz) * nxy;
+#pragma unroll
+        for (int i = 0; i < TS::RING_PER_T; ++i) {
+            ringA[i] = ld(p0 + ring_glb[i]);
+            ringB[i] = ld(p1 + ring_glb[i]);
+        }
+    }
+    T qn1[RY], qn2[RY];
+    {
+        const int64_t f1 = (int64_t)wrapi(zb + R + 1, g.nz) * nxy;
+        const int64_t f2 = (int64_t)wrapi(zb + R + 2, g.nz) * nxy;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            qn1[r] = ld(f1 + own[r]);
+            qn2[r] = ld(f2 + own[r]);
+        }
+    }
+    int kr = wrapi(zb + 2, g.nz);          // plane of the next ring prefetch
+    int kf = wrapi(zb + R + 3, g.nz);      // plane of the next queue-front prefetch
 
-    int kf = wrapi(zb + R + 1, g.nz);   // plane index of the next queue front
-    for (int k = zb; k < ze; ++k) {
-        const int64_t pk = (int64_t)k * nxy;
-        // prefetch the next queue front and this plane's halo ring
+    // One plane.  `ring`/`qn` hold loads issued two planes earlier; they are
+    // consumed and then refilled in place (no register rotation of in-flight
+    // loads, so the waits only cover old loads).  `active` is false for the
+    // padding plane of an odd-length chunk: it still loads (in bounds) but
+    // stores nothing.
+    auto plane = [&](int k, T (&ring)[TS::RING_PER_T], T (&qn)[RY], bool active, int parity) {
+        const int kk = active ? k : zb;
+        const int64_t pk = (int64_t)kk * nxy;
+        T *buf = lds + parity * (W * H + 1);
+#pragma unroll
+        for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[R][r];
+#pragma unroll
+        for (int i = 0; i < TS::RING_PER_T; ++i) buf[ring_lds[i]] = ring[i];
+        // epilogue operands of this plane first, then the prefetches
+#pragma unroll
+        for (int r = 0; r < RY; ++r) ep.pre(r, pk + own[r]);
         T nxt[RY];
-        const int64_t pf = (int64_t)kf * nxy;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) nxt[r] = ld(pf + own[r]);
-        T ring[TS::RING_PER_T];
+        for (int r = 0; r < RY; ++r) nxt[r] = qn[r];
+        {
+            const int64_t pr = (int64_t)kr * nxy, pf = (int64_t)kf * nxy;
 #pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i)
-            ring[i] = ring_lds[i] >= 0 ? ld(pk + ring_glb[i]) : V::zero();
-
+            for (int i = 0; i < TS::RING_PER_T; ++i) ring[i] = ld(pr + ring_glb[i]);
 #pragma unroll
-        for (int r = 0; r < RY; ++r) lds[(ty * RY + r + R) * W + tx + R] = q[R][r];
-#pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i)
-            if (ring_lds[i] >= 0) lds[ring_lds[i]] = ring[i];
+            for (int r = 0; r < RY; ++r) qn[r] = ld(pf + own[r]);
+        }
         __syncthreads();
 
         // y column values of this thread's x, rows ty*RY - R .. ty*RY + RY - 1 + R
         T col[RY + 2 * R];
 #pragma unroll
-        for (int j = 0; j < RY + 2 * R; ++j) col[j] = lds[(ty * RY + j) * W + tx + R];
+        for (int j = 0; j < RY + 2 * R; ++j) col[j] = buf[(ty * RY + j) * W + tx + R];
 
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             const T c = q[R][r];
-            T s = V::mul(w.c0, c);
-            const T *row = lds + (ty * RY + r + R) * W + tx + R;
+            T sacc = V::mul(w.c0, c);
+            const T *row = buf + (ty * RY + r + R) * W + tx + R;
 #pragma unroll
             for (int p = 1; p <= R; ++p) {
-                s = V::fma(w.wx[p], V::add(row[p], row[-p]), s);
-                s = V::fma(w.wy[p], V::add(col[r + R + p], col[r + R - p]), s);
-                s = V::fma(w.wz[p], V::add(q[R + p][r], q[R - p][r]), s);
+                sacc = V::fma(w.wx[p], V::add(row[p], row[-p]), sacc);
+                sacc = V::fma(w.wy[p], V::add(col[r + R + p], col[r + R - p]), sacc);
+                sacc = V::fma(w.wz[p], V::add(q[R + p][r], q[R - p][r]), sacc);
             }
-            if (xvalid && yvalid[r]) ep.point(pk + own[r], c, s);
+            if (active && xvalid && yvalid[r]) ep.point(r, pk + own[r], c, sacc);
         }
-        __syncthreads();
 
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j)
@@ -181,8 +215,16 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
             for (int r = 0; r < RY; ++r) q[j][r] = q[j + 1][r];
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[2 * R][r] = nxt[r];
+        kr = (kr + 1 == g.nz) ? 0 : kr + 1;
         kf = (kf + 1 == g.nz) ? 0 : kf + 1;
+    };
+
+    for (int k = zb; k < ze; k += 2) {
+        plane(k, ringA, qn1, true, 0);
+        plane(k + 1, ringB, qn2, k + 1 < ze, 1);
     }
+    // the LDS buffers are reused by the next tile of a persistent caller
+    __syncthreads();
 }
 
 // Plain kernel wrapper: one tile per workgroup, XCD-aware tile order, then the
@@ -191,7 +233,7 @@ template <typename T, int TX, int TYT, int RY, class Load, class Epi>
 __global__ void __launch_bounds__(TX * TYT)
 stencil_kernel(TileGeom g, Coef<typename VT<T>::S> w, Load ld, Epi ep) {
     using TS = TileShape<TX, TYT, RY>;
-    __shared__ T lds[TS::W * TS::H];
+    __shared__ T lds[2 * (TS::W * TS::H + 1)];
     __shared__ double red_scratch[64];
     if (ep.skip()) return;
     ld.prepare();
@@ -208,15 +250,19 @@ struct LoadPlain {
     __device__ T operator()(int64_t i) const { return x[i]; }
 };
 
-template <typename T>
-struct EpiAxpby {        // y = alpha * L x + beta * y
+template <typename T, bool ReadY>
+struct EpiAxpby {        // y = alpha * L x + beta * y  (ReadY: beta != 0)
     T *__restrict__ y;
     typename VT<T>::S alpha, beta;
+    T yold[4];
     __device__ bool skip() const { return false; }
-    __device__ void point(int64_t i, T, T s) {
+    __device__ void pre(int r, int64_t i) {
+        if constexpr (ReadY) yold[r] = y[i];
+    }
+    __device__ void point(int r, int64_t i, T, T s) {
         using V = VT<T>;
         T v = V::mul(alpha, s);
-        if (beta != typename VT<T>::S(0)) v = V::fma(beta, y[i], v);
+        if constexpr (ReadY) v = V::fma(beta, yold[r], v);
         y[i] = v;
     }
     __device__ void finish(int, int, double *) {}
