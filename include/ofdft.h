@@ -230,6 +230,45 @@ int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
                          double *residual, double *eta, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Learned solver aid (not in the paper, whose conclusion calls for real-space
+ * preconditioners, Section 5.5).  A 4-level periodic 3D convolutional U-Net
+ * (channels 16/32/64/64, 3x3x3 periodic convolutions, bias-free, ReLU, 2x
+ * average pooling, nearest upsampling, skip concatenation [upsampled, skip])
+ * approximating the inverse of -h^2 L_h.  BF16 weights and activations, FP32
+ * accumulation on the matrix cores, FP32 master weights and Adam.
+ * Grids must be multiples of 8 per axis.
+ *
+ * ofdft_nn_create: He-normal weights from `seed`.
+ * ofdft_nn_param_count: number of FP32 parameters (layer after layer, each
+ *   W[t][ci][co] with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1)).
+ * ofdft_nn_set_weights / ofdft_nn_get_weights: host FP32 arrays of that size;
+ *   get with gradients = 1 returns the last computed weight gradients.
+ * ofdft_nn_reserve: allocate the workspace for one grid (done implicitly by
+ *   forward/train calls; solves require it beforehand).
+ * ofdft_nn_forward: out = scale * rms(in) * N(in / rms(in)) (device FP64).
+ * ofdft_nn_gradients / ofdft_nn_train_step: loss
+ *   ||N(g/rms g) - phi/(h^2 rms g)||^2 / ||phi/(h^2 rms g)||^2 for one pair
+ *   (device FP64 g, phi); train_step also applies Adam (beta 0.9/0.999,
+ *   eps 1e-8) with learning rate lr.  loss (host) may be NULL.
+ * ofdft_poisson_set_network: attach a network to an OFDFT_LEARNED solver
+ *   (the solver keeps the pointer; the network must outlive its use).
+ * ------------------------------------------------------------------------ */
+typedef struct ofdft_nn ofdft_nn;
+int ofdft_nn_create(uint64_t seed, ofdft_nn **out);
+int ofdft_nn_destroy(ofdft_nn *net);
+size_t ofdft_nn_param_count(void);
+int ofdft_nn_set_weights(ofdft_nn *net, const float *w, size_t count);
+int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int gradients);
+int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid);
+int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const double *in, double *out,
+                     double scale, void *stream);
+int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const double *g, const double *phi,
+                       double *loss, void *stream);
+int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g, const double *phi,
+                        double lr, double *loss, void *stream);
+int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
+
+/* ------------------------------------------------------------------------
  * Launch configuration and accounting (not part of the method; used by the
  * tuner, the benchmark and the tests).
  *
@@ -243,7 +282,7 @@ int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
  *   is set in timed_mask are timed with HIP events on their launch stream.
  *   Classes: 0 apply, 1 CG stencil pass, 2 CG vector update, 3 true-residual
  *   passes, 4 persistent COCG, 5 density-update stencil passes, 6 density-update
- *   vector passes, 7 Anderson, 8 other vector passes.
+ *   vector passes, 7 Anderson, 8 other vector passes, 9 network kernels.
  * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
  *   each result written once), timed launches and their summed milliseconds
  *   for one class since the last reset (synchronises on pending events).

@@ -86,6 +86,16 @@ def _declare(l):
                                       ctypes.POINTER(_D), _V]),
         "ofdft_stencil_set_config": (_I, [_I, _I, _I, _I, _I, _I]),
         "ofdft_batch_set_config": (_I, [_V, _I, _I]),
+        "ofdft_nn_create": (_I, [ctypes.c_uint64, ctypes.POINTER(_V)]),
+        "ofdft_nn_destroy": (_I, [_V]),
+        "ofdft_nn_param_count": (ctypes.c_size_t, []),
+        "ofdft_nn_set_weights": (_I, [_V, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+        "ofdft_nn_get_weights": (_I, [_V, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t, _I]),
+        "ofdft_nn_reserve": (_I, [_V, _GP]),
+        "ofdft_nn_forward": (_I, [_V, _GP, _V, _V, _D, _V]),
+        "ofdft_nn_gradients": (_I, [_V, _GP, _V, _V, ctypes.POINTER(_D), _V]),
+        "ofdft_nn_train_step": (_I, [_V, _GP, _V, _V, _D, ctypes.POINTER(_D), _V]),
+        "ofdft_poisson_set_network": (_I, [_V, _V]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
         "ofdft_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
@@ -165,7 +175,7 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
 
 
 KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
-                  "anderson", "pointwise")
+                  "anderson", "pointwise", "nn")
 
 
 def profile_reset(timed=()):
@@ -202,6 +212,11 @@ class PoissonSolver:
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_poisson_create(ctypes.byref(self.grid), int(radius), int(mode),
                                           ctypes.byref(self._h)))
+
+    def set_network(self, net):
+        """Attach a Network (learned mode only); the solver keeps a reference."""
+        self._net = net
+        _check(lib().ofdft_poisson_set_network(self._h, net._h if net is not None else None))
 
     def solve(self, rhs, x, rel_tol: float = 1e-10, max_iter: int = 100000, stream=None,
               allow_not_converged: bool = False) -> dict:
@@ -373,6 +388,76 @@ class SCF:
     def close(self):
         if self._h:
             lib().ofdft_scf_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+NN_LAYERS = (("c0a", 1, 16), ("c0b", 16, 16), ("c1a", 16, 32), ("c1b", 32, 32), ("c2a", 32, 64),
+             ("c2b", 64, 64), ("c3a", 64, 64), ("c3b", 64, 64), ("d2a", 128, 64), ("d2b", 64, 64),
+             ("d1a", 96, 32), ("d1b", 32, 32), ("d0a", 48, 16), ("d0b", 16, 16), ("out", 16, 1))
+
+
+class Network:
+    """The learned solver aid's U-Net (weights on the GPU; see include/ofdft.h)."""
+
+    def __init__(self, seed: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().ofdft_nn_create(int(seed), ctypes.byref(self._h)))
+        self.count = int(lib().ofdft_nn_param_count())
+
+    def _flat(self, layers):
+        import numpy as np
+        return np.ascontiguousarray(np.concatenate(
+            [np.asarray(layers[name], dtype=np.float32).reshape(-1) for name, _, _ in NN_LAYERS]))
+
+    def _split(self, flat):
+        out, off = {}, 0
+        for name, ci, co in NN_LAYERS:
+            k = 27 * ci * co
+            out[name] = flat[off:off + k].reshape(27, ci, co)
+            off += k
+        return out
+
+    def set_weights(self, layers):
+        flat = self._flat(layers)
+        _check(lib().ofdft_nn_set_weights(self._h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          flat.size))
+
+    def get_weights(self, gradients: bool = False):
+        import numpy as np
+        flat = np.empty(self.count, dtype=np.float32)
+        _check(lib().ofdft_nn_get_weights(self._h, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                          flat.size, 1 if gradients else 0))
+        return self._split(flat)
+
+    def forward(self, x, out, h_xyz, scale: float = 1.0, stream=None):
+        g = grid_of(x.shape, h_xyz)
+        _check(lib().ofdft_nn_forward(self._h, ctypes.byref(g), _dev(x), _dev(out, x.shape),
+                                      float(scale), _stream(stream)))
+        return out
+
+    def gradients(self, g_rhs, phi, h_xyz, stream=None) -> float:
+        g = grid_of(g_rhs.shape, h_xyz)
+        loss = ctypes.c_double()
+        _check(lib().ofdft_nn_gradients(self._h, ctypes.byref(g), _dev(g_rhs), _dev(phi, g_rhs.shape),
+                                        ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def train_step(self, g_rhs, phi, h_xyz, lr: float, stream=None) -> float:
+        g = grid_of(g_rhs.shape, h_xyz)
+        loss = ctypes.c_double()
+        _check(lib().ofdft_nn_train_step(self._h, ctypes.byref(g), _dev(g_rhs), _dev(phi, g_rhs.shape),
+                                         float(lr), ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def close(self):
+        if self._h:
+            lib().ofdft_nn_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,55 @@
+// Network context of the learned solver aid.
+#pragma once
+
+#include <vector>
+
+#include "nn_kernels.hpp"
+#include "vec.hpp"
+
+namespace ofdft {
+namespace nn {
+
+constexpr int kLayers = 15;
+struct LayerDef {
+    const char *name;
+    int cin, cout;
+};
+extern const LayerDef kDefs[kLayers];
+
+struct Level {                   // tensors of one resolution level
+    Geo g{};
+    std::vector<u16 *> t;        // activation / gradient buffers (see nn_net.hip)
+};
+
+}  // namespace nn
+}  // namespace ofdft
+
+struct ofdft_nn {
+    // parameters
+    float *w[ofdft::nn::kLayers] = {}, *m[ofdft::nn::kLayers] = {}, *v[ofdft::nn::kLayers] = {},
+          *gr[ofdft::nn::kLayers] = {};
+    ofdft::nn::u16 *wf[ofdft::nn::kLayers] = {}, *wb[ofdft::nn::kLayers] = {};
+    int adam_t = 0;
+    // workspace for one grid
+    int nx = 0, ny = 0, nz = 0;
+    std::vector<void *> ws;
+    ofdft::nn::u16 *buf[64] = {};
+    float *out = nullptr;
+    float *part = nullptr;
+    size_t part_cap = 0;
+    double *totals = nullptr;
+    ofdft::RedBuf rb{};
+    std::vector<void *> allocs;
+};
+
+namespace ofdft {
+namespace nn {
+
+int net_reserve(ofdft_nn *net, const ofdft_grid &g);
+// out (FP64) = h^2 * rms(in) * N(in / rms(in)), optionally shifted to zero mean
+// (scale = h^2).  Workspace must have been reserved for g.
+int net_apply(ofdft_nn *net, const ofdft_grid &g, const double *in, double *out, double h2,
+              bool zero_mean, hipStream_t s);
+
+}  // namespace nn
+}  // namespace ofdft

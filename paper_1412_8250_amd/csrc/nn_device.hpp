@@ -1,0 +1,324 @@
+// Device kernels of the learned solver aid (included by nn_net.hip only).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <random>
+#include <vector>
+
+#include "nn.hpp"
+#include "profile.hpp"
+#include "vec.hpp"
+
+namespace ofdft {
+namespace nn {
+
+// ---------------------------------------------------------------------------
+// Convolution, C_in a multiple of 16.  Block = 4 waves, each 16 points.
+// Weights Wt: [27][NTILE*16][Cin] BF16 (zero rows for co >= Cout).
+// Output: BF16 (with or without ReLU) or FP32 (no ReLU), channels-last Cout.
+template <int NTILE>
+__global__ void __launch_bounds__(256)
+conv_k16(InDesc in, Geo g, const u16 *__restrict__ Wt, int cin, int cout, u16 *out_bf,
+         float *out_f32, int relu) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p0 = (blockIdx.x * 4 + wave) * 16;
+    if (p0 >= g.npts) return;
+    const int m = lane & 15, kq = lane >> 4;
+    int p = p0 + m;
+    if (p >= g.npts) p = p0;
+    const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+    const int xs[3] = {wrapc(x - 1, g.nx), x, wrapc(x + 1, g.nx)};
+    const int ys[3] = {wrapc(y - 1, g.ny), y, wrapc(y + 1, g.ny)};
+    const int zs[3] = {wrapc(z - 1, g.nz), z, wrapc(z + 1, g.nz)};
+    f32x4 acc[NTILE];
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    constexpr int CO = NTILE * 16;
+    for (int t = 0; t < 27; ++t) {
+        const int xx = xs[t % 3], yy = ys[(t / 3) % 3], zz = zs[t / 9];
+        const u16 *wt = Wt + (size_t)t * CO * cin;
+        for (int c0 = 0; c0 < cin; c0 += 16) {
+            const s16x4 a = fetch4(in, xx, yy, zz, c0 + 4 * kq, g);
+#pragma unroll
+            for (int nt = 0; nt < NTILE; ++nt) {
+                const uint2 raw = *reinterpret_cast<const uint2 *>(wt + (size_t)(nt * 16 + m) * cin + c0 + 4 * kq);
+                const s16x4 b = __builtin_bit_cast(s16x4, raw);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) {
+        const int co = nt * 16 + m;
+        if (co >= cout) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = p0 + 4 * kq + i;
+            if (q >= g.npts) continue;
+            float v = acc[nt][i];
+            if (relu) v = fmaxf(v, 0.f);
+            if (out_f32) out_f32[(size_t)q * cout + co] = v;
+            else out_bf[(size_t)q * cout + co] = f2bf(v);
+        }
+    }
+}
+
+// Convolution with one input channel: the 27 taps (padded to 32) form K of a
+// single 16x16x32 step.  W1: [NTILE*16][32] BF16.
+template <int NTILE>
+__global__ void __launch_bounds__(256)
+conv_c1(InDesc in, Geo g, const u16 *__restrict__ W1, int cout, u16 *out_bf, float *out_f32, int relu) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p0 = (blockIdx.x * 4 + wave) * 16;
+    if (p0 >= g.npts) return;
+    const int m = lane & 15, kq = lane >> 4;
+    int p = p0 + m;
+    if (p >= g.npts) p = p0;
+    const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+    s16x8 a;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int t = 8 * kq + j;
+        short v = 0;
+        if (t < 27) {
+            const int xx = wrapc(x + (t % 3) - 1, g.nx), yy = wrapc(y + (t / 3) % 3 - 1, g.ny),
+                      zz = wrapc(z + t / 9 - 1, g.nz);
+            v = (short)fetch1(in, xx, yy, zz, 0, g);
+        }
+        a[j] = v;
+    }
+    const bf16x8 av = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+    for (int nt = 0; nt < NTILE; ++nt) {
+        const uint4 raw = *reinterpret_cast<const uint4 *>(W1 + (size_t)(nt * 16 + m) * 32 + 8 * kq);
+        const bf16x8 b = __builtin_bit_cast(bf16x8, raw);
+        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const int co = nt * 16 + m;
+        if (co >= cout) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int q = p0 + 4 * kq + i;
+            if (q >= g.npts) continue;
+            float v = acc[i];
+            if (relu) v = fmaxf(v, 0.f);
+            if (out_f32) out_f32[(size_t)q * cout + co] = v;
+            else out_bf[(size_t)q * cout + co] = f2bf(v);
+        }
+    }
+}
+
+// Weight gradient partials: part[chunk][t][ci][co] = sum over the chunk's
+// points p of X[p + off_t][ci] * dYm[p][co], dYm = dY * (Y > 0) if ymask.
+// Grid: (chunks, 27, ci_tiles * co_tiles); one wave per block.
+__global__ void __launch_bounds__(64)
+conv_wgrad(InDesc x_in, Geo g, const u16 *__restrict__ dy, const u16 *__restrict__ ymask, int cin,
+           int cout, int chunk_pts, float *__restrict__ part) {
+    const int lane = threadIdx.x;
+    const int chunk = blockIdx.x, t = blockIdx.y;
+    const int cot = (cout + 15) / 16;
+    const int cit = blockIdx.z / cot, co_t = blockIdx.z % cot;
+    const int m = lane & 15, kq = lane >> 4;
+    const int ci = cit * 16 + m, co = co_t * 16 + m;
+    const int dx = t % 3 - 1, dyo = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int pb = chunk * chunk_pts;
+    const int pe = min(pb + chunk_pts, g.npts);
+    for (int k0 = pb; k0 < pe; k0 += 16) {
+        s16x4 a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = k0 + 4 * kq + j;
+            short av = 0, bv = 0;
+            if (p < pe) {
+                const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+                if (ci < cin)
+                    av = (short)fetch1(x_in, wrapc(x + dx, g.nx), wrapc(y + dyo, g.ny), wrapc(z + dz, g.nz), ci, g);
+                if (co < cout) {
+                    u16 d = dy[(size_t)p * cout + co];
+                    if (ymask && !((short)ymask[(size_t)p * cout + co] > 0)) d = 0;
+                    bv = (short)d;
+                }
+            }
+            a[j] = av;
+            b[j] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    // lane holds D[ci = cit*16 + 4*kq + i][co = co_t*16 + m]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int cii = cit * 16 + 4 * kq + i;
+        if (cii < cin && co < cout)
+            part[(((size_t)chunk * 27 + t) * cin + cii) * cout + co] = acc[i];
+    }
+}
+
+// dW[i] = sum over chunks (fixed order) of part[chunk][i]
+__global__ void wgrad_reduce(const float *__restrict__ part, int chunks, int count, float *__restrict__ dw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * count + i];
+    dw[i] = s;
+}
+
+// 2x2x2 average pooling (fine grid g, C channels).
+__global__ void pool2(const u16 *__restrict__ in, Geo g, int C, u16 *__restrict__ out) {
+    const int hx = g.nx / 2, hy = g.ny / 2, hz = g.nz / 2;
+    const int64_t total = (int64_t)hx * hy * hz * C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % C);
+        const int64_t q = i / C;
+        const int x = (int)(q % hx), y = (int)((q / hx) % hy), z = (int)(q / ((int64_t)hx * hy));
+        float s = 0.f;
+        for (int d = 0; d < 8; ++d) {
+            const int xx = 2 * x + (d & 1), yy = 2 * y + ((d >> 1) & 1), zz = 2 * z + (d >> 2);
+            s += bf2f(in[((size_t)(zz * g.ny + yy) * g.nx + xx) * C + c]);
+        }
+        out[i] = f2bf(0.125f * s);
+    }
+}
+
+// Gradient through [up(coarse), skip] concatenation at the fine level:
+// dcoarse[q][c] = sum of dcat[child][c] over the 8 children (c < c1).
+__global__ void up_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1, u16 *__restrict__ dcoarse) {
+    const int hx = g.nx / 2, hy = g.ny / 2, hz = g.nz / 2;
+    const int64_t total = (int64_t)hx * hy * hz * c1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % c1);
+        const int64_t q = i / c1;
+        const int x = (int)(q % hx), y = (int)((q / hx) % hy), z = (int)(q / ((int64_t)hx * hy));
+        float s = 0.f;
+        for (int d = 0; d < 8; ++d) {
+            const int xx = 2 * x + (d & 1), yy = 2 * y + ((d >> 1) & 1), zz = 2 * z + (d >> 2);
+            s += bf2f(dcat[((size_t)(zz * g.ny + yy) * g.nx + xx) * ccat + c]);
+        }
+        dcoarse[i] = f2bf(s);
+    }
+}
+
+// dskip[p][c] = dcat[p][c1 + c] + pool_grad(dpool)[p][c]  (pool_grad = 1/8 of the parent)
+__global__ void skip_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1, int cs,
+                          const u16 *__restrict__ dpool, u16 *__restrict__ dskip) {
+    const int64_t total = (int64_t)g.npts * cs;
+    const int hx = g.nx / 2, hy = g.ny / 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % cs);
+        const int64_t p = i / cs;
+        const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((int64_t)g.nx * g.ny));
+        const size_t parent = ((size_t)(z / 2) * hy + (y / 2)) * hx + (x / 2);
+        dskip[i] = f2bf(bf2f(dcat[(size_t)p * ccat + c1 + c]) + 0.125f * bf2f(dpool[parent * cs + c]));
+    }
+}
+
+// Adam (FP32 masters) + BF16 copies in the forward and transposed layouts.
+struct LayerPtrs {
+    float *w, *m, *v, *g;
+    u16 *wf, *wb;
+    int cin, cout, ntf, ntb;   // padded tile counts of the forward / transposed layouts
+};
+
+__global__ void adam_kernel(LayerPtrs L, float lr, float b1, float b2, float c1, float c2, float eps) {
+    const int count = 27 * L.cin * L.cout;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const float gr = L.g[i];
+        const float m = b1 * L.m[i] + (1.f - b1) * gr;
+        const float v = b2 * L.v[i] + (1.f - b2) * gr * gr;
+        L.m[i] = m;
+        L.v[i] = v;
+        L.w[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+    }
+}
+
+// BF16 copies of layer weights W[t][ci][co] (FP32).
+//   forward, cin >= 16: wf[t][co_pad][ci]; cin == 1: wf[co_pad][32 taps]
+//   transposed (input gradient), flipped taps t' = 26 - t, roles swapped:
+//   cout >= 16: wb[t'][ci_pad][co]; cout == 1: wb[ci_pad][32 taps]
+__global__ void pack_weights(const float *__restrict__ w, int cin, int cout, int ntf, int ntb,
+                             u16 *__restrict__ wf, u16 *__restrict__ wb) {
+    const int cof = ntf * 16, cib = ntb * 16;
+    const int nf = cin == 1 ? cof * 32 : 27 * cof * cin;
+    const int nb = cout == 1 ? cib * 32 : 27 * cib * cout;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nf + nb; i += gridDim.x * blockDim.x) {
+        if (i < nf) {
+            float v = 0.f;
+            if (cin == 1) {
+                const int co = i / 32, t = i % 32;
+                if (co < cout && t < 27) v = w[(size_t)t * cout + co];
+            } else {
+                const int ci = i % cin, co = (i / cin) % cof, t = i / (cin * cof);
+                if (co < cout) v = w[((size_t)t * cin + ci) * cout + co];
+            }
+            wf[i] = f2bf(v);
+        } else {
+            const int j = i - nf;
+            float v = 0.f;
+            if (cout == 1) {
+                const int ci = j / 32, t = j % 32;
+                if (ci < cin && t < 27) v = w[(size_t)(26 - t) * cin + ci];
+            } else {
+                const int co = j % cout, ci = (j / cout) % cib, t = j / (cout * cib);
+                if (ci < cin) v = w[((size_t)(26 - t) * cin + ci) * cout + co];
+            }
+            wb[j] = f2bf(v);
+        }
+    }
+}
+
+// Network input: x = bf16(a * scale); totals of a^2 are computed beforehand.
+struct CastInOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 10;
+    const double *a;
+    u16 *x;
+    const double *totals;       // {sum a^2}
+    double inv_n, scale;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {
+        const double ms = totals[0] * inv_n;
+        scale = ms > 0 ? 1.0 / sqrt(ms) : 0.0;
+    }
+    __device__ void operator()(int64_t i, double (&)[1]) const { x[i] = f2bf((float)(a[i] * scale)); }
+};
+
+struct SqOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 8;
+    const double *a;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const { acc[0] = ::fma(a[i], a[i], acc[0]); }
+};
+
+// Loss ||out - t||^2 / ||t||^2 and dout = 2 (out - t) / ||t||^2 (BF16), with
+// t = phi / (h^2 rms(g)).  totals: {sum g^2 (input), sum phi^2} precomputed.
+struct LossOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 14;
+    const float *out;
+    const double *phi;
+    u16 *dout;
+    const double *totals;
+    double inv_n, h2, tscale, den;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {
+        const double rms = sqrt(totals[0] * inv_n);
+        tscale = rms > 0 ? 1.0 / (h2 * rms) : 0.0;
+        den = totals[1] * tscale * tscale;
+    }
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double t = phi[i] * tscale;
+        const double d = (double)out[i] - t;
+        acc[0] = ::fma(d, d, acc[0]);
+        dout[i] = f2bf((float)(2.0 * d / den));
+    }
+};
+
+}  // namespace nn
+}  // namespace ofdft

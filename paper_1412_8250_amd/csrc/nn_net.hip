@@ -1,0 +1,474 @@
+// Network context: parameters, per-grid workspaces, forward / backward
+// orchestration, Adam, and the C entry points of the learned solver aid.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <random>
+
+#include "nn.hpp"
+#include "nn_device.hpp"
+#include "profile.hpp"
+
+namespace ofdft {
+namespace nn {
+
+const LayerDef kDefs[kLayers] = {
+    {"c0a", 1, 16}, {"c0b", 16, 16}, {"c1a", 16, 32}, {"c1b", 32, 32}, {"c2a", 32, 64},
+    {"c2b", 64, 64}, {"c3a", 64, 64}, {"c3b", 64, 64}, {"d2a", 128, 64}, {"d2b", 64, 64},
+    {"d1a", 96, 32}, {"d1b", 32, 32}, {"d0a", 48, 16}, {"d0b", 16, 16}, {"out", 16, 1},
+};
+
+namespace {
+
+// workspace tensors: (level, channels)
+enum Buf {
+    X0, A0, S0, D0A, D0, P0, A1, S1, D1A, D1, P1, A2, S2, D2A, D2, P2, A3, B3,
+    dOUT, dD0, dD0A, dCAT0, dS0, dA0, dD1, dD1A, dCAT1, dP0, dS1, dA1,
+    dD2, dD2A, dCAT2, dP1, dS2, dA2, dB3, dA3, dP2, NBUF
+};
+const int kBufLevel[NBUF] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 3, 3, 3,
+                             0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 2, 3, 3, 3};
+const int kBufCh[NBUF] = {1, 16, 16, 16, 16, 16, 32, 32, 32, 32, 32, 64, 64, 64, 64, 64, 64, 64,
+                          1, 16, 16, 48, 16, 16, 32, 32, 96, 16, 32, 32, 64, 64, 128, 32, 64, 64,
+                          64, 64, 64};
+constexpr int kChunk = 4096;
+
+int ntile(int c) { return (c + 15) / 16; }
+
+Geo geo_of(const ofdft_nn *net, int level) {
+    Geo g;
+    g.nx = net->nx >> level;
+    g.ny = net->ny >> level;
+    g.nz = net->nz >> level;
+    g.npts = g.nx * g.ny * g.nz;
+    return g;
+}
+
+template <typename P>
+int nalloc(ofdft_nn *net, P **p, size_t bytes, std::vector<void *> &list) {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 256)) != hipSuccess) {
+        set_error("network: out of device memory (%zu bytes)", bytes);
+        return OFDFT_NO_MEMORY;
+    }
+    list.push_back(q);
+    *p = (P *)q;
+    return OFDFT_OK;
+}
+
+InDesc one(const u16 *s, int c, const u16 *mask = nullptr) {
+    InDesc d{};
+    d.s1 = s;
+    d.mask1 = mask;
+    d.c1 = c;
+    return d;
+}
+InDesc cat(const u16 *coarse, int c1, const u16 *skip, int c2) {
+    InDesc d{};
+    d.s1 = coarse;
+    d.c1 = c1;
+    d.up1 = 1;
+    d.s2 = skip;
+    d.c2 = c2;
+    return d;
+}
+
+// launch a convolution: cin == 1 uses the tap-packed path
+int conv(const InDesc &in, const Geo &g, const u16 *w, int cin, int cout, u16 *out_bf, float *out_f32,
+         bool relu, hipStream_t s) {
+    const int blocks = (g.npts + 63) / 64;
+    // algorithmic bytes: read the input once, write the output once (BF16)
+    ProfScope ps(K_NN, (double)g.npts * 2.0 * (cin + cout), s);
+    const int r = relu ? 1 : 0;
+    if (cin == 1) {
+        switch (ntile(cout)) {
+            case 1: hipLaunchKernelGGL((conv_c1<1>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
+            case 2: hipLaunchKernelGGL((conv_c1<2>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
+            default: hipLaunchKernelGGL((conv_c1<4>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
+        }
+    } else {
+        switch (ntile(cout)) {
+            case 1: hipLaunchKernelGGL((conv_k16<1>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 2: hipLaunchKernelGGL((conv_k16<2>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 3: hipLaunchKernelGGL((conv_k16<3>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 4: hipLaunchKernelGGL((conv_k16<4>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 6: hipLaunchKernelGGL((conv_k16<6>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 8: hipLaunchKernelGGL((conv_k16<8>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            default:
+                set_error("network: unsupported channel count %d", cout);
+                return OFDFT_INVALID_ARG;
+        }
+    }
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+int wgrad(ofdft_nn *net, int layer, const InDesc &x, const Geo &g, const u16 *dy, const u16 *ymask,
+          hipStream_t s) {
+    const int cin = kDefs[layer].cin, cout = kDefs[layer].cout;
+    const int chunks = (g.npts + kChunk - 1) / kChunk;
+    const size_t count = (size_t)27 * cin * cout;
+    if ((size_t)chunks * count > net->part_cap) {
+        set_error("network: weight-gradient scratch too small");
+        return OFDFT_INVALID_ARG;
+    }
+    ProfScope ps(K_NN, (double)g.npts * 2.0 * (cin + cout), s);
+    hipLaunchKernelGGL(conv_wgrad, dim3(chunks, 27, ntile(cin) * ntile(cout)), dim3(64), 0, s, x, g, dy,
+                       ymask, cin, cout, kChunk, net->part);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, net->part,
+                       chunks, (int)count, net->gr[layer]);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 8192); }
+
+}  // namespace
+
+int net_reserve(ofdft_nn *net, const ofdft_grid &g) {
+    if (g.nx % 8 || g.ny % 8 || g.nz % 8) {
+        set_error("network: grid sizes must be multiples of 8 (got %d x %d x %d)", g.nx, g.ny, g.nz);
+        return OFDFT_INVALID_ARG;
+    }
+    if (net->nx == g.nx && net->ny == g.ny && net->nz == g.nz) return OFDFT_OK;
+    for (void *p : net->ws) (void)hipFree(p);
+    net->ws.clear();
+    net->nx = g.nx;
+    net->ny = g.ny;
+    net->nz = g.nz;
+    for (int b = 0; b < NBUF; ++b) {
+        const Geo gg = geo_of(net, kBufLevel[b]);
+        OFDFT_TRY(nalloc(net, &net->buf[b], sizeof(u16) * (size_t)gg.npts * kBufCh[b], net->ws));
+    }
+    const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    OFDFT_TRY(nalloc(net, &net->out, sizeof(float) * n, net->ws));
+    size_t cap = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        // layer l runs on the level of its output
+        static const int lvl[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
+        const Geo gg = geo_of(net, lvl[l]);
+        const size_t chunks = (gg.npts + kChunk - 1) / kChunk;
+        cap = std::max(cap, chunks * 27 * kDefs[l].cin * kDefs[l].cout);
+    }
+    OFDFT_TRY(nalloc(net, &net->part, sizeof(float) * cap, net->ws));
+    net->part_cap = cap;
+    return OFDFT_OK;
+}
+
+// forward pass from net->buf[X0]; output FP32 in net->out
+static int forward(ofdft_nn *net, hipStream_t s) {
+    u16 **B = net->buf;
+    const Geo g0 = geo_of(net, 0), g1 = geo_of(net, 1), g2 = geo_of(net, 2), g3 = geo_of(net, 3);
+    auto W = [&](int l) { return net->wf[l]; };
+    OFDFT_TRY(conv(one(B[X0], 1), g0, W(0), 1, 16, B[A0], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[A0], 16), g0, W(1), 16, 16, B[S0], nullptr, true, s));
+    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g1.npts * 16)), dim3(256), 0, s, B[S0], g0, 16, B[P0]);
+    OFDFT_TRY(conv(one(B[P0], 16), g1, W(2), 16, 32, B[A1], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[A1], 32), g1, W(3), 32, 32, B[S1], nullptr, true, s));
+    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g2.npts * 32)), dim3(256), 0, s, B[S1], g1, 32, B[P1]);
+    OFDFT_TRY(conv(one(B[P1], 32), g2, W(4), 32, 64, B[A2], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[A2], 64), g2, W(5), 64, 64, B[S2], nullptr, true, s));
+    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, B[S2], g2, 64, B[P2]);
+    OFDFT_TRY(conv(one(B[P2], 64), g3, W(6), 64, 64, B[A3], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[A3], 64), g3, W(7), 64, 64, B[B3], nullptr, true, s));
+    OFDFT_TRY(conv(cat(B[B3], 64, B[S2], 64), g2, W(8), 128, 64, B[D2A], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[D2A], 64), g2, W(9), 64, 64, B[D2], nullptr, true, s));
+    OFDFT_TRY(conv(cat(B[D2], 64, B[S1], 32), g1, W(10), 96, 32, B[D1A], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[D1A], 32), g1, W(11), 32, 32, B[D1], nullptr, true, s));
+    OFDFT_TRY(conv(cat(B[D1], 32, B[S0], 16), g0, W(12), 48, 16, B[D0A], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[D0A], 16), g0, W(13), 16, 16, B[D0], nullptr, true, s));
+    OFDFT_TRY(conv(one(B[D0], 16), g0, W(14), 16, 1, nullptr, net->out, false, s));
+    return OFDFT_OK;
+}
+
+// backward pass from net->buf[dOUT]; weight gradients into net->gr
+static int backward(ofdft_nn *net, hipStream_t s) {
+    u16 **B = net->buf;
+    const Geo g0 = geo_of(net, 0), g1 = geo_of(net, 1), g2 = geo_of(net, 2), g3 = geo_of(net, 3);
+    auto WB = [&](int l) { return net->wb[l]; };
+    // out (no activation)
+    OFDFT_TRY(wgrad(net, 14, one(B[D0], 16), g0, B[dOUT], nullptr, s));
+    OFDFT_TRY(conv(one(B[dOUT], 1), g0, WB(14), 1, 16, B[dD0], nullptr, false, s));
+    // level 0 decoder
+    OFDFT_TRY(wgrad(net, 13, one(B[D0A], 16), g0, B[dD0], B[D0], s));
+    OFDFT_TRY(conv(one(B[dD0], 16, B[D0]), g0, WB(13), 16, 16, B[dD0A], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 12, cat(B[D1], 32, B[S0], 16), g0, B[dD0A], B[D0A], s));
+    OFDFT_TRY(conv(one(B[dD0A], 16, B[D0A]), g0, WB(12), 16, 48, B[dCAT0], nullptr, false, s));
+    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, B[dCAT0], g0, 48, 32, B[dD1]);
+    // level 1 decoder
+    OFDFT_TRY(wgrad(net, 11, one(B[D1A], 32), g1, B[dD1], B[D1], s));
+    OFDFT_TRY(conv(one(B[dD1], 32, B[D1]), g1, WB(11), 32, 32, B[dD1A], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 10, cat(B[D2], 64, B[S1], 32), g1, B[dD1A], B[D1A], s));
+    OFDFT_TRY(conv(one(B[dD1A], 32, B[D1A]), g1, WB(10), 32, 96, B[dCAT1], nullptr, false, s));
+    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, B[dCAT1], g1, 96, 64, B[dD2]);
+    // level 2 decoder
+    OFDFT_TRY(wgrad(net, 9, one(B[D2A], 64), g2, B[dD2], B[D2], s));
+    OFDFT_TRY(conv(one(B[dD2], 64, B[D2]), g2, WB(9), 64, 64, B[dD2A], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 8, cat(B[B3], 64, B[S2], 64), g2, B[dD2A], B[D2A], s));
+    OFDFT_TRY(conv(one(B[dD2A], 64, B[D2A]), g2, WB(8), 64, 128, B[dCAT2], nullptr, false, s));
+    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, B[dCAT2], g2, 128, 64, B[dB3]);
+    // bottleneck
+    OFDFT_TRY(wgrad(net, 7, one(B[A3], 64), g3, B[dB3], B[B3], s));
+    OFDFT_TRY(conv(one(B[dB3], 64, B[B3]), g3, WB(7), 64, 64, B[dA3], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 6, one(B[P2], 64), g3, B[dA3], B[A3], s));
+    OFDFT_TRY(conv(one(B[dA3], 64, B[A3]), g3, WB(6), 64, 64, B[dP2], nullptr, false, s));
+    // level 2 encoder: skip gradient + pooled path
+    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, B[dCAT2], g2, 128, 64, 64, B[dP2], B[dS2]);
+    OFDFT_TRY(wgrad(net, 5, one(B[A2], 64), g2, B[dS2], B[S2], s));
+    OFDFT_TRY(conv(one(B[dS2], 64, B[S2]), g2, WB(5), 64, 64, B[dA2], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 4, one(B[P1], 32), g2, B[dA2], B[A2], s));
+    OFDFT_TRY(conv(one(B[dA2], 64, B[A2]), g2, WB(4), 64, 32, B[dP1], nullptr, false, s));
+    // level 1 encoder
+    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, B[dCAT1], g1, 96, 64, 32, B[dP1], B[dS1]);
+    OFDFT_TRY(wgrad(net, 3, one(B[A1], 32), g1, B[dS1], B[S1], s));
+    OFDFT_TRY(conv(one(B[dS1], 32, B[S1]), g1, WB(3), 32, 32, B[dA1], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 2, one(B[P0], 16), g1, B[dA1], B[A1], s));
+    OFDFT_TRY(conv(one(B[dA1], 32, B[A1]), g1, WB(2), 32, 16, B[dP0], nullptr, false, s));
+    // level 0 encoder
+    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g0.npts * 16)), dim3(256), 0, s, B[dCAT0], g0, 48, 32, 16, B[dP0], B[dS0]);
+    OFDFT_TRY(wgrad(net, 1, one(B[A0], 16), g0, B[dS0], B[S0], s));
+    OFDFT_TRY(conv(one(B[dS0], 16, B[S0]), g0, WB(1), 16, 16, B[dA0], nullptr, false, s));
+    OFDFT_TRY(wgrad(net, 0, one(B[X0], 1), g0, B[dA0], B[A0], s));
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+static int pack_all(ofdft_nn *net, hipStream_t s) {
+    for (int l = 0; l < kLayers; ++l) {
+        hipLaunchKernelGGL(pack_weights, dim3(64), dim3(256), 0, s, net->w[l], kDefs[l].cin, kDefs[l].cout,
+                           ntile(kDefs[l].cout), ntile(kDefs[l].cin), net->wf[l], net->wb[l]);
+        OFDFT_CHECK_HIP(hipGetLastError());
+    }
+    return OFDFT_OK;
+}
+
+struct ToF64Op {          // out = h2 * rms * out32 (rms from totals {sum in^2})
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 12;
+    const float *o;
+    double *out;
+    const double *totals;
+    double inv_n, h2, scale;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() { scale = h2 * sqrt(totals[0] * inv_n); }
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double v = scale * (double)o[i];
+        out[i] = v;
+        acc[0] += v;
+    }
+};
+
+struct SubMeanOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
+    double *a;
+    const double *totals;
+    double inv_n, mean;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() { mean = totals[0] * inv_n; }
+    __device__ void operator()(int64_t i, double (&)[1]) const { a[i] -= mean; }
+};
+
+int net_apply(ofdft_nn *net, const ofdft_grid &g, const double *in, double *out, double h2,
+              bool zero_mean, hipStream_t s) {
+    if (g.nx != net->nx || g.ny != net->ny || g.nz != net->nz) {
+        set_error("network: workspace not reserved for this grid");
+        return OFDFT_INVALID_ARG;
+    }
+    const int64_t n = npoints(g);
+    OFDFT_TRY((launch_reduce<1>(n, SqOp{in}, StoreTotals<1>{net->totals}, net->rb, s)));
+    OFDFT_TRY((launch_reduce<1>(n, CastInOp{in, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(forward(net, s));
+    OFDFT_TRY((launch_reduce<1>(n, ToF64Op{net->out, out, net->totals, 1.0 / n, h2, 0.0},
+                                StoreTotals<1>{net->totals + 4}, net->rb, s)));
+    if (zero_mean)
+        OFDFT_TRY((launch_reduce<1>(n, SubMeanOp{out, net->totals + 4, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    return OFDFT_OK;
+}
+
+}  // namespace nn
+}  // namespace ofdft
+
+using namespace ofdft;
+using namespace ofdft::nn;
+
+static void net_free(ofdft_nn *net) {
+    for (void *p : net->ws) (void)hipFree(p);
+    for (void *p : net->allocs) (void)hipFree(p);
+    net->ws.clear();
+    net->allocs.clear();
+    redbuf_free(net->rb);
+}
+
+extern "C" size_t ofdft_nn_param_count(void) {
+    size_t c = 0;
+    for (int l = 0; l < kLayers; ++l) c += (size_t)27 * kDefs[l].cin * kDefs[l].cout;
+    return c;
+}
+
+extern "C" int ofdft_nn_create(uint64_t seed, ofdft_nn **out) {
+    if (!out) return OFDFT_INVALID_ARG;
+    ofdft_nn *net = new (std::nothrow) ofdft_nn();
+    if (!net) return OFDFT_NO_MEMORY;
+    auto fail = [&](int st) {
+        net_free(net);
+        delete net;
+        return st;
+    };
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < kLayers; ++l) {
+        const int cin = kDefs[l].cin, cout = kDefs[l].cout;
+        const size_t cnt = (size_t)27 * cin * cout;
+        int st;
+        if ((st = nalloc(net, &net->w[l], sizeof(float) * cnt, net->allocs)) ||
+            (st = nalloc(net, &net->m[l], sizeof(float) * cnt, net->allocs)) ||
+            (st = nalloc(net, &net->v[l], sizeof(float) * cnt, net->allocs)) ||
+            (st = nalloc(net, &net->gr[l], sizeof(float) * cnt, net->allocs)) ||
+            (st = nalloc(net, &net->wf[l], sizeof(u16) * (cin == 1 ? ntile(cout) * 16 * 32 : 27 * ntile(cout) * 16 * cin), net->allocs)) ||
+            (st = nalloc(net, &net->wb[l], sizeof(u16) * (cout == 1 ? ntile(cin) * 16 * 32 : 27 * ntile(cin) * 16 * cout), net->allocs)))
+            return fail(st);
+        // He-normal initialisation, fan-in 27 cin
+        std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (27.f * cin)));
+        std::vector<float> h(cnt);
+        for (auto &x : h) x = nd(rng);
+        if (hipMemcpy(net->w[l], h.data(), sizeof(float) * cnt, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(net->m[l], 0, sizeof(float) * cnt) != hipSuccess ||
+            hipMemset(net->v[l], 0, sizeof(float) * cnt) != hipSuccess)
+            return fail(OFDFT_HIP_ERROR);
+    }
+    int st;
+    if ((st = nalloc(net, &net->totals, sizeof(double) * 16, net->allocs)) || (st = redbuf_alloc(net->rb)))
+        return fail(st);
+    if ((st = pack_all(net, nullptr))) return fail(st);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(OFDFT_HIP_ERROR);
+    *out = net;
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_nn_destroy(ofdft_nn *net) {
+    if (!net) return OFDFT_OK;
+    net_free(net);
+    delete net;
+    return OFDFT_OK;
+}
+
+// weights: host FP32 array of ofdft_nn_param_count() values, layer after layer,
+// each W[t][ci][co] with tap t = (dz+1)*9 + (dy+1)*3 + (dx+1)
+extern "C" int ofdft_nn_set_weights(ofdft_nn *net, const float *w, size_t count) {
+    if (!net || !w || count != ofdft_nn_param_count()) {
+        set_error("ofdft_nn_set_weights: expected %zu values", ofdft_nn_param_count());
+        return OFDFT_INVALID_ARG;
+    }
+    size_t off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t cnt = (size_t)27 * kDefs[l].cin * kDefs[l].cout;
+        OFDFT_CHECK_HIP(hipMemcpy(net->w[l], w + off, sizeof(float) * cnt, hipMemcpyHostToDevice));
+        off += cnt;
+    }
+    OFDFT_TRY(pack_all(net, nullptr));
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
+    net->adam_t = 0;
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int gradients) {
+    if (!net || !w || count != ofdft_nn_param_count()) {
+        set_error("ofdft_nn_get_weights: expected %zu values", ofdft_nn_param_count());
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
+    size_t off = 0;
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t cnt = (size_t)27 * kDefs[l].cin * kDefs[l].cout;
+        OFDFT_CHECK_HIP(hipMemcpy(w + off, gradients ? net->gr[l] : net->w[l], sizeof(float) * cnt,
+                                  hipMemcpyDeviceToHost));
+        off += cnt;
+    }
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid) {
+    if (!net) return OFDFT_INVALID_ARG;
+    OFDFT_TRY(check_grid(grid, 1));
+    return net_reserve(net, *grid);
+}
+
+// out = N(in) with the scaling used by the solver: in / rms(in) -> network ->
+// times scale * rms(in) (scale = h^2 for a preconditioner / initial guess).
+extern "C" int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const double *in, double *out,
+                                double scale, void *stream) {
+    if (!net || !in || !out) return OFDFT_INVALID_ARG;
+    OFDFT_TRY(check_grid(grid, 1));
+    OFDFT_TRY(net_reserve(net, *grid));
+    return net_apply(net, *grid, in, out, scale, false, (hipStream_t)stream);
+}
+
+// One training step on a pair (g, phi): loss = ||N(g/rms g) - phi/(h^2 rms g)||^2 / ||.||^2,
+// backward pass, Adam update (lr; beta1 0.9, beta2 0.999, eps 1e-8).
+// loss (host, optional) receives the loss before the update.
+extern "C" int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g_rhs,
+                                   const double *phi, double lr, double *loss, void *stream) {
+    if (!net || !g_rhs || !phi) return OFDFT_INVALID_ARG;
+    OFDFT_TRY(check_grid(grid, 1));
+    OFDFT_TRY(net_reserve(net, *grid));
+    hipStream_t s = (hipStream_t)stream;
+    const ofdft_grid &g = *grid;
+    const int64_t n = npoints(g);
+    const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
+    OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
+    OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
+    OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(forward(net, s));
+    OFDFT_TRY((launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
+                                StoreTotals<1>{net->totals + 2}, net->rb, s)));
+    OFDFT_TRY(backward(net, s));
+    net->adam_t += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)net->adam_t), c2 = 1.f - std::pow(b2, (float)net->adam_t);
+    for (int l = 0; l < kLayers; ++l) {
+        LayerPtrs L{net->w[l], net->m[l], net->v[l], net->gr[l], net->wf[l], net->wb[l], kDefs[l].cin,
+                    kDefs[l].cout, ntile(kDefs[l].cout), ntile(kDefs[l].cin)};
+        hipLaunchKernelGGL(adam_kernel, dim3(64), dim3(256), 0, s, L, (float)lr, b1, b2, c1, c2, 1e-8f);
+        OFDFT_CHECK_HIP(hipGetLastError());
+    }
+    OFDFT_TRY(pack_all(net, s));
+    if (loss) {
+        double t[4];
+        OFDFT_CHECK_HIP(hipMemcpyAsync(t, net->totals, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+        const double rms = std::sqrt(t[0] / n);
+        const double ts = rms > 0 ? 1.0 / (h2 * rms) : 0.0;
+        *loss = t[2] / (t[1] * ts * ts);
+    }
+    return OFDFT_OK;
+}
+
+// Gradients only (no update), for checking against the reference: loss as in
+// ofdft_nn_train_step, gradients readable with ofdft_nn_get_weights(..., 1).
+extern "C" int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const double *g_rhs,
+                                  const double *phi, double *loss, void *stream) {
+    if (!net || !g_rhs || !phi) return OFDFT_INVALID_ARG;
+    OFDFT_TRY(check_grid(grid, 1));
+    OFDFT_TRY(net_reserve(net, *grid));
+    hipStream_t s = (hipStream_t)stream;
+    const ofdft_grid &g = *grid;
+    const int64_t n = npoints(g);
+    const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
+    OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
+    OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
+    OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(forward(net, s));
+    OFDFT_TRY((launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
+                                StoreTotals<1>{net->totals + 2}, net->rb, s)));
+    OFDFT_TRY(backward(net, s));
+    double t[4];
+    OFDFT_CHECK_HIP(hipMemcpyAsync(t, net->totals, sizeof(double) * 4, hipMemcpyDeviceToHost, s));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+    if (loss) {
+        const double rms = std::sqrt(t[0] / n);
+        const double ts = rms > 0 ? 1.0 / (h2 * rms) : 0.0;
+        *loss = t[2] / (t[1] * ts * ts);
+    }
+    return OFDFT_OK;
+}

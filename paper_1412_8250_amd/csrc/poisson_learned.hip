@@ -1,15 +1,270 @@
-// Learned form of the Poisson solve (network initial guess + flexible CG).
+// Learned form of the Poisson solve: a network initial guess and flexible CG
+// with the network as preconditioner (the paper calls for real-space
+// preconditioners to make iteration counts size-independent, Section 5.5).
+//
+//   M(r) = h^2 rms(r) N(r / rms(r)), projected to zero mean
+//   x_0 = x + M(g - A x);  r_0 = g - A x_0;  z_0 = M(r_0);  p_0 = z_0
+//   flexible CG (truncation 1, Polak-Ribiere form):
+//     alpha = <r,z> / <p,Ap>;  x += alpha p;  r_new = r - alpha Ap
+//     z_new = M(r_new);  beta = <z_new, r_new - r> / <z, r>;  p = z_new + beta p
+// All vectors FP64.  Plain FP64 CG from the best iterate takes over if the
+// residual has not dropped 10x after 20 iterations, or on NaN/Inf.
+#include <algorithm>
+#include <cmath>
+
+#include "nn.hpp"
 #include "poisson.hpp"
 
 namespace ofdft {
 
-int poisson_solve_learned(ofdft_poisson *s, double *, double, int, ofdft_solve_stats &, hipStream_t) {
+namespace {
+
+struct EpiAp {           // Ap = -L p, acc <p, Ap>
+    double *__restrict__ Ap;
+    double *totals;
+    double *partials;
+    unsigned int *counter;
+    double acc;
+    __device__ bool skip() const { return false; }
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, double c, double s) {
+        Ap[i] = -s;
+        acc = ::fma(c, -s, acc);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[1] = {acc};
+        block_sum<1>(x, scratch);
+        if (publish_partial<1>(x, partials, nblocks, block, counter)) {
+            double t[1];
+            sum_partials<1>(partials, nblocks, t);
+            totals[0] = t[0];
+        }
+    }
+};
+
+struct FcgStepOp {       // x += a p; r_old = r; r -= a Ap; totals {<r,r>}
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 56;
+    double *x, *r, *r_old;
+    const double *p, *Ap;
+    double a;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        x[i] = ::fma(a, p[i], x[i]);
+        const double ro = r[i];
+        r_old[i] = ro;
+        const double rn = ::fma(-a, Ap[i], ro);
+        r[i] = rn;
+        acc[0] = ::fma(rn, rn, acc[0]);
+    }
+};
+
+struct FcgDotsOp {       // totals {<z, r - r_old>, <r, z>}
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 24;
+    const double *z, *r, *r_old;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double zi = z[i], ri = r[i];
+        acc[0] = ::fma(zi, ri - r_old[i], acc[0]);
+        acc[1] = ::fma(ri, zi, acc[1]);
+    }
+};
+
+struct DirOp {           // p = z + b p
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 24;
+    double *p;
+    const double *z;
+    double b;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { p[i] = ::fma(b, p[i], z[i]); }
+};
+
+struct AxpyOp {          // y += a x
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    double *y;
+    const double *x;
+    double a;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { y[i] = ::fma(a, x[i], y[i]); }
+};
+
+struct CopyOp2 {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
+    double *dst;
+    const double *src;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { dst[i] = src[i]; }
+};
+
+template <class Load, class Epi>
+int pass64(const ofdft_grid &g, const Coef<double> &c, const Load &ld, const Epi &ep, hipStream_t s,
+           double bytes_per_point, int cls) {
+    const StencilCfg cfg = pick_stencil_cfg(g, 8);
+    ProfScope ps(cls, (double)npoints(g) * bytes_per_point, s);
+    switch (cfg.shape) {
+        case SHAPE_64x4x4: {
+            TileGeom tg = make_tile_geom<64, 4, 4>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 4, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
+            break;
+        }
+        case SHAPE_32x8x2: {
+            TileGeom tg = make_tile_geom<32, 8, 2>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 32, 8, 2, Load, Epi>), dim3(tg.nblocks), dim3(32, 8), 0, s, tg, c, ld, ep);
+            break;
+        }
+        default: {
+            TileGeom tg = make_tile_geom<64, 4, 2>(g, cfg.zlen);
+            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 2, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
+            break;
+        }
+    }
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+}  // namespace
+
+int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                          ofdft_solve_stats &stats, hipStream_t st) {
     if (!s->net) {
         set_error("cg_poisson_solve: learned mode needs a network (ofdft_poisson_set_network)");
         return OFDFT_INVALID_ARG;
     }
-    set_error("cg_poisson_solve: learned mode not available");
-    return OFDFT_INVALID_ARG;
+    const ofdft_grid &g = s->g;
+    const int64_t n = npoints(g);
+    const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
+    double *r = s->r, *p = s->pA, *r_old = s->pB, *Ap = s->Ap, *z = s->z, *xb = s->xbest;
+    double *tot = s->totals + 8, *th = s->totals_host + 8;
+    auto sync_tot = [&](int count) -> int {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(th, tot, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+        return OFDFT_OK;
+    };
+    auto residual = [&](double &r2) -> int {      // r = gp + L x, totals {sum r, sum r^2}
+        OFDFT_TRY(residual_pass<double>(g, s->coef, x, s->gp, r, tot, s->rb, st));
+        OFDFT_TRY(sync_tot(2));
+        r2 = th[1];
+        return OFDFT_OK;
+    };
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->totals_host, s->totals, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+    const double g2 = s->totals_host[3];
+    const double tol2 = rel_tol * rel_tol * g2;
+    int applies = 0, iters = 0;
+    double r2;
+    OFDFT_TRY(residual(r2));
+    if (!std::isfinite(r2)) return OFDFT_NONFINITE;
+    if (r2 > tol2 && r2 > 0.25 * g2) {            // poor guess: add the network's correction
+        OFDFT_TRY(nn::net_apply(s->net, g, r, z, h2, true, st));
+        ++applies;
+        OFDFT_TRY((launch_reduce<1>(n, AxpyOp{x, z, 1.0}, NoFin{}, s->rb, st)));
+        OFDFT_TRY(residual(r2));
+    }
+    double best = r2;
+    OFDFT_TRY((launch_reduce<1>(n, CopyOp2{xb, x}, NoFin{}, s->rb, st)));
+    const double r2_start = r2;
+    bool fall_back = !std::isfinite(r2);
+    if (!fall_back && r2 > tol2) {
+        OFDFT_TRY(nn::net_apply(s->net, g, r, z, h2, true, st));
+        ++applies;
+        OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r}, StoreTotals<2>{tot}, s->rb, st)));
+        OFDFT_TRY(sync_tot(2));
+        double rz = th[1];
+        OFDFT_TRY((launch_reduce<1>(n, CopyOp2{p, z}, NoFin{}, s->rb, st)));
+        while (iters < max_iter) {
+            OFDFT_TRY(pass64(g, s->coef, LoadPlain<double>{p},
+                             EpiAp{Ap, tot, s->rb.partials, s->rb.counter, 0.0}, st, 16.0, K_CG_STENCIL));
+            OFDFT_TRY(sync_tot(1));
+            const double pAp = th[0];
+            if (!std::isfinite(pAp) || !(pAp > 0) || !std::isfinite(rz)) {
+                fall_back = true;
+                break;
+            }
+            const double a = rz / pAp;
+            OFDFT_TRY((launch_reduce<1>(n, FcgStepOp{x, r, r_old, p, Ap, a}, StoreTotals<1>{tot}, s->rb, st)));
+            OFDFT_TRY(sync_tot(1));
+            r2 = th[0];
+            ++iters;
+            if (!std::isfinite(r2)) {
+                fall_back = true;
+                break;
+            }
+            if (r2 < best) {
+                best = r2;
+                OFDFT_TRY((launch_reduce<1>(n, CopyOp2{xb, x}, NoFin{}, s->rb, st)));
+            }
+            if (r2 <= tol2) break;
+            if (iters >= 20 && best > 0.01 * r2_start) {   // less than 10x in residual norm
+                fall_back = true;
+                break;
+            }
+            OFDFT_TRY(nn::net_apply(s->net, g, r, z, h2, true, st));
+            ++applies;
+            OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r_old}, StoreTotals<2>{tot}, s->rb, st)));
+            OFDFT_TRY(sync_tot(2));
+            const double b = th[0] / rz;
+            rz = th[1];
+            OFDFT_TRY((launch_reduce<1>(n, DirOp{p, z, std::isfinite(b) ? b : 0.0}, NoFin{}, s->rb, st)));
+        }
+    }
+    stats.nn_applies = applies;
+    stats.fell_back = fall_back ? 1 : 0;
+    int status = OFDFT_OK;
+    if (fall_back) {
+        OFDFT_TRY((launch_reduce<1>(n, CopyOp2{x, xb}, NoFin{}, s->rb, st)));
+        OFDFT_TRY(residual_pass<double>(g, s->coef, x, s->gp, s->r, s->totals + 4, s->rb, st));
+        OFDFT_CHECK_HIP(hipMemcpyAsync(s->totals_host + 4, s->totals + 4, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+        const double rr = s->totals_host[5];
+        CgState &init = *s->st_host;
+        init = CgState{};
+        init.rr = rr;
+        init.tol2 = tol2;
+        init.maxit = std::max(1, max_iter - iters);
+        init.first = 1;
+        init.done = std::isfinite(rr) ? (rr <= tol2 ? CG_CONVERGED : CG_RUNNING) : CG_NONFINITE;
+        OFDFT_CHECK_HIP(hipMemcpyAsync(s->st, s->st_host, sizeof(CgState), hipMemcpyHostToDevice, st));
+        int it2 = 0, done = init.done;
+        if (done == CG_RUNNING)
+            OFDFT_TRY(cg_iterate<double>(g, s->coef, x, s->r, s->pA, s->pB, s->Ap, s->st, s->st_host,
+                                         s->rb, st, it2, done));
+        iters += it2;
+        status = status_from_done(done);
+    } else if (r2 > tol2) {
+        status = OFDFT_NOT_CONVERGED;
+    }
+    stats.iters = iters;
+    return status;
 }
 
 }  // namespace ofdft
+
+using namespace ofdft;
+
+extern "C" int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net) {
+    if (!s || s->mode != OFDFT_LEARNED) {
+        set_error("ofdft_poisson_set_network: solver must be created with OFDFT_LEARNED");
+        return OFDFT_INVALID_ARG;
+    }
+    if (!net) {
+        s->net = nullptr;
+        return OFDFT_OK;
+    }
+    OFDFT_TRY(nn::net_reserve(net, s->g));
+    if (!s->z) {
+        const size_t b8 = sizeof(double) * npoints(s->g);
+        OFDFT_CHECK_HIP(hipMalloc(&s->z, b8));
+        OFDFT_CHECK_HIP(hipMalloc(&s->xbest, b8));
+    }
+    s->net = net;
+    return OFDFT_OK;
+}

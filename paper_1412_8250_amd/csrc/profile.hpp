@@ -20,6 +20,7 @@ enum KClass {
     K_U_VECTOR,        // density update: residual, line-search probes, step
     K_ANDERSON,
     K_POINTWISE,       // other vector passes (projections, casts, assembly)
+    K_NN,              // network convolutions and their gradients
     K_CLASSES
 };
 

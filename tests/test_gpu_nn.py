@@ -1,0 +1,107 @@
+"""Parity of the learned solver aid's network kernels (BF16 MFMA forward and
+backward) against the FP64 network oracle, and the learned Poisson form.
+
+BF16 error model: the oracle runs on the same BF16-rounded weights and input;
+the GPU additionally stores every activation and activation gradient in BF16
+(relative rounding 2^-9 per value) and accumulates in FP32, so outputs are
+expected within a few percent in relative L2 norm over the 15 layers."""
+import numpy as np
+import pytest
+
+import paper_1412_8250_amd as ofd
+from oracle import nn, poisson
+from paper_1412_8250_amd import inputs
+from tests.gpu_util import announce, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16(a):
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _net(seed):
+    W = nn.init_weights(np.random.default_rng(seed))
+    net = ofd.Network(seed)
+    net.set_weights({k: v.astype(np.float32) for k, v in W.items()})
+    return net, {k: bf16(v) for k, v in W.items()}
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (8, 16, 24), (32, 32, 32)])
+def test_forward_matches_oracle(shape):
+    torch = torch_cuda()
+    announce("nn forward", shape)
+    net, Wb = _net(3)
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=shape) + 0.3
+    xd = to_dev(x)
+    out = torch.empty_like(xd)
+    net.forward(xd, out, (0.5, 0.5, 0.5), scale=1.0)
+    rms = np.sqrt((x * x).mean())
+    ref = rms * nn.forward(Wb, bf16(x / rms))[0]
+    e = rel(to_host(out), ref)
+    print("forward rel err", e)
+    assert e < 3e-2
+
+
+def test_gradients_match_oracle():
+    torch = torch_cuda()
+    announce("nn gradients")
+    net, Wb = _net(5)
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    loss = net.gradients(to_dev(g), to_dev(phi), w.cell.h)
+    grads = net.get_weights(gradients=True)
+    h2 = w.cell.h[0] ** 2
+    rms = np.sqrt((g * g).mean())
+    out, cache = nn.forward(Wb, bf16(g / rms))
+    L, dout = nn.loss(out, phi / (h2 * rms))
+    ref = nn.backward(Wb, cache, dout)
+    assert abs(loss - L) <= 2e-2 * L
+    errs = {k: rel(grads[k], ref[k]) for k in ref}
+    print("gradient rel errs", errs)
+    assert max(errs.values()) < 0.1
+
+
+def test_training_reduces_loss():
+    torch = torch_cuda()
+    announce("nn training")
+    net = ofd.Network(7)
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    gd, pd = to_dev(g), to_dev(phi)
+    losses = [net.train_step(gd, pd, w.cell.h, 1e-3) for _ in range(60)]
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_learned_poisson_solve_reaches_tolerance():
+    torch = torch_cuda()
+    announce("learned poisson")
+    net = ofd.Network(11)
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    gd, pd = to_dev(g), to_dev(phi)
+    for _ in range(40):
+        net.train_step(gd, pd, w.cell.h, 1e-3)
+    s = ofd.PoissonSolver(g.shape, w.cell.h, 6, ofd.LEARNED)
+    s.set_network(net)
+    x = torch.zeros_like(gd)
+    st = s.solve(gd, x, 1e-8)
+    assert st["nn_applies"] >= 1
+    assert poisson.residual(to_host(x), g, w.cell.h) <= 1e-8
+    # an untrained network: the solve still reaches the tolerance (falls back if needed)
+    s2 = ofd.PoissonSolver(g.shape, w.cell.h, 6, ofd.LEARNED)
+    s2.set_network(ofd.Network(12))
+    x2 = torch.zeros_like(gd)
+    st2 = s2.solve(gd, x2, 1e-8)
+    assert poisson.residual(to_host(x2), g, w.cell.h) <= 1e-8
