@@ -118,6 +118,10 @@ int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode, ofdft_poi
 int ofdft_poisson_destroy(ofdft_poisson *s);
 int cg_poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol,
                      int max_iter, ofdft_solve_stats *stats, void *stream);
+/* Blocks of 16 CG iterations are captured once as a HIP graph (on a private
+ * stream) and replayed; kernels leave early once converged.  enable = 0 turns
+ * this off for the solver (results are bitwise identical either way). */
+int ofdft_poisson_set_graphs(ofdft_poisson *s, int enable);
 
 /* ------------------------------------------------------------------------
  * Batched complex shifted solves (Section 3.1, Helmholtz equations):

@@ -159,19 +159,87 @@ struct InitCgFin {       // set rr, tol2 from totals and arm the solver
     }
 };
 
+// Enqueue `count` (even) CG iterations; the p buffers return to their roles.
+template <typename T>
+static int cg_block(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r, T *pA, T *pB,
+                    T *Ap, CgState *st, const RedBuf &rb, hipStream_t s, int count) {
+    const int64_t n = npoints(g);
+    T *p_old = pA, *p_new = pB;
+    for (int k = 0; k < count; ++k) {
+        OFDFT_TRY(cg_k1<T>(g, c, r, p_old, p_new, Ap, st, rb, s));
+        CgUpdate<T> up{x, r, p_new, Ap, st, 0};
+        OFDFT_TRY((launch_reduce<1>(n, up, CgUpdateFin{st}, rb, s)));
+        std::swap(p_old, p_new);
+    }
+    return OFDFT_OK;
+}
+
+// A captured block of kGraphIters iterations for one set of buffers.
+constexpr int kGraphIters = 16;
+struct CgGraph {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    const void *key[6] = {};
+};
+
+static void graph_release(CgGraph &gr) {
+    if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+    if (gr.cap) (void)hipStreamDestroy(gr.cap);
+    gr = CgGraph{};
+}
+
+template <typename T>
+static int graph_get(CgGraph &gr, const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r,
+                     T *pA, T *pB, T *Ap, CgState *st, const RedBuf &rb) {
+    const void *key[6] = {x, r, pA, pB, Ap, st};
+    bool same = gr.exec != nullptr;
+    for (int i = 0; i < 6 && same; ++i) same = gr.key[i] == key[i];
+    if (same) return OFDFT_OK;
+    if (gr.exec) {
+        (void)hipGraphExecDestroy(gr.exec);
+        gr.exec = nullptr;
+    }
+    if (!gr.cap) OFDFT_CHECK_HIP(hipStreamCreateWithFlags(&gr.cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    OFDFT_CHECK_HIP(hipStreamBeginCapture(gr.cap, hipStreamCaptureModeThreadLocal));
+    const int rc = cg_block<T>(g, c, x, r, pA, pB, Ap, st, rb, gr.cap, kGraphIters);
+    const hipError_t e = hipStreamEndCapture(gr.cap, &graph);
+    if (rc != OFDFT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    OFDFT_CHECK_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    OFDFT_CHECK_HIP(ei);
+    for (int i = 0; i < 6; ++i) gr.key[i] = key[i];
+    return OFDFT_OK;
+}
+
+// Per-iteration algorithmic bytes, to account replayed blocks.
+template <typename T>
+static void account_block(const ofdft_grid &g, int iters) {
+    const double n = (double)npoints(g);
+    prof_add(K_CG_STENCIL, n * sizeof(T) * 4 * iters, iters);
+    prof_add(K_CG_UPDATE, n * sizeof(T) * 6 * iters, iters);
+}
+
 template <typename T>
 int cg_iterate(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r, T *pA, T *pB,
                T *Ap, CgState *st, CgState *st_host, const RedBuf &rb, hipStream_t s, int &iters,
-               int &done) {
-    const int64_t n = npoints(g);
+               int &done, CgGraph *graph) {
+    // Captured blocks replace per-kernel launches unless launches are being
+    // timed individually.
+    const bool use_graph = graph && !prof_timed(K_CG_STENCIL) && !prof_timed(K_CG_UPDATE);
     int chunk = 8;
-    T *p_old = pA, *p_new = pB;
     for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            OFDFT_TRY(cg_k1<T>(g, c, r, p_old, p_new, Ap, st, rb, s));
-            CgUpdate<T> up{x, r, p_new, Ap, st, 0};
-            OFDFT_TRY((launch_reduce<1>(n, up, CgUpdateFin{st}, rb, s)));
-            std::swap(p_old, p_new);
+        if (use_graph) {
+            OFDFT_TRY(graph_get<T>(*graph, g, c, x, r, pA, pB, Ap, st, rb));
+            const int reps = std::max(1, chunk / kGraphIters);
+            for (int k = 0; k < reps; ++k) OFDFT_CHECK_HIP(hipGraphLaunch(graph->exec, s));
+            account_block<T>(g, reps * kGraphIters);
+        } else {
+            OFDFT_TRY(cg_block<T>(g, c, x, r, pA, pB, Ap, st, rb, s, chunk));
         }
         OFDFT_CHECK_HIP(hipMemcpyAsync(st_host, st, sizeof(CgState), hipMemcpyDeviceToHost, s));
         OFDFT_CHECK_HIP(hipStreamSynchronize(s));
@@ -185,10 +253,10 @@ int cg_iterate(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r
 
 template int cg_iterate<double>(const ofdft_grid &, const Coef<double> &, double *, double *,
                                 double *, double *, double *, CgState *, CgState *,
-                                const RedBuf &, hipStream_t, int &, int &);
+                                const RedBuf &, hipStream_t, int &, int &, CgGraph *);
 template int cg_iterate<float>(const ofdft_grid &, const Coef<float> &, float *, float *, float *,
                                float *, float *, CgState *, CgState *, const RedBuf &,
-                               hipStream_t, int &, int &);
+                               hipStream_t, int &, int &, CgGraph *);
 
 int status_from_done(int done) {
     switch (done) {
@@ -223,10 +291,20 @@ int poisson_alloc(ofdft_poisson *s) {
     OFDFT_TRY(redbuf_alloc(s->rb));
     OFDFT_CHECK_HIP(hipEventCreate(&s->ev0));
     OFDFT_CHECK_HIP(hipEventCreate(&s->ev1));
+    s->graph64 = new CgGraph();
+    s->graph32 = new CgGraph();
     return OFDFT_OK;
 }
 
 void poisson_free(ofdft_poisson *s) {
+    if (s->graph64) {
+        graph_release(*s->graph64);
+        delete s->graph64;
+    }
+    if (s->graph32) {
+        graph_release(*s->graph32);
+        delete s->graph32;
+    }
     void *dev[] = {s->gp, s->r, s->pA, s->pB, s->Ap, s->r32, s->d32, s->qA, s->qB, s->Aq, s->st,
                    s->totals};
     for (void *p : dev)
@@ -279,7 +357,7 @@ static int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter
     int iters = 0, done = init.done;
     if (done == CG_RUNNING)
         OFDFT_TRY(cg_iterate<double>(s->g, s->coef, x, s->r, s->pA, s->pB, s->Ap, s->st, s->st_host,
-                                     s->rb, st, iters, done));
+                                     s->rb, st, iters, done, s->use_graphs ? s->graph64 : nullptr));
     stats.iters = iters;
     (void)n;
     return status_from_done(done);
@@ -319,7 +397,7 @@ static int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_it
                                     s->rb, st)));
         int iters = 0, done = 0;
         OFDFT_TRY(cg_iterate<float>(s->g, s->coef32, s->d32, s->r32, s->qA, s->qB, s->Aq, s->st,
-                                    s->st_host, s->rb, st, iters, done));
+                                    s->st_host, s->rb, st, iters, done, s->use_graphs ? s->graph32 : nullptr));
         total += iters;
         if (done == CG_NONFINITE) {
             status = OFDFT_NONFINITE;
@@ -396,6 +474,13 @@ extern "C" int ofdft_poisson_destroy(ofdft_poisson *s) {
     if (!s) return OFDFT_OK;
     poisson_free(s);
     delete s;
+    return OFDFT_OK;
+}
+
+// Enable (1, default) or disable (0) captured iteration blocks for a solver.
+extern "C" int ofdft_poisson_set_graphs(ofdft_poisson *s, int enable) {
+    if (!s) return OFDFT_INVALID_ARG;
+    s->use_graphs = enable != 0;
     return OFDFT_OK;
 }
 

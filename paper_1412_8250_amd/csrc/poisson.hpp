@@ -4,6 +4,9 @@
 #include "cg.hpp"
 
 struct ofdft_nn;
+namespace ofdft {
+struct CgGraph;
+}
 
 struct ofdft_poisson {
     ofdft_grid g{};
@@ -17,6 +20,9 @@ struct ofdft_poisson {
     double *totals = nullptr, *totals_host = nullptr;
     ofdft::RedBuf rb{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // captured iteration blocks (FP64 and FP32 loops)
+    ofdft::CgGraph *graph64 = nullptr, *graph32 = nullptr;
+    bool use_graphs = true;
     // learned form
     ofdft_nn *net = nullptr;
     double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
@@ -33,7 +39,7 @@ int residual_pass(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T
 template <typename T>
 int cg_iterate(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, T *x, T *r, T *pA, T *pB,
                T *Ap, CgState *st, CgState *st_host, const RedBuf &rb, hipStream_t s, int &iters,
-               int &done);
+               int &done, CgGraph *graph = nullptr);
 int status_from_done(int done);
 int poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol, int max_iter,
                   ofdft_solve_stats &stats, hipStream_t st);

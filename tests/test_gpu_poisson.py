@@ -114,3 +114,26 @@ def test_large_cell_320():
         x, st = _solve(g, w.cell.h, mode, 1e-8)
         assert poisson.residual(x, g, w.cell.h) <= 1e-8
         assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("mode", [ofd.PLAIN_F64, ofd.REFINED_F32])
+def test_graph_replays_equal_eager(mode):
+    """Captured 16-iteration blocks replayed with host synchronisations in
+    between give bitwise the eager result, on every repeat."""
+    torch = torch_cuda()
+    announce("poisson graphs", mode)
+    w = inputs.supercell_500()
+    g, _ = poisson.rhs(w.rho, w.b)
+    gd = to_dev(g)
+    eager = ofd.PoissonSolver(g.shape, w.cell.h, 6, mode)
+    eager.set_graphs(False)
+    xe = torch.zeros_like(gd)
+    ste = eager.solve(gd, xe, 1e-8)
+    graphed = ofd.PoissonSolver(g.shape, w.cell.h, 6, mode)
+    for rep in range(3):
+        xg = torch.zeros_like(gd)
+        stg = graphed.solve(gd, xg, 1e-8)
+        torch.cuda.synchronize()
+        assert stg["iters"] == ste["iters"]
+        assert torch.equal(xg, xe), rep
+        _ = (xg * 2).sum().item()          # eager work between replays
