@@ -97,6 +97,7 @@ def _declare(l):
         "ofdft_nn_train_step": (_I, [_V, _GP, _V, _V, _D, ctypes.POINTER(_D), _V]),
         "ofdft_poisson_set_network": (_I, [_V, _V]),
         "ofdft_poisson_set_graphs": (_I, [_V, _I]),
+        "ofdft_poisson_set_refinement": (_I, [_V, _D, _D]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
         "ofdft_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
@@ -213,6 +214,9 @@ class PoissonSolver:
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_poisson_create(ctypes.byref(self.grid), int(radius), int(mode),
                                           ctypes.byref(self._h)))
+
+    def set_refinement(self, inner_min: float, inner_max: float):
+        _check(lib().ofdft_poisson_set_refinement(self._h, float(inner_min), float(inner_max)))
 
     def set_graphs(self, enable: bool):
         _check(lib().ofdft_poisson_set_graphs(self._h, 1 if enable else 0))

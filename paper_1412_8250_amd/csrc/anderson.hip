@@ -90,9 +90,8 @@ and_push_gram(int64_t n, const double *__restrict__ v, const double *__restrict_
         }
     }
     block_sum<K>(acc, scratch);
-    if (publish_partial<K>(acc, partials, gridDim.x, blockIdx.x, counter)) {
-        double tot[K];
-        sum_partials<K>(partials, gridDim.x, tot);
+    double tot[K];
+    if (reduce_grid<K>(acc, partials, gridDim.x, blockIdx.x, counter, scratch, tot)) {
         for (int k = 0; k < K; ++k) st->totals[k] = tot[k];
         st->head = head;
         st->count = count;

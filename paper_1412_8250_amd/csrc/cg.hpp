@@ -10,8 +10,7 @@
 // that the host can enqueue iterations in blocks and check rarely.
 #pragma once
 
-#include "stencil_core.hpp"
-#include "tuning.hpp"
+#include "stencil_launch.hpp"
 #include "vec.hpp"
 
 namespace ofdft {
@@ -63,9 +62,8 @@ struct EpiCgAp {
     __device__ void finish(int block, int nblocks, double *scratch) {
         double x[1] = {acc};
         block_sum<1>(x, scratch);
-        if (publish_partial<1>(x, partials, nblocks, block, counter)) {
-            double t[1];
-            sum_partials<1>(partials, nblocks, t);
+        double t[1];
+        if (reduce_grid<1>(x, partials, nblocks, block, counter, scratch, t)) {
             const double pAp = t[0];
             st->pAp = pAp;
             if (!isfinite(pAp)) st->done = CG_NONFINITE;
@@ -130,9 +128,8 @@ struct EpiResidual {
     __device__ void finish(int block, int nblocks, double *scratch) {
         double x[2] = {acc0, acc1};
         block_sum<2>(x, scratch);
-        if (publish_partial<2>(x, partials, nblocks, block, counter)) {
-            double t[2];
-            sum_partials<2>(partials, nblocks, t);
+        double t[2];
+        if (reduce_grid<2>(x, partials, nblocks, block, counter, scratch, t)) {
             totals[0] = t[0];
             totals[1] = t[1];
         }

@@ -33,6 +33,8 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 constexpr int kMaxRadius = 6;
+// Block-partial slots of the reduction buffers (upper bound on reducing grids).
+constexpr int kRedSlots = 8192;
 
 // Coefficients of the order-2N Laplacian in the form used by the kernels:
 //   L x = c0 * x + sum_{p=1..6} (wx[p] (x_{i+p}+x_{i-p}) + wy[p] (...) + wz[p] (...))
@@ -111,7 +113,8 @@ __device__ __host__ inline double2 cdiv(double2 a, double2 b) {
 // Deterministic reductions.  A block reduces its threads' values with wave64
 // shuffles and LDS in a fixed pattern; each block writes its partial to a
 // slot; the last block to finish (counted with a vector-memory atomic) sums
-// the slots in index order.  Results are bitwise repeatable.
+// the slots with all its threads in a fixed assignment and a fixed tree.
+// Results are bitwise repeatable.
 // ---------------------------------------------------------------------------
 template <int K>
 struct DVec {
@@ -170,24 +173,41 @@ __device__ inline bool publish_partial(const double (&x)[K], double *partials, i
     return last;
 }
 
-// Sum K partial arrays in fixed order (called by one thread of the last block).
+// Sum K partial arrays with the whole last block: thread t sums partials t,
+// t + nthreads, ... in order, then a fixed tree combines the threads.
+// Deterministic (the assignment does not depend on timing).  All threads of the block must call it; the result
+// is valid in thread 0.  `scratch` as for block_sum.
 template <int K>
-__device__ inline void sum_partials(const double *partials, int nblocks, double (&out)[K]) {
+__device__ inline void sum_partials_block(const double *partials, int nblocks, double (&out)[K],
+                                          double *scratch) {
+    const int nt = blockDim.x * blockDim.y;
+    const int t = threadIdx.x + threadIdx.y * blockDim.x;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const volatile double *p = partials + (size_t)k * nblocks;
-        // four interleaved accumulators, combined in fixed order
-        double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        int i = 0;
-        for (; i + 3 < nblocks; i += 4) {
-            a0 += p[i];
-            a1 += p[i + 1];
-            a2 += p[i + 2];
-            a3 += p[i + 3];
-        }
-        for (; i < nblocks; ++i) a0 += p[i];
-        out[k] = (a0 + a1) + (a2 + a3);
+        double a = 0.0;
+        for (int i = t; i < nblocks; i += nt)
+            a += __hip_atomic_load(partials + (size_t)k * nblocks + i, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        out[k] = a;
     }
+    block_sum<K>(out, scratch);
+}
+
+// publish + (in the last block) whole-block sum.  Returns true in thread 0 of
+// the last block, whose tot[] then holds the totals.  Every thread of every
+// block must call it (it contains barriers).
+template <int K>
+__device__ inline bool reduce_grid(const double (&x)[K], double *partials, int nblocks, int block,
+                                   unsigned int *counter, double *scratch, double (&tot)[K]) {
+    __shared__ int s_last;
+    const bool last0 = publish_partial<K>(x, partials, nblocks, block, counter);
+    if (threadIdx.x == 0 && threadIdx.y == 0) s_last = last0 ? 1 : 0;
+    __syncthreads();
+    const bool last = s_last != 0;
+    if (!last) return false;
+    __threadfence();
+    sum_partials_block<K>(partials, nblocks, tot, scratch);
+    return threadIdx.x == 0 && threadIdx.y == 0;
 }
 
 // Logical block index such that the hardware's round-robin placement of

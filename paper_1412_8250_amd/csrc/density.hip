@@ -54,9 +54,8 @@ struct EpiHu {
     __device__ void finish(int block, int nblocks, double *scratch) {
         double x[3] = {a0, a1, a2};
         block_sum<3>(x, scratch);
-        if (publish_partial<3>(x, partials, nblocks, block, counter)) {
-            double t[3];
-            sum_partials<3>(partials, nblocks, t);
+        double t[3];
+        if (reduce_grid<3>(x, partials, nblocks, block, counter, scratch, t)) {
             dsc[S_UHU] = t[0];
             dsc[S_ULU] = t[1];
             dsc[S_UU] = t[2];
@@ -116,9 +115,8 @@ struct EpiLd {
     __device__ void finish(int block, int nblocks, double *scratch) {
         double x[4] = {a0, a1, a2, a3};
         block_sum<4>(x, scratch);
-        if (publish_partial<4>(x, partials, nblocks, block, counter)) {
-            double t[4];
-            sum_partials<4>(partials, nblocks, t);
+        double t[4];
+        if (reduce_grid<4>(x, partials, nblocks, block, counter, scratch, t)) {
             for (int k = 0; k < 4; ++k) totals[k] = t[k];
         }
     }
@@ -153,27 +151,8 @@ struct StepOp {         // u <- c (u + s d)
 template <class Load, class Epi>
 int stencil_pass(const ofdft_grid &g, const Coef<double> &c, const Load &ld, const Epi &ep, hipStream_t s,
                  int bytes_per_point) {
-    const StencilCfg cfg = pick_stencil_cfg(g, 8);
     ProfScope ps(K_U_STENCIL, (double)npoints(g) * bytes_per_point, s);
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: {
-            TileGeom tg = make_tile_geom<64, 4, 4>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 4, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
-            break;
-        }
-        case SHAPE_32x8x2: {
-            TileGeom tg = make_tile_geom<32, 8, 2>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 32, 8, 2, Load, Epi>), dim3(tg.nblocks), dim3(32, 8), 0, s, tg, c, ld, ep);
-            break;
-        }
-        default: {
-            TileGeom tg = make_tile_geom<64, 4, 2>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 2, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
-            break;
-        }
-    }
-    OFDFT_CHECK_HIP(hipGetLastError());
-    return OFDFT_OK;
+    return launch_stencil<double>(g, c, ld, ep, s);
 }
 
 int fetch(ofdft_scf *s, int first, int count, hipStream_t st) {

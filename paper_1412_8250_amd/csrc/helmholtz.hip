@@ -362,9 +362,8 @@ struct EpiHRes {         // r = f - A x in complex128; totals {|r|^2, |f|^2}
     __device__ void finish(int block, int nblocks, double *scratch) {
         double v[2] = {acc0, acc1};
         block_sum<2>(v, scratch);
-        if (publish_partial<2>(v, partials, nblocks, block, counter)) {
-            double t[2];
-            sum_partials<2>(partials, nblocks, t);
+        double t[2];
+        if (reduce_grid<2>(v, partials, nblocks, block, counter, scratch, t)) {
             totals[0] = t[0];
             totals[1] = t[1];
         }

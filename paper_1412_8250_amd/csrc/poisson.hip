@@ -16,56 +16,20 @@
 
 namespace ofdft {
 
-namespace {
-
-template <typename T, int TX, int TYT, int RY>
-int launch_k1(const ofdft_grid &g, int zlen, const Coef<typename VT<T>::S> &c, const T *r,
-              const T *p_old, T *p_new, T *Ap, CgState *st, const RedBuf &rb, hipStream_t s) {
-    TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
-    LoadCgP<T> ld{r, p_old, st, 0};
-    EpiCgAp<T> ep{p_new, Ap, st, rb.partials, rb.counter, 0.0};
-    ProfScope ps(K_CG_STENCIL, (double)npoints(g) * sizeof(T) * 4, s);
-    hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadCgP<T>, EpiCgAp<T>>), dim3(tg.nblocks),
-                       dim3(TX, TYT), 0, s, tg, c, ld, ep);
-    OFDFT_CHECK_HIP(hipGetLastError());
-    return OFDFT_OK;
-}
-
-template <typename T, int TX, int TYT, int RY>
-int launch_residual(const ofdft_grid &g, int zlen, const Coef<typename VT<T>::S> &c, const T *x,
-                    const double *gp, T *r, double *totals, const RedBuf &rb, hipStream_t s) {
-    TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
-    LoadPlain<T> ld{x};
-    EpiResidual<T> ep{gp, r, totals, rb.partials, rb.counter, 0.0, 0.0};
-    ProfScope ps(K_RESIDUAL, (double)npoints(g) * (2 * sizeof(T) + 8), s);
-    hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiResidual<T>>),
-                       dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
-    OFDFT_CHECK_HIP(hipGetLastError());
-    return OFDFT_OK;
-}
-
-}  // namespace
-
 template <typename T>
 int cg_k1(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *r, const T *p_old,
           T *p_new, T *Ap, CgState *st, const RedBuf &rb, hipStream_t s) {
-    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: return launch_k1<T, 64, 4, 4>(g, cfg.zlen, c, r, p_old, p_new, Ap, st, rb, s);
-        case SHAPE_32x8x2: return launch_k1<T, 32, 8, 2>(g, cfg.zlen, c, r, p_old, p_new, Ap, st, rb, s);
-        default: return launch_k1<T, 64, 4, 2>(g, cfg.zlen, c, r, p_old, p_new, Ap, st, rb, s);
-    }
+    ProfScope ps(K_CG_STENCIL, (double)npoints(g) * sizeof(T) * 4, s);
+    return launch_stencil<T>(g, c, LoadCgP<T>{r, p_old, st, 0},
+                             EpiCgAp<T>{p_new, Ap, st, rb.partials, rb.counter, 0.0}, s);
 }
 
 template <typename T>
 int residual_pass(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *x,
                   const double *gp, T *r, double *totals, const RedBuf &rb, hipStream_t s) {
-    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: return launch_residual<T, 64, 4, 4>(g, cfg.zlen, c, x, gp, r, totals, rb, s);
-        case SHAPE_32x8x2: return launch_residual<T, 32, 8, 2>(g, cfg.zlen, c, x, gp, r, totals, rb, s);
-        default: return launch_residual<T, 64, 4, 2>(g, cfg.zlen, c, x, gp, r, totals, rb, s);
-    }
+    ProfScope ps(K_RESIDUAL, (double)npoints(g) * (2 * sizeof(T) + 8), s);
+    return launch_stencil<T>(g, c, LoadPlain<T>{x},
+                             EpiResidual<T>{gp, r, totals, rb.partials, rb.counter, 0.0, 0.0}, s);
 }
 
 template int cg_k1<double>(const ofdft_grid &, const Coef<double> &, const double *, const double *,
@@ -369,7 +333,7 @@ static int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_it
     // Each FP32 inner solve targets the reduction still needed (with margin),
     // bounded below by what FP32 CG reliably reaches and above so that every
     // outer step makes real progress.
-    const double inner_min = 1e-5, inner_max = 1e-2;
+    const double inner_min = s->inner_min, inner_max = s->inner_max;
     const int max_outer = 12;
     int total = 0, outer = 0, status = OFDFT_NOT_CONVERGED;
     for (; outer <= max_outer; ++outer) {
@@ -474,6 +438,17 @@ extern "C" int ofdft_poisson_destroy(ofdft_poisson *s) {
     if (!s) return OFDFT_OK;
     poisson_free(s);
     delete s;
+    return OFDFT_OK;
+}
+
+// Bounds of the FP32 inner tolerance of the refined form (defaults 1e-5, 1e-2).
+extern "C" int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inner_max) {
+    if (!s || !(inner_min > 0) || !(inner_max >= inner_min) || !(inner_max < 1)) {
+        set_error("ofdft_poisson_set_refinement: need 0 < inner_min <= inner_max < 1");
+        return OFDFT_INVALID_ARG;
+    }
+    s->inner_min = inner_min;
+    s->inner_max = inner_max;
     return OFDFT_OK;
 }
 

@@ -34,9 +34,8 @@ struct EpiAp {           // Ap = -L p, acc <p, Ap>
     __device__ void finish(int block, int nblocks, double *scratch) {
         double x[1] = {acc};
         block_sum<1>(x, scratch);
-        if (publish_partial<1>(x, partials, nblocks, block, counter)) {
-            double t[1];
-            sum_partials<1>(partials, nblocks, t);
+        double t[1];
+        if (reduce_grid<1>(x, partials, nblocks, block, counter, scratch, t)) {
             totals[0] = t[0];
         }
     }
@@ -108,27 +107,8 @@ struct CopyOp2 {
 template <class Load, class Epi>
 int pass64(const ofdft_grid &g, const Coef<double> &c, const Load &ld, const Epi &ep, hipStream_t s,
            double bytes_per_point, int cls) {
-    const StencilCfg cfg = pick_stencil_cfg(g, 8);
     ProfScope ps(cls, (double)npoints(g) * bytes_per_point, s);
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: {
-            TileGeom tg = make_tile_geom<64, 4, 4>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 4, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
-            break;
-        }
-        case SHAPE_32x8x2: {
-            TileGeom tg = make_tile_geom<32, 8, 2>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 32, 8, 2, Load, Epi>), dim3(tg.nblocks), dim3(32, 8), 0, s, tg, c, ld, ep);
-            break;
-        }
-        default: {
-            TileGeom tg = make_tile_geom<64, 4, 2>(g, cfg.zlen);
-            hipLaunchKernelGGL((stencil_kernel<double, 64, 4, 2, Load, Epi>), dim3(tg.nblocks), dim3(64, 4), 0, s, tg, c, ld, ep);
-            break;
-        }
-    }
-    OFDFT_CHECK_HIP(hipGetLastError());
-    return OFDFT_OK;
+    return launch_stencil<double>(g, c, ld, ep, s);
 }
 
 }  // namespace

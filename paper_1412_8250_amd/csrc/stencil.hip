@@ -1,39 +1,17 @@
 // fd_laplacian_apply: y = alpha L_h x + beta y for f64 / f32 / c128 / c64.
-#include "stencil_core.hpp"
-#include "tuning.hpp"
+#include "stencil_launch.hpp"
 
 namespace ofdft {
-
-template <typename T, int TX, int TYT, int RY>
-static int apply_cfg(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x, void *y,
-                     double alpha, double beta, hipStream_t s, int zlen) {
-    using S = typename VT<T>::S;
-    TileGeom tg = make_tile_geom<TX, TYT, RY>(g, zlen);
-    LoadPlain<T> ld{(const T *)x};
-    ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
-    if (beta != 0.0) {
-        EpiAxpby<T, true> ep{(T *)y, (S)alpha, (S)beta, {}};
-        hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T, true>>),
-                           dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
-    } else {
-        EpiAxpby<T, false> ep{(T *)y, (S)alpha, (S)beta, {}};
-        hipLaunchKernelGGL((stencil_kernel<T, TX, TYT, RY, LoadPlain<T>, EpiAxpby<T, false>>),
-                           dim3(tg.nblocks), dim3(TX, TYT), 0, s, tg, c, ld, ep);
-    }
-    OFDFT_CHECK_HIP(hipGetLastError());
-    return OFDFT_OK;
-}
 
 template <typename T>
 static int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x, void *y,
                    double alpha, double beta, hipStream_t s) {
-    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: return apply_cfg<T, 64, 4, 4>(g, c, x, y, alpha, beta, s, cfg.zlen);
-        case SHAPE_64x4x2: return apply_cfg<T, 64, 4, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
-        case SHAPE_32x8x2: return apply_cfg<T, 32, 8, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
-        default: return apply_cfg<T, 64, 4, 2>(g, c, x, y, alpha, beta, s, cfg.zlen);
-    }
+    using S = typename VT<T>::S;
+    LoadPlain<T> ld{(const T *)x};
+    ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
+    if (beta != 0.0)
+        return launch_stencil<T>(g, c, ld, EpiAxpby<T, true>{(T *)y, (S)alpha, (S)beta, {}}, s);
+    return launch_stencil<T>(g, c, ld, EpiAxpby<T, false>{(T *)y, (S)alpha, (S)beta, {}}, s);
 }
 
 }  // namespace ofdft

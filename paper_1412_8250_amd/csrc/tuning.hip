@@ -25,6 +25,27 @@ int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks) {
     return (int)((g.nz + chunks - 1) / chunks);
 }
 
+int zlen_auto(const ofdft_grid &g, int tx, int ty, int resident) {
+    if (resident < 1) resident = 1;
+    const int64_t tiles = (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    const int max_chunks = g.nz / 8 > 0 ? g.nz / 8 : 1;     // chunks of at least 8 planes
+    constexpr int kWarm = 8;                                 // warm-up cost in plane steps
+    int best = g.nz;
+    int64_t best_cost = -1;
+    for (int c = 1; c <= max_chunks; ++c) {
+        const int zl = (g.nz + c - 1) / c;
+        const int64_t blocks = tiles * ((g.nz + zl - 1) / zl);
+        if (blocks > kRedSlots) break;
+        const int64_t waves = (blocks + resident - 1) / resident;
+        const int64_t cost = waves * (zl + kWarm);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = zl;
+        }
+    }
+    return best;
+}
+
 StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -33,9 +54,10 @@ StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes) {
     }
     StencilCfg c;
     if (elem_bytes >= 16) c.shape = SHAPE_64x4x2;        // complex128: 2 rows keep the queue in registers
-    else if (g.nx <= 40) c.shape = SHAPE_32x8x2;
+    else if (g.nx <= 40 || (g.nx % 64 != 0 && g.nx % 64 <= 32 && g.nx < 256))
+        c.shape = SHAPE_32x8x2;                          // avoid a mostly idle last x tile
     else c.shape = SHAPE_64x4x4;
-    c.zlen = zlen_for_blocks(g, c.shape, 1024);
+    c.zlen = 0;
     return c;
 }
 

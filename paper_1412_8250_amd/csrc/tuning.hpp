@@ -11,8 +11,10 @@ enum StencilShape { SHAPE_64x4x4 = 0, SHAPE_64x4x2 = 1, SHAPE_32x8x2 = 2, SHAPE_
 
 struct StencilCfg {
     int shape;
-    int zlen;     // planes per z chunk (0 = whole axis)
+    int zlen;     // planes per z chunk (0 = chosen from the kernel's residency)
 };
+
+constexpr int kMaxDevices = 16;
 
 // Tile extents of each shape (x, y).
 inline void shape_extent(int shape, int &tx, int &ty) {
@@ -25,5 +27,8 @@ inline void shape_extent(int shape, int &tx, int &ty) {
 
 StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes);
 int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks);
+// z-chunk length minimising (waves of workgroups) x (chunk planes + warm-up)
+// for `resident` workgroups in flight; tiles of tx x ty points.
+int zlen_auto(const ofdft_grid &g, int tx, int ty, int resident);
 
 }  // namespace ofdft

@@ -26,11 +26,8 @@ reduce_kernel(int64_t n, F f, Fin fin, double *partials, unsigned int *counter) 
     const int64_t stride = (int64_t)gridDim.x * kVecThreads;
     for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) f(i, acc);
     block_sum<K>(acc, scratch);
-    if (publish_partial<K>(acc, partials, gridDim.x, blockIdx.x, counter)) {
-        double tot[K];
-        sum_partials<K>(partials, gridDim.x, tot);
-        fin(tot);
-    }
+    double tot[K];
+    if (reduce_grid<K>(acc, partials, gridDim.x, blockIdx.x, counter, scratch, tot)) fin(tot);
 }
 
 inline int vec_blocks(int64_t n) {
@@ -45,7 +42,6 @@ struct RedBuf {
     double *partials = nullptr;   // capacity kRedSlots * 8 doubles
     unsigned int *counter = nullptr;
 };
-constexpr int kRedSlots = 8192;
 constexpr int kRedMaxK = 8;
 
 // Accounting class and algorithmic bytes per element of an elementwise op
