@@ -284,13 +284,19 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   element size (elem_bytes 4, 8 or 16): shape 0 = 64x16 tile (4 rows per
  *   thread), 1 = 64x8 tile, 2 = 32x16 tile; zlen = planes per z chunk (0 =
  *   automatic).  shape < 0 removes the entry.  INVALID_ARG for unknown shapes.
- * ofdft_batch_set_config: launch shape and workgroups per system (1..16) of
- *   the persistent shifted-system kernel; shape < 0 / group 0 = automatic.
+ * ofdft_batch_set_config: schedule of the shifted-system solver.  group 0
+ *   (default) = stepped schedule: one launch per COCG phase over all systems,
+ *   replayed from a HIP graph; group P in 1..1024 = persistent schedule, one
+ *   cooperative launch in which groups of P workgroups solve whole systems.
+ *   shape = stencil tile shape (as for ofdft_stencil_set_config), < 0 =
+ *   automatic.
  * ofdft_profile_reset: clear the per-class launch counters; classes whose bit
  *   is set in timed_mask are timed with HIP events on their launch stream.
  *   Classes: 0 apply, 1 CG stencil pass, 2 CG vector update, 3 true-residual
- *   passes, 4 persistent COCG, 5 density-update stencil passes, 6 density-update
- *   vector passes, 7 Anderson, 8 other vector passes, 9 network kernels.
+ *   passes, 4 COCG stencil phases (the whole solve when persistent),
+ *   5 density-update stencil passes, 6 density-update vector passes,
+ *   7 Anderson, 8 other vector passes, 9 network kernels, 10 COCG vector
+ *   phase (stepped schedule).
  * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
  *   each result written once), timed launches and their summed milliseconds
  *   for one class since the last reset (synchronises on pending events).

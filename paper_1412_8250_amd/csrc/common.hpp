@@ -155,20 +155,28 @@ __device__ inline void block_sum(double (&x)[K], double *scratch) {
 // Publish a block partial (thread 0 holds it) and return true in thread 0 of
 // the last block to arrive.  `counter` must start at 0; the last block resets
 // it.  `partials` has K * gridDim slots laid out [k][block].
+//
+// Visibility without a device-wide cache flush: the partials are written
+// with agent-scope atomic stores (coherent at the device level), a
+// workgroup-scope release makes the thread wait until those stores have
+// completed, and only then is the arrival counted.  The last block reads the
+// partials with agent-scope atomic loads.  No other data crosses blocks
+// inside the kernel, so no agent-scope fence (which writes back and
+// invalidates the L2 of every XCD) is needed.
 template <int K>
 __device__ inline bool publish_partial(const double (&x)[K], double *partials, int nblocks,
                                        int block, unsigned int *counter) {
     bool last = false;
     if (threadIdx.x == 0 && threadIdx.y == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) partials[(size_t)k * nblocks + block] = x[k];
-        __threadfence();
-        unsigned int prev = atomicAdd(counter, 1u);
+        for (int k = 0; k < K; ++k)
+            __hip_atomic_store(partials + (size_t)k * nblocks + block, x[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        const unsigned int prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == (unsigned int)nblocks - 1);
-        if (last) {
-            __threadfence();
-            *counter = 0u;
-        }
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return last;
 }
@@ -205,10 +213,47 @@ __device__ inline bool reduce_grid(const double (&x)[K], double *partials, int n
     __syncthreads();
     const bool last = s_last != 0;
     if (!last) return false;
-    __threadfence();
     sum_partials_block<K>(partials, nblocks, tot, scratch);
     return threadIdx.x == 0 && threadIdx.y == 0;
 }
+
+// Global-address-space array view.  A pointer loaded from a device table is
+// generic to the compiler, which then emits flat loads; those share a wait
+// counter with LDS traffic, so every LDS wait would also wait for the
+// prefetched loads.  GPtr casts to the global space (global loads/stores);
+// two-component types go through the compiler's native vector types.
+template <typename T> struct GNative { using type = T; };
+template <> struct GNative<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct GNative<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+
+template <typename T>
+struct GPtr {
+    using N = typename GNative<T>::type;
+    __attribute__((address_space(1))) N *p;
+    GPtr() = default;
+    __device__ explicit GPtr(const void *q) : p((__attribute__((address_space(1))) N *)q) {}
+    __device__ T operator[](int64_t i) const {
+        if constexpr (VT<T>::ncomp == 2) {
+            const N v = p[i];
+            T o;
+            o.x = v.x;
+            o.y = v.y;
+            return o;
+        } else {
+            return p[i];
+        }
+    }
+    __device__ void st(int64_t i, T v) const {
+        if constexpr (VT<T>::ncomp == 2) {
+            N w;
+            w.x = v.x;
+            w.y = v.y;
+            p[i] = w;
+        } else {
+            p[i] = v;
+        }
+    }
+};
 
 // Logical block index such that the hardware's round-robin placement of
 // consecutive workgroups over the 8 XCDs gives each XCD a contiguous range of

@@ -3,7 +3,10 @@
 //
 // The matrix -L_h + kappa is complex symmetric (L_h is real symmetric), so the
 // solver is COCG: conjugate gradients with the unconjugated bilinear form
-// x^T y.  All systems run in ONE persistent cooperative launch:
+// x^T y.  The default schedule is the stepped one (helmholtz_stepped.hip:
+// one launch per COCG phase over all systems, replayed from a HIP graph).
+// The persistent schedule, selected with a group size, runs all systems in
+// ONE cooperative launch:
 //  * the grid is split into groups of P workgroups; a group takes systems from
 //    a device work queue ordered longest-first (LPT: estimated iterations
 //    times points) and runs a whole COCG solve on it;
@@ -25,28 +28,14 @@
 #include <numeric>
 #include <vector>
 
-#include "stencil_core.hpp"
-#include "tuning.hpp"
-#include "vec.hpp"
+#include "helmholtz.hpp"
 
 namespace ofdft {
 
 constexpr int kMaxGroupP = 1024;
 constexpr long kSpinLimit = 1L << 22;
 
-enum HDone { H_RUNNING = 0, H_CONVERGED = 1, H_BREAKDOWN = 2, H_NONFINITE = 3, H_MAXIT = 4 };
 
-struct HSys {
-    int nx, ny, nz;
-    int nunits;
-    TileGeom tg;
-    int64_t n;
-    Coef<double> coef;
-    Coef<float> coef32;
-    double kre, kim;
-    void *x, *r, *pA, *pB, *Ap;
-    const void *f;
-};
 
 struct HState {
     double rr_re, rr_im, al_re, al_im, be_re, be_im, tol2, rnorm2, fnorm2;
@@ -57,24 +46,6 @@ struct GroupCtl {
     unsigned int count, gen;
     int sys, pad;
 };
-
-template <typename T> struct CX;
-template <> struct CX<double2> {
-    using S = double;
-    __device__ static double2 mk(double a, double b) { return make_double2(a, b); }
-};
-template <> struct CX<float2> {
-    using S = float;
-    __device__ static float2 mk(double a, double b) { return make_float2((float)a, (float)b); }
-};
-
-template <typename T>
-__device__ inline T cfma(T a, T b, T c) {     // a*b + c (complex)
-    T o;
-    o.x = c.x + a.x * b.x - a.y * b.y;
-    o.y = c.y + a.x * b.y + a.y * b.x;
-    return o;
-}
 
 // Bounded global-memory barrier for the P workgroups of one group.  Returns
 // false (in every thread) if the wait expired or the abort flag is raised.
@@ -114,15 +85,14 @@ __device__ inline bool group_barrier(GroupCtl *c, int P, int *abort_flag, int *s
 // ---- loaders / epilogues of the stencil phases -------------------------------
 template <typename T>
 struct LoadX {
-    const T *__restrict__ x;
+    GPtr<T> x;
     __device__ void prepare() {}
     __device__ T operator()(int64_t i) const { return x[i]; }
 };
 
 template <typename T>
 struct LoadCocgP {       // r + beta p_old (complex beta); first iteration: p_old = r, beta = 0
-    const T *__restrict__ r;
-    const T *__restrict__ p_old;
+    GPtr<T> r, p_old;
     T beta;
     __device__ void prepare() {}
     __device__ T operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
@@ -130,8 +100,7 @@ struct LoadCocgP {       // r + beta p_old (complex beta); first iteration: p_ol
 
 template <typename T>
 struct EpiInitRes {      // r = f - (-L x + kappa x); acc {r.r re, r.r im, |r|^2, |f|^2}
-    const T *__restrict__ f;
-    T *__restrict__ r;
+    GPtr<T> f, r;
     T kappa;
     double acc[4];
     T fv[4];
@@ -140,7 +109,7 @@ struct EpiInitRes {      // r = f - (-L x + kappa x); acc {r.r re, r.r im, |r|^2
         T ax = cfma(kappa, c, T{-s.x, -s.y});
         const T fi = fv[q];
         T rv{fi.x - ax.x, fi.y - ax.y};
-        r[i] = rv;
+        r.st(i, rv);
         const double a = rv.x, b = rv.y;
         acc[0] += a * a - b * b;
         acc[1] += 2.0 * a * b;
@@ -151,15 +120,14 @@ struct EpiInitRes {      // r = f - (-L x + kappa x); acc {r.r re, r.r im, |r|^2
 
 template <typename T>
 struct EpiCocgAp {       // p_new = centre, Ap = -L p + kappa p; acc {p.Ap re, im}
-    T *__restrict__ p_out;
-    T *__restrict__ Ap;
+    GPtr<T> p_out, Ap;
     T kappa;
     double acc[4];
     __device__ void pre(int, int64_t) {}
     __device__ void point(int, int64_t i, T c, T s) {
         T a = cfma(kappa, c, T{-s.x, -s.y});
-        p_out[i] = c;
-        Ap[i] = a;
+        p_out.st(i, c);
+        Ap.st(i, a);
         acc[0] += (double)c.x * a.x - (double)c.y * a.y;
         acc[1] += (double)c.x * a.y + (double)c.y * a.x;
     }
@@ -192,12 +160,6 @@ __device__ inline void stencil_units(const HSys &s, const Coef<typename VT<T>::S
     for (int u = rank; u < s.nunits; u += P) stencil_tile<T, TX, TYT, RY>(s.tg, w, ld, ep, u, lds);
 }
 
-template <typename T>
-__device__ inline const Coef<typename VT<T>::S> &coef_of(const HSys &s);
-template <>
-__device__ inline const Coef<double> &coef_of<double2>(const HSys &s) { return s.coef; }
-template <>
-__device__ inline const Coef<float> &coef_of<float2>(const HSys &s) { return s.coef32; }
 
 // Block-reduce acc[4] and publish it in part[rank]; leader only writes.
 __device__ inline void publish4(double (&acc)[4], double (*part)[4], int rank, double *scratch) {
@@ -217,8 +179,7 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, double (*
     constexpr int NT = TX * TYT;
     const Coef<typename VT<T>::S> &w = coef_of<T>(s);
     const T kappa = CT::mk(s.kre, s.kim);
-    T *x = (T *)s.x, *r = (T *)s.r, *Ap = (T *)s.Ap;
-    const T *f = (const T *)s.f;
+    const GPtr<T> x(s.x), r(s.r), Ap(s.Ap), f(s.f);
     const int maxit = st->maxit;
 
     // initial residual r = f - A x
@@ -238,7 +199,7 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, double (*
     if (done == H_RUNNING && maxit <= 0) done = H_MAXIT;
     int iter = 0;
     double be_re = 0.0, be_im = 0.0;
-    T *p_old = (T *)s.pA, *p_new = (T *)s.pB;
+    GPtr<T> p_old(s.pA), p_new(s.pB);
     __syncthreads();
 
     while (done == H_RUNNING) {
@@ -266,9 +227,9 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, double (*
             double acc[4] = {0, 0, 0, 0};
             const int64_t stride = (int64_t)P * NT;
             for (int64_t i = (int64_t)rank * NT + tid; i < s.n; i += stride) {
-                x[i] = cfma(al, p_new[i], x[i]);
+                x.st(i, cfma(al, p_new[i], x[i]));
                 const T rv = cfma(nal, Ap[i], r[i]);
-                r[i] = rv;
+                r.st(i, rv);
                 const double a = rv.x, b = rv.y;
                 acc[0] += a * a - b * b;
                 acc[1] += 2.0 * a * b;
@@ -288,7 +249,7 @@ __device__ void cocg_solve_one(const HSys &s, HState *st, GroupCtl *c, double (*
         rr_re = nr_re;
         rr_im = nr_im;
         ++iter;
-        T *tmp = p_old;
+        GPtr<T> tmp = p_old;
         p_old = p_new;
         p_new = tmp;
         if (!isfinite(rn2)) done = H_NONFINITE;
@@ -310,7 +271,7 @@ __global__ void __launch_bounds__(TX * TYT)
 cocg_persistent(const HSys *sys, HState *st, const int *order, int nsys, GroupCtl *ctl,
                 double (*part)[4], int P, unsigned int *queue, int *abort_flag, double tol) {
     using TS = TileShape<TX, TYT, RY>;
-    __shared__ T lds[2 * (TS::W * TS::H + 1)];
+    __shared__ T lds[StencilLds<T, TX, TYT, RY>::kElems];
     __shared__ double scratch[4 * (TX * TYT / 64)];
     __shared__ double bcast[4];
     __shared__ int s_flag, s_sys;
@@ -406,27 +367,6 @@ struct AddC64 {          // x += ||r|| x32
 
 using namespace ofdft;
 
-struct ofdft_batch {
-    int nsys = 0, radius = 6;
-    ofdft_dtype dtype = OFDFT_C128;
-    std::vector<ofdft_grid> grids;
-    std::vector<void *> allocs;
-    // per system workspaces (complex128: r, pA, pB, Ap; complex64 adds r128, f32, x32)
-    std::vector<void *> r, pA, pB, Ap, r128, f32, x32;
-    HSys *d_sys = nullptr;
-    HState *d_st = nullptr;
-    int *d_order = nullptr;
-    GroupCtl *d_ctl = nullptr;
-    double (*d_part)[4] = nullptr;    // 2 * groups_cap rows of 4 partial sums
-    unsigned int *d_queue = nullptr;
-    int *d_abort = nullptr;
-    double *d_totals = nullptr;   // 2 per system
-    RedBuf rb{};
-    int groups_cap = 0;
-    // launch configuration chosen by the tuner (or the default)
-    int shape = -1, P = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
 
 namespace {
 
@@ -485,13 +425,10 @@ int launch_persistent(ofdft_batch *b, int P, int nsys_run, double tol, hipStream
 
 template <typename T>
 int run_persistent(ofdft_batch *b, int shape, int P, int nsys_run, double tol, hipStream_t s) {
-    if constexpr (sizeof(T) == 8) {      // complex64 can afford four rows per thread
-        if (shape == SHAPE_64x4x4) return launch_persistent<T, 64, 4, 4>(b, P, nsys_run, tol, s);
-    }
-    switch (shape) {
-        case SHAPE_32x8x2: return launch_persistent<T, 32, 8, 2>(b, P, nsys_run, tol, s);
-        default: return launch_persistent<T, 64, 4, 2>(b, P, nsys_run, tol, s);
-    }
+    return dispatch_cocg_shape<T>(shape, [&](auto sh) {
+        using S = decltype(sh);
+        return launch_persistent<T, S::TX, S::TYT, S::RY>(b, P, nsys_run, tol, s);
+    });
 }
 
 int residual_c128(ofdft_batch *b, int j, const double2 *f, const double2 *x, double2 *r,
@@ -509,6 +446,7 @@ int residual_c128(ofdft_batch *b, int j, const double2 *f, const double2 *x, dou
 }
 
 void batch_free(ofdft_batch *b) {
+    stepped_free(b);
     for (void *p : b->allocs)
         if (p) (void)hipFree(p);
     b->allocs.clear();
@@ -532,23 +470,22 @@ int dalloc(ofdft_batch *b, P_ **p, size_t bytes) {
 // Fill the device system table for one pass.  elem = complex element type of
 // the inner solve; x/f pointers per system.
 int upload_systems(ofdft_batch *b, const double *kappa, const std::vector<const void *> &f,
-                   const std::vector<void *> &x, bool c64, int shape, hipStream_t s) {
-    std::vector<HSys> hs(b->nsys);
+                   const std::vector<void *> &x, bool c64, int shape, bool stepped,
+                   std::vector<HSys> &hs, hipStream_t s) {
+    hs.assign(b->nsys, HSys{});
     for (int j = 0; j < b->nsys; ++j) {
         const ofdft_grid &g = b->grids[j];
         HSys &h = hs[j];
         h.nx = g.nx;
         h.ny = g.ny;
         h.nz = g.nz;
-        int tx, ty;
-        shape_extent(shape, tx, ty);
-        const int zl = zlen_for_units(g, shape);
-        const int eff = (shape == SHAPE_64x4x4 && !c64) ? SHAPE_64x4x2 : shape;
-        switch (eff) {
-            case SHAPE_64x4x4: h.tg = make_tile_geom<64, 4, 4>(g, zl); break;
-            case SHAPE_32x8x2: h.tg = make_tile_geom<32, 8, 2>(g, zl); break;
-            default: h.tg = make_tile_geom<64, 4, 2>(g, zl); break;
-        }
+        const int eff = c64 ? cocg_shape<float2>(shape) : cocg_shape<double2>(shape);
+        const int zl = stepped ? stepped_zlen(g, c64, eff) : zlen_for_units(g, eff);
+        dispatch_shape(eff, [&](auto sh) {
+            using S = decltype(sh);
+            h.tg = make_tile_geom<S::TX, S::TYT, S::RY>(g, zl);
+            return 0;
+        });
         h.nunits = h.tg.nblocks;
         h.n = npoints(g);
         h.coef = make_coef(g, b->radius);
@@ -578,7 +515,7 @@ int default_shape(const ofdft_batch *b) {
     if (b->dtype == OFDFT_C64) return SHAPE_64x4x2;
     int small = 0;
     for (auto &g : b->grids) small += g.nx <= 40;
-    return small * 2 > b->nsys ? SHAPE_32x8x2 : SHAPE_64x4x2;
+    return small * 2 > b->nsys ? SHAPE_32x8x2 : SHAPE_64x8x1;
 }
 
 }  // namespace
@@ -666,7 +603,7 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
     const int nsys = b->nsys;
     const bool c64 = b->dtype == OFDFT_C64;
     const int shape = b->shape >= 0 ? b->shape : default_shape(b);
-    const int P = b->P;      // 0: chosen per launch from the residency and the system count
+    const int P = b->P;      // 0: stepped schedule; > 0: persistent groups of P workgroups
     // LPT order: longest estimated solve first
     std::vector<double> cost(nsys);
     for (int j = 0; j < nsys; ++j) cost[j] = est_cost(b->grids[j], kappa[2 * j], kappa[2 * j + 1]);
@@ -677,9 +614,30 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
     std::vector<HState> hst(nsys);
     std::vector<double> tot(2 * nsys);
     std::vector<int> iters(nsys, 0), outer(nsys, 0), done(nsys, H_RUNNING);
+    std::vector<HSys> hs;
+    std::vector<int> caps(nsys), it_pass(nsys), done_pass(nsys);
     auto run_pass = [&](const std::vector<int> &which, double tol, int cap,
                         const std::vector<const void *> &fs, const std::vector<void *> &xs) -> int {
-        OFDFT_TRY(upload_systems(b, kappa, fs, xs, c64, shape, s));
+        const bool stepped = P == 0;
+        OFDFT_TRY(upload_systems(b, kappa, fs, xs, c64, shape, stepped, hs, s));
+        const double e = c64 ? 8.0 : 16.0;
+        if (stepped) {
+            for (int j = 0; j < nsys; ++j) caps[j] = std::max(0, cap - iters[j]);
+            OFDFT_TRY(stepped_run(b, c64, shape, hs, which, caps, tol, it_pass, done_pass, s));
+            double bs = 0.0, bu = 0.0;
+            for (int j : which) {
+                iters[j] += it_pass[j];
+                done[j] = done_pass[j];
+                // init: read x, f, write r; stencil phase: read r, p_old, write
+                // p, Ap; vector phase: read x, p, r, Ap, write x, r
+                const double n = (double)npoints(b->grids[j]);
+                bs += n * e * (3.0 + 4.0 * it_pass[j]);
+                bu += n * e * 6.0 * it_pass[j];
+            }
+            prof_add(K_COCG, bs, 0);
+            prof_add(K_COCG_UPDATE, bu, 0);
+            return OFDFT_OK;
+        }
         for (int j = 0; j < nsys; ++j) {
             hst[j] = HState{};
             hst[j].maxit = std::max(0, cap - iters[j]);
@@ -698,7 +656,6 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
             return OFDFT_HIP_ERROR;
         }
         double bytes = 0.0;
-        const double e = c64 ? 8.0 : 16.0;
         for (int j : which) {
             iters[j] += hst[j].iter;
             done[j] = hst[j].done;

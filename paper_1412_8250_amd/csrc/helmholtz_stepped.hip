@@ -1,0 +1,411 @@
+// Stepped schedule of the batched COCG solver for the shifted systems
+// (-L_h + kappa_j) u_j = f_j (Section 3.1; COCG = conjugate gradients with
+// the unconjugated bilinear form x^T y, valid because -L_h + kappa is complex
+// symmetric).
+//
+// Each COCG phase is ONE launch over all running systems of the batch:
+//  * stencil phase: p = r + beta p_old formed on the fly, p and Ap = -L p +
+//    kappa p written, p^T Ap reduced;  the grid holds the stencil tiles of
+//    every system (block -> system by a prefix table, XCD-aware order), so
+//    eight 320^3 systems give thousands of workgroups per launch;
+//  * vector phase: x += alpha p, r -= alpha Ap, r^T r and |r|^2 reduced.
+// The scalars of every system (alpha, beta, r^T r, status) live on the
+// device: the last workgroup of a system to finish a phase combines that
+// system's partial sums (fixed order, so results do not depend on timing or
+// on the other systems of the batch) and updates its scalars.  Converged
+// systems' workgroups exit at once.  Iterations are captured once in a HIP
+// graph and replayed; the host only polls the status array between replays.
+// No workgroup ever waits for another inside a launch.
+#include <algorithm>
+#include <cmath>
+
+#include "helmholtz.hpp"
+
+namespace ofdft {
+
+struct StepState {
+    double rr_re, rr_im;     // r^T r of the current residual
+    double al_re, al_im;     // alpha of the current iteration
+    double be_re, be_im;     // beta of the next direction
+    double rn2, fn2, tol2;   // |r|^2, |f|^2, tol^2 |f|^2
+    int iter, done, maxit, parity;   // parity: 0 -> p_old in pA, 1 -> p_old in pB
+};
+
+namespace {
+
+constexpr int kStepIters = 4;          // iterations per captured graph
+constexpr int kVecThreadsStep = 256;
+constexpr int kVecMaxBlocks = 1024;    // per system
+
+// System of logical block b: start[j] <= b < start[j + 1].
+__device__ inline int find_sys(const int *start, int nsys, int b) {
+    int lo = 0, hi = nsys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T>
+struct StepLoadX {
+    GPtr<T> x;
+    __device__ T operator()(int64_t i) const { return x[i]; }
+};
+
+template <typename T>
+struct StepLoadP {       // r + beta p_old (first iteration: p_old = r, beta = 0)
+    GPtr<T> r, p_old;
+    T beta;
+    __device__ T operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
+};
+
+template <typename T>
+struct StepEpiInit {     // r = f - (-L x + kappa x); acc {r^T r re, im, |r|^2, |f|^2}
+    GPtr<T> f, r;
+    T kappa;
+    double acc[4];
+    T fv[4];
+    __device__ void pre(int q, int64_t i) { fv[q] = f[i]; }
+    __device__ void point(int q, int64_t i, T c, T s) {
+        const T ax = cfma(kappa, c, T{-s.x, -s.y});
+        const T fi = fv[q];
+        const T rv{fi.x - ax.x, fi.y - ax.y};
+        r.st(i, rv);
+        const double a = rv.x, b = rv.y;
+        acc[0] += a * a - b * b;
+        acc[1] += 2.0 * a * b;
+        acc[2] += a * a + b * b;
+        acc[3] += (double)fi.x * fi.x + (double)fi.y * fi.y;
+    }
+};
+
+template <typename T>
+struct StepEpiPAp {      // p_new = centre, Ap = -L p + kappa p; acc {p^T Ap re, im}
+    GPtr<T> p_out, Ap;
+    T kappa;
+    double acc[2];
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, T c, T s) {
+        const T a = cfma(kappa, c, T{-s.x, -s.y});
+        p_out.st(i, c);
+        Ap.st(i, a);
+        acc[0] += (double)c.x * a.x - (double)c.y * a.y;
+        acc[1] += (double)c.x * a.y + (double)c.y * a.x;
+    }
+};
+
+enum StepPhase { PH_INIT = 0, PH_PAP = 1 };
+
+// Stencil phases.  part: 4 slots per unit, system j's region starts at
+// 4 * ublk[j] and is laid out [k][unit].
+template <typename T, int TX, int TYT, int RY, int Phase>
+__global__ void __launch_bounds__(TX * TYT)
+step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int total,
+             unsigned int *ctr, double *part, double tol) {
+    using CT = CX<T>;
+    __shared__ T lds[StencilLds<T, TX, TYT, RY>::kElems];
+    __shared__ double scratch[4 * (TX * TYT / 64)];
+    const int lb = xcd_remap(blockIdx.x, total);
+    const int j = find_sys(ublk, nsys, lb);
+    StepState *sj = st + j;
+    const int done = sj->done;
+    if (done != H_RUNNING) return;
+    const HSys &h = sys[j];
+    const int unit = lb - ublk[j];
+    const int nunits = ublk[j + 1] - ublk[j];
+    double *pj = part + 4 * (size_t)ublk[j];
+    const T kappa = CT::mk(h.kre, h.kim);
+    if constexpr (Phase == PH_INIT) {
+        StepLoadX<T> ld{GPtr<T>(h.x)};
+        StepEpiInit<T> ep{GPtr<T>(h.f), GPtr<T>(h.r), kappa, {0, 0, 0, 0}, {}};
+        stencil_tile<T, TX, TYT, RY>(h.tg, coef_of<T>(h), ld, ep, unit, lds);
+        double acc[4] = {ep.acc[0], ep.acc[1], ep.acc[2], ep.acc[3]};
+        block_sum<4>(acc, scratch);
+        double t[4];
+        if (reduce_grid<4>(acc, pj, nunits, unit, ctr + j, scratch, t)) {
+            sj->rr_re = t[0];
+            sj->rr_im = t[1];
+            sj->rn2 = t[2];
+            sj->fn2 = t[3];
+            sj->tol2 = tol * tol * t[3];
+            sj->iter = 0;
+            sj->parity = 0;
+            int d = !isfinite(t[2]) ? H_NONFINITE : (t[2] <= sj->tol2 ? H_CONVERGED : H_RUNNING);
+            if (d == H_RUNNING && sj->maxit <= 0) d = H_MAXIT;
+            sj->done = d;
+        }
+    } else {
+        const bool first = sj->iter == 0;
+        const void *p_old = sj->parity ? h.pB : h.pA;
+        const void *p_new = sj->parity ? h.pA : h.pB;
+        StepLoadP<T> ld{GPtr<T>(h.r), GPtr<T>(first ? h.r : p_old),
+                        first ? CT::mk(0.0, 0.0) : CT::mk(sj->be_re, sj->be_im)};
+        StepEpiPAp<T> ep{GPtr<T>(p_new), GPtr<T>(h.Ap), kappa, {0, 0}};
+        stencil_tile<T, TX, TYT, RY>(h.tg, coef_of<T>(h), ld, ep, unit, lds);
+        double acc[2] = {ep.acc[0], ep.acc[1]};
+        block_sum<2>(acc, scratch);
+        double t[2];
+        if (reduce_grid<2>(acc, pj, nunits, unit, ctr + j, scratch, t)) {
+            const double den = t[0] * t[0] + t[1] * t[1];
+            if (!isfinite(den)) {
+                sj->done = H_NONFINITE;
+            } else if (den == 0.0) {
+                sj->done = H_BREAKDOWN;
+            } else {
+                sj->al_re = (sj->rr_re * t[0] + sj->rr_im * t[1]) / den;
+                sj->al_im = (sj->rr_im * t[0] - sj->rr_re * t[1]) / den;
+            }
+        }
+    }
+}
+
+// Vector phase: x += alpha p, r -= alpha Ap; then beta, status.  part region
+// of system j starts at 4 * vblk[j] (the caller offsets part past the stencil
+// slots).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreadsStep)
+step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned int *ctr,
+            double *part) {
+    using CT = CX<T>;
+    __shared__ double scratch[3 * (kVecThreadsStep / 64)];
+    const int b = blockIdx.x;
+    const int j = find_sys(vblk, nsys, b);
+    StepState *sj = st + j;
+    if (sj->done != H_RUNNING) return;
+    const HSys &h = sys[j];
+    const int lb = b - vblk[j], nb = vblk[j + 1] - vblk[j];
+    const GPtr<T> x(h.x), r(h.r), Ap(h.Ap), p(sj->parity ? h.pA : h.pB);
+    const T al = CT::mk(sj->al_re, sj->al_im), nal = CT::mk(-sj->al_re, -sj->al_im);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)nb * kVecThreadsStep;
+    for (int64_t i = (int64_t)lb * kVecThreadsStep + threadIdx.x; i < h.n; i += stride) {
+        x.st(i, cfma(al, p[i], x[i]));
+        const T rv = cfma(nal, Ap[i], r[i]);
+        r.st(i, rv);
+        const double a = rv.x, c = rv.y;
+        acc[0] += a * a - c * c;
+        acc[1] += 2.0 * a * c;
+        acc[2] += a * a + c * c;
+    }
+    block_sum<3>(acc, scratch);
+    double t[3];
+    if (reduce_grid<3>(acc, part + 4 * (size_t)vblk[j], nb, lb, ctr + j, scratch, t)) {
+        const double rr_re = sj->rr_re, rr_im = sj->rr_im;
+        const double d2 = rr_re * rr_re + rr_im * rr_im;
+        sj->be_re = (t[0] * rr_re + t[1] * rr_im) / d2;
+        sj->be_im = (t[1] * rr_re - t[0] * rr_im) / d2;
+        sj->rr_re = t[0];
+        sj->rr_im = t[1];
+        sj->rn2 = t[2];
+        const int iter = sj->iter + 1;
+        sj->iter = iter;
+        sj->parity ^= 1;
+        int d = H_RUNNING;
+        if (!isfinite(t[2])) d = H_NONFINITE;
+        else if (t[2] <= sj->tol2) d = H_CONVERGED;
+        else if (t[0] * t[0] + t[1] * t[1] <= 1e-60 * t[2] * t[2]) d = H_BREAKDOWN;
+        else if (iter >= sj->maxit) d = H_MAXIT;
+        sj->done = d;
+    }
+}
+
+template <typename T, int TX, int TYT, int RY>
+int launch_phase(ofdft_batch *b, int phase, double tol, hipStream_t s) {
+    const int total = b->step_units;
+    if (phase == PH_INIT)
+        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_INIT>), dim3(total), dim3(TX, TYT), 0, s,
+                           b->d_sys, b->d_step, b->d_ublk, b->nsys, total, b->d_ctr, b->d_spart, tol);
+    else
+        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_PAP>), dim3(total), dim3(TX, TYT), 0, s,
+                           b->d_sys, b->d_step, b->d_ublk, b->nsys, total, b->d_ctr, b->d_spart, tol);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+template <typename T>
+int launch_stencil_phase(ofdft_batch *b, int shape, int phase, double tol, hipStream_t s) {
+    return dispatch_cocg_shape<T>(shape, [&](auto sh) {
+        using S = decltype(sh);
+        return launch_phase<T, S::TX, S::TYT, S::RY>(b, phase, tol, s);
+    });
+}
+
+template <typename T>
+int launch_update(ofdft_batch *b, hipStream_t s) {
+    hipLaunchKernelGGL(step_update<T>, dim3(b->step_vblocks), dim3(kVecThreadsStep), 0, s, b->d_sys,
+                       b->d_step, b->d_vblk, b->nsys, b->d_ctr, b->d_spart + 4 * (size_t)b->step_units);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+// `iters` iterations of both phases.  Timed: each launch is accounted and
+// timed on its own; otherwise (graph capture) the caller accounts replays.
+template <typename T>
+int step_iterations(ofdft_batch *b, int shape, int iters, hipStream_t s, bool timed) {
+    for (int k = 0; k < iters; ++k) {
+        if (timed) {
+            {
+                ProfScope ps(K_COCG, 0.0, s);
+                OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_PAP, 0.0, s));
+            }
+            ProfScope ps(K_COCG_UPDATE, 0.0, s);
+            OFDFT_TRY(launch_update<T>(b, s));
+        } else {
+            OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_PAP, 0.0, s));
+            OFDFT_TRY(launch_update<T>(b, s));
+        }
+    }
+    return OFDFT_OK;
+}
+
+template <typename T>
+int graph_get(ofdft_batch *b, int shape) {
+    const int key[3] = {shape, (int)sizeof(T), b->step_units};
+    if (b->step_graph && key[0] == b->step_graph_key[0] && key[1] == b->step_graph_key[1] &&
+        key[2] == b->step_graph_key[2])
+        return OFDFT_OK;
+    if (b->step_graph) {
+        (void)hipGraphExecDestroy(b->step_graph);
+        b->step_graph = nullptr;
+    }
+    if (!b->step_cap) OFDFT_CHECK_HIP(hipStreamCreateWithFlags(&b->step_cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    OFDFT_CHECK_HIP(hipStreamBeginCapture(b->step_cap, hipStreamCaptureModeThreadLocal));
+    const int rc = step_iterations<T>(b, shape, kStepIters, b->step_cap, false);
+    const hipError_t e = hipStreamEndCapture(b->step_cap, &graph);
+    if (rc != OFDFT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    OFDFT_CHECK_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&b->step_graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    OFDFT_CHECK_HIP(ei);
+    for (int i = 0; i < 3; ++i) b->step_graph_key[i] = key[i];
+    return OFDFT_OK;
+}
+
+// Block tables of the current system table (units from the uploaded tile
+// geometries, vector blocks from the sizes) and the partial-slot buffer.
+int prepare_layout(ofdft_batch *b, const std::vector<HSys> &hs, hipStream_t s) {
+    const int nsys = b->nsys;
+    std::vector<int> ublk(nsys + 1, 0), vblk(nsys + 1, 0);
+    for (int j = 0; j < nsys; ++j) {
+        ublk[j + 1] = ublk[j] + hs[j].tg.nblocks;
+        const int64_t want = (hs[j].n + 8 * kVecThreadsStep - 1) / (8 * kVecThreadsStep);
+        vblk[j + 1] = vblk[j] + (int)std::max<int64_t>(1, std::min<int64_t>(want, kVecMaxBlocks));
+    }
+    if (ublk == b->h_ublk && vblk == b->h_vblk) return OFDFT_OK;
+    if (b->step_graph) {                    // captured with the old tables
+        OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+        (void)hipGraphExecDestroy(b->step_graph);
+        b->step_graph = nullptr;
+    }
+    if (!b->d_ublk) {
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_ublk, sizeof(int) * (nsys + 1)));
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_vblk, sizeof(int) * (nsys + 1)));
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_ctr, sizeof(unsigned int) * nsys));
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_step, sizeof(StepState) * nsys));
+        OFDFT_CHECK_HIP(hipHostMalloc(&b->h_step, sizeof(StepState) * nsys, hipHostMallocDefault));
+        OFDFT_CHECK_HIP(hipMemsetAsync(b->d_ctr, 0, sizeof(unsigned int) * nsys, s));
+    }
+    const size_t slots = 4 * ((size_t)ublk[nsys] + (size_t)vblk[nsys]);
+    const size_t have = 4 * ((size_t)(b->h_ublk.empty() ? 0 : b->h_ublk[nsys]) +
+                             (size_t)(b->h_vblk.empty() ? 0 : b->h_vblk[nsys]));
+    if (!b->d_spart || slots > have) {
+        if (b->d_spart) OFDFT_CHECK_HIP(hipFree(b->d_spart));
+        b->d_spart = nullptr;
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_spart, sizeof(double) * slots));
+    }
+    OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_ublk, ublk.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+    OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_vblk, vblk.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+    b->h_ublk = ublk;
+    b->h_vblk = vblk;
+    b->step_units = ublk[nsys];
+    b->step_vblocks = vblk[nsys];
+    return OFDFT_OK;
+}
+
+template <typename T>
+int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::vector<int> &maxit,
+          double tol, std::vector<int> &iters, std::vector<int> &done, hipStream_t s) {
+    const int nsys = b->nsys;
+    for (int j = 0; j < nsys; ++j) {
+        b->h_step[j] = StepState{};
+        b->h_step[j].done = H_IDLE;
+        b->h_step[j].maxit = maxit[j];
+    }
+    for (int j : which) b->h_step[j].done = H_RUNNING;
+    OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_step, b->h_step, sizeof(StepState) * nsys, hipMemcpyHostToDevice, s));
+    {
+        ProfScope ps(K_COCG, 0.0, s);
+        OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_INIT, tol, s));
+    }
+    const bool timed = prof_timed(K_COCG) || prof_timed(K_COCG_UPDATE);
+    int reps = 1;
+    for (;;) {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * nsys, hipMemcpyDeviceToHost, s));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+        bool running = false;
+        for (int j : which) running = running || b->h_step[j].done == H_RUNNING;
+        if (!running) break;
+        if (timed) {
+            OFDFT_TRY(step_iterations<T>(b, shape, reps * kStepIters, s, true));
+        } else {
+            OFDFT_TRY(graph_get<T>(b, shape));
+            for (int k = 0; k < reps; ++k) OFDFT_CHECK_HIP(hipGraphLaunch(b->step_graph, s));
+            prof_add(K_COCG, 0.0, reps * kStepIters);
+            prof_add(K_COCG_UPDATE, 0.0, reps * kStepIters);
+        }
+        reps = std::min(reps * 2, 32);
+    }
+    for (int j = 0; j < nsys; ++j) {
+        iters[j] = b->h_step[j].iter;
+        done[j] = b->h_step[j].done;
+    }
+    return OFDFT_OK;
+}
+
+}  // namespace
+
+// The systems of a batch fill the GPU together, so chunks are long (about
+// 160 planes, little queue warm-up) unless a system would have fewer than 32
+// tiles; then they shrink down to 8 planes.
+int stepped_zlen(const ofdft_grid &g, bool, int shape) {
+    int tx, ty;
+    shape_extent(shape, tx, ty);
+    const int64_t tiles = (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
+    int chunks = std::max(1, (g.nz + 159) / 160);
+    while (tiles * chunks < 32 && g.nz / (chunks + 1) >= 8) ++chunks;
+    return (g.nz + chunks - 1) / chunks;
+}
+
+int stepped_run(ofdft_batch *b, bool c64, int shape, const std::vector<HSys> &hs,
+                const std::vector<int> &which, const std::vector<int> &maxit, double tol,
+                std::vector<int> &iters, std::vector<int> &done, hipStream_t s) {
+    OFDFT_TRY(prepare_layout(b, hs, s));
+    if (c64) return run_t<float2>(b, shape, which, maxit, tol, iters, done, s);
+    return run_t<double2>(b, shape, which, maxit, tol, iters, done, s);
+}
+
+void stepped_free(ofdft_batch *b) {
+    if (b->step_graph) (void)hipGraphExecDestroy(b->step_graph);
+    if (b->step_cap) (void)hipStreamDestroy(b->step_cap);
+    if (b->d_ublk) (void)hipFree(b->d_ublk);
+    if (b->d_vblk) (void)hipFree(b->d_vblk);
+    if (b->d_ctr) (void)hipFree(b->d_ctr);
+    if (b->d_step) (void)hipFree(b->d_step);
+    if (b->h_step) (void)hipHostFree(b->h_step);
+    if (b->d_spart) (void)hipFree(b->d_spart);
+    b->step_graph = nullptr;
+    b->step_cap = nullptr;
+    b->d_ublk = b->d_vblk = nullptr;
+    b->d_ctr = nullptr;
+    b->d_step = b->h_step = nullptr;
+    b->d_spart = nullptr;
+}
+
+}  // namespace ofdft

@@ -15,12 +15,13 @@ enum KClass {
     K_CG_STENCIL,      // CG: p update + stencil + p.Ap
     K_CG_UPDATE,       // CG: x, r update + r.r
     K_RESIDUAL,        // true-residual stencil passes
-    K_COCG,            // persistent batched COCG
+    K_COCG,            // batched COCG: stencil phases (the whole solve when persistent)
     K_U_STENCIL,       // density update: H u and L d passes
     K_U_VECTOR,        // density update: residual, line-search probes, step
     K_ANDERSON,
     K_POINTWISE,       // other vector passes (projections, casts, assembly)
     K_NN,              // network convolutions and their gradients
+    K_COCG_UPDATE,     // batched COCG (stepped): x, r update + r.r
     K_CLASSES
 };
 

@@ -6,12 +6,14 @@
 //    over a chunk of planes.  Each thread owns one x column and RY
 //    consecutive y rows.
 //  * z-neighbours come from a per-thread register queue of 13 planes, filled
-//    by one coalesced load per point per plane (the queue front, 7 planes
-//    ahead of the output plane).
+//    by one coalesced load per point per plane (the queue front, fetched
+//    R + 3 planes ahead of the output plane).
 //  * x- and y-neighbours come from an LDS copy of the current plane with a
 //    6-wide halo: the tile centre is written from the queue, only the halo
-//    ring is fetched from global memory (mostly L2/MALL hits, since the
-//    neighbouring tiles stream the same planes on the same XCD).
+//    ring is fetched from global memory.  The ring of a plane is fetched at
+//    the same time as the neighbouring tiles (same XCD, launched together)
+//    fetch that plane as their queue front, so it is served by L2, and
+//    waits in an LDS slot until the plane is computed.
 //  * y-register blocking: a thread reads RY+12 column values once and uses
 //    them for its RY outputs.
 //  * Periodic wrap: all wrapped x/y offsets are computed once per thread
@@ -161,16 +163,47 @@ __device__ inline void stencil_plane_compute(const Coef<typename VT<T>::S> &w, c
     }
 }
 
-// Two-buffer form (used where LDS is scarce: complex128 tiles and the
-// persistent COCG kernel).  `lds` holds 2 * (W*H + 1) elements.
-template <typename T, int TX, int TYT, int RY, class Load, class Epi>
+// LDS plan of a tile shape and element type.  The halo ring of plane P is
+// fetched L planes before P is computed and parked in one of L plane buffers
+// (slot (P - zb) mod L) until then; the centre is written from the z queue at
+// P.  L = R + 3 fetches the ring together with the queue front of plane P,
+// i.e. when the tiles around this one fetch P's centre, so that the halo
+// reads hit in L2.  L is the largest value up to R + 3 whose buffers fit in
+// 150 KiB (at least 2: a plain double buffer).
+template <typename T, int TX, int TYT, int RY>
+struct StencilLds {
+    using TS = TileShape<TX, TYT, RY>;
+    static constexpr int kPlane = TS::W * TS::H + 1;
+    static constexpr int kFit = (int)((150 * 1024) / ((size_t)kPlane * sizeof(T)));
+    static_assert(kFit >= 2, "tile too large for a double-buffered LDS plane");
+    static constexpr int kLead = kFit > kMaxRadius + 3 ? kMaxRadius + 3 : kFit;
+    static constexpr int kElems = kLead * kPlane;
+};
+
+// One tile: march the z chunk, calling the epilogue for every owned point.
+// `lds` holds L plane buffers of W*H + 1 elements (the last element of each
+// is a dummy target for spare ring slots).
+//
+// Timeline of output plane k: write q[R] (plane k) into slot(k) and the ring
+// fetched two planes ago (plane k + L - 2) into slot(k + L - 2); issue the
+// epilogue's loads for plane k, then the fetches of ring k + L and of queue
+// front k + R + 3; barrier; compute plane k.  A slot is rewritten two planes
+// after its last reader, so one barrier per plane suffices.  In-flight
+// fetches land in fixed registers (the loop is unrolled by two), so waiting
+// for one plane's data never waits for younger loads.  Ring fetches past the
+// chunk end are clamped to its last plane (never used, an L2 hit).
+template <typename T, int TX, int TYT, int RY, class Load, class Epi,
+          int L = StencilLds<T, TX, TYT, RY>::kLead>
 __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>::S> &w,
                                     const Load &ld, Epi &ep, int logical_block, T *lds) {
     using TS = TileShape<TX, TYT, RY>;
     constexpr int R = TS::R, W = TS::W, H = TS::H;
+    constexpr int SL = W * H + 1;
+    static_assert(L >= 2 && L <= R + 3, "ring lead out of range");
     const TileCtx<TX, TYT, RY> tc(g, logical_block);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int zb = tc.zb, ze = tc.ze;
+    const int zlast = ze - 1;
     const int64_t nxy = (int64_t)g.nx * g.ny;
 
     // z queue: q[j][r] holds plane (k - R + j) for output plane k.
@@ -181,121 +214,20 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[j][r] = ld(pb + tc.own[r]);
     }
-    // Software pipeline: the halo ring is fetched two planes ahead and the
-    // queue front (plane k + R + 1) two planes ahead of its use, so each
-    // plane's global loads overlap two planes of compute.
-    T ringA[TS::RING_PER_T], ringB[TS::RING_PER_T];
-    {
-        const int64_t p0 = (int64_t)zb * nxy, p1 = (int64_t)wrapi(zb + 1, g.nz) * nxy;
+    // rings of planes zb .. zb + L - 3 go straight to their slots
 #pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i) {
-            ringA[i] = ld(p0 + tc.ring_glb[i]);
-            ringB[i] = ld(p1 + tc.ring_glb[i]);
-        }
-    }
-    T qn1[RY], qn2[RY];
-    {
-        const int64_t f1 = (int64_t)wrapi(zb + R + 1, g.nz) * nxy;
-        const int64_t f2 = (int64_t)wrapi(zb + R + 2, g.nz) * nxy;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            qn1[r] = ld(f1 + tc.own[r]);
-            qn2[r] = ld(f2 + tc.own[r]);
-        }
-    }
-    int kr = wrapi(zb + 2, g.nz);          // plane of the next ring prefetch
-    int kf = wrapi(zb + R + 3, g.nz);      // plane of the next queue-front prefetch
-
-    // One plane.  `ring`/`qn` hold loads issued two planes earlier; they are
-    // consumed and then refilled in place (no register rotation of in-flight
-    // loads, so the waits only cover old loads).  `active` is false for the
-    // padding plane of an odd-length chunk: it still loads (in bounds) but
-    // stores nothing.
-    auto plane = [&](int k, T (&ring)[TS::RING_PER_T], T (&qn)[RY], bool active, int parity) {
-        const int kk = active ? k : zb;
-        const int64_t pk = (int64_t)kk * nxy;
-        T *buf = lds + parity * (W * H + 1);
-#pragma unroll
-        for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[R][r];
-#pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i) buf[tc.ring_lds[i]] = ring[i];
-        // epilogue operands of this plane first, then the prefetches
-#pragma unroll
-        for (int r = 0; r < RY; ++r) ep.pre(r, pk + tc.own[r]);
-        T nxt[RY];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) nxt[r] = qn[r];
-        {
-            const int64_t pr = (int64_t)kr * nxy, pf = (int64_t)kf * nxy;
-#pragma unroll
-            for (int i = 0; i < TS::RING_PER_T; ++i) ring[i] = ld(pr + tc.ring_glb[i]);
-#pragma unroll
-            for (int r = 0; r < RY; ++r) qn[r] = ld(pf + tc.own[r]);
-        }
-        __syncthreads();
-        stencil_plane_compute<T, TX, TYT, RY>(w, buf, q, tc, active, pk, ep);
-#pragma unroll
-        for (int j = 0; j < 2 * R; ++j)
-#pragma unroll
-            for (int r = 0; r < RY; ++r) q[j][r] = q[j + 1][r];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) q[2 * R][r] = nxt[r];
-        kr = (kr + 1 == g.nz) ? 0 : kr + 1;
-        kf = (kf + 1 == g.nz) ? 0 : kf + 1;
-    };
-
-    for (int k = zb; k < ze; k += 2) {
-        plane(k, ringA, qn1, true, 0);
-        plane(k + 1, ringB, qn2, k + 1 < ze, 1);
-    }
-    // the LDS buffers are reused by the next tile of a persistent caller
-    __syncthreads();
-}
-
-// Slot form: the halo ring of plane P is fetched together with the queue
-// front of plane P (R + 3 planes before P is computed), i.e. at the moment
-// the tiles around it fetch P's centre, so that the halo reads hit L2 while
-// the neighbours' lines are fresh.  The ring waits in one of kDeepSlots LDS
-// plane buffers: plane P uses slot (P - zb) mod kDeepSlots; the ring is
-// written R + 1 planes ahead and the centre at P, before P's barrier.  Nine
-// slots keep the slot written at plane k clear of the slots still read at
-// planes k - 1 and k.  Planes past the chunk end are never computed, so
-// their ring fetches are clamped to the chunk's last plane (an L2 hit).
-constexpr int kDeepSlots = kMaxRadius + 3;
-
-template <typename T, int TX, int TYT, int RY, class Load, class Epi>
-__device__ inline void stencil_tile_deep(const TileGeom &g, const Coef<typename VT<T>::S> &w,
-                                         const Load &ld, Epi &ep, int logical_block, T *lds) {
-    using TS = TileShape<TX, TYT, RY>;
-    constexpr int R = TS::R, W = TS::W, H = TS::H;
-    constexpr int SL = W * H + 1;
-    const TileCtx<TX, TYT, RY> tc(g, logical_block);
-    const int tx = threadIdx.x, ty = threadIdx.y;
-    const int zb = tc.zb, ze = tc.ze;
-    const int zlast = ze - 1;
-    const int64_t nxy = (int64_t)g.nx * g.ny;
-
-    T q[2 * R + 1][RY];
-#pragma unroll
-    for (int j = 0; j < 2 * R + 1; ++j) {
-        const int64_t pb = (int64_t)wrapi(zb - R + j, g.nz) * nxy;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) q[j][r] = ld(pb + tc.own[r]);
-    }
-    // rings of planes zb .. zb + R go straight to their slots
-#pragma unroll
-    for (int j = 0; j <= R; ++j) {
+    for (int j = 0; j < L - 2; ++j) {
         const int64_t pb = (int64_t)min(zb + j, zlast) * nxy;
         T *slot = lds + j * SL;
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) slot[tc.ring_lds[i]] = ld(pb + tc.ring_glb[i]);
     }
-    // rings and queue fronts of planes zb + R + 1 and zb + R + 2 in flight
+    // rings of planes zb + L - 2, zb + L - 1 and queue fronts R + 1, R + 2 in flight
     T ringA[TS::RING_PER_T], ringB[TS::RING_PER_T];
     T qn1[RY], qn2[RY];
     {
-        const int64_t r1 = (int64_t)min(zb + R + 1, zlast) * nxy;
-        const int64_t r2 = (int64_t)min(zb + R + 2, zlast) * nxy;
+        const int64_t r1 = (int64_t)min(zb + L - 2, zlast) * nxy;
+        const int64_t r2 = (int64_t)min(zb + L - 1, zlast) * nxy;
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) {
             ringA[i] = ld(r1 + tc.ring_glb[i]);
@@ -309,15 +241,17 @@ __device__ inline void stencil_tile_deep(const TileGeom &g, const Coef<typename 
             qn2[r] = ld(f2 + tc.own[r]);
         }
     }
-    int kr = zb + R + 3;                   // plane of the next ring fetch (clamped at use)
+    int kr = zb + L;                       // plane of the next ring fetch (clamped at use)
     int kf = wrapi(zb + R + 3, g.nz);      // plane of the next queue-front fetch
     int sc = 0;                            // slot of the output plane
 
+    // `active` is false for the padding plane of an odd-length chunk: it
+    // still loads (in bounds) but stores nothing.
     auto plane = [&](int k, T (&ring)[TS::RING_PER_T], T (&qn)[RY], bool active) {
         const int kk = active ? k : zb;
         const int64_t pk = (int64_t)kk * nxy;
         T *buf = lds + sc * SL;
-        const int sr = sc + R + 1 >= kDeepSlots ? sc + R + 1 - kDeepSlots : sc + R + 1;
+        const int sr = sc + L - 2 >= L ? sc - 2 : sc + L - 2;
         T *rbuf = lds + sr * SL;
 #pragma unroll
         for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[R][r];
@@ -345,41 +279,28 @@ __device__ inline void stencil_tile_deep(const TileGeom &g, const Coef<typename 
         for (int r = 0; r < RY; ++r) q[2 * R][r] = nxt[r];
         ++kr;
         kf = (kf + 1 == g.nz) ? 0 : kf + 1;
-        sc = (sc + 1 == kDeepSlots) ? 0 : sc + 1;
+        sc = (sc + 1 == L) ? 0 : sc + 1;
     };
 
     for (int k = zb; k < ze; k += 2) {
         plane(k, ringA, qn1, true);
         plane(k + 1, ringB, qn2, k + 1 < ze);
     }
+    // the LDS buffers are reused by the next tile of a persistent caller
     __syncthreads();
 }
-
-// LDS plan of a tile shape and element type: the slot form where nine plane
-// buffers fit in 150 KiB, otherwise the two-buffer form.
-template <typename T, int TX, int TYT, int RY>
-struct StencilLds {
-    using TS = TileShape<TX, TYT, RY>;
-    static constexpr int kPlane = TS::W * TS::H + 1;
-    static constexpr bool kDeep = (size_t)kDeepSlots * kPlane * sizeof(T) <= 150 * 1024;
-    static constexpr int kElems = (kDeep ? kDeepSlots : 2) * kPlane;
-};
 
 // Plain kernel wrapper: one tile per workgroup, XCD-aware tile order, then the
 // epilogue's block-level finish (reductions).
 template <typename T, int TX, int TYT, int RY, class Load, class Epi>
 __global__ void __launch_bounds__(TX * TYT)
 stencil_kernel(TileGeom g, Coef<typename VT<T>::S> w, Load ld, Epi ep) {
-    using SL = StencilLds<T, TX, TYT, RY>;
-    __shared__ T lds[SL::kElems];
+    __shared__ T lds[StencilLds<T, TX, TYT, RY>::kElems];
     __shared__ double red_scratch[64];
     if (ep.skip()) return;
     ld.prepare();
     const int lb = xcd_remap(blockIdx.x, g.nblocks);
-    if constexpr (SL::kDeep)
-        stencil_tile_deep<T, TX, TYT, RY>(g, w, ld, ep, lb, lds);
-    else
-        stencil_tile<T, TX, TYT, RY>(g, w, ld, ep, lb, lds);
+    stencil_tile<T, TX, TYT, RY>(g, w, ld, ep, lb, lds);
     ep.finish(blockIdx.x, g.nblocks, red_scratch);
 }
 

@@ -45,11 +45,10 @@ template <typename T, class Load, class Epi>
 inline int launch_stencil(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const Load &ld,
                           const Epi &ep, hipStream_t s) {
     const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
-    switch (cfg.shape) {
-        case SHAPE_64x4x4: return launch_stencil_shape<T, 64, 4, 4>(g, cfg.zlen, c, ld, ep, s);
-        case SHAPE_32x8x2: return launch_stencil_shape<T, 32, 8, 2>(g, cfg.zlen, c, ld, ep, s);
-        default: return launch_stencil_shape<T, 64, 4, 2>(g, cfg.zlen, c, ld, ep, s);
-    }
+    return dispatch_shape(cfg.shape, [&](auto sh) {
+        using S = decltype(sh);
+        return launch_stencil_shape<T, S::TX, S::TYT, S::RY>(g, cfg.zlen, c, ld, ep, s);
+    });
 }
 
 }  // namespace ofdft

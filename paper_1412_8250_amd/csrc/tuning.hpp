@@ -7,7 +7,32 @@
 
 namespace ofdft {
 
-enum StencilShape { SHAPE_64x4x4 = 0, SHAPE_64x4x2 = 1, SHAPE_32x8x2 = 2, SHAPE_COUNT = 3 };
+// Tile shapes: TX x TYT threads, RY rows per thread, tile TX x (TYT * RY).
+enum StencilShape {
+    SHAPE_64x4x4 = 0,    // 64 x 16 tile, 256 threads
+    SHAPE_64x4x2 = 1,    // 64 x 8 tile, 256 threads
+    SHAPE_32x8x2 = 2,    // 32 x 16 tile, 256 threads
+    SHAPE_64x8x2 = 3,    // 64 x 16 tile, 512 threads
+    SHAPE_64x8x1 = 4,    // 64 x 8 tile, 512 threads
+    SHAPE_COUNT = 5
+};
+
+template <int TX_, int TYT_, int RY_>
+struct ShapeTag {
+    static constexpr int TX = TX_, TYT = TYT_, RY = RY_;
+};
+
+// Calls f(ShapeTag<...>{}) for the shape id (unknown ids: 64x4x2).
+template <class F>
+inline int dispatch_shape(int shape, F &&f) {
+    switch (shape) {
+        case SHAPE_64x4x4: return f(ShapeTag<64, 4, 4>{});
+        case SHAPE_32x8x2: return f(ShapeTag<32, 8, 2>{});
+        case SHAPE_64x8x2: return f(ShapeTag<64, 8, 2>{});
+        case SHAPE_64x8x1: return f(ShapeTag<64, 8, 1>{});
+        default: return f(ShapeTag<64, 4, 2>{});
+    }
+}
 
 struct StencilCfg {
     int shape;
@@ -21,6 +46,7 @@ inline void shape_extent(int shape, int &tx, int &ty) {
     switch (shape) {
         case SHAPE_64x4x4: tx = 64; ty = 16; break;
         case SHAPE_32x8x2: tx = 32; ty = 16; break;
+        case SHAPE_64x8x2: tx = 64; ty = 16; break;
         default: tx = 64; ty = 8; break;
     }
 }

@@ -36,8 +36,10 @@ def _random_cells(count, seed):
     return cells
 
 
+# config: None = default (stepped schedule); (shape, 0) = stepped with that
+# tile shape; (shape, P) with P > 0 = persistent groups of P workgroups.
 @pytest.mark.parametrize("dtype", [ofd.C128, ofd.C64])
-@pytest.mark.parametrize("config", [None, (2, 1), (2, 4), (1, 2), (0, 3)])
+@pytest.mark.parametrize("config", [None, (2, 0), (1, 0), (0, 0), (2, 1), (2, 4), (1, 2), (0, 3)])
 def test_uneven_batch_matches_exact(dtype, config):
     announce("helmholtz batch", dtype, config)
     cells = _random_cells(11, 5)
@@ -67,16 +69,40 @@ def test_paper_shifts_and_conjugate_pairs():
     assert np.linalg.norm(xs[3] - np.conj(xs[2])) / np.linalg.norm(xs[2]) < 1e-8
 
 
-def test_batch_equals_single_and_is_repeatable():
-    announce("helmholtz batch==single")
+@pytest.mark.parametrize("config", [None, (2, 1)])
+def test_batch_equals_single_and_is_repeatable(config):
+    """A system's result does not depend on the rest of the batch or on timing."""
+    announce("helmholtz batch==single", config)
     cells = _random_cells(5, 9)
-    xs, _ = _batch(cells, ofd.C128, 1e-9, (2, 1))
-    xs2, _ = _batch(cells, ofd.C128, 1e-9, (2, 1))
+    xs, _ = _batch(cells, ofd.C128, 1e-9, config)
+    xs2, _ = _batch(cells, ofd.C128, 1e-9, config)
     for a, b in zip(xs, xs2):
         assert np.array_equal(a, b)
     for j in (0, 3):
-        xj, _ = _batch([cells[j]], ofd.C128, 1e-9, (2, 1))
+        xj, _ = _batch([cells[j]], ofd.C128, 1e-9, config)
         assert np.array_equal(xj[0], xs[j])
+
+
+def test_stepped_and_persistent_agree():
+    announce("helmholtz stepped vs persistent")
+    cells = _random_cells(4, 21)
+    xa, sa = _batch(cells, ofd.C128, 1e-10)
+    xb, sb = _batch(cells, ofd.C128, 1e-10, (2, 2))
+    for a, b, s1, s2 in zip(xa, xb, sa, sb):
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-8
+        assert abs(s1["iters"] - s2["iters"]) <= 2
+
+
+def test_max_iter_cap_reports_not_converged():
+    announce("helmholtz max_iter")
+    cells = _random_cells(3, 17)
+    torch = torch_cuda()
+    b = ofd.HelmholtzBatch([c[0] for c in cells], [c[1] for c in cells], 6, ofd.C128)
+    rhs = [to_dev(c[3].astype(np.complex128)) for c in cells]
+    xs = [to_dev(np.zeros(c[0], np.complex128)) for c in cells]
+    status, st = b.solve([c[2] for c in cells], rhs, xs, 1e-12, max_iter=3, allow_not_converged=True)
+    assert all(s["iters"] == 3 for s in st)
+    assert all(s["status"] == ofd.NOT_CONVERGED for s in st)
 
 
 def test_warm_start_converged_guess():
