@@ -6,7 +6,7 @@ the same state each time (v_0, u_0 and the solves' warm starts restored, empty
 Anderson history): 16x16x16 FCC Al-like
 cells (16384 atoms, 120 bohr box, 320^3 grid), TFW + K_00 linear-response
 kernel (lambda = 1, mu = 1): the density update U(v) (Algorithm 1), one
-Poisson solve, the 8 complex shifted kernel solves in one persistent launch,
+Poisson solve, the 8 complex shifted kernel solves batched in each launch,
 the kernel-potential assembly and Anderson mixing (history 7, zeta 0.3).
 All solves run to relative residual 1e-8.
 
@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy"], default=None,
+                    help="only launch the named kernel(s) a few times at the workload's grid "
+                         "(for rocprofv3 counter runs) and exit")
     return ap.parse_args()
 
 
@@ -61,6 +64,74 @@ def cpu_baseline(w, iters=40):
                       f"({dt:.1f} s), bytes counted as 80 B/point/iteration like the GPU path"}
 
 
+def source_sha():
+    """Digest of the kernel sources, to tell whether stored counter data still applies."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    dig = hashlib.sha256()
+    csrc = os.path.join(here, "paper_1412_8250_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(f, "rb") as fh:
+            dig.update(fh.read())
+    return dig.hexdigest()[:16]
+
+
+def stored_traffic(cls):
+    """HBM traffic per launch of kernel class `cls` from the rocprofv3 counter
+    summaries under profiles/ (FETCH_SIZE and WRITE_SIZE runs scaled by a copy
+    kernel's reading); None if there is none for the current kernel sources."""
+    import glob
+    here = os.path.dirname(os.path.abspath(__file__))
+    sha = source_sha()
+    for f in sorted(glob.glob(os.path.join(here, "profiles", "*.txt"))):
+        kv = {}
+        with open(f) as fh:
+            for line in fh:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
+        if kv.get("class") == cls and kv.get("source_sha") == sha and "traffic_bytes_per_launch" in kv:
+            return {"bytes_per_launch": float(kv["traffic_bytes_per_launch"]),
+                    "algorithmic_bytes_per_launch": float(kv["algorithmic_bytes_per_launch"]),
+                    "source": os.path.relpath(f, here)}
+    return None
+
+
+def profile_kernel(which, shape, h, reps=5):
+    """A few launches of one kernel family at the benchmark grid, nothing else."""
+    import torch
+    import paper_1412_8250_amd as ofd
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(0)
+    if which == "copy":        # calibration: a plain copy of known size
+        a = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+        c = torch.empty_like(a)
+        for _ in range(reps):
+            c.copy_(a)
+    elif which == "stencil":
+        x = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+        y = torch.empty_like(x)
+        for _ in range(reps):
+            ofd.fd_laplacian_apply(x, y, h, 6)
+    elif which == "cg":
+        g = torch.randn(shape, dtype=torch.float64, device=dev, generator=gen)
+        s = ofd.PoissonSolver(shape, h, 6, ofd.PLAIN_F64)
+        s.set_graphs(False)
+        x = torch.zeros_like(g)
+        s.solve(g, x, 1e-30, max_iter=reps, allow_not_converged=True)
+    else:                      # 8 complex shifted systems at the grid, `reps` COCG iterations
+        kappas = [complex(-1.68, -1.66), complex(-1.68, 1.66), complex(0.236, -0.926),
+                  complex(0.236, 0.926)] * 2
+        rhs = [torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen) for _ in kappas]
+        xs = [torch.zeros_like(f) for f in rhs]
+        bt = ofd.HelmholtzBatch([shape] * 8, [h] * 8, 6, ofd.C128)
+        bt.solve(kappas, rhs, xs, 1e-30, max_iter=reps, allow_not_converged=True)
+        bt.close()
+    torch.cuda.synchronize()
+    print(f"profiled {which} x{reps}", flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -75,6 +146,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.profile_kernel:
+        n = 320 if args.workload == "large" else 16
+        profile_kernel(args.profile_kernel, (n, n, n), ((120.0 if n == 320 else 7.5) / n,) * 3)
+        return
     t0 = time.perf_counter()
     w = inputs.large_cell() if args.workload == "large" else inputs.small_cell()
     log(f"inputs {w.rho.shape} in {time.perf_counter() - t0:.1f}s")
@@ -119,8 +194,13 @@ def main():
     value = total_bytes / elapsed / 1e9
     dom = prof[dominant]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else None
+    tr = stored_traffic(dominant)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+                # HBM bytes per full launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (copy-calibrated)
+                "traffic": tr["bytes_per_launch"] if tr else None,
+                "traffic_algorithmic_per_launch": tr["algorithmic_bytes_per_launch"] if tr else None,
+                "traffic_source": tr["source"] if tr else None,
                 "kernel": dominant, "launches": dom["launches"],
                 "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                 "avg_launch_ms": dom["ms"] / max(dom["timed"], 1)}
