@@ -254,12 +254,21 @@ int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
  * ofdft_nn_reserve: allocate the workspace for one grid (done implicitly by
  *   forward/train calls; solves require it beforehand).
  * ofdft_nn_forward: out = scale * rms(in) * N(in / rms(in)) (device FP64).
- * ofdft_nn_gradients / ofdft_nn_train_step: loss
- *   ||N(g/rms g) - phi/(h^2 rms g)||^2 / ||phi/(h^2 rms g)||^2 for one pair
- *   (device FP64 g, phi); train_step also applies Adam (beta 0.9/0.999,
- *   eps 1e-8) with learning rate lr.  loss (host) may be NULL.
+ * ofdft_nn_gradients / ofdft_nn_train_step: for one pair (device FP64 g,
+ *   phi) with t = phi / (h^2 rms g) and e = N(g / rms g) - t, the loss is
+ *   kind 0: ||e||^2 / ||t||^2, kind 1 (energy norm): e^T A e / t^T A t,
+ *   kind 2 (residual norm): ||A e||^2 / ||A t||^2, with A = -h^2 L_h (12th
+ *   order); train_step also applies Adam (beta 0.9/0.999, eps 1e-8) with
+ *   learning rate lr.  loss (host) may be NULL.
+ * ofdft_nn_set_loss: choose the loss kind (0 default, 1, 2); INVALID_ARG else.
  * ofdft_poisson_set_network: attach a network to an OFDFT_LEARNED solver
  *   (the solver keeps the pointer; the network must outlive its use).
+ * ofdft_poisson_set_learned_mode: what the learned form does after the
+ *   network's correction of the starting guess (x += a N(r) with the step a
+ *   minimising the energy-norm error): precondition 0 (default) = plain FP64
+ *   CG to the tolerance; 1 = flexible CG preconditioned by the network,
+ *   falling back to plain CG from the best iterate when it stalls (less than
+ *   10x residual reduction in 20 iterations) or breaks down.
  * ------------------------------------------------------------------------ */
 typedef struct ofdft_nn ofdft_nn;
 int ofdft_nn_create(uint64_t seed, ofdft_nn **out);
@@ -267,6 +276,7 @@ int ofdft_nn_destroy(ofdft_nn *net);
 size_t ofdft_nn_param_count(void);
 int ofdft_nn_set_weights(ofdft_nn *net, const float *w, size_t count);
 int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int gradients);
+int ofdft_nn_set_loss(ofdft_nn *net, int kind);
 int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid);
 int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const double *in, double *out,
                      double scale, void *stream);
@@ -274,6 +284,7 @@ int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const double *g, c
                        double *loss, void *stream);
 int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g, const double *phi,
                         double lr, double *loss, void *stream);
+int ofdft_poisson_set_learned_mode(ofdft_poisson *s, int precondition);
 int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
 
 /* ------------------------------------------------------------------------

@@ -141,3 +141,34 @@ def loss(out, target):
     den = float((target * target).sum())
     diff = out - target
     return float((diff * diff).sum()) / den, 2.0 * diff / den
+
+
+def loss_energy(out, target, h):
+    """Relative energy-norm error e^T A e / t^T A t, e = out - target, with
+    A = -h2 L_h the order-12 FD operator of Section 4 (h2 = (hx hy hz)^(2/3)),
+    and its gradient 2 A e / t^T A t (A is symmetric)."""
+    from . import fd
+    h2 = float(np.cbrt(h[0] * h[1] * h[2])) ** 2
+
+    def A(v):
+        return -h2 * fd.laplacian(v, h)
+
+    den = float((target * A(target)).sum())
+    e = out - target
+    Ae = A(e)
+    return float((e * Ae).sum()) / den, 2.0 * Ae / den
+
+
+def loss_residual(out, target, h):
+    """Relative residual-norm error ||A e||^2 / ||A target||^2 (A as in
+    loss_energy) and its gradient 2 A A e / ||A target||^2."""
+    from . import fd
+    h2 = float(np.cbrt(h[0] * h[1] * h[2])) ** 2
+
+    def A(v):
+        return -h2 * fd.laplacian(v, h)
+
+    At = A(target)
+    den = float((At * At).sum())
+    Ae = A(out - target)
+    return float((Ae * Ae).sum()) / den, 2.0 * A(Ae) / den

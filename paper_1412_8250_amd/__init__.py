@@ -226,6 +226,11 @@ class PoissonSolver:
         self._net = net
         _check(lib().ofdft_poisson_set_network(self._h, net._h if net is not None else None))
 
+    def set_learned_mode(self, precondition: bool):
+        """Learned form after the network's starting correction: plain CG
+        (False, default) or network-preconditioned flexible CG (True)."""
+        _check(lib().ofdft_poisson_set_learned_mode(self._h, 1 if precondition else 0))
+
     def solve(self, rhs, x, rel_tol: float = 1e-10, max_iter: int = 100000, stream=None,
               allow_not_converged: bool = False) -> dict:
         st = SolveStats()
@@ -448,6 +453,13 @@ class Network:
         _check(lib().ofdft_nn_forward(self._h, ctypes.byref(g), _dev(x), _dev(out, x.shape),
                                       float(scale), _stream(stream)))
         return out
+
+    L2, ENERGY, RESIDUAL = 0, 1, 2
+
+    def set_loss(self, kind: int):
+        """Training loss: Network.L2 (solution error), Network.ENERGY (A-norm
+        error) or Network.RESIDUAL (norm of the residual the output leaves)."""
+        _check(lib().ofdft_nn_set_loss(self._h, int(kind)))
 
     def gradients(self, g_rhs, phi, h_xyz, stream=None) -> float:
         g = grid_of(g_rhs.shape, h_xyz)

@@ -39,6 +39,11 @@ struct ofdft_nn {
     size_t part_cap = 0;
     double *totals = nullptr;
     ofdft::RedBuf rb{};
+    // training loss: 0 = relative L2 error of the solution, 1 = relative
+    // energy-norm error; FP64 scratch of the energy loss (n each)
+    int loss_kind = 0;
+    double *e64 = nullptr, *ae64 = nullptr;
+    size_t e_cap = 0;
     std::vector<void *> allocs;
 };
 

@@ -320,5 +320,57 @@ struct LossOp {
     }
 };
 
+// Operator-weighted losses with A = -h^2 L_h, e = out - t, t = phi / (h^2 rms g):
+// energy norm e^T A e / t^T A t (the norm CG minimises) and residual norm
+// |A e|^2 / |A t|^2 (the residual a correction leaves).  EnergyErrOp forms e;
+// the caller applies A, puts the unscaled denominator (phi^T A phi or
+// |A phi|^2) in totals[1]; EnergyLossOp sums the numerator and writes the
+// BF16 gradient.
+struct EnergyErrOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 20;
+    const float *out;
+    const double *phi;
+    double *e;
+    const double *totals;
+    double inv_n, h2, tscale;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {
+        const double rms = sqrt(totals[0] * inv_n);
+        tscale = rms > 0 ? 1.0 / (h2 * rms) : 0.0;
+    }
+    __device__ void operator()(int64_t i, double (&)[1]) const { e[i] = (double)out[i] - phi[i] * tscale; }
+};
+
+struct DotOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16;
+    const double *a, *b;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const { acc[0] = ::fma(a[i], b[i], acc[0]); }
+};
+
+// Sums a.b and writes dout = 2 grad / den (BF16): energy norm (a = e, b =
+// grad = A e) or residual norm (a = b = A e, grad = A A e).
+struct EnergyLossOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 26;
+    const double *a, *b, *grad;
+    u16 *dout;
+    const double *totals;
+    double inv_n, h2, den;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {
+        const double rms = sqrt(totals[0] * inv_n);
+        const double tscale = rms > 0 ? 1.0 / (h2 * rms) : 0.0;
+        den = totals[1] * tscale * tscale;
+    }
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        acc[0] = ::fma(a[i], b[i], acc[0]);
+        dout[i] = f2bf((float)(2.0 * grad[i] / den));
+    }
+};
+
 }  // namespace nn
 }  // namespace ofdft

@@ -298,6 +298,10 @@ static void net_free(ofdft_nn *net) {
     for (void *p : net->allocs) (void)hipFree(p);
     net->ws.clear();
     net->allocs.clear();
+    if (net->e64) (void)hipFree(net->e64);
+    if (net->ae64) (void)hipFree(net->ae64);
+    net->e64 = net->ae64 = nullptr;
+    net->e_cap = 0;
     redbuf_free(net->rb);
 }
 
@@ -388,6 +392,15 @@ extern "C" int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int g
     return OFDFT_OK;
 }
 
+extern "C" int ofdft_nn_set_loss(ofdft_nn *net, int kind) {
+    if (!net || kind < 0 || kind > 2) {
+        set_error("ofdft_nn_set_loss: kind must be 0 (L2), 1 (energy norm) or 2 (residual norm)");
+        return OFDFT_INVALID_ARG;
+    }
+    net->loss_kind = kind;
+    return OFDFT_OK;
+}
+
 extern "C" int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid) {
     if (!net) return OFDFT_INVALID_ARG;
     OFDFT_TRY(check_grid(grid, 1));
@@ -404,8 +417,49 @@ extern "C" int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const dou
     return net_apply(net, *grid, in, out, scale, false, (hipStream_t)stream);
 }
 
-// One training step on a pair (g, phi): loss = ||N(g/rms g) - phi/(h^2 rms g)||^2 / ||.||^2,
-// backward pass, Adam update (lr; beta1 0.9, beta2 0.999, eps 1e-8).
+// Loss of the current output against phi, and dL/d(out) into buf[dOUT].
+// totals[0] = sum g^2 must be set; leaves totals[1] = the loss denominator
+// before scaling and totals[2] = its numerator.
+static int loss_pass(ofdft_nn *net, const ofdft_grid &g, const double *phi, double h2, hipStream_t s) {
+    const int64_t n = npoints(g);
+    if (net->loss_kind == 0) {
+        OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
+        OFDFT_TRY(forward(net, s));
+        return launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
+                                StoreTotals<1>{net->totals + 2}, net->rb, s);
+    }
+    if (net->e_cap < (size_t)n) {
+        if (net->e64) OFDFT_CHECK_HIP(hipFree(net->e64));
+        if (net->ae64) OFDFT_CHECK_HIP(hipFree(net->ae64));
+        net->e64 = net->ae64 = nullptr;
+        net->e_cap = 0;
+        OFDFT_CHECK_HIP(hipMalloc(&net->e64, sizeof(double) * n));
+        OFDFT_CHECK_HIP(hipMalloc(&net->ae64, sizeof(double) * n));
+        net->e_cap = (size_t)n;
+    }
+    // denominator up to the tscale^2 factor: kind 1 phi^T A phi, kind 2 |A phi|^2
+    const bool res = net->loss_kind == 2;
+    OFDFT_TRY(fd_laplacian_apply(&g, 6, OFDFT_F64, phi, net->ae64, -h2, 0.0, s));
+    if (res) OFDFT_TRY((launch_reduce<1>(n, SqOp{net->ae64}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
+    else OFDFT_TRY((launch_reduce<1>(n, DotOp{phi, net->ae64}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
+    OFDFT_TRY(forward(net, s));
+    OFDFT_TRY((launch_reduce<1>(n, EnergyErrOp{net->out, phi, net->e64, net->totals, 1.0 / n, h2, 0},
+                                NoFin{}, net->rb, s)));
+    OFDFT_TRY(fd_laplacian_apply(&g, 6, OFDFT_F64, net->e64, net->ae64, -h2, 0.0, s));
+    if (res) {     // e <- A (A e): numerator |A e|^2, gradient 2 A A e / den
+        OFDFT_TRY(fd_laplacian_apply(&g, 6, OFDFT_F64, net->ae64, net->e64, -h2, 0.0, s));
+        return launch_reduce<1>(n, EnergyLossOp{net->ae64, net->ae64, net->e64, net->buf[dOUT], net->totals,
+                                                1.0 / n, h2, 0},
+                                StoreTotals<1>{net->totals + 2}, net->rb, s);
+    }
+    return launch_reduce<1>(n, EnergyLossOp{net->e64, net->ae64, net->ae64, net->buf[dOUT], net->totals,
+                                            1.0 / n, h2, 0},
+                            StoreTotals<1>{net->totals + 2}, net->rb, s);
+}
+
+// One training step on a pair (g, phi): loss (kind set by ofdft_nn_set_loss)
+// of N(g / rms g) against t = phi / (h^2 rms g), backward pass, Adam update
+// (lr; beta1 0.9, beta2 0.999, eps 1e-8).
 // loss (host, optional) receives the loss before the update.
 extern "C" int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g_rhs,
                                    const double *phi, double lr, double *loss, void *stream) {
@@ -417,11 +471,8 @@ extern "C" int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const 
     const int64_t n = npoints(g);
     const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
     OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
-    OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
     OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
-    OFDFT_TRY(forward(net, s));
-    OFDFT_TRY((launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
-                                StoreTotals<1>{net->totals + 2}, net->rb, s)));
+    OFDFT_TRY(loss_pass(net, g, phi, h2, s));
     OFDFT_TRY(backward(net, s));
     net->adam_t += 1;
     const float b1 = 0.9f, b2 = 0.999f;
@@ -456,11 +507,8 @@ extern "C" int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const d
     const int64_t n = npoints(g);
     const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
     OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
-    OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
     OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
-    OFDFT_TRY(forward(net, s));
-    OFDFT_TRY((launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
-                                StoreTotals<1>{net->totals + 2}, net->rb, s)));
+    OFDFT_TRY(loss_pass(net, g, phi, h2, s));
     OFDFT_TRY(backward(net, s));
     double t[4];
     OFDFT_CHECK_HIP(hipMemcpyAsync(t, net->totals, sizeof(double) * 4, hipMemcpyDeviceToHost, s));

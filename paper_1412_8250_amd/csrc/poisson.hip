@@ -300,8 +300,8 @@ int finalize_solution(ofdft_poisson *s, double *x, hipStream_t st) {
     return OFDFT_OK;
 }
 
-static int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
-                       ofdft_solve_stats &stats, hipStream_t st) {
+int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                ofdft_solve_stats &stats, hipStream_t st) {
     const int64_t n = npoints(s->g);
     OFDFT_TRY(residual_pass<double>(s->g, s->coef, x, s->gp, s->r, s->totals + 4, s->rb, st));
     // arm: rr = ||r||^2, tol2 = rel_tol^2 ||P g||^2

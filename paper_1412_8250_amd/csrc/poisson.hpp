@@ -27,9 +27,14 @@ struct ofdft_poisson {
     // learned form
     ofdft_nn *net = nullptr;
     double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
+    int learned_fcg = 0;     // 0: network correction + plain CG; 1: + network-preconditioned FCG
 };
 
 namespace ofdft {
+
+// Plain FP64 CG from the iterate x (residual recomputed first); stats.iters set.
+int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                ofdft_solve_stats &stats, hipStream_t st);
 
 template <typename T>
 int cg_k1(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *r, const T *p_old,

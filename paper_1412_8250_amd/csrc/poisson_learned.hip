@@ -143,11 +143,28 @@ int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_i
     double r2;
     OFDFT_TRY(residual(r2));
     if (!std::isfinite(r2)) return OFDFT_NONFINITE;
-    if (r2 > tol2 && r2 > 0.25 * g2) {            // poor guess: add the network's correction
+    // Network correction of the starting guess: z = N(r), then the step a
+    // along z that minimises the energy-norm error, a = z.r / z.Az (a
+    // correction can only lower that error; a useless one gets a ~ 0).
+    if (r2 > tol2) {
         OFDFT_TRY(nn::net_apply(s->net, g, r, z, h2, true, st));
         ++applies;
-        OFDFT_TRY((launch_reduce<1>(n, AxpyOp{x, z, 1.0}, NoFin{}, s->rb, st)));
+        OFDFT_TRY(pass64(g, s->coef, LoadPlain<double>{z}, EpiAp{Ap, tot, s->rb.partials, s->rb.counter, 0.0},
+                         st, 16.0, K_CG_STENCIL));
+        OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r}, StoreTotals<2>{tot + 1}, s->rb, st)));
+        OFDFT_TRY(sync_tot(3));
+        const double zAz = th[0], zr = th[2];
+        if (std::isfinite(zAz) && std::isfinite(zr) && zAz > 0.0)
+            OFDFT_TRY((launch_reduce<1>(n, AxpyOp{x, z, zr / zAz}, NoFin{}, s->rb, st)));
         OFDFT_TRY(residual(r2));
+    }
+    stats.nn_applies = applies;
+    if (!s->learned_fcg) {
+        ofdft_solve_stats rest{};
+        const int status = solve_plain(s, x, rel_tol, max_iter, rest, st);
+        stats.iters = rest.iters;
+        stats.fell_back = 0;
+        return status;
     }
     double best = r2;
     OFDFT_TRY((launch_reduce<1>(n, CopyOp2{xb, x}, NoFin{}, s->rb, st)));
@@ -201,24 +218,9 @@ int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_i
     int status = OFDFT_OK;
     if (fall_back) {
         OFDFT_TRY((launch_reduce<1>(n, CopyOp2{x, xb}, NoFin{}, s->rb, st)));
-        OFDFT_TRY(residual_pass<double>(g, s->coef, x, s->gp, s->r, s->totals + 4, s->rb, st));
-        OFDFT_CHECK_HIP(hipMemcpyAsync(s->totals_host + 4, s->totals + 4, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
-        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
-        const double rr = s->totals_host[5];
-        CgState &init = *s->st_host;
-        init = CgState{};
-        init.rr = rr;
-        init.tol2 = tol2;
-        init.maxit = std::max(1, max_iter - iters);
-        init.first = 1;
-        init.done = std::isfinite(rr) ? (rr <= tol2 ? CG_CONVERGED : CG_RUNNING) : CG_NONFINITE;
-        OFDFT_CHECK_HIP(hipMemcpyAsync(s->st, s->st_host, sizeof(CgState), hipMemcpyHostToDevice, st));
-        int it2 = 0, done = init.done;
-        if (done == CG_RUNNING)
-            OFDFT_TRY(cg_iterate<double>(g, s->coef, x, s->r, s->pA, s->pB, s->Ap, s->st, s->st_host,
-                                         s->rb, st, it2, done));
-        iters += it2;
-        status = status_from_done(done);
+        ofdft_solve_stats rest{};
+        status = solve_plain(s, x, rel_tol, std::max(1, max_iter - iters), rest, st);
+        iters += rest.iters;
     } else if (r2 > tol2) {
         status = OFDFT_NOT_CONVERGED;
     }
@@ -229,6 +231,15 @@ int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_i
 }  // namespace ofdft
 
 using namespace ofdft;
+
+extern "C" int ofdft_poisson_set_learned_mode(ofdft_poisson *s, int precondition) {
+    if (!s || s->mode != OFDFT_LEARNED || precondition < 0 || precondition > 1) {
+        set_error("ofdft_poisson_set_learned_mode: learned solver and 0/1 expected");
+        return OFDFT_INVALID_ARG;
+    }
+    s->learned_fcg = precondition;
+    return OFDFT_OK;
+}
 
 extern "C" int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net) {
     if (!s || s->mode != OFDFT_LEARNED) {

@@ -24,9 +24,16 @@ def _torch():
     return torch
 
 
-def solve_pairs(workloads, tol: float = 1e-10):
-    """[(g, phi, h)] device tensors, phi from the plain FP64 solver to `tol`."""
+def solve_pairs(workloads, tol: float = 1e-10, snapshots=(0,)):
+    """[(rhs, solution, h)] device tensors from the plain FP64 solver.
+
+    For each cell, g = 4 pi (rho + b) (zero mean) is solved to `tol` (phi).
+    Every k > 0 in `snapshots` adds the pair (r_k, phi - x_k), where x_k is
+    the iterate after k plain CG iterations from zero and r_k = g + L x_k its
+    residual: the residuals a preconditioner meets inside a solve, with their
+    exact corrections (A^-1 r_k = phi - x_k).  k = 0 adds (g, phi)."""
     torch = _torch()
+    from . import fd_laplacian_apply
     out = []
     solvers = {}
     for w in workloads:
@@ -37,7 +44,15 @@ def solve_pairs(workloads, tol: float = 1e-10):
             solvers[key] = PoissonSolver(g.shape, w.cell.h, 6, PLAIN_F64)
         phi = torch.zeros_like(g)
         solvers[key].solve(g, phi, tol)
-        out.append((g, phi, w.cell.h))
+        for k in snapshots:
+            if k == 0:
+                out.append((g, phi, w.cell.h))
+                continue
+            x = torch.zeros_like(g)
+            solvers[key].solve(g, x, 1e-30, max_iter=k, allow_not_converged=True)
+            r = g.clone()
+            fd_laplacian_apply(x, r, w.cell.h, 6, alpha=1.0, beta=1.0)
+            out.append((r, phi - x, w.cell.h))
     return out
 
 
@@ -83,44 +98,93 @@ def train(net: Network, pairs, steps: int, lr: float = 1e-3, lr_final: float = 1
     return losses
 
 
-def evaluate(net: Network, w, tol: float = 1e-8) -> dict:
-    """Plain FP64 CG vs the learned form on one cell, from a zero guess."""
+def correction_quality(net: Network, g, h) -> dict:
+    """How the network's correction of a zero guess acts on the system with
+    right-hand side g (zero mean): the step a = z.g / z.Az along z = N(g)
+    (the solver's choice), and the energy-norm error and residual left,
+    relative to the zero guess.  The exact solution comes from plain CG."""
+    torch = _torch()
+    from . import fd_laplacian_apply
+    phi = torch.zeros_like(g)
+    PoissonSolver(g.shape, h, 6, PLAIN_F64).solve(g, phi, 1e-11, allow_not_converged=True)
+    h2 = float(np.cbrt(h[0] * h[1] * h[2])) ** 2
+    z = torch.empty_like(g)
+    net.forward(g, z, h, scale=h2)
+    z -= z.mean()
+
+    def A(v):                       # -L_h v
+        out = torch.zeros_like(v)
+        fd_laplacian_apply(v, out, h, 6, alpha=-1.0)
+        return out
+
+    Az = A(z)
+    a = float((z * g).sum() / (z * Az).sum())
+    e1 = phi - a * z
+    return {"step": a,
+            "energy_error_ratio": float(torch.sqrt((e1 * A(e1)).sum() / (phi * g).sum())),
+            "residual_ratio": float((g - a * Az).norm() / g.norm())}
+
+
+def evaluate(net: Network, w, tol: float = 1e-8, repeats: int = 3) -> dict:
+    """Plain FP64 CG vs the learned forms on one cell, from a zero guess: best
+    of `repeats` timed solves each (after one warm-up), iterations, network
+    applications, fallback, the correction's quality, the solutions'
+    difference and the time of one network application."""
     torch = _torch()
     g = torch.from_numpy(4.0 * math.pi * (w.rho + w.b)).cuda()
+    g -= g.mean()
     res = {}
-    plain = PoissonSolver(g.shape, w.cell.h, 6, PLAIN_F64)
-    x = torch.zeros_like(g)
-    plain.solve(g, x, tol)                         # warm-up of the code path
-    x.zero_()
-    st = plain.solve(g, x, tol)
-    res["plain"] = {k: st[k] for k in ("iters", "seconds", "rel_res")}
-    learned = PoissonSolver(g.shape, w.cell.h, 6, LEARNED)
-    learned.set_network(net)
-    y = torch.zeros_like(g)
-    learned.solve(g, y, tol)
-    y.zero_()
-    st = learned.solve(g, y, tol)
-    res["learned"] = {k: st[k] for k in ("iters", "seconds", "rel_res", "nn_applies", "fell_back")}
-    res["max_abs_diff"] = float((x - y).abs().max().item())
+    xs = {}
+    for name, mode, fcg in (("plain", PLAIN_F64, False), ("learned", LEARNED, False),
+                            ("learned_fcg", LEARNED, True)):
+        s = PoissonSolver(g.shape, w.cell.h, 6, mode)
+        if mode == LEARNED:
+            s.set_network(net)
+            s.set_learned_mode(fcg)
+        x = torch.zeros_like(g)
+        s.solve(g, x, tol, allow_not_converged=True)
+        best = None
+        for _ in range(repeats):
+            x.zero_()
+            st = s.solve(g, x, tol, allow_not_converged=True)
+            if best is None or st["seconds"] < best["seconds"]:
+                best = st
+        keys = ("iters", "seconds", "rel_res", "status") + (("nn_applies", "fell_back") if mode == LEARNED else ())
+        res[name] = {k: best[k] for k in keys}
+        xs[name] = x
+        s.close()
+    res["max_abs_diff"] = float((xs["plain"] - xs["learned"]).abs().max().item())
+    res["max_abs_diff_fcg"] = float((xs["plain"] - xs["learned_fcg"]).abs().max().item())
+    res["correction"] = correction_quality(net, g, w.cell.h)
+    z = torch.empty_like(g)
+    net.forward(g, z, w.cell.h, scale=1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        net.forward(g, z, w.cell.h, scale=1.0)
+    torch.cuda.synchronize()
+    res["nn_forward_s"] = (time.perf_counter() - t0) / 5
     return res
 
 
-def train_and_evaluate(n_cells: int = 96, augment_per_cell: int = 200, steps: int = 6000,
-                       heldout=(0,), log_every: int = 500) -> dict:
+def train_and_evaluate(n_cells: int = 96, steps: int = 6000, snapshots=(0, 10, 40, 120),
+                       loss_kind: int = Network.ENERGY, heldout=(0,), log_every: int = 500,
+                       lr: float = 1e-3, seed: int = 0) -> dict:
     """End-to-end: generate and solve training cells, train, evaluate held-out cells."""
     t0 = time.perf_counter()
     cells = [inputs.training_workload(i) for i in range(n_cells)]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    pairs = solve_pairs(cells)
+    pairs = solve_pairs(cells, snapshots=snapshots)
     t_solve = time.perf_counter() - t0
-    net = Network(0)
+    net = Network(seed)
+    net.set_loss(loss_kind)
     t0 = time.perf_counter()
-    losses = train(net, pairs, steps, log_every=log_every)
+    losses = train(net, pairs, steps, lr=lr, log_every=log_every, seed=seed)
     t_train = time.perf_counter() - t0
-    report = {"cells": n_cells, "pairs_available": n_cells * augment_per_cell, "steps": steps,
-              "t_generate_s": t_gen, "t_solve_s": t_solve, "t_train_s": t_train,
+    report = {"cells": n_cells, "pairs": len(pairs), "snapshots": list(snapshots), "steps": steps,
+              "loss_kind": loss_kind, "t_generate_s": t_gen, "t_solve_s": t_solve, "t_train_s": t_train,
               "loss_first": float(np.mean(losses[:50])), "loss_last": float(np.mean(losses[-50:]))}
     for which in heldout:
         report[f"heldout_{which}"] = evaluate(net, inputs.heldout_workload(which))
-    return report
+    return report, net

@@ -62,3 +62,34 @@ def test_positive_homogeneity_and_translation_equivariance():
     assert np.abs(nn.forward(W, 3.7 * g)[0] - 3.7 * out).max() < 1e-10 * np.abs(out).max()
     sh = np.roll(g, (8, 0, 8), (0, 1, 2))
     assert np.abs(nn.forward(W, sh)[0] - np.roll(out, (8, 0, 8), (0, 1, 2))).max() < 1e-10 * np.abs(out).max()
+
+
+@pytest.mark.parametrize("power", [1, 2])
+def test_operator_loss_spectral_form_and_gradient(power):
+    """The energy-norm (power 1) and residual-norm (power 2) losses equal
+    their Fourier forms sum lambda^p |e_k|^2 / sum lambda^p |t_k|^2 with the
+    exact symbol of -h2 L_h, are unchanged by a constant added to the output
+    (constants are the null space), vanish at the target, and their
+    gradients match central differences."""
+    fn = nn.loss_energy if power == 1 else nn.loss_residual
+    from oracle import fd
+    rng = np.random.default_rng(3)
+    shape, h = (8, 10, 12), (0.4, 0.45, 0.5)
+    out = rng.normal(size=shape)
+    t = rng.normal(size=shape)
+    L, dout = fn(out, t, h)
+    h2 = np.cbrt(h[0] * h[1] * h[2]) ** 2
+    lam = (-h2 * fd.symbol(shape, h, 6)) ** power
+    ek, tk = np.fft.fftn(out - t), np.fft.fftn(t)
+    spec = float((lam * abs(ek) ** 2).sum() / (lam * abs(tk) ** 2).sum())
+    assert abs(L - spec) <= 1e-12 * spec
+    assert abs(fn(out + 3.7, t, h)[0] - L) <= 1e-11 * L
+    assert fn(t, t, h)[0] == 0.0
+    eps = 1e-6
+    for _ in range(5):
+        idx = tuple(int(rng.integers(s)) for s in shape)
+        op, om = out.copy(), out.copy()
+        op[idx] += eps
+        om[idx] -= eps
+        num = (fn(op, t, h)[0] - fn(om, t, h)[0]) / (2 * eps)
+        assert abs(num - dout[idx]) <= 1e-6 * abs(dout[idx]) + 1e-10
