@@ -16,7 +16,9 @@ value  = algorithmic HBM bytes of every kernel launched in the timed steps
 roofline = the dominant kernel class in the timed steps, its algorithmic
          bytes / its summed launch durations (HIP events on its stream).
 Extras: stand-alone stencil GB/s at 320^3 (f64, f32, c128), and Poisson
-time-to-1e-8 for the plain FP64 and the FP32-in-FP64 refined forms.
+time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined and the
+learned forms (the network trained here first, on 16 small perturbed cells,
+about 20 s).
 cpu_baseline: the oracle (C, OpenMP) running textbook CG iterations of the
 same 320^3 Poisson problem, counted with the same per-iteration bytes.
 """
@@ -38,6 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip training/evaluating the learned aid")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy"], default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
@@ -222,13 +225,41 @@ def main():
             extras[f"stencil_{str(dt).split('.')[-1]}_GBps"] = 2 * x.numel() * eb / t / 1e9
             del x, y
         g = torch.from_numpy(4 * np.pi * (w.rho + w.b)).to(dev)
-        for name, mode in (("plain_f64", ofd.PLAIN_F64), ("refined_f32", ofd.REFINED_F32)):
+        net = None
+        if not args.no_learned:
+            # the learned aid, trained here on solver-generated pairs of small
+            # perturbed cells (the same recipe as the library's training module)
+            from paper_1412_8250_amd import learned
+            t0 = time.perf_counter()
+            cells = [inputs.training_workload(i) for i in range(16)]
+            pairs = learned.solve_pairs(cells, snapshots=(0, 10, 40, 120))
+            net = ofd.Network(0)
+            net.set_loss(ofd.Network.ENERGY)
+            losses = learned.train(net, pairs, 1000, lr=1e-3, lr_final=1e-4, seed=0)
+            extras["learned_training"] = {"cells": 16, "pairs": len(pairs), "steps": 1000,
+                                          "seconds": time.perf_counter() - t0,
+                                          "loss_first": float(np.mean(losses[:50])),
+                                          "loss_last": float(np.mean(losses[-50:]))}
+            gp = g - g.mean()
+            extras["learned_correction_320"] = learned.correction_quality(net, gp, h)
+        forms = [("plain_f64", ofd.PLAIN_F64, None), ("refined_f32", ofd.REFINED_F32, None)]
+        if net is not None:
+            forms += [("learned", ofd.LEARNED, False), ("learned_fcg", ofd.LEARNED, True)]
+        for name, mode, fcg in forms:
             s = ofd.PoissonSolver(shape, h, 6, mode)
+            if mode == ofd.LEARNED:
+                s.set_network(net)
+                s.set_learned_mode(fcg)
             x = torch.zeros_like(g)
-            st = s.solve(g, x, 1e-8)
+            s.solve(g, x, 1e-8, allow_not_converged=True)      # warm-up (graphs, workspaces)
+            x.zero_()
+            st = s.solve(g, x, 1e-8, allow_not_converged=True)
             extras[f"poisson_{name}_time_to_1e-8_s"] = st["seconds"]
             extras[f"poisson_{name}_iters"] = st["iters"]
             extras[f"poisson_{name}_rel_res"] = st["rel_res"]
+            if mode == ofd.LEARNED:
+                extras[f"poisson_{name}_nn_applies"] = st["nn_applies"]
+                extras[f"poisson_{name}_fell_back"] = st["fell_back"]
             s.close()
         log("extras", extras)
 

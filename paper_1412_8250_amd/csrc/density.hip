@@ -92,17 +92,25 @@ struct LoadDir {        // d = r + xi d_prev (xi = 0: steepest descent, with d_p
     __device__ double operator()(int64_t i) const { return ::fma(xi, d_prev[i], r[i]); }
 };
 
+// d = r + xi d_prev, L d; totals {<u,d>, <d,d>, <u,L d>, <d,L d>, <H u,d>}.
+// The last gives the line-search slope at s = 0 without an evaluation pass:
+// with u normalised, (V_loc + v) u = H u + (lambda/2) L u, and the lambda
+// terms of dE/ds cancel, leaving dE/ds(0) ~ <H u, d> - t <u, H u>.
 struct EpiLd {
     const double *__restrict__ u;
+    const double *__restrict__ Hu;
     double *__restrict__ d;
     double *__restrict__ Ld;
     double *totals;
     double *partials;
     unsigned int *counter;
-    double a0, a1, a2, a3;
-    double uv[4];
+    double a0, a1, a2, a3, a4;
+    double uv[4], hv[4];
     __device__ bool skip() const { return false; }
-    __device__ void pre(int q, int64_t i) { uv[q] = u[i]; }
+    __device__ void pre(int q, int64_t i) {
+        uv[q] = u[i];
+        hv[q] = Hu[i];
+    }
     __device__ void point(int q, int64_t i, double c, double s) {
         const double ui = uv[q];
         d[i] = c;
@@ -111,13 +119,14 @@ struct EpiLd {
         a1 = ::fma(c, c, a1);
         a2 = ::fma(ui, s, a2);
         a3 = ::fma(c, s, a3);
+        a4 = ::fma(hv[q], c, a4);
     }
     __device__ void finish(int block, int nblocks, double *scratch) {
-        double x[4] = {a0, a1, a2, a3};
-        block_sum<4>(x, scratch);
-        double t[4];
-        if (reduce_grid<4>(x, partials, nblocks, block, counter, scratch, t)) {
-            for (int k = 0; k < 4; ++k) totals[k] = t[k];
+        double x[5] = {a0, a1, a2, a3, a4};
+        block_sum<5>(x, scratch);
+        double t[5];
+        if (reduce_grid<5>(x, partials, nblocks, block, counter, scratch, t)) {
+            for (int k = 0; k < 5; ++k) totals[k] = t[k];
         }
     }
 };
@@ -257,14 +266,17 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         // Kd: d = r + xi d_prev, L d
         auto make_dir = [&](double xiv) -> int {
             OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{r_cur, d_prev, xiv},
-                                   EpiLd{u, d_cur, s->Ld, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0}, st, 40));
-            OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 16, tot, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+                                   EpiLd{u, s->Hu, d_cur, s->Ld, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0, 0},
+                                   st, 48));
+            OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 16, tot, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
             OFDFT_CHECK_HIP(hipStreamSynchronize(st));
             return OFDFT_OK;
         };
         OFDFT_TRY(make_dir(xi));
-        double ud = s->hsc[16], dd = s->hsc[17], uLd = s->hsc[18], dLd = s->hsc[19];
-        const double uLu = h[S_ULU];
+        double ud = s->hsc[16], dd = s->hsc[17], uLd = s->hsc[18], dLd = s->hsc[19], dHu = s->hsc[20];
+        const double uLu = h[S_ULU], uHu = h[S_UHU];
+        // slope at s = 0 from the direction pass (u is normalised, so c2 = N_e / (h^3 <u,u>))
+        auto slope0 = [&]() { return ne / (dv * uu) * (dHu - ud / uu * uHu); };
         if (!(dd > 0.0)) break;
         // dE/ds (up to the positive factor 2 h^3)
         auto slope = [&](double sv, double &out) -> int {
@@ -278,13 +290,12 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
             out = c2 * (s->hsc[S_EVAL] - 0.5 * lam * vw);
             return OFDFT_OK;
         };
-        double f0;
-        OFDFT_TRY(slope(0.0, f0));
+        double f0 = slope0();
         if (!(f0 < 0.0) && xi != 0.0) {          // not a descent direction: restart along r
             xi = 0.0;
             OFDFT_TRY(make_dir(0.0));
-            ud = s->hsc[16]; dd = s->hsc[17]; uLd = s->hsc[18]; dLd = s->hsc[19];
-            OFDFT_TRY(slope(0.0, f0));
+            ud = s->hsc[16]; dd = s->hsc[17]; uLd = s->hsc[18]; dLd = s->hsc[19]; dHu = s->hsc[20];
+            f0 = slope0();
         }
         if (!(f0 < 0.0)) break;                  // no descent possible at this precision
         double lo = 0.0, flo = f0;
