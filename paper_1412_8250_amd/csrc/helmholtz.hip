@@ -157,7 +157,9 @@ struct CocgShape {
 template <typename T, int TX, int TYT, int RY, class Load, class Epi>
 __device__ inline void stencil_units(const HSys &s, const Coef<typename VT<T>::S> &w, const Load &ld,
                                      Epi &ep, int rank, int P, T *lds) {
-    for (int u = rank; u < s.nunits; u += P) stencil_tile<T, TX, TYT, RY>(s.tg, w, ld, ep, u, lds);
+    // two ring buffers: this kernel also holds the COCG scalars in registers
+    for (int u = rank; u < s.nunits; u += P)
+        stencil_tile<T, TX, TYT, RY, Load, Epi, StencilLds<T, TX, TYT, RY>::kLead, 2>(s.tg, w, ld, ep, u, lds);
 }
 
 

@@ -143,7 +143,13 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int tota
         StepLoadP<T> ld{GPtr<T>(h.r), GPtr<T>(first ? h.r : p_old),
                         first ? CT::mk(0.0, 0.0) : CT::mk(sj->be_re, sj->be_im)};
         StepEpiPAp<T> ep{GPtr<T>(p_new), GPtr<T>(h.Ap), kappa, {0, 0}};
-        stencil_tile<T, TX, TYT, RY>(h.tg, coef_of<T>(h), ld, ep, unit, lds);
+        // The two-array loader doubles the registers of in-flight ring fetches:
+        // with 512 threads (at most 256 registers per lane) complex128 keeps
+        // two ring buffers, deeper staging would spill.
+        using SLd = StencilLds<T, TX, TYT, RY>;
+        constexpr int PR = (sizeof(T) == 16 && TX * TYT >= 512) ? 2 : SLd::kRingDepth;
+        stencil_tile<T, TX, TYT, RY, StepLoadP<T>, StepEpiPAp<T>, SLd::kLead, PR>(h.tg, coef_of<T>(h), ld,
+                                                                                 ep, unit, lds);
         double acc[2] = {ep.acc[0], ep.acc[1]};
         block_sum<2>(acc, scratch);
         double t[2];

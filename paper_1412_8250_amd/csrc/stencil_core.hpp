@@ -170,6 +170,12 @@ __device__ inline void stencil_plane_compute(const Coef<typename VT<T>::S> &w, c
 // i.e. when the tiles around this one fetch P's centre, so that the halo
 // reads hit in L2.  L is the largest value up to R + 3 whose buffers fit in
 // 150 KiB (at least 2: a plain double buffer).
+//
+// Ring fetches wait in kRingDepth register buffers before going to LDS, so
+// the ring of plane P is fetched L - 2 + kRingDepth planes ahead and the
+// queue front (two register buffers) R + 3 planes ahead: a depth of
+// R + 5 - L (2..4) keeps the two fetches of a plane close together when
+// fewer than R + 3 LDS slots fit.
 template <typename T, int TX, int TYT, int RY>
 struct StencilLds {
     using TS = TileShape<TX, TYT, RY>;
@@ -178,6 +184,8 @@ struct StencilLds {
     static_assert(kFit >= 2, "tile too large for a double-buffered LDS plane");
     static constexpr int kLead = kFit > kMaxRadius + 3 ? kMaxRadius + 3 : kFit;
     static constexpr int kElems = kLead * kPlane;
+    static constexpr int kDepthWanted = kMaxRadius + 5 - kLead;
+    static constexpr int kRingDepth = kDepthWanted <= 2 ? 2 : 4;
 };
 
 // One tile: march the z chunk, calling the epilogue for every owned point.
@@ -185,21 +193,23 @@ struct StencilLds {
 // is a dummy target for spare ring slots).
 //
 // Timeline of output plane k: write q[R] (plane k) into slot(k) and the ring
-// fetched two planes ago (plane k + L - 2) into slot(k + L - 2); issue the
-// epilogue's loads for plane k, then the fetches of ring k + L and of queue
-// front k + R + 3; barrier; compute plane k.  A slot is rewritten two planes
-// after its last reader, so one barrier per plane suffices.  In-flight
-// fetches land in fixed registers (the loop is unrolled by two), so waiting
-// for one plane's data never waits for younger loads.  Ring fetches past the
-// chunk end are clamped to its last plane (never used, an L2 hit).
+// fetched PR planes ago (plane k + L - 2) into slot(k + L - 2); issue the
+// epilogue's loads for plane k, then the fetches of ring k + L - 2 + PR and
+// of queue front k + R + 3; barrier; compute plane k.  A slot is rewritten
+// two planes after its last reader, so one barrier per plane suffices.
+// In-flight fetches land in fixed registers (the loop is unrolled by U), so
+// waiting for one plane's data never waits for younger loads.  Ring fetches
+// past the chunk end are clamped to its last plane (never used, an L2 hit).
 template <typename T, int TX, int TYT, int RY, class Load, class Epi,
-          int L = StencilLds<T, TX, TYT, RY>::kLead>
+          int L = StencilLds<T, TX, TYT, RY>::kLead, int PR = StencilLds<T, TX, TYT, RY>::kRingDepth>
 __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>::S> &w,
                                     const Load &ld, Epi &ep, int logical_block, T *lds) {
     using TS = TileShape<TX, TYT, RY>;
     constexpr int R = TS::R, W = TS::W, H = TS::H;
     constexpr int SL = W * H + 1;
+    constexpr int U = PR == 2 ? 2 : 4;     // planes per unrolled step (multiple of PR and of 2)
     static_assert(L >= 2 && L <= R + 3, "ring lead out of range");
+    static_assert(PR == 2 || PR == 4, "ring depth 2 or 4");
     const TileCtx<TX, TYT, RY> tc(g, logical_block);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int zb = tc.zb, ze = tc.ze;
@@ -222,32 +232,28 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) slot[tc.ring_lds[i]] = ld(pb + tc.ring_glb[i]);
     }
-    // rings of planes zb + L - 2, zb + L - 1 and queue fronts R + 1, R + 2 in flight
-    T ringA[TS::RING_PER_T], ringB[TS::RING_PER_T];
-    T qn1[RY], qn2[RY];
-    {
-        const int64_t r1 = (int64_t)min(zb + L - 2, zlast) * nxy;
-        const int64_t r2 = (int64_t)min(zb + L - 1, zlast) * nxy;
+    // rings of planes zb + L - 2 .. zb + L - 3 + PR and queue fronts R + 1, R + 2 in flight
+    T ring[PR][TS::RING_PER_T];
+    T qn[2][RY];
 #pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i) {
-            ringA[i] = ld(r1 + tc.ring_glb[i]);
-            ringB[i] = ld(r2 + tc.ring_glb[i]);
-        }
-        const int64_t f1 = (int64_t)wrapi(zb + R + 1, g.nz) * nxy;
-        const int64_t f2 = (int64_t)wrapi(zb + R + 2, g.nz) * nxy;
+    for (int j = 0; j < PR; ++j) {
+        const int64_t rp = (int64_t)min(zb + L - 2 + j, zlast) * nxy;
 #pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            qn1[r] = ld(f1 + tc.own[r]);
-            qn2[r] = ld(f2 + tc.own[r]);
-        }
+        for (int i = 0; i < TS::RING_PER_T; ++i) ring[j][i] = ld(rp + tc.ring_glb[i]);
     }
-    int kr = zb + L;                       // plane of the next ring fetch (clamped at use)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int64_t fp = (int64_t)wrapi(zb + R + 1 + j, g.nz) * nxy;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) qn[j][r] = ld(fp + tc.own[r]);
+    }
+    int kr = zb + L - 2 + PR;              // plane of the next ring fetch (clamped at use)
     int kf = wrapi(zb + R + 3, g.nz);      // plane of the next queue-front fetch
     int sc = 0;                            // slot of the output plane
 
-    // `active` is false for the padding plane of an odd-length chunk: it
-    // still loads (in bounds) but stores nothing.
-    auto plane = [&](int k, T (&ring)[TS::RING_PER_T], T (&qn)[RY], bool active) {
+    // `active` is false for the padding planes past the chunk end: they
+    // still load (in bounds) but store nothing.
+    auto plane = [&](int k, T (&rb)[TS::RING_PER_T], T (&qb)[RY], bool active) {
         const int kk = active ? k : zb;
         const int64_t pk = (int64_t)kk * nxy;
         T *buf = lds + sc * SL;
@@ -256,18 +262,18 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
 #pragma unroll
         for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[R][r];
 #pragma unroll
-        for (int i = 0; i < TS::RING_PER_T; ++i) rbuf[tc.ring_lds[i]] = ring[i];
+        for (int i = 0; i < TS::RING_PER_T; ++i) rbuf[tc.ring_lds[i]] = rb[i];
 #pragma unroll
         for (int r = 0; r < RY; ++r) ep.pre(r, pk + tc.own[r]);
         T nxt[RY];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) nxt[r] = qn[r];
+        for (int r = 0; r < RY; ++r) nxt[r] = qb[r];
         {
             const int64_t pr = (int64_t)min(kr, zlast) * nxy, pf = (int64_t)kf * nxy;
 #pragma unroll
-            for (int i = 0; i < TS::RING_PER_T; ++i) ring[i] = ld(pr + tc.ring_glb[i]);
+            for (int i = 0; i < TS::RING_PER_T; ++i) rb[i] = ld(pr + tc.ring_glb[i]);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) qn[r] = ld(pf + tc.own[r]);
+            for (int r = 0; r < RY; ++r) qb[r] = ld(pf + tc.own[r]);
         }
         __syncthreads();
         stencil_plane_compute<T, TX, TYT, RY>(w, buf, q, tc, active, pk, ep);
@@ -282,9 +288,9 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
         sc = (sc + 1 == L) ? 0 : sc + 1;
     };
 
-    for (int k = zb; k < ze; k += 2) {
-        plane(k, ringA, qn1, true);
-        plane(k + 1, ringB, qn2, k + 1 < ze);
+    for (int k = zb; k < ze; k += U) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) plane(k + j, ring[j % PR], qn[j % 2], k + j < ze);
     }
     // the LDS buffers are reused by the next tile of a persistent caller
     __syncthreads();
