@@ -1,0 +1,96 @@
+"""Parity at the full size of the benchmark workload (the large cell: 16x16x16
+FCC cells, 320^3 grid), in the launch configuration the benchmark uses.
+
+The oracle checks whole 320^3 results where its C stencil makes that cheap:
+the true complex128 residual of each of the 8 shifted solves (Section 3.1,
+paper shifts of Appendix A), the Euler-Lagrange residual of the density
+update (Appendix C), and Anderson mixing (Appendix D) over several steps."""
+import numpy as np
+import pytest
+
+import paper_1412_8250_amd as ofd
+from oracle import density, fd, helmholtz, kernel, poisson
+from oracle.anderson import Anderson as OracleAnderson
+from paper_1412_8250_amd import inputs
+from tests.gpu_util import announce, to_dev, to_host, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def large():
+    return inputs.large_cell()
+
+
+def test_shifted_batch_320(large):
+    """The 8 K_00 systems of the large cell, batched as in the SCF step, to 1e-8."""
+    torch = torch_cuda()
+    announce("shifted batch 320^3")
+    w = large
+    h = w.cell.h
+    ks = kernel.shifts(w.cell.n_electrons, w.cell.volume)
+    lb = -fd.laplacian(w.rho ** kernel.BETA, h)
+    la = -fd.laplacian(w.rho ** kernel.ALPHA, h)
+    base = [to_dev(lb), to_dev(la)]
+    rhs = [(kernel.P00[j % 4] * base[j // 4]).contiguous() for j in range(8)]
+    xs = [torch.zeros_like(f) for f in rhs]
+    b = ofd.HelmholtzBatch([w.rho.shape] * 8, [h] * 8, 6, ofd.C128)
+    status, st = b.solve(list(ks), rhs, xs, 1e-8)
+    for j in range(8):
+        announce("shifted batch 320^3 system", j, st[j]["iters"])
+        assert st[j]["rel_res"] <= 1e-8
+        u = to_host(xs[j])
+        f = kernel.P00[j % 4] * (lb if j < 4 else la)
+        assert helmholtz.residual(u, f, ks[j], h) <= 1.05e-8
+        del u, f
+    # conjugate pairs: real density, conjugate shifts and factors
+    for j in (0, 2, 4, 6):
+        d = (xs[j + 1] - torch.conj(xs[j])).abs().max().item()
+        assert d <= 1e-8 * xs[j].abs().max().item()
+    b.close()
+
+
+def test_density_update_320(large):
+    """U(v) on the large cell with v = the Poisson potential, lambda = 1, to
+    1e-8 (the benchmark's settings); the oracle recomputes the residual and
+    eta from the returned u over the whole grid."""
+    torch = torch_cuda()
+    announce("density update 320^3")
+    w = large
+    g, _ = poisson.rhs(w.rho, w.b)
+    gd = to_dev(g)
+    phi = torch.zeros_like(gd)
+    ofd.PoissonSolver(g.shape, w.cell.h, 6, ofd.PLAIN_F64).solve(gd, phi, 1e-10)
+    ctx = ofd.SCF(w.rho.shape, w.cell.h, to_dev(w.b), to_dev(np.sqrt(w.rho)), w.cell.n_electrons,
+                  lam=1.0, u_tol=1e-8)
+    ud = to_dev(np.sqrt(w.rho))
+    it, res, eta = ctx.density_update(phi, ud)
+    announce("density update 320^3 iterations", it, res)
+    assert res <= 1e-8
+    u = to_host(ud)
+    dv = float(np.prod(w.cell.h))
+    assert abs(dv * float((u * u).sum()) - w.cell.n_electrons) <= 1e-10 * w.cell.n_electrons
+    r_orc, eta_orc = density.el_residual(u, to_host(phi), w.cell.h, 1.0, w.cell.n_electrons)
+    assert r_orc <= 1.05e-8
+    assert abs(eta - eta_orc) <= 1e-10 * max(1.0, abs(eta_orc))
+
+
+def test_anderson_320():
+    """Anderson (m = 7, zeta = 0.3) on 320^3 vectors for 4 steps against the oracle."""
+    torch = torch_cuda()
+    announce("anderson 320^3")
+    n = 320 ** 3
+    rng = np.random.default_rng(7)
+    c = rng.normal(size=n)
+    v = rng.normal(size=n)
+    gpu = ofd.Anderson(n, 7, 0.3)
+    orc = OracleAnderson(7, 0.3)
+    vd = to_dev(v)
+    for k in range(4):
+        f = 0.5 * np.tanh(v) + c - v
+        ref = orc.step(v, f)
+        gpu.mix(vd, to_dev(f))
+        got = to_host(vd)
+        assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), k
+        v = ref
+        vd = to_dev(v)
