@@ -219,15 +219,18 @@ int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream);
 /* State access for checkpointing and inspection.  which: 0 = v, 1 = u, 2 = phi,
  * 3 = V_LR (device FP64 arrays of nx*ny*nz values); 4..11 = the solution of
  * shifted system which-4, kept as its next warm start (device complex128
- * arrays, 2*nx*ny*nz doubles; mu = 1 only).  INVALID_ARG for other values. */
+ * arrays, 2*nx*ny*nz doubles; mu = 1 only; the odd systems are the
+ * conjugates of the even ones and are rewritten from them after each
+ * step).  INVALID_ARG for other values. */
 int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream);
 int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
 /* Forget the Anderson history and the line-search step memory, so that the
  * next step behaves like the first step from the current state. */
 int ofdft_scf_reset_history(ofdft_scf *s);
 /* Statistics of the last step: [0] U iterations, [1] Poisson iterations,
- * [2] total shifted-solve iterations, [3] U residual, [4] Poisson residual,
- * [5] worst shifted-solve residual, [6] eta. */
+ * [2] total shifted-solve iterations (of the 4 systems solved: r = 1, 3 for
+ * both powers; r = 2, 4 are their complex conjugates, Appendix A), [3] U
+ * residual, [4] Poisson residual, [5] worst shifted-solve residual, [6] eta. */
 int ofdft_scf_stats(ofdft_scf *s, double *out7);
 
 /* The density update U(v) alone (Algorithm 1), using the context's parameters:

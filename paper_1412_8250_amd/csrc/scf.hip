@@ -54,40 +54,59 @@ struct PowersOp {       // rho^alpha, rho^beta
     }
 };
 
-struct ShiftRhsOp {     // F_j = P_j f_beta (j < 4), P_{j-4} f_alpha (j >= 4)
+// The K_00 row of Appendix A lists r = 2, 4 as the complex conjugates of
+// r = 1, 3 (both P and Q).  With a real density the right-hand sides of
+// systems r = 2, 4 are then the conjugates of those of r = 1, 3, and so are
+// their solutions: only systems 0, 2, 4, 6 (r = 1, 3 for beta and alpha) are
+// solved; 1, 3, 5, 7 are their conjugates.
+struct ShiftRhsOp {     // F_j = P_r f_beta (j = 0, 2), P_r f_alpha (j = 4, 6), r = j % 4
     static constexpr int kClass = K_POINTWISE;
-    static constexpr int kBytes = 144;
+    static constexpr int kBytes = 80;
     const double *fa, *fb;
-    double2 *F0, *F1, *F2, *F3, *F4, *F5, *F6, *F7;
+    double2 *F0, *F2, *F4, *F6;
     double pr[4], pi[4];
     __device__ bool skip() const { return false; }
     __device__ void prepare() {}
     __device__ void operator()(int64_t i, double (&)[1]) const {
         const double b_ = fb[i], a_ = fa[i];
         F0[i] = make_double2(pr[0] * b_, pi[0] * b_);
-        F1[i] = make_double2(pr[1] * b_, pi[1] * b_);
         F2[i] = make_double2(pr[2] * b_, pi[2] * b_);
-        F3[i] = make_double2(pr[3] * b_, pi[3] * b_);
         F4[i] = make_double2(pr[0] * a_, pi[0] * a_);
-        F5[i] = make_double2(pr[1] * a_, pi[1] * a_);
         F6[i] = make_double2(pr[2] * a_, pi[2] * a_);
-        F7[i] = make_double2(pr[3] * a_, pi[3] * a_);
     }
 };
 
-struct VlrOp {          // V_LR = C_F Re sum [alpha rho^(alpha-1) V_beta,r + beta rho^(beta-1) V_alpha,r]
+struct ConjOp {         // V_{j+1} = conj(V_j), j = 0, 2, 4, 6
     static constexpr int kClass = K_POINTWISE;
-    static constexpr int kBytes = 144;
+    static constexpr int kBytes = 128;
+    const double2 *V0, *V2, *V4, *V6;
+    double2 *V1, *V3, *V5, *V7;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double2 a = V0[i], b = V2[i], c = V4[i], d = V6[i];
+        V1[i] = make_double2(a.x, -a.y);
+        V3[i] = make_double2(b.x, -b.y);
+        V5[i] = make_double2(c.x, -c.y);
+        V7[i] = make_double2(d.x, -d.y);
+    }
+};
+
+// V_LR = C_F Re sum_r [alpha rho^(alpha-1) V_beta,r + beta rho^(beta-1) V_alpha,r];
+// Re V_{r=2} = Re V_{r=1} and Re V_{r=4} = Re V_{r=3} (conjugate pairs).
+struct VlrOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 80;
     const double *u;
-    const double2 *V0, *V1, *V2, *V3, *V4, *V5, *V6, *V7;
+    const double2 *V0, *V2, *V4, *V6;
     double *vlr;
     double floor_rho, a, bb;
     __device__ bool skip() const { return false; }
     __device__ void prepare() {}
     __device__ void operator()(int64_t i, double (&)[1]) const {
         const double rho = fmax(u[i] * u[i], floor_rho);
-        const double vb = V0[i].x + V1[i].x + V2[i].x + V3[i].x;
-        const double va = V4[i].x + V5[i].x + V6[i].x + V7[i].x;
+        const double vb = 2.0 * (V0[i].x + V2[i].x);
+        const double va = 2.0 * (V4[i].x + V6[i].x);
         vlr[i] = kCF * (a * pow(rho, a - 1.0) * vb + bb * pow(rho, bb - 1.0) * va);
     }
 };
@@ -159,30 +178,35 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
         OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
-        ShiftRhsOp sr{s->f_a, s->f_b, s->Fr[0], s->Fr[1], s->Fr[2], s->Fr[3], s->Fr[4], s->Fr[5],
-                      s->Fr[6], s->Fr[7], {}, {}};
+        ShiftRhsOp sr{s->f_a, s->f_b, s->Fr[0], s->Fr[2], s->Fr[4], s->Fr[6], {}, {}};
         for (int r = 0; r < 4; ++r) {
             sr.pr[r] = kP00[r][0];
             sr.pi[r] = kP00[r][1];
         }
         OFDFT_TRY((launch_reduce<1>(n, sr, NoFin{}, s->rb, st)));
-        const void *rhs[8];
-        void *xs[8];
-        for (int j = 0; j < 8; ++j) {
-            rhs[j] = s->Fr[j];
-            xs[j] = s->Vr[j];
+        const void *rhs[4];
+        void *xs[4];
+        double kap[8];
+        for (int q = 0; q < 4; ++q) {
+            rhs[q] = s->Fr[2 * q];
+            xs[q] = s->Vr[2 * q];
+            kap[2 * q] = s->kappa[4 * q];
+            kap[2 * q + 1] = s->kappa[4 * q + 1];
         }
-        ofdft_solve_stats hs[8];
-        int hst = cg_helmholtz_solve_batched(s->batch, s->kappa, rhs, xs, s->p.helmholtz_tol,
+        ofdft_solve_stats hs[4];
+        int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol,
                                              s->p.max_iter, hs, st);
         if (hst < 0) return hst;
-        for (int j = 0; j < 8; ++j) {
-            helm_it += hs[j].iters;
-            helm_res = std::max(helm_res, hs[j].rel_res);
+        for (int q = 0; q < 4; ++q) {
+            helm_it += hs[q].iters;
+            helm_res = std::max(helm_res, hs[q].rel_res);
         }
+        ConjOp co{(const double2 *)s->Vr[0], (const double2 *)s->Vr[2], (const double2 *)s->Vr[4],
+                  (const double2 *)s->Vr[6], (double2 *)s->Vr[1], (double2 *)s->Vr[3],
+                  (double2 *)s->Vr[5], (double2 *)s->Vr[7]};
+        OFDFT_TRY((launch_reduce<1>(n, co, NoFin{}, s->rb, st)));
         const double rho_bar = s->p.n_electrons / ((double)n * s->dv);
-        VlrOp vo{s->u, s->Vr[0], s->Vr[1], s->Vr[2], s->Vr[3], s->Vr[4], s->Vr[5], s->Vr[6], s->Vr[7],
-                 s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
+        VlrOp vo{s->u, s->Vr[0], s->Vr[2], s->Vr[4], s->Vr[6], s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
         OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
     }
     return OFDFT_OK;
@@ -234,7 +258,8 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
             (rc = salloc(s, &s->f_a, b8)) || (rc = salloc(s, &s->f_b, b8)))
             return fail(rc);
         for (int j = 0; j < 8; ++j)
-            if ((rc = salloc(s, &s->Fr[j], 2 * b8)) || (rc = salloc(s, &s->Vr[j], 2 * b8))) return fail(rc);
+            if ((j % 2 == 0 && (rc = salloc(s, &s->Fr[j], 2 * b8))) || (rc = salloc(s, &s->Vr[j], 2 * b8)))
+                return fail(rc);
         const double volume = (double)s->n * s->dv;
         const double kf = std::cbrt(3.0 * kPi * kPi * p->n_electrons / volume);
         const double k2 = 4.0 * kf * kf;
@@ -242,9 +267,9 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
             s->kappa[2 * j] = k2 * kQ00[j % 4][0];
             s->kappa[2 * j + 1] = k2 * kQ00[j % 4][1];
         }
-        ofdft_grid grids[8];
-        for (int j = 0; j < 8; ++j) grids[j] = p->grid;
-        if ((rc = ofdft_batch_create(8, grids, p->radius,
+        ofdft_grid grids[4];
+        for (int q = 0; q < 4; ++q) grids[q] = p->grid;
+        if ((rc = ofdft_batch_create(4, grids, p->radius,
                                      p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
             return fail(rc);
         for (int j = 0; j < 8; ++j)

@@ -98,3 +98,15 @@ def test_lr_kernel_step_matches_oracle():
     assert np.abs(to_host(vd) - orc.v).max() < 1e-7 * np.abs(orc.v).max()
     st = ctx.stats()
     assert st["helmholtz_res"] <= 1e-10 and st["poisson_res"] <= 1e-10
+    # all 8 shifted solutions (4 solved, 4 taken as conjugates) solve their
+    # systems for the density the step used, per the oracle
+    from oracle import helmholtz, kernel
+    ud = torch.empty(w.rho.shape, dtype=torch.float64, device="cuda")
+    ctx.get(ofd.SCF.U, ud)
+    rho = to_host(ud) ** 2
+    fs = kernel.rhs(rho, w.cell.h)
+    ks = kernel.shifts(w.cell.n_electrons, w.cell.volume)
+    for j in range(8):
+        vj = torch.empty(w.rho.shape, dtype=torch.complex128, device="cuda")
+        ctx.get(4 + j, vj)
+        assert helmholtz.residual(to_host(vj), fs[j], ks[j], w.cell.h) <= 1.05e-10, j
