@@ -206,6 +206,7 @@ typedef struct {
     double helmholtz_tol;      /* relative residual of each shifted solve                 */
     ofdft_dtype helmholtz_dtype; /* OFDFT_C128 or OFDFT_C64                               */
     int max_iter;              /* Krylov iteration cap per solve                          */
+    double line_tol;           /* line search: relative tolerance on the step, 0 = 1e-8  */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

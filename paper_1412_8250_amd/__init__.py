@@ -48,7 +48,7 @@ class ScfParams(ctypes.Structure):
                 ("zeta", ctypes.c_double), ("u_tol", ctypes.c_double), ("n_restart", ctypes.c_int),
                 ("u_max_iter", ctypes.c_int), ("poisson_tol", ctypes.c_double),
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
-                ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int)]
+                ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double)]
 
 
 _lib = None
@@ -338,7 +338,7 @@ class SCF:
                  history: int = 7, zeta: float = 0.3, u_tol: float = 1e-10, n_restart: int = 50,
                  u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
-                 radius: int = 6, stream=None):
+                 radius: int = 6, line_tol: float = 0.0, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -346,6 +346,7 @@ class SCF:
         p.history, p.zeta, p.u_tol, p.n_restart = int(history), float(zeta), float(u_tol), int(n_restart)
         p.u_max_iter, p.poisson_tol, p.poisson_mode = int(u_max_iter), float(poisson_tol), int(poisson_mode)
         p.helmholtz_tol, p.helmholtz_dtype, p.max_iter = float(helmholtz_tol), int(helmholtz_dtype), int(max_iter)
+        p.line_tol = float(line_tol)
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

@@ -173,8 +173,10 @@ int fetch(ofdft_scf *s, int first, int count, hipStream_t st) {
 
 // Brent's method for a root of f on [a, b] with f(a) f(b) <= 0 (Brent 1973:
 // bisection safeguarding secant / inverse quadratic interpolation steps).
+// Stops when the bracket is below tol or when |f| <= ftol at the iterate.
 template <class F>
-int brent_root(F &&f, double a, double b, double fa, double fb, double tol, int maxit, double &root) {
+int brent_root(F &&f, double a, double b, double fa, double fb, double tol, double ftol, int maxit,
+               double &root) {
     double c = a, fc = fa, d = b - a, e = d;
     for (int it = 0; it < maxit; ++it) {
         if ((fb > 0) == (fc > 0)) {
@@ -188,7 +190,7 @@ int brent_root(F &&f, double a, double b, double fa, double fb, double tol, int 
         }
         const double tol1 = 2.0 * 2.220446049250313e-16 * std::fabs(b) + 0.5 * tol;
         const double xm = 0.5 * (c - b);
-        if (std::fabs(xm) <= tol1 || fb == 0.0) {
+        if (std::fabs(xm) <= tol1 || std::fabs(fb) <= ftol) {
             root = b;
             return OFDFT_OK;
         }
@@ -302,17 +304,28 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         double hi = s_prev > 0 ? s_prev : 1.0 / std::sqrt(std::max(dd * dv / ne, 1e-300));
         double fhi;
         OFDFT_TRY(slope(hi, fhi));
+        // Bracket the root of dE/ds: while the slope is still negative, step
+        // just past the secant estimate of its zero (at least 1.1x, at most
+        // 8x further), which the nearly linear slope usually brackets at once.
         int grow = 0;
         while (fhi < 0.0 && grow < 80) {
+            double next = 2.0 * hi;
+            if (fhi > flo) {
+                const double sec = hi + (hi - lo) * (-fhi) / (fhi - flo);
+                next = std::min(std::max(1.1 * sec, 1.1 * hi), 8.0 * hi);
+            }
             lo = hi;
             flo = fhi;
-            hi *= 2.0;
+            hi = next;
             OFDFT_TRY(slope(hi, fhi));
             ++grow;
         }
         if (!std::isfinite(fhi)) return OFDFT_NONFINITE;
         double sstar = hi;
-        OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, 1e-15 * hi, 200, sstar));
+        const double ltol = s->p.line_tol > 0.0 ? s->p.line_tol : 1e-8;
+        // the slope is reduced a million-fold at the accepted step (an exact
+        // line search for NLCG purposes), or the bracket is below ltol
+        OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, ltol * hi, 1e-6 * std::fabs(f0), 200, sstar));
         const double ww = uu + sstar * (2.0 * ud + sstar * dd);
         const double c = sqn / std::sqrt(dv * ww);
         StepOp so{u, d_cur, sstar, c};
