@@ -6,7 +6,9 @@ the same state each time (v_0, u_0 and the solves' warm starts restored, empty
 Anderson history): 16x16x16 FCC Al-like
 cells (16384 atoms, 120 bohr box, 320^3 grid), TFW + K_00 linear-response
 kernel (lambda = 1, mu = 1): the density update U(v) (Algorithm 1), one
-Poisson solve, the 8 complex shifted kernel solves batched in each launch,
+Poisson solve (CG preconditioned by a multigrid V-cycle; --plain-poisson for
+plain CG), the 8 complex shifted kernel solves (4 solved, their conjugate
+partners taken as conjugates) batched in each launch,
 the kernel-potential assembly and Anderson mixing (history 7, zeta 0.3).
 All solves run to relative residual 1e-8.
 
@@ -16,8 +18,8 @@ value  = algorithmic HBM bytes of every kernel launched in the timed steps
 roofline = the dominant kernel class in the timed steps, its algorithmic
          bytes / its summed launch durations (HIP events on its stream).
 Extras: stand-alone stencil GB/s at 320^3 (f64, f32, c128), and Poisson
-time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined and the
-learned forms (the network trained here first, on 16 small perturbed cells,
+time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined, the
+multigrid-preconditioned and the learned forms (the network trained here first, on 16 small perturbed cells,
 about 20 s).
 cpu_baseline: the oracle (C, OpenMP) running textbook CG iterations of the
 same 320^3 Poisson problem, counted with the same per-iteration bytes.
@@ -41,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training/evaluating the learned aid")
+    ap.add_argument("--plain-poisson", action="store_true",
+                    help="SCF Poisson solve by plain FP64 CG instead of multigrid-preconditioned CG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy"], default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
@@ -162,7 +166,8 @@ def main():
 
     t0 = time.perf_counter()
     scf = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3,
-                  u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8)
+                  u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8,
+                  poisson_mode=ofd.PLAIN_F64 if args.plain_poisson else ofd.MULTIGRID)
     torch.cuda.synchronize()
     log(f"context + v0 in {time.perf_counter() - t0:.1f}s")
 
@@ -242,7 +247,8 @@ def main():
                                           "loss_last": float(np.mean(losses[-50:]))}
             gp = g - g.mean()
             extras["learned_correction_320"] = learned.correction_quality(net, gp, h)
-        forms = [("plain_f64", ofd.PLAIN_F64, None), ("refined_f32", ofd.REFINED_F32, None)]
+        forms = [("plain_f64", ofd.PLAIN_F64, None), ("refined_f32", ofd.REFINED_F32, None),
+                 ("multigrid", ofd.MULTIGRID, None)]
         if net is not None:
             forms += [("learned", ofd.LEARNED, False), ("learned_fcg", ofd.LEARNED, True)]
         for name, mode, fcg in forms:

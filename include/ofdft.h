@@ -48,6 +48,8 @@ typedef enum {
     OFDFT_REFINED_F32 = 1,     /* FP32 stencil + FP32 CG inside FP64 residual refinement  */
     OFDFT_LEARNED = 2,         /* network initial guess + flexible CG with the network as
                                   preconditioner, FP64 vectors; plain CG as fallback      */
+    OFDFT_MULTIGRID = 3,       /* CG preconditioned by a geometric multigrid V-cycle of
+                                  the second-order operator, FP64 vectors                 */
 } ofdft_mode;
 
 typedef struct {
@@ -100,8 +102,14 @@ int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
  * and reported in stats->removed_mean.
  *
  * ofdft_poisson_create allocates the workspace for one grid and one mode.
- *   mode  OFDFT_PLAIN_F64 or OFDFT_REFINED_F32 (OFDFT_LEARNED needs a network,
- *         see ofdft_poisson_set_network)
+ *   mode  OFDFT_PLAIN_F64, OFDFT_REFINED_F32, OFDFT_MULTIGRID (every axis must
+ *         halve evenly down to at most 16 points; INVALID_ARG otherwise) or
+ *         OFDFT_LEARNED (needs a network, see ofdft_poisson_set_network).
+ *         Multigrid: M = one V(2,2) cycle of the periodic 7-point operator
+ *         (damped Jacobi, omega 0.8; full weighting; trilinear
+ *         prolongation; exact DFT solve on the coarsest grid), a fixed
+ *         symmetric positive definite approximation of the inverse of
+ *         -L_h, so the iteration count does not grow with the grid.
  * cg_poisson_solve:
  *   rhs      device FP64 array g (not modified)
  *   x        device FP64 array: initial guess on entry (warm start), solution on
@@ -202,7 +210,7 @@ typedef struct {
     int n_restart;             /* Polak-Ribiere restart period                            */
     int u_max_iter;
     double poisson_tol;        /* relative residual of the Poisson solve                  */
-    int poisson_mode;          /* OFDFT_PLAIN_F64 or OFDFT_REFINED_F32                    */
+    int poisson_mode;          /* OFDFT_PLAIN_F64, OFDFT_REFINED_F32 or OFDFT_MULTIGRID   */
     double helmholtz_tol;      /* relative residual of each shifted solve                 */
     ofdft_dtype helmholtz_dtype; /* OFDFT_C128 or OFDFT_C64                               */
     int max_iter;              /* Krylov iteration cap per solve                          */
@@ -288,6 +296,10 @@ int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const double *g, c
                        double *loss, void *stream);
 int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g, const double *phi,
                         double lr, double *loss, void *stream);
+/* z = M r with the multigrid preconditioner of an OFDFT_MULTIGRID solver
+ * (device FP64 arrays of the solver's grid, z != r); INVALID_ARG for other
+ * modes. */
+int ofdft_poisson_apply_preconditioner(ofdft_poisson *s, const double *r, double *z, void *stream);
 int ofdft_poisson_set_learned_mode(ofdft_poisson *s, int precondition);
 int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
 
@@ -311,7 +323,7 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   passes, 4 COCG stencil phases (the whole solve when persistent),
  *   5 density-update stencil passes, 6 density-update vector passes,
  *   7 Anderson, 8 other vector passes, 9 network kernels, 10 COCG vector
- *   phase (stepped schedule).
+ *   phase (stepped schedule), 11 multigrid V-cycles.
  * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
  *   each result written once), timed launches and their summed milliseconds
  *   for one class since the last reset (synchronises on pending events).

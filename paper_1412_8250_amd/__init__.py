@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libofdft.so")
 
 OK, NOT_CONVERGED, INVALID_ARG, NONFINITE, BREAKDOWN, HIP_ERROR, NO_MEMORY = 0, 1, -1, -2, -3, -4, -5
 F64, F32, C128, C64 = 0, 1, 2, 3
-PLAIN_F64, REFINED_F32, LEARNED = 0, 1, 2
+PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID = 0, 1, 2, 3
 
 
 class OfdftError(RuntimeError):
@@ -98,6 +98,9 @@ def _declare(l):
         "ofdft_poisson_set_network": (_I, [_V, _V]),
         "ofdft_poisson_set_graphs": (_I, [_V, _I]),
         "ofdft_poisson_set_refinement": (_I, [_V, _D, _D]),
+        "ofdft_poisson_set_learned_mode": (_I, [_V, _I]),
+        "ofdft_poisson_apply_preconditioner": (_I, [_V, _V, _V, _V]),
+        "ofdft_nn_set_loss": (_I, [_V, _I]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
         "ofdft_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
@@ -177,7 +180,8 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
 
 
 KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
-                  "anderson", "pointwise", "nn", "cocg_update")
+                  "anderson", "pointwise", "nn", "cocg_update",
+                  "multigrid")
 
 
 def profile_reset(timed=()):
@@ -225,6 +229,12 @@ class PoissonSolver:
         """Attach a Network (learned mode only); the solver keeps a reference."""
         self._net = net
         _check(lib().ofdft_poisson_set_network(self._h, net._h if net is not None else None))
+
+    def apply_preconditioner(self, r, z, stream=None):
+        """z = M r (multigrid solvers only)."""
+        _check(lib().ofdft_poisson_apply_preconditioner(self._h, _dev(r, self.shape), _dev(z, self.shape),
+                                                        _stream(stream)))
+        return z
 
     def set_learned_mode(self, precondition: bool):
         """Learned form after the network's starting correction: plain CG

@@ -1,0 +1,359 @@
+// Geometric multigrid V-cycle (see multigrid.hpp) and the Poisson form that
+// uses it as the preconditioner of CG.
+#include <algorithm>
+#include <cmath>
+#include <utility>
+
+#include "fcg.hpp"
+#include "multigrid.hpp"
+#include "profile.hpp"
+
+namespace ofdft {
+
+namespace {
+
+constexpr int kMgThreads = 256;
+
+struct MgDims {
+    int nx, ny, nz;
+    double cx, cy, cz, diag;
+    int64_t n;
+};
+
+MgDims dims_of(const MgLevel &L) {
+    return MgDims{L.nx, L.ny, L.nz, L.cx, L.cy, L.cz, 2.0 * (L.cx + L.cy + L.cz), L.n};
+}
+
+int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + kMgThreads - 1) / kMgThreads, 8192); }
+
+// (A u)_i of the periodic 7-point operator A = -Delta_h (second order).
+__device__ inline double apply7(const double *__restrict__ u, const MgDims &d, int64_t i) {
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const int x = (int)(i % d.nx);
+    const int y = (int)((i / d.nx) % d.ny);
+    const int z = (int)(i / nxy);
+    const int64_t xp = x + 1 == d.nx ? i - x : i + 1;
+    const int64_t xm = x == 0 ? i + d.nx - 1 : i - 1;
+    const int64_t yp = y + 1 == d.ny ? i - (int64_t)y * d.nx : i + d.nx;
+    const int64_t ym = y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
+    const int64_t zp = z + 1 == d.nz ? i - (int64_t)z * nxy : i + nxy;
+    const int64_t zm = z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
+    return d.diag * u[i] - d.cx * (u[xp] + u[xm]) - d.cy * (u[yp] + u[ym]) - d.cz * (u[zp] + u[zm]);
+}
+
+// u = omega f / diag (first sweep from a zero guess)
+__global__ void __launch_bounds__(kMgThreads) mg_smooth0(MgDims d, double w, const double *__restrict__ f,
+                                                         double *__restrict__ u) {
+    const double s = w / d.diag;
+    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
+         i += (int64_t)gridDim.x * kMgThreads)
+        u[i] = s * f[i];
+}
+
+// t = u + omega (f - A u) / diag
+__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const double *__restrict__ f,
+                                                        const double *__restrict__ u, double *__restrict__ t) {
+    const double s = w / d.diag;
+    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
+         i += (int64_t)gridDim.x * kMgThreads)
+        t[i] = ::fma(s, f[i] - apply7(u, d, i), u[i]);
+}
+
+// r = f - A u
+__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const double *__restrict__ f,
+                                                          const double *__restrict__ u, double *__restrict__ r) {
+    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
+         i += (int64_t)gridDim.x * kMgThreads)
+        r[i] = f[i] - apply7(u, d, i);
+}
+
+// Full weighting: fc[I] = sum over the 27 fine points around 2I of
+// (1/8) w(dx) w(dy) w(dz) r, w(0) = 1, w(+-1) = 1/2 (= P^T / 8).
+__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const double *__restrict__ r,
+                                                          double *__restrict__ fc) {
+    const int64_t fnxy = (int64_t)fd.nx * fd.ny;
+    for (int64_t I = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; I < cd.n;
+         I += (int64_t)gridDim.x * kMgThreads) {
+        const int X = (int)(I % cd.nx), Y = (int)((I / cd.nx) % cd.ny), Z = (int)(I / ((int64_t)cd.nx * cd.ny));
+        double acc = 0.0;
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int z = (2 * Z + dz + fd.nz) % fd.nz;
+            const double wz = dz == 0 ? 1.0 : 0.5;
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = (2 * Y + dy + fd.ny) % fd.ny;
+                const double wy = dy == 0 ? wz : 0.5 * wz;
+                const int64_t row = (int64_t)z * fnxy + (int64_t)y * fd.nx;
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = (2 * X + dx + fd.nx) % fd.nx;
+                    const double wxy = dx == 0 ? wy : 0.5 * wy;
+                    acc = ::fma(wxy, r[row + x], acc);
+                }
+            }
+        }
+        fc[I] = 0.125 * acc;
+    }
+}
+
+// Trilinear prolongation added to u: fine point i takes coarse i/2 (even i)
+// or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.
+__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const double *__restrict__ uc,
+                                                             double *__restrict__ u) {
+    const int64_t fnxy = (int64_t)fd.nx * fd.ny, cnxy = (int64_t)cd.nx * cd.ny;
+    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < fd.n;
+         i += (int64_t)gridDim.x * kMgThreads) {
+        const int x = (int)(i % fd.nx), y = (int)((i / fd.nx) % fd.ny), z = (int)(i / fnxy);
+        int xs[2], ys[2], zs[2];
+        double wx[2], wy[2], wz[2];
+        int nxs, nys, nzs;
+        if (x % 2 == 0) { xs[0] = x / 2; wx[0] = 1.0; nxs = 1; }
+        else { xs[0] = x / 2; xs[1] = (x / 2 + 1) % cd.nx; wx[0] = wx[1] = 0.5; nxs = 2; }
+        if (y % 2 == 0) { ys[0] = y / 2; wy[0] = 1.0; nys = 1; }
+        else { ys[0] = y / 2; ys[1] = (y / 2 + 1) % cd.ny; wy[0] = wy[1] = 0.5; nys = 2; }
+        if (z % 2 == 0) { zs[0] = z / 2; wz[0] = 1.0; nzs = 1; }
+        else { zs[0] = z / 2; zs[1] = (z / 2 + 1) % cd.nz; wz[0] = wz[1] = 0.5; nzs = 2; }
+        double acc = 0.0;
+        for (int c = 0; c < nzs; ++c)
+            for (int b = 0; b < nys; ++b)
+                for (int a = 0; a < nxs; ++a)
+                    acc = ::fma(wz[c] * wy[b] * wx[a], uc[(int64_t)zs[c] * cnxy + (int64_t)ys[b] * cd.nx + xs[a]], acc);
+        u[i] += acc;
+    }
+}
+
+// Exact solve on the coarsest grid (at most 16^3 points, one workgroup):
+// A is diagonalised by the DFT, eigenvalue sum_a c_a (2 - 2 cos(2 pi k_a / n_a));
+// the k = 0 (constant) component is set to zero.
+__device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz, int axis, double sign) {
+    const int n = nx * ny * nz;
+    const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
+    const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int x = o % nx, y = (o / nx) % ny, z = o / (nx * ny);
+        const int k = axis == 0 ? x : (axis == 1 ? y : z);
+        const int base = o - k * stride;
+        double re = 0.0, im = 0.0;
+        for (int j = 0; j < len; ++j) {
+            double sn, cs;
+            sincospi(2.0 * (double)((j * k) % len) / (double)len, &sn, &cs);
+            sn *= sign;
+            const double2 v = in[base + j * stride];
+            re += v.x * cs - v.y * sn;
+            im += v.x * sn + v.y * cs;
+        }
+        out[o] = make_double2(re, im);
+    }
+}
+
+__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const double *__restrict__ f,
+                                                              double *__restrict__ u) {
+    __shared__ double2 a[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
+    __shared__ double2 b[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
+    const int n = (int)d.n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = make_double2(f[i], 0.0);
+    __syncthreads();
+    dft_axis(a, b, d.nx, d.ny, d.nz, 0, -1.0);
+    __syncthreads();
+    dft_axis(b, a, d.nx, d.ny, d.nz, 1, -1.0);
+    __syncthreads();
+    dft_axis(a, b, d.nx, d.ny, d.nz, 2, -1.0);
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += blockDim.x) {
+        const int x = o % d.nx, y = (o / d.nx) % d.ny, z = o / (d.nx * d.ny);
+        const double lam = d.cx * (2.0 - 2.0 * cospi(2.0 * x / d.nx)) +
+                           d.cy * (2.0 - 2.0 * cospi(2.0 * y / d.ny)) +
+                           d.cz * (2.0 - 2.0 * cospi(2.0 * z / d.nz));
+        const double s = (x == 0 && y == 0 && z == 0) ? 0.0 : 1.0 / (lam * (double)n);
+        b[o] = make_double2(b[o].x * s, b[o].y * s);
+    }
+    __syncthreads();
+    dft_axis(b, a, d.nx, d.ny, d.nz, 0, 1.0);
+    __syncthreads();
+    dft_axis(a, b, d.nx, d.ny, d.nz, 1, 1.0);
+    __syncthreads();
+    dft_axis(b, a, d.nx, d.ny, d.nz, 2, 1.0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = a[i].x;
+}
+
+int vcycle(Multigrid &mg, int l, hipStream_t s) {
+    MgLevel &L = mg.lv[l];
+    const MgDims d = dims_of(L);
+    const int nb = blocks_for(L.n);
+    if (l + 1 == (int)mg.lv.size()) {
+        hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kMgThreads), 0, s, d, L.f, L.u);
+        OFDFT_CHECK_HIP(hipGetLastError());
+        return OFDFT_OK;
+    }
+    // 2 nu sweeps in all; the first writes t, so after an even count the
+    // result is back in u
+    double *cur = L.t, *nxt = L.u;
+    hipLaunchKernelGGL(mg_smooth0, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur);
+    for (int k = 1; k < mg.nu; ++k) {
+        hipLaunchKernelGGL(mg_smooth, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur, nxt);
+        std::swap(cur, nxt);
+    }
+    hipLaunchKernelGGL(mg_residual, dim3(nb), dim3(kMgThreads), 0, s, d, L.f, cur, L.r);
+    MgLevel &C = mg.lv[l + 1];
+    const MgDims cd = dims_of(C);
+    hipLaunchKernelGGL(mg_restrict, dim3(blocks_for(C.n)), dim3(kMgThreads), 0, s, d, cd, L.r, C.f);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    OFDFT_TRY(vcycle(mg, l + 1, s));
+    hipLaunchKernelGGL(mg_prolong_add, dim3(nb), dim3(kMgThreads), 0, s, d, cd, C.u, cur);
+    for (int k = 0; k < mg.nu; ++k) {
+        hipLaunchKernelGGL(mg_smooth, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur, nxt);
+        std::swap(cur, nxt);
+    }
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+}  // namespace
+
+int mg_create(Multigrid &mg, const ofdft_grid &g) {
+    mg_free(mg);
+    MgLevel L;
+    L.nx = g.nx;
+    L.ny = g.ny;
+    L.nz = g.nz;
+    L.cx = 1.0 / (g.hx * g.hx);
+    L.cy = 1.0 / (g.hy * g.hy);
+    L.cz = 1.0 / (g.hz * g.hz);
+    for (;;) {
+        L.n = (int64_t)L.nx * L.ny * L.nz;
+        mg.lv.push_back(L);
+        const bool small = L.nx <= kMgCoarseMax && L.ny <= kMgCoarseMax && L.nz <= kMgCoarseMax;
+        if (small) break;
+        if (L.nx % 2 || L.ny % 2 || L.nz % 2) {
+            set_error("multigrid: grid %dx%dx%d cannot be halved down to %d per axis", g.nx, g.ny, g.nz,
+                      kMgCoarseMax);
+            mg.lv.clear();
+            return OFDFT_INVALID_ARG;
+        }
+        L.nx /= 2;
+        L.ny /= 2;
+        L.nz /= 2;
+        L.cx /= 4.0;
+        L.cy /= 4.0;
+        L.cz /= 4.0;
+    }
+    for (size_t l = 0; l < mg.lv.size(); ++l) {
+        MgLevel &M = mg.lv[l];
+        const size_t b = sizeof(double) * (size_t)M.n;
+        double **own[4] = {&M.t, &M.r, &M.u, &M.f};
+        const int count = l == 0 ? 2 : 4;          // level 0 uses the caller's r and z
+        for (int k = 0; k < count; ++k) {
+            void *p = nullptr;
+            if (hipMalloc(&p, b) != hipSuccess) {
+                mg_free(mg);
+                set_error("multigrid: out of device memory");
+                return OFDFT_NO_MEMORY;
+            }
+            mg.allocs.push_back(p);
+            *own[k] = (double *)p;
+        }
+    }
+    return OFDFT_OK;
+}
+
+void mg_free(Multigrid &mg) {
+    for (void *p : mg.allocs) (void)hipFree(p);
+    mg.allocs.clear();
+    mg.lv.clear();
+}
+
+int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s) {
+    if (mg.lv.empty()) return OFDFT_INVALID_ARG;
+    MgLevel &L0 = mg.lv[0];
+    L0.f = const_cast<double *>(r);
+    L0.u = z;
+    // algorithmic bytes of the fine level (the coarser ones add about 1/7):
+    // 2 nu sweeps and a residual (24 B/pt each), restriction (8), prolongation (16)
+    ProfScope ps(K_MULTIGRID, (double)L0.n * (24.0 * (2 * mg.nu + 1) + 24.0) * 8.0 / 7.0, s);
+    return vcycle(mg, 0, s);
+}
+
+// CG on the projected Poisson system preconditioned by the V-cycle (flexible
+// CG form, which equals preconditioned CG for this fixed SPD operator).
+int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter, ofdft_solve_stats &stats,
+                     hipStream_t st) {
+    const ofdft_grid &g = s->g;
+    const int64_t n = npoints(g);
+    double *r = s->r, *p = s->pA, *r_old = s->pB, *Ap = s->Ap, *z = s->z;
+    double *tot = s->totals + 8, *th = s->totals_host + 8;
+    auto sync_tot = [&](int count) -> int {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(th, tot, sizeof(double) * count, hipMemcpyDeviceToHost, st));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+        return OFDFT_OK;
+    };
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->totals_host, s->totals, sizeof(double) * 4, hipMemcpyDeviceToHost, st));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+    const double g2 = s->totals_host[3];
+    const double tol2 = rel_tol * rel_tol * g2;
+    OFDFT_TRY(residual_pass<double>(g, s->coef, x, s->gp, r, tot, s->rb, st));
+    OFDFT_TRY(sync_tot(2));
+    double r2 = th[1];
+    int iters = 0;
+    stats.iters = 0;
+    if (!std::isfinite(r2)) return OFDFT_NONFINITE;
+    if (r2 <= tol2) return OFDFT_OK;
+    if (max_iter <= 0) return OFDFT_NOT_CONVERGED;
+    OFDFT_TRY(mg_apply(*s->mg, r, z, st));
+    OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r}, StoreTotals<2>{tot}, s->rb, st)));
+    OFDFT_TRY(sync_tot(2));
+    double rz = th[1];
+    OFDFT_TRY((launch_reduce<1>(n, CopyOp2{p, z}, NoFin{}, s->rb, st)));
+    int status = OFDFT_NOT_CONVERGED;
+    while (iters < max_iter) {
+        OFDFT_TRY(pass64(g, s->coef, LoadPlain<double>{p}, EpiAp{Ap, tot, s->rb.partials, s->rb.counter, 0.0},
+                         st, 16.0, K_CG_STENCIL));
+        OFDFT_TRY(sync_tot(1));
+        const double pAp = th[0];
+        if (!std::isfinite(pAp) || !std::isfinite(rz)) {
+            status = OFDFT_NONFINITE;
+            break;
+        }
+        if (!(pAp > 0.0) || !(rz > 0.0)) {
+            status = OFDFT_BREAKDOWN;
+            break;
+        }
+        const double a = rz / pAp;
+        OFDFT_TRY((launch_reduce<1>(n, FcgStepOp{x, r, r_old, p, Ap, a}, StoreTotals<1>{tot}, s->rb, st)));
+        OFDFT_TRY(sync_tot(1));
+        r2 = th[0];
+        ++iters;
+        if (!std::isfinite(r2)) {
+            status = OFDFT_NONFINITE;
+            break;
+        }
+        if (r2 <= tol2) {
+            status = OFDFT_OK;
+            break;
+        }
+        OFDFT_TRY(mg_apply(*s->mg, r, z, st));
+        OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r_old}, StoreTotals<2>{tot}, s->rb, st)));
+        OFDFT_TRY(sync_tot(2));
+        const double b = th[0] / rz;
+        rz = th[1];
+        OFDFT_TRY((launch_reduce<1>(n, DirOp{p, z, std::isfinite(b) ? b : 0.0}, NoFin{}, s->rb, st)));
+    }
+    stats.iters = iters;
+    return status;
+}
+
+}  // namespace ofdft
+
+using namespace ofdft;
+
+// z = M r for a multigrid solver (for inspection and for callers that build
+// their own Krylov loop around the preconditioner).
+extern "C" int ofdft_poisson_apply_preconditioner(ofdft_poisson *s, const double *r, double *z,
+                                                  void *stream) {
+    if (!s || !r || !z || r == z || s->mode != OFDFT_MULTIGRID || !s->mg) {
+        set_error("ofdft_poisson_apply_preconditioner: multigrid solver and distinct r, z required");
+        return OFDFT_INVALID_ARG;
+    }
+    return mg_apply(*s->mg, r, z, (hipStream_t)stream);
+}

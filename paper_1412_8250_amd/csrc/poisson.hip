@@ -269,8 +269,12 @@ void poisson_free(ofdft_poisson *s) {
         graph_release(*s->graph32);
         delete s->graph32;
     }
+    if (s->mg) {
+        mg_free(*s->mg);
+        delete s->mg;
+    }
     void *dev[] = {s->gp, s->r, s->pA, s->pB, s->Ap, s->r32, s->d32, s->qA, s->qB, s->Aq, s->st,
-                   s->totals};
+                   s->totals, s->z, s->xbest};
     for (void *p : dev)
         if (p) (void)hipFree(p);
     if (s->st_host) (void)hipHostFree(s->st_host);
@@ -386,6 +390,7 @@ int poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol
     int status;
     if (s->mode == OFDFT_REFINED_F32) status = solve_refined(s, x, rel_tol, max_iter, stats, st);
     else if (s->mode == OFDFT_LEARNED) status = poisson_solve_learned(s, x, rel_tol, max_iter, stats, st);
+    else if (s->mode == OFDFT_MULTIGRID) status = poisson_solve_mg(s, x, rel_tol, max_iter, stats, st);
     else status = solve_plain(s, x, rel_tol, max_iter, stats, st);
     if (status < 0 && status != OFDFT_BREAKDOWN && status != OFDFT_NONFINITE) return status;
     OFDFT_TRY(finalize_solution(s, x, st));
@@ -413,7 +418,8 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
         set_error("ofdft_poisson_create: out is NULL");
         return OFDFT_INVALID_ARG;
     }
-    if (mode != OFDFT_PLAIN_F64 && mode != OFDFT_REFINED_F32 && mode != OFDFT_LEARNED) {
+    if (mode != OFDFT_PLAIN_F64 && mode != OFDFT_REFINED_F32 && mode != OFDFT_LEARNED &&
+        mode != OFDFT_MULTIGRID) {
         set_error("ofdft_poisson_create: unknown mode %d", mode);
         return OFDFT_INVALID_ARG;
     }
@@ -425,6 +431,15 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
     s->coef = make_coef(*grid, radius);
     s->coef32 = to_float(s->coef);
     int st = poisson_alloc(s);
+    if (st == OFDFT_OK && mode == OFDFT_MULTIGRID) {
+        s->mg = new (std::nothrow) Multigrid();
+        if (!s->mg) st = OFDFT_NO_MEMORY;
+        else st = mg_create(*s->mg, *grid);
+        if (st == OFDFT_OK && hipMalloc(&s->z, sizeof(double) * npoints(*grid)) != hipSuccess) {
+            set_error("ofdft_poisson_create: out of device memory");
+            st = OFDFT_NO_MEMORY;
+        }
+    }
     if (st != OFDFT_OK) {
         poisson_free(s);
         delete s;

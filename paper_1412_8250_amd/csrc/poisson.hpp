@@ -2,6 +2,7 @@
 #pragma once
 
 #include "cg.hpp"
+#include "multigrid.hpp"
 
 struct ofdft_nn;
 namespace ofdft {
@@ -28,9 +29,15 @@ struct ofdft_poisson {
     ofdft_nn *net = nullptr;
     double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
     int learned_fcg = 0;     // 0: network correction + plain CG; 1: + network-preconditioned FCG
+    // multigrid form
+    ofdft::Multigrid *mg = nullptr;
 };
 
 namespace ofdft {
+
+// CG preconditioned by the multigrid V-cycle (s->mg), from the iterate x.
+int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                     ofdft_solve_stats &stats, hipStream_t st);
 
 // Plain FP64 CG from the iterate x (residual recomputed first); stats.iters set.
 int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,

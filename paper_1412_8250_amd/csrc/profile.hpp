@@ -22,6 +22,7 @@ enum KClass {
     K_POINTWISE,       // other vector passes (projections, casts, assembly)
     K_NN,              // network convolutions and their gradients
     K_COCG_UPDATE,     // batched COCG (stepped): x, r update + r.r
+    K_MULTIGRID,       // multigrid V-cycles (Poisson preconditioner)
     K_CLASSES
 };
 

@@ -275,7 +275,9 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         for (int j = 0; j < 8; ++j)
             if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     }
-    const int pmode = p->poisson_mode == OFDFT_REFINED_F32 ? OFDFT_REFINED_F32 : OFDFT_PLAIN_F64;
+    const int pmode = (p->poisson_mode == OFDFT_REFINED_F32 || p->poisson_mode == OFDFT_MULTIGRID)
+                          ? p->poisson_mode
+                          : OFDFT_PLAIN_F64;
     if ((rc = ofdft_poisson_create(&p->grid, p->radius, pmode, &s->pois))) return fail(rc);
     if ((rc = ofdft_anderson_create(s->n, p->history, p->zeta, &s->mix))) return fail(rc);
     if (hipMemcpyAsync(s->b, b, b8, hipMemcpyDeviceToDevice, st) != hipSuccess ||

@@ -105,11 +105,11 @@ def test_bitwise_repeatable():
 
 def test_large_cell_320():
     """16x16x16 FCC cells (16384 atoms) on 320^3: true FP64 residual from the
-    oracle's stencil, plain FP64 and refined FP32 forms."""
+    oracle's stencil, plain FP64, refined FP32 and multigrid forms."""
     announce("poisson 320^3")
     w = inputs.large_cell()
     g, _ = poisson.rhs(w.rho, w.b)
-    for mode in (ofd.PLAIN_F64, ofd.REFINED_F32):
+    for mode in (ofd.PLAIN_F64, ofd.REFINED_F32, ofd.MULTIGRID):
         announce("poisson 320^3 mode", mode)
         x, st = _solve(g, w.cell.h, mode, 1e-8)
         assert poisson.residual(x, g, w.cell.h) <= 1e-8
@@ -137,3 +137,71 @@ def test_graph_replays_equal_eager(mode):
         assert stg["iters"] == ste["iters"]
         assert torch.equal(xg, xe), rep
         _ = (xg * 2).sum().item()          # eager work between replays
+
+
+@pytest.mark.parametrize("which", ["small", "noncubic", "supercell"])
+def test_multigrid_form_matches_exact(which):
+    """CG preconditioned by the multigrid V-cycle reaches the same solution
+    (exact spectral solve of the oracle) in a handful of iterations."""
+    torch = torch_cuda()
+    announce("poisson multigrid", which)
+    if which == "small":
+        w = inputs.small_cell()
+        g, _ = poisson.rhs(w.rho, w.b)
+        h = w.cell.h
+    elif which == "noncubic":
+        rng = np.random.default_rng(12)
+        g = rng.normal(size=(32, 48, 64))
+        g -= g.mean()
+        h = (0.45, 0.4, 0.5)
+    else:
+        w = inputs.supercell_500()
+        g, _ = poisson.rhs(w.rho, w.b)
+        h = w.cell.h
+    x, st = _solve(g, h, ofd.MULTIGRID, 1e-10)
+    ref = poisson.solve_exact(g, h)
+    assert poisson.residual(x, g, h) <= 1e-10
+    assert np.abs(x - ref).max() <= 1e-8 * np.abs(ref).max()
+    assert st["iters"] <= 25
+
+
+def test_multigrid_preconditioner_is_symmetric_positive():
+    """M = one V-cycle is a fixed symmetric positive definite operator on
+    zero-mean vectors: <M a, b> = <a, M b>, <a, M a> > 0, and M is linear."""
+    torch = torch_cuda()
+    announce("multigrid operator")
+    shape, h = (48, 32, 64), (0.4, 0.5, 0.45)
+    s = ofd.PoissonSolver(shape, h, 6, ofd.MULTIGRID)
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=shape)
+    b = rng.normal(size=shape)
+    a -= a.mean()
+    b -= b.mean()
+    ad, bd = to_dev(a), to_dev(b)
+    Ma, Mb, Mab = (torch.empty_like(ad) for _ in range(3))
+    s.apply_preconditioner(ad, Ma)
+    s.apply_preconditioner(bd, Mb)
+    s.apply_preconditioner(2.0 * ad - 3.0 * bd, Mab)
+    x1 = float((Ma * bd).sum())
+    x2 = float((ad * Mb).sum())
+    assert abs(x1 - x2) <= 1e-12 * (Ma.norm() * bd.norm()).item()
+    assert float((ad * Ma).sum()) > 0 and float((bd * Mb).sum()) > 0
+    assert (Mab - (2.0 * Ma - 3.0 * Mb)).abs().max().item() <= 1e-12 * Mab.abs().max().item()
+
+
+def test_multigrid_iterations_do_not_grow_with_the_grid():
+    torch = torch_cuda()
+    its = []
+    for n in (32, 64, 128):
+        rng = np.random.default_rng(n)
+        g = rng.normal(size=(n, n, n))
+        g -= g.mean()
+        _, st = _solve(g, (12.0 / n,) * 3, ofd.MULTIGRID, 1e-8)
+        its.append(st["iters"])
+    print("multigrid iterations", its)
+    assert max(its) <= 20 and its[-1] <= its[0] + 4
+
+
+def test_multigrid_rejects_grids_it_cannot_coarsen():
+    with pytest.raises(ofd.OfdftError):
+        ofd.PoissonSolver((24, 24, 50), (0.4,) * 3, 6, ofd.MULTIGRID)
