@@ -141,7 +141,8 @@ int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inne
  * the paper's  -(2kF)^-2 Lap V + Q V = P f  multiplied by (2kF)^2
  * (kappa = (2kF)^2 Q).  Each system may live on its own grid.  The matrix is
  * complex symmetric; the solver is COCG (conjugate gradients with the
- * unconjugated bilinear form).  All systems run in one persistent launch.
+ * unconjugated bilinear form).  Every COCG phase of all systems is one launch
+ * (ofdft_batch_set_config below selects the schedule).
  *
  * ofdft_batch_create: nsys systems, grids[j] (host array), one radius, dtype
  *   OFDFT_C128 or OFDFT_C64 (C64 runs COCG in complex64 inside complex128
@@ -155,7 +156,20 @@ int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inne
  *   stats    optional host array of nsys records
  * Returns OK, NOT_CONVERGED if any system missed the tolerance, BREAKDOWN,
  * NONFINITE, INVALID_ARG, HIP_ERROR.
+ * ofdft_batch_set_preconditioner: kind OFDFT_PRECOND_NONE (default) or
+ *   OFDFT_PRECOND_MULTIGRID: COCG preconditioned by one V(2,2) multigrid cycle
+ *   of the second-order operator -Delta_h + kappa_j (damped Jacobi smoothing,
+ *   full weighting, trilinear prolongation, exact DFT solve on the coarsest
+ *   grid), the real-space preconditioner of Section 5.5 applied to the shifted
+ *   systems.  The cycle is complex symmetric, so the preconditioned iteration
+ *   keeps the bilinear form r^T z.  Requires dtype C128 and the stepped
+ *   schedule (group 0 at solve time, else the solve returns INVALID_ARG);
+ *   every axis of every grid must halve evenly down to at most 16 points.
+ *   Allocates one complex128 vector per system and one hierarchy per distinct
+ *   grid (about 1.3 fine-grid vectors).  INVALID_ARG (nothing changed) or
+ *   NO_MEMORY.
  * ------------------------------------------------------------------------ */
+typedef enum { OFDFT_PRECOND_NONE = 0, OFDFT_PRECOND_MULTIGRID = 1 } ofdft_precond;
 typedef struct ofdft_batch ofdft_batch;
 int ofdft_batch_create(int nsys, const ofdft_grid *grids, int radius, ofdft_dtype dtype,
                        ofdft_batch **out);
@@ -163,6 +177,12 @@ int ofdft_batch_destroy(ofdft_batch *b);
 int cg_helmholtz_solve_batched(ofdft_batch *b, const double *kappa, const void *const *rhs,
                                void *const *x, double rel_tol, int max_iter,
                                ofdft_solve_stats *stats, void *stream);
+int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind);
+/* z = M_j r: one cycle of the preconditioner of system j's grid with shift
+ * kappa (host {Re, Im}); r, z device complex128 arrays of that grid, z != r.
+ * Synchronises the stream.  INVALID_ARG without a preconditioner set. */
+int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa, const void *r, void *z,
+                                     void *stream);
 
 /* ------------------------------------------------------------------------
  * Anderson mixing (Appendix D):
@@ -215,6 +235,7 @@ typedef struct {
     ofdft_dtype helmholtz_dtype; /* OFDFT_C128 or OFDFT_C64                               */
     int max_iter;              /* Krylov iteration cap per solve                          */
     double line_tol;           /* line search: relative tolerance on the step, 0 = 1e-8  */
+    int helmholtz_precond;     /* OFDFT_PRECOND_NONE or OFDFT_PRECOND_MULTIGRID (C128)   */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

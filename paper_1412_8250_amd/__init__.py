@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libofdft.so")
 OK, NOT_CONVERGED, INVALID_ARG, NONFINITE, BREAKDOWN, HIP_ERROR, NO_MEMORY = 0, 1, -1, -2, -3, -4, -5
 F64, F32, C128, C64 = 0, 1, 2, 3
 PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_MULTIGRID = 0, 1
 
 
 class OfdftError(RuntimeError):
@@ -48,7 +49,8 @@ class ScfParams(ctypes.Structure):
                 ("zeta", ctypes.c_double), ("u_tol", ctypes.c_double), ("n_restart", ctypes.c_int),
                 ("u_max_iter", ctypes.c_int), ("poisson_tol", ctypes.c_double),
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
-                ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double)]
+                ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
+                ("helmholtz_precond", ctypes.c_int)]
 
 
 _lib = None
@@ -86,6 +88,8 @@ def _declare(l):
                                       ctypes.POINTER(_D), _V]),
         "ofdft_stencil_set_config": (_I, [_I, _I, _I, _I, _I, _I]),
         "ofdft_batch_set_config": (_I, [_V, _I, _I]),
+        "ofdft_batch_set_preconditioner": (_I, [_V, _I]),
+        "ofdft_batch_apply_preconditioner": (_I, [_V, _I, ctypes.POINTER(_D), _V, _V, _V]),
         "ofdft_nn_create": (_I, [ctypes.c_uint64, ctypes.POINTER(_V)]),
         "ofdft_nn_destroy": (_I, [_V]),
         "ofdft_nn_param_count": (ctypes.c_size_t, []),
@@ -279,6 +283,20 @@ class HelmholtzBatch:
     def set_config(self, shape_id: int, group: int):
         _check(lib().ofdft_batch_set_config(self._h, int(shape_id), int(group)))
 
+    def set_preconditioner(self, kind: int):
+        """PRECOND_NONE or PRECOND_MULTIGRID (complex128, stepped schedule)."""
+        _check(lib().ofdft_batch_set_preconditioner(self._h, int(kind)))
+
+    def apply_preconditioner(self, j: int, kappa, r, z, stream=None):
+        """z = M_j r (complex128 tensors of system j's grid) for shift kappa."""
+        k = (ctypes.c_double * 2)(float(complex(kappa).real), float(complex(kappa).imag))
+        for t in (r, z):
+            if str(t.dtype) != "torch.complex128":
+                raise TypeError("the preconditioner takes complex128 arrays")
+        _check(lib().ofdft_batch_apply_preconditioner(self._h, int(j), k, _dev(r, self.shapes[j]),
+                                                      _dev(z, self.shapes[j]), _stream(stream)))
+        return z
+
     def solve(self, kappas, rhs, xs, rel_tol: float = 1e-8, max_iter: int = 100000, stream=None,
               allow_not_converged: bool = False):
         """kappas: sequence of complex; rhs, xs: complex128 CUDA tensors (x = guess in, solution out)."""
@@ -348,7 +366,7 @@ class SCF:
                  history: int = 7, zeta: float = 0.3, u_tol: float = 1e-10, n_restart: int = 50,
                  u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
-                 radius: int = 6, line_tol: float = 0.0, stream=None):
+                 radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -357,6 +375,7 @@ class SCF:
         p.u_max_iter, p.poisson_tol, p.poisson_mode = int(u_max_iter), float(poisson_tol), int(poisson_mode)
         p.helmholtz_tol, p.helmholtz_dtype, p.max_iter = float(helmholtz_tol), int(helmholtz_dtype), int(max_iter)
         p.line_tol = float(line_tol)
+        p.helmholtz_precond = int(helmholtz_precond)
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

@@ -447,8 +447,30 @@ int residual_c128(ofdft_batch *b, int j, const double2 *f, const double2 *x, dou
     return OFDFT_OK;
 }
 
+// Frees the preconditioner's buffers; the captured iteration graph holds
+// their addresses, so it goes too (the caller has synchronised).
+void precond_free(ofdft_batch *b) {
+    if (b->step_graph) {
+        (void)hipGraphExecDestroy(b->step_graph);
+        b->step_graph = nullptr;
+    }
+    for (Multigrid *mg : b->mg_own) {
+        mg_free(*mg);
+        delete mg;
+    }
+    for (void *p : b->z)
+        if (p) (void)hipFree(p);
+    if (b->d_kap) (void)hipFree(b->d_kap);
+    b->d_kap = nullptr;
+    b->mg_own.clear();
+    b->mg_of.clear();
+    b->z.clear();
+    b->precond = OFDFT_PRECOND_NONE;
+}
+
 void batch_free(ofdft_batch *b) {
     stepped_free(b);
+    precond_free(b);
     for (void *p : b->allocs)
         if (p) (void)hipFree(p);
     b->allocs.clear();
@@ -496,6 +518,7 @@ int upload_systems(ofdft_batch *b, const double *kappa, const std::vector<const 
         h.kim = kappa[2 * j + 1];
         h.x = x[j];
         h.f = f[j];
+        h.z = b->precond ? b->z[j] : nullptr;
         if (c64) {
             h.r = b->r[j];
             h.pA = b->pA[j];
@@ -600,12 +623,94 @@ extern "C" int ofdft_batch_set_config(ofdft_batch *b, int shape, int P) {
     return OFDFT_OK;
 }
 
+extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
+    if (!b || (kind != OFDFT_PRECOND_NONE && kind != OFDFT_PRECOND_MULTIGRID)) {
+        set_error("ofdft_batch_set_preconditioner: unknown kind %d", kind);
+        return OFDFT_INVALID_ARG;
+    }
+    if (kind == b->precond) return OFDFT_OK;
+    if (kind == OFDFT_PRECOND_NONE) {
+        OFDFT_CHECK_HIP(hipDeviceSynchronize());
+        precond_free(b);
+        return OFDFT_OK;
+    }
+    if (b->dtype != OFDFT_C128) {
+        set_error("ofdft_batch_set_preconditioner: multigrid needs dtype C128");
+        return OFDFT_INVALID_ARG;
+    }
+    // build everything first, so a failure leaves the batch unchanged
+    std::vector<Multigrid *> own, of(b->nsys, nullptr);
+    std::vector<void *> z(b->nsys, nullptr);
+    double *kap = nullptr;
+    auto undo = [&](int st) {
+        for (Multigrid *mg : own) {
+            mg_free(*mg);
+            delete mg;
+        }
+        for (void *p : z)
+            if (p) (void)hipFree(p);
+        if (kap) (void)hipFree(kap);
+        return st;
+    };
+    if (hipMalloc(&kap, 2 * sizeof(double)) != hipSuccess) {
+        kap = nullptr;
+        set_error("ofdft_batch_set_preconditioner: out of device memory");
+        return undo(OFDFT_NO_MEMORY);
+    }
+    for (int j = 0; j < b->nsys; ++j) {
+        const ofdft_grid &g = b->grids[j];
+        for (int i = 0; i < j && !of[j]; ++i) {
+            const ofdft_grid &q = b->grids[i];
+            if (q.nx == g.nx && q.ny == g.ny && q.nz == g.nz && q.hx == g.hx && q.hy == g.hy && q.hz == g.hz)
+                of[j] = of[i];
+        }
+        if (!of[j]) {
+            Multigrid *mg = new (std::nothrow) Multigrid();
+            if (!mg) return undo(OFDFT_NO_MEMORY);
+            own.push_back(mg);
+            const int st = mg_create(*mg, g, 16);
+            if (st != OFDFT_OK) return undo(st);
+            of[j] = mg;
+        }
+        if (hipMalloc(&z[j], sizeof(double2) * (size_t)npoints(g)) != hipSuccess) {
+            z[j] = nullptr;
+            set_error("ofdft_batch_set_preconditioner: out of device memory");
+            return undo(OFDFT_NO_MEMORY);
+        }
+    }
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
+    precond_free(b);
+    b->mg_own = own;
+    b->mg_of = of;
+    b->z = z;
+    b->d_kap = kap;
+    b->precond = kind;
+    return OFDFT_OK;
+}
+
+extern "C" int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa, const void *r,
+                                                void *z, void *stream) {
+    if (!b || !b->precond || j < 0 || j >= b->nsys || !kappa || !r || !z || r == z) {
+        set_error("ofdft_batch_apply_preconditioner: bad arguments (preconditioner set, 0 <= j < nsys, z != r)");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_kap, kappa, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+    OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], (const double2 *)r, (double2 *)z, b->d_kap, nullptr, s));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+    return OFDFT_OK;
+}
+
 static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *rhs, void *const *x,
                        double rel_tol, int max_iter, ofdft_solve_stats *stats, hipStream_t s) {
     const int nsys = b->nsys;
     const bool c64 = b->dtype == OFDFT_C64;
     const int shape = b->shape >= 0 ? b->shape : default_shape(b);
     const int P = b->P;      // 0: stepped schedule; > 0: persistent groups of P workgroups
+    if (b->precond && P > 0) {
+        set_error("cg_helmholtz_solve_batched: the preconditioner needs the stepped schedule (group 0)");
+        return OFDFT_INVALID_ARG;
+    }
     // LPT order: longest estimated solve first
     std::vector<double> cost(nsys);
     for (int j = 0; j < nsys; ++j) cost[j] = est_cost(b->grids[j], kappa[2 * j], kappa[2 * j + 1]);
@@ -635,6 +740,13 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
                 const double n = (double)npoints(b->grids[j]);
                 bs += n * e * (3.0 + 4.0 * it_pass[j]);
                 bu += n * e * 6.0 * it_pass[j];
+                if (b->precond) {
+                    // one cycle and one dot phase (read r, z) after the init
+                    // phase and after each iteration but the last
+                    const int cycles = std::max(1, it_pass[j]);
+                    bu += n * e * 2.0 * cycles;
+                    prof_add(K_MULTIGRID, mg_cycle_bytes(*b->mg_of[j]) * cycles, 0);
+                }
             }
             prof_add(K_COCG, bs, 0);
             prof_add(K_COCG_UPDATE, bu, 0);

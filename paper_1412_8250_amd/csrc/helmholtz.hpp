@@ -8,6 +8,7 @@
 
 #include <vector>
 
+#include "multigrid.hpp"
 #include "stencil_core.hpp"
 #include "tuning.hpp"
 #include "vec.hpp"
@@ -24,8 +25,9 @@ struct HSys {
     int64_t n;
     Coef<double> coef;
     Coef<float> coef32;
-    double kre, kim;
+    double kre, kim;          // adjacent: the multigrid cycle reads them as {Re, Im}
     void *x, *r, *pA, *pB, *Ap;
+    void *z;                  // preconditioned residual M r (nullptr: no preconditioner)
     const void *f;
 };
 
@@ -113,7 +115,13 @@ struct ofdft_batch {
     std::vector<int> h_ublk, h_vblk;
     hipGraphExec_t step_graph = nullptr;
     hipStream_t step_cap = nullptr;
-    int step_graph_key[3] = {-1, -1, -1};
+    int step_graph_key[4] = {-1, -1, -1, -1};
+    // preconditioner (OFDFT_PRECOND_*): z = M r per system; systems on equal
+    // grids share one multigrid hierarchy (their cycles run one after another)
+    int precond = 0;
+    double *d_kap = nullptr;      // {Re, Im} for ofdft_batch_apply_preconditioner
+    std::vector<void *> z;
+    std::vector<ofdft::Multigrid *> mg_of, mg_own;
 };
 
 namespace ofdft {

@@ -16,6 +16,12 @@
 // systems' workgroups exit at once.  Iterations are captured once in a HIP
 // graph and replayed; the host only polls the status array between replays.
 // No workgroup ever waits for another inside a launch.
+//
+// With a preconditioner M (one multigrid cycle per system, complex
+// symmetric) the iteration is preconditioned COCG: after the vector phase
+// z = M r is formed by the cycle's own launches, a dot phase reduces
+// rho = r^T z and sets beta = rho_new / rho, and the stencil phase builds
+// p = z + beta p_old.
 #include <algorithm>
 #include <cmath>
 
@@ -24,7 +30,7 @@
 namespace ofdft {
 
 struct StepState {
-    double rr_re, rr_im;     // r^T r of the current residual
+    double rr_re, rr_im;     // r^T r (preconditioned: r^T z) of the current residual
     double al_re, al_im;     // alpha of the current iteration
     double be_re, be_im;     // beta of the next direction
     double rn2, fn2, tol2;   // |r|^2, |f|^2, tol^2 |f|^2
@@ -55,7 +61,7 @@ struct StepLoadX {
 };
 
 template <typename T>
-struct StepLoadP {       // r + beta p_old (first iteration: p_old = r, beta = 0)
+struct StepLoadP {       // r + beta p_old (first iteration: p_old = r, beta = 0); z for r when preconditioned
     GPtr<T> r, p_old;
     T beta;
     __device__ T operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
@@ -140,7 +146,8 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int tota
         const bool first = sj->iter == 0;
         const void *p_old = sj->parity ? h.pB : h.pA;
         const void *p_new = sj->parity ? h.pA : h.pB;
-        StepLoadP<T> ld{GPtr<T>(h.r), GPtr<T>(first ? h.r : p_old),
+        const void *base = h.z ? h.z : h.r;
+        StepLoadP<T> ld{GPtr<T>(base), GPtr<T>(first ? base : p_old),
                         first ? CT::mk(0.0, 0.0) : CT::mk(sj->be_re, sj->be_im)};
         StepEpiPAp<T> ep{GPtr<T>(p_new), GPtr<T>(h.Ap), kappa, {0, 0}};
         // The two-array loader doubles the registers of in-flight ring fetches:
@@ -167,9 +174,9 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int tota
     }
 }
 
-// Vector phase: x += alpha p, r -= alpha Ap; then beta, status.  part region
-// of system j starts at 4 * vblk[j] (the caller offsets part past the stencil
-// slots).
+// Vector phase: x += alpha p, r -= alpha Ap; then beta (unpreconditioned)
+// and status.  part region of system j starts at 4 * vblk[j] (the caller
+// offsets part past the stencil slots).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreadsStep)
 step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned int *ctr,
@@ -198,12 +205,15 @@ step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned 
     block_sum<3>(acc, scratch);
     double t[3];
     if (reduce_grid<3>(acc, part + 4 * (size_t)vblk[j], nb, lb, ctr + j, scratch, t)) {
-        const double rr_re = sj->rr_re, rr_im = sj->rr_im;
-        const double d2 = rr_re * rr_re + rr_im * rr_im;
-        sj->be_re = (t[0] * rr_re + t[1] * rr_im) / d2;
-        sj->be_im = (t[1] * rr_re - t[0] * rr_im) / d2;
-        sj->rr_re = t[0];
-        sj->rr_im = t[1];
+        const bool pre = h.z != nullptr;        // rho and beta come from the dot phase
+        if (!pre) {
+            const double rr_re = sj->rr_re, rr_im = sj->rr_im;
+            const double d2 = rr_re * rr_re + rr_im * rr_im;
+            sj->be_re = (t[0] * rr_re + t[1] * rr_im) / d2;
+            sj->be_im = (t[1] * rr_re - t[0] * rr_im) / d2;
+            sj->rr_re = t[0];
+            sj->rr_im = t[1];
+        }
         sj->rn2 = t[2];
         const int iter = sj->iter + 1;
         sj->iter = iter;
@@ -211,9 +221,50 @@ step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned 
         int d = H_RUNNING;
         if (!isfinite(t[2])) d = H_NONFINITE;
         else if (t[2] <= sj->tol2) d = H_CONVERGED;
-        else if (t[0] * t[0] + t[1] * t[1] <= 1e-60 * t[2] * t[2]) d = H_BREAKDOWN;
+        else if (!pre && t[0] * t[0] + t[1] * t[1] <= 1e-60 * t[2] * t[2]) d = H_BREAKDOWN;
         else if (iter >= sj->maxit) d = H_MAXIT;
         sj->done = d;
+    }
+}
+
+// Dot phase of the preconditioned iteration: rho = r^T z, |z|^2; first call
+// of a solve (iter 0) sets rho, later ones beta = rho_new / rho and rho.
+template <typename T>
+__global__ void __launch_bounds__(kVecThreadsStep)
+step_dot(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned int *ctr, double *part) {
+    __shared__ double scratch[3 * (kVecThreadsStep / 64)];
+    const int b = blockIdx.x;
+    const int j = find_sys(vblk, nsys, b);
+    StepState *sj = st + j;
+    const HSys &h = sys[j];
+    if (sj->done != H_RUNNING || !h.z) return;
+    const int lb = b - vblk[j], nb = vblk[j + 1] - vblk[j];
+    const GPtr<T> r(h.r), z(h.z);
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t stride = (int64_t)nb * kVecThreadsStep;
+    for (int64_t i = (int64_t)lb * kVecThreadsStep + threadIdx.x; i < h.n; i += stride) {
+        const T a = r[i], c = z[i];
+        acc[0] += (double)a.x * c.x - (double)a.y * c.y;
+        acc[1] += (double)a.x * c.y + (double)a.y * c.x;
+        acc[2] += (double)c.x * c.x + (double)c.y * c.y;
+    }
+    block_sum<3>(acc, scratch);
+    double t[3];
+    if (reduce_grid<3>(acc, part + 4 * (size_t)vblk[j], nb, lb, ctr + j, scratch, t)) {
+        if (!isfinite(t[0]) || !isfinite(t[1]) || !isfinite(t[2])) {
+            sj->done = H_NONFINITE;
+        } else if (t[0] * t[0] + t[1] * t[1] <= 1e-60 * sj->rn2 * t[2]) {
+            sj->done = H_BREAKDOWN;
+        } else {
+            if (sj->iter > 0) {
+                const double rr_re = sj->rr_re, rr_im = sj->rr_im;
+                const double d2 = rr_re * rr_re + rr_im * rr_im;
+                sj->be_re = (t[0] * rr_re + t[1] * rr_im) / d2;
+                sj->be_im = (t[1] * rr_re - t[0] * rr_im) / d2;
+            }
+            sj->rr_re = t[0];
+            sj->rr_im = t[1];
+        }
     }
 }
 
@@ -246,32 +297,50 @@ int launch_update(ofdft_batch *b, hipStream_t s) {
     return OFDFT_OK;
 }
 
-// `iters` iterations of both phases.  Timed: each launch is accounted and
+// z = M r of every preconditioned system, then rho = r^T z (and beta).
+// Systems that are not running skip both inside the kernels.  Timed: each
+// cycle and the dot launch are timed; otherwise the caller accounts them.
+int precondition(ofdft_batch *b, hipStream_t s, bool timed) {
+    for (int j = 0; j < b->nsys; ++j) {
+        Multigrid *mg = b->mg_of[j];
+        const double *kap = &b->d_sys[j].kre;      // {kre, kim} of system j (device)
+        const int *run = &b->d_step[j].done;
+        if (timed) {
+            ProfScope ps(K_MULTIGRID, mg_cycle_bytes(*mg), s);
+            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
+        } else {
+            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
+        }
+    }
+    ProfScope ps(K_COCG_UPDATE, 0.0, s, timed);
+    hipLaunchKernelGGL(step_dot<double2>, dim3(b->step_vblocks), dim3(kVecThreadsStep), 0, s, b->d_sys,
+                       b->d_step, b->d_vblk, b->nsys, b->d_ctr, b->d_spart + 4 * (size_t)b->step_units);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+// `iters` iterations of all phases.  Timed: each launch is accounted and
 // timed on its own; otherwise (graph capture) the caller accounts replays.
 template <typename T>
 int step_iterations(ofdft_batch *b, int shape, int iters, hipStream_t s, bool timed) {
     for (int k = 0; k < iters; ++k) {
-        if (timed) {
-            {
-                ProfScope ps(K_COCG, 0.0, s);
-                OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_PAP, 0.0, s));
-            }
-            ProfScope ps(K_COCG_UPDATE, 0.0, s);
-            OFDFT_TRY(launch_update<T>(b, s));
-        } else {
+        {
+            ProfScope ps(K_COCG, 0.0, s, timed);
             OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_PAP, 0.0, s));
+        }
+        {
+            ProfScope ps(K_COCG_UPDATE, 0.0, s, timed);
             OFDFT_TRY(launch_update<T>(b, s));
         }
+        if (b->precond) OFDFT_TRY(precondition(b, s, timed));
     }
     return OFDFT_OK;
 }
 
 template <typename T>
 int graph_get(ofdft_batch *b, int shape) {
-    const int key[3] = {shape, (int)sizeof(T), b->step_units};
-    if (b->step_graph && key[0] == b->step_graph_key[0] && key[1] == b->step_graph_key[1] &&
-        key[2] == b->step_graph_key[2])
-        return OFDFT_OK;
+    const int key[4] = {shape, (int)sizeof(T), b->step_units, b->precond};
+    if (b->step_graph && std::equal(key, key + 4, b->step_graph_key)) return OFDFT_OK;
     if (b->step_graph) {
         (void)hipGraphExecDestroy(b->step_graph);
         b->step_graph = nullptr;
@@ -289,7 +358,7 @@ int graph_get(ofdft_batch *b, int shape) {
     const hipError_t ei = hipGraphInstantiate(&b->step_graph, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     OFDFT_CHECK_HIP(ei);
-    for (int i = 0; i < 3; ++i) b->step_graph_key[i] = key[i];
+    for (int i = 0; i < 4; ++i) b->step_graph_key[i] = key[i];
     return OFDFT_OK;
 }
 
@@ -346,11 +415,19 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
     }
     for (int j : which) b->h_step[j].done = H_RUNNING;
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_step, b->h_step, sizeof(StepState) * nsys, hipMemcpyHostToDevice, s));
+    const bool timed = prof_timed(K_COCG) || prof_timed(K_COCG_UPDATE) ||
+                       (b->precond && prof_timed(K_MULTIGRID));
     {
         ProfScope ps(K_COCG, 0.0, s);
         OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_INIT, tol, s));
     }
-    const bool timed = prof_timed(K_COCG) || prof_timed(K_COCG_UPDATE);
+    if (b->precond) {
+        OFDFT_TRY(precondition(b, s, timed));
+        if (!timed) {
+            prof_add(K_COCG_UPDATE, 0.0, 1);
+            prof_add(K_MULTIGRID, 0.0, nsys);
+        }
+    }
     int reps = 1;
     for (;;) {
         OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * nsys, hipMemcpyDeviceToHost, s));
@@ -364,7 +441,8 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
             OFDFT_TRY(graph_get<T>(b, shape));
             for (int k = 0; k < reps; ++k) OFDFT_CHECK_HIP(hipGraphLaunch(b->step_graph, s));
             prof_add(K_COCG, 0.0, reps * kStepIters);
-            prof_add(K_COCG_UPDATE, 0.0, reps * kStepIters);
+            prof_add(K_COCG_UPDATE, 0.0, reps * kStepIters * (b->precond ? 2 : 1));
+            if (b->precond) prof_add(K_MULTIGRID, 0.0, (int64_t)reps * kStepIters * nsys);
         }
         reps = std::min(reps * 2, 32);
     }
@@ -392,6 +470,7 @@ int stepped_zlen(const ofdft_grid &g, bool, int shape) {
 int stepped_run(ofdft_batch *b, bool c64, int shape, const std::vector<HSys> &hs,
                 const std::vector<int> &which, const std::vector<int> &maxit, double tol,
                 std::vector<int> &iters, std::vector<int> &done, hipStream_t s) {
+    if (b->precond && c64) return OFDFT_INVALID_ARG;
     OFDFT_TRY(prepare_layout(b, hs, s));
     if (c64) return run_t<float2>(b, shape, which, maxit, tol, iters, done, s);
     return run_t<double2>(b, shape, which, maxit, tol, iters, done, s);

@@ -17,17 +17,30 @@ constexpr int kMgThreads = 256;
 struct MgDims {
     int nx, ny, nz;
     double cx, cy, cz, diag;
+    double kre, kim;          // shift kappa of A = -Delta_h + kappa
     int64_t n;
 };
 
-MgDims dims_of(const MgLevel &L) {
-    return MgDims{L.nx, L.ny, L.nz, L.cx, L.cy, L.cz, 2.0 * (L.cx + L.cy + L.cz), L.n};
+MgDims dims_of(const MgLevel &L, double2 kappa) {
+    return MgDims{L.nx, L.ny, L.nz, L.cx, L.cy, L.cz, 2.0 * (L.cx + L.cy + L.cz), kappa.x, kappa.y, L.n};
 }
 
 int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + kMgThreads - 1) / kMgThreads, 8192); }
 
-// (A u)_i of the periodic 7-point operator A = -Delta_h (second order).
-__device__ inline double apply7(const double *__restrict__ u, const MgDims &d, int64_t i) {
+// Element arithmetic for real (Poisson) and complex (shifted) levels.
+__device__ inline double mg_scale(double2 s, double v) { return s.x * v; }
+__device__ inline double2 mg_scale(double2 s, double2 v) {
+    return make_double2(s.x * v.x - s.y * v.y, s.x * v.y + s.y * v.x);
+}
+__device__ inline double mg_axpy(double a, double x, double y) { return ::fma(a, x, y); }
+__device__ inline double2 mg_axpy(double a, double2 x, double2 y) {
+    return make_double2(::fma(a, x.x, y.x), ::fma(a, x.y, y.y));
+}
+
+// (A u)_i of the periodic 7-point operator A = -Delta_h + kappa (second order).
+template <typename T>
+__device__ inline T apply7(const T *__restrict__ u, const MgDims &d, int64_t i) {
+    using V = VT<T>;
     const int64_t nxy = (int64_t)d.nx * d.ny;
     const int x = (int)(i % d.nx);
     const int y = (int)((i / d.nx) % d.ny);
@@ -38,44 +51,85 @@ __device__ inline double apply7(const double *__restrict__ u, const MgDims &d, i
     const int64_t ym = y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
     const int64_t zp = z + 1 == d.nz ? i - (int64_t)z * nxy : i + nxy;
     const int64_t zm = z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
-    return d.diag * u[i] - d.cx * (u[xp] + u[xm]) - d.cy * (u[yp] + u[ym]) - d.cz * (u[zp] + u[zm]);
+    const T c = u[i];
+    T a = V::mul(d.diag, c);
+    a = mg_axpy(-d.cx, V::add(u[xp], u[xm]), a);
+    a = mg_axpy(-d.cy, V::add(u[yp], u[ym]), a);
+    a = mg_axpy(-d.cz, V::add(u[zp], u[zm]), a);
+    return V::add(a, mg_scale(make_double2(d.kre, d.kim), c));
 }
 
-// u = omega f / diag (first sweep from a zero guess)
-__global__ void __launch_bounds__(kMgThreads) mg_smooth0(MgDims d, double w, const double *__restrict__ f,
-                                                         double *__restrict__ u) {
-    const double s = w / d.diag;
-    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
-         i += (int64_t)gridDim.x * kMgThreads)
-        u[i] = s * f[i];
+// Per-launch shift source: when `kap` is given, kappa is read from device
+// memory (so a captured launch follows the current shift); when `run` is
+// given the kernel returns at once unless *run == 0 (a converged system of a
+// batch).
+struct MgShift {
+    const double *kap;
+    const int *run;
+};
+
+// Returns false when the launch is to be skipped; otherwise sets d's shift.
+__device__ inline bool take_shift(const MgShift &sh, MgDims &d) {
+    if (sh.run && *sh.run != 0) return false;
+    if (sh.kap) {
+        d.kre = sh.kap[0];
+        d.kim = sh.kap[1];
+    }
+    return true;
 }
 
-// t = u + omega (f - A u) / diag
-__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const double *__restrict__ f,
-                                                        const double *__restrict__ u, double *__restrict__ t) {
-    const double s = w / d.diag;
+// omega / (diag + kappa)
+__device__ inline double2 jacobi_factor(const MgDims &d, double w) {
+    const double re = d.diag + d.kre, im = d.kim, den = re * re + im * im;
+    return make_double2(w * re / den, -w * im / den);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_smooth0(MgDims d, double w, const T *__restrict__ f,
+                                                         T *__restrict__ u, MgShift sh) {
+    if (!take_shift(sh, d)) return;
+    const double2 s = jacobi_factor(d, w);
     for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
          i += (int64_t)gridDim.x * kMgThreads)
-        t[i] = ::fma(s, f[i] - apply7(u, d, i), u[i]);
+        u[i] = mg_scale(s, f[i]);
+}
+
+// t = u + omega (f - A u) / (diag + kappa)
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const T *__restrict__ f,
+                                                        const T *__restrict__ u, T *__restrict__ t,
+                                                        MgShift sh) {
+    if (!take_shift(sh, d)) return;
+    using V = VT<T>;
+    const double2 s = jacobi_factor(d, w);
+    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
+         i += (int64_t)gridDim.x * kMgThreads)
+        t[i] = V::add(u[i], mg_scale(s, V::sub(f[i], apply7(u, d, i))));
 }
 
 // r = f - A u
-__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const double *__restrict__ f,
-                                                          const double *__restrict__ u, double *__restrict__ r) {
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const T *__restrict__ f,
+                                                          const T *__restrict__ u, T *__restrict__ r,
+                                                          MgShift sh) {
+    if (!take_shift(sh, d)) return;
     for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
          i += (int64_t)gridDim.x * kMgThreads)
-        r[i] = f[i] - apply7(u, d, i);
+        r[i] = VT<T>::sub(f[i], apply7(u, d, i));
 }
 
 // Full weighting: fc[I] = sum over the 27 fine points around 2I of
 // (1/8) w(dx) w(dy) w(dz) r, w(0) = 1, w(+-1) = 1/2 (= P^T / 8).
-__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const double *__restrict__ r,
-                                                          double *__restrict__ fc) {
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const T *__restrict__ r,
+                                                          T *__restrict__ fc, MgShift sh) {
+    if (sh.run && *sh.run != 0) return;
+    using V = VT<T>;
     const int64_t fnxy = (int64_t)fd.nx * fd.ny;
     for (int64_t I = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; I < cd.n;
          I += (int64_t)gridDim.x * kMgThreads) {
         const int X = (int)(I % cd.nx), Y = (int)((I / cd.nx) % cd.ny), Z = (int)(I / ((int64_t)cd.nx * cd.ny));
-        double acc = 0.0;
+        T acc = V::zero();
 #pragma unroll
         for (int dz = -1; dz <= 1; ++dz) {
             const int z = (2 * Z + dz + fd.nz) % fd.nz;
@@ -88,19 +142,21 @@ __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, 
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int x = (2 * X + dx + fd.nx) % fd.nx;
-                    const double wxy = dx == 0 ? wy : 0.5 * wy;
-                    acc = ::fma(wxy, r[row + x], acc);
+                    acc = mg_axpy(dx == 0 ? wy : 0.5 * wy, r[row + x], acc);
                 }
             }
         }
-        fc[I] = 0.125 * acc;
+        fc[I] = V::mul(0.125, acc);
     }
 }
 
 // Trilinear prolongation added to u: fine point i takes coarse i/2 (even i)
 // or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.
-__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const double *__restrict__ uc,
-                                                             double *__restrict__ u) {
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const T *__restrict__ uc,
+                                                             T *__restrict__ u, MgShift sh) {
+    if (sh.run && *sh.run != 0) return;
+    using V = VT<T>;
     const int64_t fnxy = (int64_t)fd.nx * fd.ny, cnxy = (int64_t)cd.nx * cd.ny;
     for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < fd.n;
          i += (int64_t)gridDim.x * kMgThreads) {
@@ -114,18 +170,19 @@ __global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims c
         else { ys[0] = y / 2; ys[1] = (y / 2 + 1) % cd.ny; wy[0] = wy[1] = 0.5; nys = 2; }
         if (z % 2 == 0) { zs[0] = z / 2; wz[0] = 1.0; nzs = 1; }
         else { zs[0] = z / 2; zs[1] = (z / 2 + 1) % cd.nz; wz[0] = wz[1] = 0.5; nzs = 2; }
-        double acc = 0.0;
+        T acc = u[i];
         for (int c = 0; c < nzs; ++c)
             for (int b = 0; b < nys; ++b)
                 for (int a = 0; a < nxs; ++a)
-                    acc = ::fma(wz[c] * wy[b] * wx[a], uc[(int64_t)zs[c] * cnxy + (int64_t)ys[b] * cd.nx + xs[a]], acc);
-        u[i] += acc;
+                    acc = mg_axpy(wz[c] * wy[b] * wx[a], uc[(int64_t)zs[c] * cnxy + (int64_t)ys[b] * cd.nx + xs[a]],
+                                  acc);
+        u[i] = acc;
     }
 }
 
 // Exact solve on the coarsest grid (at most 16^3 points, one workgroup):
-// A is diagonalised by the DFT, eigenvalue sum_a c_a (2 - 2 cos(2 pi k_a / n_a));
-// the k = 0 (constant) component is set to zero.
+// A is diagonalised by the DFT, eigenvalue sum_a c_a (2 - 2 cos(2 pi k_a / n_a))
+// + kappa; with kappa = 0 the k = 0 (constant) component is set to zero.
 __device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz, int axis, double sign) {
     const int n = nx * ny * nz;
     const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
@@ -147,12 +204,19 @@ __device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz
     }
 }
 
-__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const double *__restrict__ f,
-                                                              double *__restrict__ u) {
+__device__ inline double2 mg_to_c(double v) { return make_double2(v, 0.0); }
+__device__ inline double2 mg_to_c(double2 v) { return v; }
+__device__ inline void mg_from_c(double2 v, double &o) { o = v.x; }
+__device__ inline void mg_from_c(double2 v, double2 &o) { o = v; }
+
+template <typename T>
+__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const T *__restrict__ f,
+                                                              T *__restrict__ u, MgShift sh) {
+    if (!take_shift(sh, d)) return;
     __shared__ double2 a[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     __shared__ double2 b[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     const int n = (int)d.n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = make_double2(f[i], 0.0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = mg_to_c(f[i]);
     __syncthreads();
     dft_axis(a, b, d.nx, d.ny, d.nz, 0, -1.0);
     __syncthreads();
@@ -162,11 +226,18 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const do
     __syncthreads();
     for (int o = threadIdx.x; o < n; o += blockDim.x) {
         const int x = o % d.nx, y = (o / d.nx) % d.ny, z = o / (d.nx * d.ny);
-        const double lam = d.cx * (2.0 - 2.0 * cospi(2.0 * x / d.nx)) +
-                           d.cy * (2.0 - 2.0 * cospi(2.0 * y / d.ny)) +
-                           d.cz * (2.0 - 2.0 * cospi(2.0 * z / d.nz));
-        const double s = (x == 0 && y == 0 && z == 0) ? 0.0 : 1.0 / (lam * (double)n);
-        b[o] = make_double2(b[o].x * s, b[o].y * s);
+        const double lr = d.cx * (2.0 - 2.0 * cospi(2.0 * x / d.nx)) +
+                          d.cy * (2.0 - 2.0 * cospi(2.0 * y / d.ny)) +
+                          d.cz * (2.0 - 2.0 * cospi(2.0 * z / d.nz)) + d.kre;
+        const double li = d.kim, den = lr * lr + li * li;
+        double2 v = b[o];
+        if (den == 0.0) {
+            v = make_double2(0.0, 0.0);
+        } else {   // v / (lr + i li) / n
+            const double sr = lr / (den * n), si = -li / (den * n);
+            v = make_double2(v.x * sr - v.y * si, v.x * si + v.y * sr);
+        }
+        b[o] = v;
     }
     __syncthreads();
     dft_axis(b, a, d.nx, d.ny, d.nz, 0, 1.0);
@@ -175,35 +246,38 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const do
     __syncthreads();
     dft_axis(b, a, d.nx, d.ny, d.nz, 2, 1.0);
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = a[i].x;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mg_from_c(a[i], u[i]);
 }
 
-int vcycle(Multigrid &mg, int l, hipStream_t s) {
+template <typename T>
+int vcycle(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
     MgLevel &L = mg.lv[l];
-    const MgDims d = dims_of(L);
+    const MgDims d = dims_of(L, kappa);
     const int nb = blocks_for(L.n);
+    T *f = (T *)L.f;
     if (l + 1 == (int)mg.lv.size()) {
-        hipLaunchKernelGGL(mg_coarse_solve, dim3(1), dim3(kMgThreads), 0, s, d, L.f, L.u);
+        hipLaunchKernelGGL(mg_coarse_solve<T>, dim3(1), dim3(kMgThreads), 0, s, d, f, (T *)L.u, sh);
         OFDFT_CHECK_HIP(hipGetLastError());
         return OFDFT_OK;
     }
     // 2 nu sweeps in all; the first writes t, so after an even count the
     // result is back in u
-    double *cur = L.t, *nxt = L.u;
-    hipLaunchKernelGGL(mg_smooth0, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur);
+    T *cur = (T *)L.t, *nxt = (T *)L.u;
+    hipLaunchKernelGGL(mg_smooth0<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, sh);
     for (int k = 1; k < mg.nu; ++k) {
-        hipLaunchKernelGGL(mg_smooth, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur, nxt);
+        hipLaunchKernelGGL(mg_smooth<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, nxt, sh);
         std::swap(cur, nxt);
     }
-    hipLaunchKernelGGL(mg_residual, dim3(nb), dim3(kMgThreads), 0, s, d, L.f, cur, L.r);
+    hipLaunchKernelGGL(mg_residual<T>, dim3(nb), dim3(kMgThreads), 0, s, d, f, cur, (T *)L.r, sh);
     MgLevel &C = mg.lv[l + 1];
-    const MgDims cd = dims_of(C);
-    hipLaunchKernelGGL(mg_restrict, dim3(blocks_for(C.n)), dim3(kMgThreads), 0, s, d, cd, L.r, C.f);
+    const MgDims cd = dims_of(C, kappa);
+    hipLaunchKernelGGL(mg_restrict<T>, dim3(blocks_for(C.n)), dim3(kMgThreads), 0, s, d, cd, (const T *)L.r,
+                       (T *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
-    OFDFT_TRY(vcycle(mg, l + 1, s));
-    hipLaunchKernelGGL(mg_prolong_add, dim3(nb), dim3(kMgThreads), 0, s, d, cd, C.u, cur);
+    OFDFT_TRY(vcycle<T>(mg, l + 1, kappa, sh, s));
+    hipLaunchKernelGGL(mg_prolong_add<T>, dim3(nb), dim3(kMgThreads), 0, s, d, cd, (const T *)C.u, cur, sh);
     for (int k = 0; k < mg.nu; ++k) {
-        hipLaunchKernelGGL(mg_smooth, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, L.f, cur, nxt);
+        hipLaunchKernelGGL(mg_smooth<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, nxt, sh);
         std::swap(cur, nxt);
     }
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -212,8 +286,10 @@ int vcycle(Multigrid &mg, int l, hipStream_t s) {
 
 }  // namespace
 
-int mg_create(Multigrid &mg, const ofdft_grid &g) {
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes) {
     mg_free(mg);
+    if (elem_bytes != 8 && elem_bytes != 16) return OFDFT_INVALID_ARG;
+    mg.elem = elem_bytes;
     MgLevel L;
     L.nx = g.nx;
     L.ny = g.ny;
@@ -241,8 +317,8 @@ int mg_create(Multigrid &mg, const ofdft_grid &g) {
     }
     for (size_t l = 0; l < mg.lv.size(); ++l) {
         MgLevel &M = mg.lv[l];
-        const size_t b = sizeof(double) * (size_t)M.n;
-        double **own[4] = {&M.t, &M.r, &M.u, &M.f};
+        const size_t b = (size_t)elem_bytes * (size_t)M.n;
+        void **own[4] = {&M.t, &M.r, &M.u, &M.f};
         const int count = l == 0 ? 2 : 4;          // level 0 uses the caller's r and z
         for (int k = 0; k < count; ++k) {
             void *p = nullptr;
@@ -252,7 +328,7 @@ int mg_create(Multigrid &mg, const ofdft_grid &g) {
                 return OFDFT_NO_MEMORY;
             }
             mg.allocs.push_back(p);
-            *own[k] = (double *)p;
+            *own[k] = p;
         }
     }
     return OFDFT_OK;
@@ -265,14 +341,30 @@ void mg_free(Multigrid &mg) {
 }
 
 int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s) {
-    if (mg.lv.empty()) return OFDFT_INVALID_ARG;
+    if (mg.lv.empty() || mg.elem != 8) return OFDFT_INVALID_ARG;
     MgLevel &L0 = mg.lv[0];
     L0.f = const_cast<double *>(r);
     L0.u = z;
-    // algorithmic bytes of the fine level (the coarser ones add about 1/7):
-    // 2 nu sweeps and a residual (24 B/pt each), restriction (8), prolongation (16)
-    ProfScope ps(K_MULTIGRID, (double)L0.n * (24.0 * (2 * mg.nu + 1) + 24.0) * 8.0 / 7.0, s);
-    return vcycle(mg, 0, s);
+    ProfScope ps(K_MULTIGRID, mg_cycle_bytes(mg), s);
+    return vcycle<double>(mg, 0, make_double2(0.0, 0.0), MgShift{nullptr, nullptr}, s);
+}
+
+int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
+                     hipStream_t s) {
+    if (mg.lv.empty() || mg.elem != 16 || !kappa) return OFDFT_INVALID_ARG;
+    MgLevel &L0 = mg.lv[0];
+    L0.f = const_cast<double2 *>(r);
+    L0.u = z;
+    return vcycle<double2>(mg, 0, make_double2(0.0, 0.0), MgShift{kappa, run}, s);
+}
+
+// Algorithmic bytes of one cycle on the fine level (the coarser levels add
+// about 1/7): 2 nu sweeps and the residual read f, u and write one array,
+// restriction reads r, prolongation reads and writes u.
+double mg_cycle_bytes(const Multigrid &mg) {
+    if (mg.lv.empty()) return 0.0;
+    const double e = (double)mg.elem;
+    return (double)mg.lv[0].n * e * (3.0 * (2 * mg.nu + 1) + 3.0) * 8.0 / 7.0;
 }
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible

@@ -1,14 +1,15 @@
 // Geometric multigrid preconditioner for the periodic Poisson solve (the
 // real-space preconditioner the paper's conclusion calls for, Section 5.5).
 //
-// M approximates the inverse of the 12th-order -L_h with one V(nu, nu) cycle
-// of the second-order 7-point operator: damped Jacobi smoothing, full
+// M approximates the inverse of the 12th-order -L_h (+ kappa for the shifted
+// systems) with one V(nu, nu) cycle of the second-order 7-point operator
+// (+ kappa): damped Jacobi smoothing, full
 // weighting restriction (R = P^T / 8), trilinear prolongation, every axis
 // halved per level, and an exact DFT solve on the coarsest grid (at most 16
 // points per axis).  The cycle is a fixed linear operator, symmetric and
-// positive definite on zero-mean vectors, so CG preconditioned by it
-// converges at a rate set by the spectral equivalence of the two operators,
-// independent of the grid size.
+// positive definite on zero-mean vectors (complex symmetric for a complex
+// shift), so CG (COCG) preconditioned by it converges at a rate set by the
+// spectral equivalence of the two operators, independent of the grid size.
 #pragma once
 
 #include <vector>
@@ -21,23 +22,34 @@ struct MgLevel {
     int nx = 0, ny = 0, nz = 0;
     double cx = 0, cy = 0, cz = 0;   // 1 / h_a^2
     int64_t n = 0;
-    double *u = nullptr, *t = nullptr, *f = nullptr, *r = nullptr;
+    void *u = nullptr, *t = nullptr, *f = nullptr, *r = nullptr;   // FP64 or complex128
 };
 
 struct Multigrid {
     std::vector<MgLevel> lv;
     int nu = 2;                  // Jacobi sweeps before and after the coarse correction
     double omega = 0.8;          // Jacobi damping
+    int elem = 8;                // element bytes: 8 (FP64) or 16 (complex128)
     std::vector<void *> allocs;
 };
 
 constexpr int kMgCoarseMax = 16;     // coarsest grid: at most this many points per axis
 
-// Hierarchy for grid g: halve every axis while all are even and one exceeds
-// kMgCoarseMax.  INVALID_ARG if the coarsest grid would be larger than that.
-int mg_create(Multigrid &mg, const ofdft_grid &g);
+// Hierarchy for grid g with FP64 (elem_bytes 8) or complex128 (16) levels:
+// halve every axis while all are even and one exceeds kMgCoarseMax.
+// INVALID_ARG if the coarsest grid would be larger than that.
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes);
 void mg_free(Multigrid &mg);
-// z = M r (device FP64 arrays of the fine grid; z must not alias r).
+// z = M r for -Delta (device FP64 arrays of the fine grid; z must not alias r).
 int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s);
+// z = M r for -Delta + kappa (complex128 arrays).  kappa points to device
+// memory holding {Re, Im} and is read by every launch, so a captured launch
+// sequence follows later changes of the shift; if `run` is given, every
+// kernel returns at once unless *run == 0 (a converged system of a batch).
+// Not accounted in the profile (the caller accounts cycles).
+int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
+                     hipStream_t s);
+// Algorithmic HBM bytes of one cycle.
+double mg_cycle_bytes(const Multigrid &mg);
 
 }  // namespace ofdft

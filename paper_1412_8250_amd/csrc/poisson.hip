@@ -434,7 +434,7 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
     if (st == OFDFT_OK && mode == OFDFT_MULTIGRID) {
         s->mg = new (std::nothrow) Multigrid();
         if (!s->mg) st = OFDFT_NO_MEMORY;
-        else st = mg_create(*s->mg, *grid);
+        else st = mg_create(*s->mg, *grid, 8);
         if (st == OFDFT_OK && hipMalloc(&s->z, sizeof(double) * npoints(*grid)) != hipSuccess) {
             set_error("ofdft_poisson_create: out of device memory");
             st = OFDFT_NO_MEMORY;

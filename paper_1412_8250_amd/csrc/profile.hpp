@@ -36,7 +36,10 @@ struct ProfScope {
     int cls;
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(int c, double bytes, hipStream_t st) : cls(c), s(st) {
+    // active = false: nothing is accounted or recorded (launches captured
+    // into a graph, accounted per replay by the caller)
+    ProfScope(int c, double bytes, hipStream_t st, bool active = true) : cls(c), s(st) {
+        if (!active) return;
         prof_add(c, bytes);
         if (prof_timed(c)) {
             a = prof_event();

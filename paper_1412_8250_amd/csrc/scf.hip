@@ -272,6 +272,9 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         if ((rc = ofdft_batch_create(4, grids, p->radius,
                                      p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
             return fail(rc);
+        if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
+            (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
+            return fail(rc);
         for (int j = 0; j < 8; ++j)
             if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     }

@@ -22,10 +22,12 @@ def large():
     return inputs.large_cell()
 
 
-def test_shifted_batch_320(large):
-    """The 8 K_00 systems of the large cell, batched as in the SCF step, to 1e-8."""
+@pytest.mark.parametrize("precond", [ofd.PRECOND_NONE, ofd.PRECOND_MULTIGRID])
+def test_shifted_batch_320(large, precond):
+    """The 8 K_00 systems of the large cell to 1e-8, plain or preconditioned
+    by the multigrid cycle (the benchmark's form)."""
     torch = torch_cuda()
-    announce("shifted batch 320^3")
+    announce("shifted batch 320^3", precond)
     w = large
     h = w.cell.h
     ks = kernel.shifts(w.cell.n_electrons, w.cell.volume)
@@ -35,6 +37,7 @@ def test_shifted_batch_320(large):
     rhs = [(kernel.P00[j % 4] * base[j // 4]).contiguous() for j in range(8)]
     xs = [torch.zeros_like(f) for f in rhs]
     b = ofd.HelmholtzBatch([w.rho.shape] * 8, [h] * 8, 6, ofd.C128)
+    b.set_preconditioner(precond)
     status, st = b.solve(list(ks), rhs, xs, 1e-8)
     for j in range(8):
         announce("shifted batch 320^3 system", j, st[j]["iters"])

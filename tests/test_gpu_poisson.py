@@ -189,6 +189,24 @@ def test_multigrid_preconditioner_is_symmetric_positive():
     assert (Mab - (2.0 * Ma - 3.0 * Mb)).abs().max().item() <= 1e-12 * Mab.abs().max().item()
 
 
+def test_multigrid_cycle_matches_reference():
+    """The device V-cycle equals the reference cycle value by value."""
+    torch = torch_cuda()
+    from oracle import multigrid
+    for shape, h in (((48, 32, 64), (0.4, 0.5, 0.45)), ((96, 96, 96), (0.390625,) * 3)):
+        announce("poisson mg cycle", shape)
+        s = ofd.PoissonSolver(shape, h, 6, ofd.MULTIGRID)
+        rng = np.random.default_rng(6)
+        r = rng.normal(size=shape)
+        r -= r.mean()
+        rd = to_dev(r)
+        zd = torch.empty_like(rd)
+        s.apply_preconditioner(rd, zd)
+        ref = multigrid.vcycle(r, h)
+        assert np.abs(to_host(zd) - ref).max() <= 1e-12 * np.abs(ref).max()
+        s.close()
+
+
 def test_multigrid_iterations_do_not_grow_with_the_grid():
     torch = torch_cuda()
     its = []

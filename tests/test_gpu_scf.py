@@ -80,12 +80,15 @@ def test_jellium_fixed_point():
         assert v.abs().max().item() < 1e-10
 
 
-def test_lr_kernel_step_matches_oracle():
-    """TFW + K_00 kernel term (lambda = 1, mu = 1): the paper's shifts, one step."""
+@pytest.mark.parametrize("pmode,hpre", [(ofd.PLAIN_F64, ofd.PRECOND_NONE),
+                                        (ofd.MULTIGRID, ofd.PRECOND_MULTIGRID)])
+def test_lr_kernel_step_matches_oracle(pmode, hpre):
+    """TFW + K_00 kernel term (lambda = 1, mu = 1): the paper's shifts, two
+    steps, with plain or multigrid-preconditioned Poisson and shifted solves."""
     torch = torch_cuda()
-    announce("scf lr kernel step")
+    announce("scf lr kernel step", pmode, hpre)
     w = inputs.small_cell()
-    ctx = _ctx(w, lam=1.0, mu=1, history=7, zeta=0.3)
+    ctx = _ctx(w, lam=1.0, mu=1, history=7, zeta=0.3, poisson_mode=pmode, helmholtz_precond=hpre)
     orc = scf.SCF(w.rho, w.b, w.cell.h, w.cell.n_electrons, w.cell.volume,
                   scf.Params(lam=1.0, mu=1, history=7, zeta=0.3))
     vd = torch.empty(w.rho.shape, dtype=torch.float64, device="cuda")
