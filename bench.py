@@ -48,6 +48,8 @@ def parse():
                     help="SCF Poisson solve by plain FP64 CG instead of multigrid-preconditioned CG")
     ap.add_argument("--plain-helmholtz", action="store_true",
                     help="shifted solves by plain COCG instead of multigrid-preconditioned COCG")
+    ap.add_argument("--plain-density", action="store_true",
+                    help="density update by Algorithm 1 as printed instead of the multigrid-preconditioned NLCG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
     ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy"], default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
@@ -171,7 +173,8 @@ def main():
     scf = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3,
                   u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8,
                   poisson_mode=ofd.PLAIN_F64 if args.plain_poisson else ofd.MULTIGRID,
-                  helmholtz_precond=ofd.PRECOND_NONE if args.plain_helmholtz else ofd.PRECOND_MULTIGRID)
+                  helmholtz_precond=ofd.PRECOND_NONE if args.plain_helmholtz else ofd.PRECOND_MULTIGRID,
+                  u_precond=ofd.PRECOND_NONE if args.plain_density else ofd.PRECOND_MULTIGRID)
     torch.cuda.synchronize()
     log(f"context + v0 in {time.perf_counter() - t0:.1f}s")
 
@@ -289,7 +292,8 @@ def main():
                                "120 bohr, 320^3 grid, 12th-order FD, TFW + K_00 kernel, "
                                "Poisson + 8 shifted solves to 1e-8, Anderson m=7; "
                                + ("plain" if args.plain_poisson else "multigrid-preconditioned") + " CG, "
-                               + ("plain" if args.plain_helmholtz else "multigrid-preconditioned") + " COCG"
+                               + ("plain" if args.plain_helmholtz else "multigrid-preconditioned") + " COCG, "
+                               + ("plain" if args.plain_density else "multigrid-preconditioned") + " NLCG"
                    if args.workload == "large"
                    else "small cell SCF step: 4-atom FCC cell, 16^3 grid",
                    "grid": list(shape), "value_definition": "algorithmic HBM bytes / step time",

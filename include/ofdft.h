@@ -236,6 +236,14 @@ typedef struct {
     int max_iter;              /* Krylov iteration cap per solve                          */
     double line_tol;           /* line search: relative tolerance on the step, 0 = 1e-8  */
     int helmholtz_precond;     /* OFDFT_PRECOND_NONE or OFDFT_PRECOND_MULTIGRID (C128)   */
+    int u_precond;             /* density update: OFDFT_PRECOND_NONE (Algorithm 1 as
+                                  printed) or OFDFT_PRECOND_MULTIGRID (lambda > 0): the
+                                  steepest-descent direction r becomes z = M r projected
+                                  on <u, z> = 0, M one multigrid cycle of -Delta +
+                                  2 sigma / lambda with sigma = V_TF(N_e / volume);
+                                  Polak-Ribiere xi = <r - r_prev, z> / <r_prev, z_prev>.
+                                  Same minimiser, several times fewer iterations; every
+                                  axis must halve evenly down to at most 16 points     */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

@@ -50,7 +50,7 @@ class ScfParams(ctypes.Structure):
                 ("u_max_iter", ctypes.c_int), ("poisson_tol", ctypes.c_double),
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
-                ("helmholtz_precond", ctypes.c_int)]
+                ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int)]
 
 
 _lib = None
@@ -366,7 +366,8 @@ class SCF:
                  history: int = 7, zeta: float = 0.3, u_tol: float = 1e-10, n_restart: int = 50,
                  u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
-                 radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE, stream=None):
+                 radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
+                 u_precond: int = PRECOND_NONE, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -376,6 +377,7 @@ class SCF:
         p.helmholtz_tol, p.helmholtz_dtype, p.max_iter = float(helmholtz_tol), int(helmholtz_dtype), int(max_iter)
         p.line_tol = float(line_tol)
         p.helmholtz_precond = int(helmholtz_precond)
+        p.u_precond = int(u_precond)
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

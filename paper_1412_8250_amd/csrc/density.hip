@@ -5,15 +5,26 @@
 //   H u = -(lambda/2) L_h u + (V_TF + V_xc + v) u.
 //
 // GPU work per iteration (FP64):
-//   Ka  stencil pass on u: L u and H u; totals <u,Hu>, <u,Lu>, <u,u>; eta on device
+//   Ka  stencil pass on u: H u; totals <u,Hu>, <u,Lu>, <u,u>; eta on device
 //   Kb  r = -2 (H u - eta u); totals <r,r>, <r,r_prev>
 //   Kd  stencil pass on the new direction d = r + xi d_prev (formed while loading);
-//       stores d and L d; totals <u,d>, <d,d>, <u,Ld>, <d,Ld>
+//       stores d; totals <u,d>, <d,d>, <u,Ld>, <d,Ld>, <Hu,d>
 //   Ke  (per line-search probe) sum of (V_TF+V_xc+v)(rho_s) w (d - t w), w = u + s d
 //   Kf  u <- sqrt(N_e) (u + s d) / ||u + s d||
 // The line search finds the root of dE/ds with Brent's method; the von
 // Weizsacker part of dE/ds is a quadratic in s built from the Kd/Ka totals, so
 // each probe reads only u, d and v.
+//
+// Optional preconditioning (not in the paper; its conclusion calls for
+// real-space preconditioners, Section 5.5): the steepest-descent direction r
+// is replaced by z = M r projected onto the tangent space of the constraint,
+// z~ = z - (<u,z>/<u,u>) u, with M one multigrid cycle of -Delta + 2 sigma /
+// lambda, sigma = V_TF of the mean density (the scale of the local part of
+// the energy's second derivative); Polak-Ribiere becomes
+// xi = <r - r_prev, z~> / <r_prev, z~_prev>.  M is symmetric positive
+// definite, so z~ is a descent direction and the minimiser is unchanged;
+// the iteration count drops several-fold because M removes the h^-2 spread
+// of the -(lambda/2) L_h part of the Hessian.
 #include <algorithm>
 #include <cmath>
 
@@ -26,13 +37,13 @@ namespace {
 
 // device scalar slots
 enum {
-    S_UHU = 0, S_ULU, S_UU, S_ETA, S_RR, S_RRP, S_UD, S_DD, S_ULD, S_DLD, S_EVAL, S_COUNT
+    S_UHU = 0, S_ULU, S_UU, S_ETA, S_RR, S_RRP, S_UD, S_DD, S_ULD, S_DLD, S_EVAL, S_COUNT,
+    S_DOTS = 24     // 5 slots: <u,z>, <r,z>, <r_prev,z>, <u,r>, <u,r_prev>
 };
 
 struct EpiHu {
     const double *__restrict__ v;
     double *__restrict__ Hu;
-    double *__restrict__ Lu;
     double *dsc;
     double *partials;
     unsigned int *counter;
@@ -45,7 +56,6 @@ struct EpiHu {
         const double rho = c * c;
         const double vl = rho > 0.0 ? v_local(rho) : 0.0;
         const double hu = ::fma(-half_lam, s, (vl + vv[q]) * c);
-        Lu[i] = s;
         Hu[i] = hu;
         a0 = ::fma(c, hu, a0);
         a1 = ::fma(c, s, a1);
@@ -82,17 +92,43 @@ struct ResidOp {        // r = -2 (Hu - eta u); totals {<r,r>, <r,r_prev>}
     }
 };
 
-struct LoadDir {        // d = r + xi d_prev (xi = 0: steepest descent, with d_prev := r)
+// d = r + xi d_prev (xi = 0: steepest descent, with d_prev := r); with the
+// preconditioner r is z and the projection -cu u is added (u given).
+struct LoadDir {
     const double *__restrict__ r;
+    const double *__restrict__ u;
     const double *__restrict__ d_prev;
-    double xi;
+    double cu, xi;
     __device__ void prepare() {
         if (xi == 0.0) d_prev = r;
     }
-    __device__ double operator()(int64_t i) const { return ::fma(xi, d_prev[i], r[i]); }
+    __device__ double operator()(int64_t i) const {
+        const double base = u ? ::fma(-cu, u[i], r[i]) : r[i];
+        return ::fma(xi, d_prev[i], base);
+    }
 };
 
-// d = r + xi d_prev, L d; totals {<u,d>, <d,d>, <u,L d>, <d,L d>, <H u,d>}.
+struct DotsOp {         // totals {<u,z>, <r,z>, <r_prev,z>, <u,r>, <u,r_prev>}
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 32;
+    const double *u, *z, *r, *r_prev;
+    int have_prev;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[5]) const {
+        const double ui = u[i], zi = z[i], ri = r[i];
+        acc[0] = ::fma(ui, zi, acc[0]);
+        acc[1] = ::fma(ri, zi, acc[1]);
+        acc[3] = ::fma(ui, ri, acc[3]);
+        if (have_prev) {
+            const double pi = r_prev[i];
+            acc[2] = ::fma(pi, zi, acc[2]);
+            acc[4] = ::fma(ui, pi, acc[4]);
+        }
+    }
+};
+
+// d (from the loader), L d; totals {<u,d>, <d,d>, <u,L d>, <d,L d>, <H u,d>}.
 // The last gives the line-search slope at s = 0 without an evaluation pass:
 // with u normalised, (V_loc + v) u = H u + (lambda/2) L u, and the lambda
 // terms of dE/ds cancel, leaving dE/ds(0) ~ <H u, d> - t <u, H u>.
@@ -100,7 +136,6 @@ struct EpiLd {
     const double *__restrict__ u;
     const double *__restrict__ Hu;
     double *__restrict__ d;
-    double *__restrict__ Ld;
     double *totals;
     double *partials;
     unsigned int *counter;
@@ -114,7 +149,6 @@ struct EpiLd {
     __device__ void point(int q, int64_t i, double c, double s) {
         const double ui = uv[q];
         d[i] = c;
-        Ld[i] = s;
         a0 = ::fma(ui, c, a0);
         a1 = ::fma(c, c, a1);
         a2 = ::fma(ui, s, a2);
@@ -239,8 +273,9 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     const double sqn = std::sqrt(ne);
     double *r_cur = s->rA, *r_prev = s->rB, *d_cur = s->dA, *d_prev = s->dB;
     double *tot = s->dsc + 16;          // Kd totals
+    const bool pre = s->umg != nullptr;
     int q = 0;
-    double rr_prev = 0.0;
+    double rr_prev = 0.0, rz_prev = 0.0;
     res = INFINITY;
     eta = 0.0;
     double s_prev = s->s_prev;
@@ -249,9 +284,9 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     for (;;) {
         // Ka: H u
         OFDFT_TRY(stencil_pass(g, s->coef, LoadPlain<double>{u},
-                               EpiHu{v, s->Hu, s->Lu, s->dsc, s->rb.partials, s->rb.counter, 0.5 * lam,
+                               EpiHu{v, s->Hu, s->dsc, s->rb.partials, s->rb.counter, 0.5 * lam,
                                      dv / ne, 0, 0, 0},
-                               st, 32));
+                               st, 24));
         // Kb: r
         ResidOp ro{s->Hu, u, r_prev, r_cur, s->dsc, q > 0, 0.0};
         OFDFT_TRY((launch_reduce<2>(n, ro, StoreTotals<2>{s->dsc + S_RR}, s->rb, st)));
@@ -262,14 +297,29 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         res = 0.5 * std::sqrt(rr / uu);
         if (!std::isfinite(res)) return OFDFT_NONFINITE;
         if (res <= s->p.u_tol || q >= maxit) break;
-        double xi = 0.0;
-        if (q > 0) xi = (rr - h[S_RRP]) / rr_prev;    // <r - r_prev, r> / <r_prev, r_prev>
+        double xi = 0.0, cu = 0.0, rz = 0.0;
+        const double *base = r_cur;
+        if (pre) {
+            // z = M r, then the Polak-Ribiere terms of the projected z~ = z - cu u
+            OFDFT_TRY(mg_apply(*s->umg, r_cur, s->z, st, s->u_kappa));
+            DotsOp dop{u, s->z, r_cur, r_prev, q > 0};
+            OFDFT_TRY((launch_reduce<5>(n, dop, StoreTotals<5>{s->dsc + S_DOTS}, s->rb, st)));
+            OFDFT_TRY(fetch(s, S_DOTS, 5, st));
+            const double *t = s->hsc + S_DOTS;
+            cu = t[0] / uu;
+            rz = t[1] - cu * t[3];                                   // <r, z~>
+            if (q > 0) xi = (rz - (t[2] - cu * t[4])) / rz_prev;     // <r - r_prev, z~> / <r_prev, z~_prev>
+            if (!std::isfinite(rz) || !(rz > 0.0)) return OFDFT_NONFINITE;
+            base = s->z;
+        } else if (q > 0) {
+            xi = (rr - h[S_RRP]) / rr_prev;    // <r - r_prev, r> / <r_prev, r_prev>
+        }
         if (q % nres == 0 || !(xi > 0.0)) xi = 0.0;
-        // Kd: d = r + xi d_prev, L d
+        // Kd: d = r + xi d_prev (or z~ + xi d_prev), L d
         auto make_dir = [&](double xiv) -> int {
-            OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{r_cur, d_prev, xiv},
-                                   EpiLd{u, s->Hu, d_cur, s->Ld, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0, 0},
-                                   st, 48));
+            OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{base, pre ? u : nullptr, d_prev, cu, xiv},
+                                   EpiLd{u, s->Hu, d_cur, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0, 0},
+                                   st, 40));
             OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 16, tot, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
             OFDFT_CHECK_HIP(hipStreamSynchronize(st));
             return OFDFT_OK;
@@ -332,6 +382,7 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
         s_prev = std::fabs(sstar);
         rr_prev = rr;
+        rz_prev = rz;
         std::swap(r_cur, r_prev);
         std::swap(d_cur, d_prev);
         ++q;

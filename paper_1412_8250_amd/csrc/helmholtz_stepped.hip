@@ -306,7 +306,9 @@ int precondition(ofdft_batch *b, hipStream_t s, bool timed) {
         const double *kap = &b->d_sys[j].kre;      // {kre, kim} of system j (device)
         const int *run = &b->d_step[j].done;
         if (timed) {
-            ProfScope ps(K_MULTIGRID, mg_cycle_bytes(*mg), s);
+            // bytes are added after the pass from the iteration counts (a
+            // converged system's cycle launches return at once)
+            ProfScope ps(K_MULTIGRID, 0.0, s);
             OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
         } else {
             OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));

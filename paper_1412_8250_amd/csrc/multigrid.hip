@@ -25,7 +25,25 @@ MgDims dims_of(const MgLevel &L, double2 kappa) {
     return MgDims{L.nx, L.ny, L.nz, L.cx, L.cy, L.cz, 2.0 * (L.cx + L.cy + L.cz), kappa.x, kappa.y, L.n};
 }
 
-int blocks_for(int64_t n) { return (int)std::min<int64_t>((n + kMgThreads - 1) / kMgThreads, 8192); }
+// Launch geometry: 64 x 4 threads over (x, y), one z plane per block row of
+// the grid, so point coordinates come from the launch indices (no divisions).
+constexpr int kMgBX = 64, kMgBY = 4;
+static_assert(kMgBX * kMgBY == kMgThreads, "block shape");
+
+dim3 mg_grid(int nx, int ny, int nz) { return dim3((nx + kMgBX - 1) / kMgBX, (ny + kMgBY - 1) / kMgBY, nz); }
+
+struct MgPt {
+    int x, y, z;
+    int64_t i;
+};
+
+__device__ inline bool mg_point(int nx, int ny, MgPt &p) {
+    p.x = blockIdx.x * kMgBX + threadIdx.x;
+    p.y = blockIdx.y * kMgBY + threadIdx.y;
+    p.z = blockIdx.z;
+    p.i = ((int64_t)p.z * ny + p.y) * nx + p.x;
+    return p.x < nx && p.y < ny;
+}
 
 // Element arithmetic for real (Poisson) and complex (shifted) levels.
 __device__ inline double mg_scale(double2 s, double v) { return s.x * v; }
@@ -37,20 +55,17 @@ __device__ inline double2 mg_axpy(double a, double2 x, double2 y) {
     return make_double2(::fma(a, x.x, y.x), ::fma(a, x.y, y.y));
 }
 
-// (A u)_i of the periodic 7-point operator A = -Delta_h + kappa (second order).
+// (A u) at p for the periodic 7-point operator A = -Delta_h + kappa (second order).
 template <typename T>
-__device__ inline T apply7(const T *__restrict__ u, const MgDims &d, int64_t i) {
+__device__ inline T apply7(const T *__restrict__ u, const MgDims &d, const MgPt &p) {
     using V = VT<T>;
-    const int64_t nxy = (int64_t)d.nx * d.ny;
-    const int x = (int)(i % d.nx);
-    const int y = (int)((i / d.nx) % d.ny);
-    const int z = (int)(i / nxy);
-    const int64_t xp = x + 1 == d.nx ? i - x : i + 1;
-    const int64_t xm = x == 0 ? i + d.nx - 1 : i - 1;
-    const int64_t yp = y + 1 == d.ny ? i - (int64_t)y * d.nx : i + d.nx;
-    const int64_t ym = y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
-    const int64_t zp = z + 1 == d.nz ? i - (int64_t)z * nxy : i + nxy;
-    const int64_t zm = z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
+    const int64_t i = p.i, nxy = (int64_t)d.nx * d.ny;
+    const int64_t xp = p.x + 1 == d.nx ? i - p.x : i + 1;
+    const int64_t xm = p.x == 0 ? i + d.nx - 1 : i - 1;
+    const int64_t yp = p.y + 1 == d.ny ? i - (int64_t)p.y * d.nx : i + d.nx;
+    const int64_t ym = p.y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
+    const int64_t zp = p.z + 1 == d.nz ? i - (int64_t)p.z * nxy : i + nxy;
+    const int64_t zm = p.z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
     const T c = u[i];
     T a = V::mul(d.diag, c);
     a = mg_axpy(-d.cx, V::add(u[xp], u[xm]), a);
@@ -84,14 +99,19 @@ __device__ inline double2 jacobi_factor(const MgDims &d, double w) {
     return make_double2(w * re / den, -w * im / den);
 }
 
+// The two pre-smoothing sweeps from u = 0 in one pass: with the Jacobi factor
+// s = omega / (diag + kappa), u1 = s f and u2 = u1 + s (f - A u1) = s (2 f - s A f).
 template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_smooth0(MgDims d, double w, const T *__restrict__ f,
-                                                         T *__restrict__ u, MgShift sh) {
+__global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const T *__restrict__ f,
+                                                      T *__restrict__ u, MgShift sh) {
     if (!take_shift(sh, d)) return;
+    MgPt p;
+    if (!mg_point(d.nx, d.ny, p)) return;
+    using V = VT<T>;
     const double2 s = jacobi_factor(d, w);
-    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
-         i += (int64_t)gridDim.x * kMgThreads)
-        u[i] = mg_scale(s, f[i]);
+    const T af = apply7(f, d, p);
+    const T two_f = V::add(f[p.i], f[p.i]);
+    u[p.i] = mg_scale(s, V::sub(two_f, mg_scale(s, af)));
 }
 
 // t = u + omega (f - A u) / (diag + kappa)
@@ -100,11 +120,11 @@ __global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, cons
                                                         const T *__restrict__ u, T *__restrict__ t,
                                                         MgShift sh) {
     if (!take_shift(sh, d)) return;
+    MgPt p;
+    if (!mg_point(d.nx, d.ny, p)) return;
     using V = VT<T>;
     const double2 s = jacobi_factor(d, w);
-    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
-         i += (int64_t)gridDim.x * kMgThreads)
-        t[i] = V::add(u[i], mg_scale(s, V::sub(f[i], apply7(u, d, i))));
+    t[p.i] = V::add(u[p.i], mg_scale(s, V::sub(f[p.i], apply7(u, d, p))));
 }
 
 // r = f - A u
@@ -113,9 +133,9 @@ __global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const T *__r
                                                           const T *__restrict__ u, T *__restrict__ r,
                                                           MgShift sh) {
     if (!take_shift(sh, d)) return;
-    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < d.n;
-         i += (int64_t)gridDim.x * kMgThreads)
-        r[i] = VT<T>::sub(f[i], apply7(u, d, i));
+    MgPt p;
+    if (!mg_point(d.nx, d.ny, p)) return;
+    r[p.i] = VT<T>::sub(f[p.i], apply7(u, d, p));
 }
 
 // Full weighting: fc[I] = sum over the 27 fine points around 2I of
@@ -124,60 +144,59 @@ template <typename T>
 __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const T *__restrict__ r,
                                                           T *__restrict__ fc, MgShift sh) {
     if (sh.run && *sh.run != 0) return;
+    MgPt P;
+    if (!mg_point(cd.nx, cd.ny, P)) return;
     using V = VT<T>;
     const int64_t fnxy = (int64_t)fd.nx * fd.ny;
-    for (int64_t I = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; I < cd.n;
-         I += (int64_t)gridDim.x * kMgThreads) {
-        const int X = (int)(I % cd.nx), Y = (int)((I / cd.nx) % cd.ny), Z = (int)(I / ((int64_t)cd.nx * cd.ny));
-        T acc = V::zero();
+    int xs[3], ys[3], zs[3];
+    xs[0] = P.x == 0 ? fd.nx - 1 : 2 * P.x - 1;
+    xs[1] = 2 * P.x;
+    xs[2] = 2 * P.x + 1;         // fine axes are even, so 2X + 1 < n
+    ys[0] = P.y == 0 ? fd.ny - 1 : 2 * P.y - 1;
+    ys[1] = 2 * P.y;
+    ys[2] = 2 * P.y + 1;
+    zs[0] = P.z == 0 ? fd.nz - 1 : 2 * P.z - 1;
+    zs[1] = 2 * P.z;
+    zs[2] = 2 * P.z + 1;
+    T acc = V::zero();
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int z = (2 * Z + dz + fd.nz) % fd.nz;
-            const double wz = dz == 0 ? 1.0 : 0.5;
+    for (int c = 0; c < 3; ++c) {
+        const double wz = c == 1 ? 1.0 : 0.5;
 #pragma unroll
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int y = (2 * Y + dy + fd.ny) % fd.ny;
-                const double wy = dy == 0 ? wz : 0.5 * wz;
-                const int64_t row = (int64_t)z * fnxy + (int64_t)y * fd.nx;
+        for (int b = 0; b < 3; ++b) {
+            const double wy = b == 1 ? wz : 0.5 * wz;
+            const int64_t row = (int64_t)zs[c] * fnxy + (int64_t)ys[b] * fd.nx;
 #pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = (2 * X + dx + fd.nx) % fd.nx;
-                    acc = mg_axpy(dx == 0 ? wy : 0.5 * wy, r[row + x], acc);
-                }
-            }
+            for (int a = 0; a < 3; ++a) acc = mg_axpy(a == 1 ? wy : 0.5 * wy, r[row + xs[a]], acc);
         }
-        fc[I] = V::mul(0.125, acc);
     }
+    fc[P.i] = V::mul(0.125, acc);
 }
 
-// Trilinear prolongation added to u: fine point i takes coarse i/2 (even i)
+// Trilinear prolongation added to u: fine index i takes coarse i/2 (even i)
 // or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.
 template <typename T>
 __global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const T *__restrict__ uc,
                                                              T *__restrict__ u, MgShift sh) {
     if (sh.run && *sh.run != 0) return;
+    MgPt p;
+    if (!mg_point(fd.nx, fd.ny, p)) return;
+    const int64_t cnxy = (int64_t)cd.nx * cd.ny;
+    const int x0 = p.x >> 1, y0 = p.y >> 1, z0 = p.z >> 1;
+    const int x1 = (p.x & 1) ? (x0 + 1 == cd.nx ? 0 : x0 + 1) : x0;
+    const int y1 = (p.y & 1) ? (y0 + 1 == cd.ny ? 0 : y0 + 1) : y0;
+    const int z1 = (p.z & 1) ? (z0 + 1 == cd.nz ? 0 : z0 + 1) : z0;
+    const int64_t r00 = (int64_t)z0 * cnxy + (int64_t)y0 * cd.nx, r01 = (int64_t)z0 * cnxy + (int64_t)y1 * cd.nx;
+    const int64_t r10 = (int64_t)z1 * cnxy + (int64_t)y0 * cd.nx, r11 = (int64_t)z1 * cnxy + (int64_t)y1 * cd.nx;
+    // the 8 corner weights are 1/8 each; duplicated corners (even indices)
+    // add up to the weights 1, 1/2, 1/4 of fewer distinct points
     using V = VT<T>;
-    const int64_t fnxy = (int64_t)fd.nx * fd.ny, cnxy = (int64_t)cd.nx * cd.ny;
-    for (int64_t i = (int64_t)blockIdx.x * kMgThreads + threadIdx.x; i < fd.n;
-         i += (int64_t)gridDim.x * kMgThreads) {
-        const int x = (int)(i % fd.nx), y = (int)((i / fd.nx) % fd.ny), z = (int)(i / fnxy);
-        int xs[2], ys[2], zs[2];
-        double wx[2], wy[2], wz[2];
-        int nxs, nys, nzs;
-        if (x % 2 == 0) { xs[0] = x / 2; wx[0] = 1.0; nxs = 1; }
-        else { xs[0] = x / 2; xs[1] = (x / 2 + 1) % cd.nx; wx[0] = wx[1] = 0.5; nxs = 2; }
-        if (y % 2 == 0) { ys[0] = y / 2; wy[0] = 1.0; nys = 1; }
-        else { ys[0] = y / 2; ys[1] = (y / 2 + 1) % cd.ny; wy[0] = wy[1] = 0.5; nys = 2; }
-        if (z % 2 == 0) { zs[0] = z / 2; wz[0] = 1.0; nzs = 1; }
-        else { zs[0] = z / 2; zs[1] = (z / 2 + 1) % cd.nz; wz[0] = wz[1] = 0.5; nzs = 2; }
-        T acc = u[i];
-        for (int c = 0; c < nzs; ++c)
-            for (int b = 0; b < nys; ++b)
-                for (int a = 0; a < nxs; ++a)
-                    acc = mg_axpy(wz[c] * wy[b] * wx[a], uc[(int64_t)zs[c] * cnxy + (int64_t)ys[b] * cd.nx + xs[a]],
-                                  acc);
-        u[i] = acc;
-    }
+    T acc = V::zero();
+    acc = V::add(acc, V::add(uc[r00 + x0], uc[r00 + x1]));
+    acc = V::add(acc, V::add(uc[r01 + x0], uc[r01 + x1]));
+    acc = V::add(acc, V::add(uc[r10 + x0], uc[r10 + x1]));
+    acc = V::add(acc, V::add(uc[r11 + x0], uc[r11 + x1]));
+    u[p.i] = mg_axpy(0.125, acc, u[p.i]);
 }
 
 // Exact solve on the coarsest grid (at most 16^3 points, one workgroup):
@@ -253,33 +272,27 @@ template <typename T>
 int vcycle(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
     MgLevel &L = mg.lv[l];
     const MgDims d = dims_of(L, kappa);
-    const int nb = blocks_for(L.n);
     T *f = (T *)L.f;
     if (l + 1 == (int)mg.lv.size()) {
         hipLaunchKernelGGL(mg_coarse_solve<T>, dim3(1), dim3(kMgThreads), 0, s, d, f, (T *)L.u, sh);
         OFDFT_CHECK_HIP(hipGetLastError());
         return OFDFT_OK;
     }
-    // 2 nu sweeps in all; the first writes t, so after an even count the
-    // result is back in u
-    T *cur = (T *)L.t, *nxt = (T *)L.u;
-    hipLaunchKernelGGL(mg_smooth0<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, sh);
-    for (int k = 1; k < mg.nu; ++k) {
-        hipLaunchKernelGGL(mg_smooth<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, nxt, sh);
-        std::swap(cur, nxt);
-    }
-    hipLaunchKernelGGL(mg_residual<T>, dim3(nb), dim3(kMgThreads), 0, s, d, f, cur, (T *)L.r, sh);
+    const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
+    // V(2,2): both pre-sweeps in one pass into u, residual, coarse
+    // correction added to u, two post-sweeps (u -> t -> u)
+    T *u = (T *)L.u, *t = (T *)L.t;
+    hipLaunchKernelGGL(mg_pre2<T>, grid, block, 0, s, d, mg.omega, f, u, sh);
+    hipLaunchKernelGGL(mg_residual<T>, grid, block, 0, s, d, f, u, (T *)L.r, sh);
     MgLevel &C = mg.lv[l + 1];
     const MgDims cd = dims_of(C, kappa);
-    hipLaunchKernelGGL(mg_restrict<T>, dim3(blocks_for(C.n)), dim3(kMgThreads), 0, s, d, cd, (const T *)L.r,
+    hipLaunchKernelGGL(mg_restrict<T>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const T *)L.r,
                        (T *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     OFDFT_TRY(vcycle<T>(mg, l + 1, kappa, sh, s));
-    hipLaunchKernelGGL(mg_prolong_add<T>, dim3(nb), dim3(kMgThreads), 0, s, d, cd, (const T *)C.u, cur, sh);
-    for (int k = 0; k < mg.nu; ++k) {
-        hipLaunchKernelGGL(mg_smooth<T>, dim3(nb), dim3(kMgThreads), 0, s, d, mg.omega, f, cur, nxt, sh);
-        std::swap(cur, nxt);
-    }
+    hipLaunchKernelGGL(mg_prolong_add<T>, grid, block, 0, s, d, cd, (const T *)C.u, u, sh);
+    hipLaunchKernelGGL(mg_smooth<T>, grid, block, 0, s, d, mg.omega, f, u, t, sh);
+    hipLaunchKernelGGL(mg_smooth<T>, grid, block, 0, s, d, mg.omega, f, t, u, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
@@ -289,6 +302,10 @@ int vcycle(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
 int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes) {
     mg_free(mg);
     if (elem_bytes != 8 && elem_bytes != 16) return OFDFT_INVALID_ARG;
+    if (g.nz > 65535) {             // one z plane per grid row of the launches
+        set_error("multigrid: nz = %d exceeds 65535", g.nz);
+        return OFDFT_INVALID_ARG;
+    }
     mg.elem = elem_bytes;
     MgLevel L;
     L.nx = g.nx;
@@ -340,13 +357,13 @@ void mg_free(Multigrid &mg) {
     mg.lv.clear();
 }
 
-int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s) {
+int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa) {
     if (mg.lv.empty() || mg.elem != 8) return OFDFT_INVALID_ARG;
     MgLevel &L0 = mg.lv[0];
     L0.f = const_cast<double *>(r);
     L0.u = z;
     ProfScope ps(K_MULTIGRID, mg_cycle_bytes(mg), s);
-    return vcycle<double>(mg, 0, make_double2(0.0, 0.0), MgShift{nullptr, nullptr}, s);
+    return vcycle<double>(mg, 0, make_double2(kappa, 0.0), MgShift{nullptr, nullptr}, s);
 }
 
 int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
@@ -359,12 +376,13 @@ int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *
 }
 
 // Algorithmic bytes of one cycle on the fine level (the coarser levels add
-// about 1/7): 2 nu sweeps and the residual read f, u and write one array,
-// restriction reads r, prolongation reads and writes u.
+// about 1/7): pre-smoothing reads f and writes u, the residual and each
+// post-sweep read f, u and write one array, restriction reads r and writes
+// an eighth, prolongation reads and writes u.
 double mg_cycle_bytes(const Multigrid &mg) {
     if (mg.lv.empty()) return 0.0;
     const double e = (double)mg.elem;
-    return (double)mg.lv[0].n * e * (3.0 * (2 * mg.nu + 1) + 3.0) * 8.0 / 7.0;
+    return (double)mg.lv[0].n * e * (2.0 + 3.0 * 3 + 1.125 + 2.0) * 8.0 / 7.0;
 }
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible

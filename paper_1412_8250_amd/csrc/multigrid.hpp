@@ -27,7 +27,7 @@ struct MgLevel {
 
 struct Multigrid {
     std::vector<MgLevel> lv;
-    int nu = 2;                  // Jacobi sweeps before and after the coarse correction
+    static constexpr int nu = 2; // Jacobi sweeps before and after the coarse correction
     double omega = 0.8;          // Jacobi damping
     int elem = 8;                // element bytes: 8 (FP64) or 16 (complex128)
     std::vector<void *> allocs;
@@ -40,8 +40,9 @@ constexpr int kMgCoarseMax = 16;     // coarsest grid: at most this many points 
 // INVALID_ARG if the coarsest grid would be larger than that.
 int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes);
 void mg_free(Multigrid &mg);
-// z = M r for -Delta (device FP64 arrays of the fine grid; z must not alias r).
-int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s);
+// z = M r for -Delta + kappa, kappa >= 0 real (device FP64 arrays of the fine
+// grid; z must not alias r).
+int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa = 0.0);
 // z = M r for -Delta + kappa (complex128 arrays).  kappa points to device
 // memory holding {Re, Im} and is read by every launch, so a captured launch
 // sequence follows later changes of the shift; if `run` is given, every

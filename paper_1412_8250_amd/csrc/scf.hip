@@ -155,6 +155,11 @@ void scf_free(ofdft_scf *s) {
     if (s->pois) ofdft_poisson_destroy(s->pois);
     if (s->batch) ofdft_batch_destroy(s->batch);
     if (s->mix) ofdft_anderson_destroy(s->mix);
+    if (s->umg) {
+        mg_free(*s->umg);
+        delete s->umg;
+        s->umg = nullptr;
+    }
     for (void *p : s->allocs)
         if (p) (void)hipFree(p);
     s->allocs.clear();
@@ -246,10 +251,23 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     };
     const size_t b8 = sizeof(double) * s->n;
     int rc = OFDFT_OK;
-    double **vecs[] = {&s->b, &s->u, &s->v, &s->phi, &s->vlr, &s->fres, &s->g4, &s->Hu, &s->Lu,
-                       &s->rA, &s->rB, &s->dA, &s->dB, &s->Ld};
+    double **vecs[] = {&s->b, &s->u, &s->v, &s->phi, &s->vlr, &s->fres, &s->g4, &s->Hu,
+                       &s->rA, &s->rB, &s->dA, &s->dB};
     for (double **q : vecs)
         if ((rc = salloc(s, q, b8))) return fail(rc);
+    if (p->u_precond == OFDFT_PRECOND_MULTIGRID && p->lambda > 0) {
+        // preconditioner of the density update: -Delta + 2 sigma / lambda,
+        // sigma = V_TF(mean density)
+        if ((rc = salloc(s, &s->z, b8))) return fail(rc);
+        s->umg = new (std::nothrow) Multigrid();
+        if (!s->umg) return fail(OFDFT_NO_MEMORY);
+        if ((rc = mg_create(*s->umg, p->grid, 8))) return fail(rc);
+        const double rho_bar = p->n_electrons / ((double)s->n * s->dv);
+        s->u_kappa = 2.0 * (5.0 / 3.0) * kCF * std::cbrt(rho_bar * rho_bar) / p->lambda;
+    } else if (p->u_precond != OFDFT_PRECOND_NONE && p->u_precond != OFDFT_PRECOND_MULTIGRID) {
+        set_error("ofdft_scf_create: unknown u_precond %d", p->u_precond);
+        return fail(OFDFT_INVALID_ARG);
+    }
     if ((rc = salloc(s, &s->dsc, sizeof(double) * 64))) return fail(rc);
     if (hipHostMalloc(&s->hsc, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) return fail(OFDFT_NO_MEMORY);
     if ((rc = redbuf_alloc(s->rb))) return fail(rc);

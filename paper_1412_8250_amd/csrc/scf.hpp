@@ -20,9 +20,11 @@ struct ofdft_scf {
     double *rho_a = nullptr, *rho_b = nullptr, *f_a = nullptr, *f_b = nullptr;
     double2 *Fr[8] = {}, *Vr[8] = {};
     double kappa[16] = {};
-    // density update workspace
-    double *Hu = nullptr, *Lu = nullptr, *rA = nullptr, *rB = nullptr, *dA = nullptr, *dB = nullptr,
-           *Ld = nullptr;
+    // density update workspace; with the preconditioner, z = M r and the
+    // multigrid hierarchy of -Delta + u_kappa
+    double *Hu = nullptr, *rA = nullptr, *rB = nullptr, *dA = nullptr, *dB = nullptr, *z = nullptr;
+    ofdft::Multigrid *umg = nullptr;
+    double u_kappa = 0;
     double s_prev = 0;
     // solver contexts
     ofdft_poisson *pois = nullptr;

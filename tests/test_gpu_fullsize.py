@@ -53,19 +53,21 @@ def test_shifted_batch_320(large, precond):
     b.close()
 
 
-def test_density_update_320(large):
+@pytest.mark.parametrize("precond", [ofd.PRECOND_NONE, ofd.PRECOND_MULTIGRID])
+def test_density_update_320(large, precond):
     """U(v) on the large cell with v = the Poisson potential, lambda = 1, to
-    1e-8 (the benchmark's settings); the oracle recomputes the residual and
-    eta from the returned u over the whole grid."""
+    1e-8 (the benchmark's settings; plain and preconditioned directions); the
+    oracle recomputes the residual and eta from the returned u over the whole
+    grid."""
     torch = torch_cuda()
-    announce("density update 320^3")
+    announce("density update 320^3", precond)
     w = large
     g, _ = poisson.rhs(w.rho, w.b)
     gd = to_dev(g)
     phi = torch.zeros_like(gd)
     ofd.PoissonSolver(g.shape, w.cell.h, 6, ofd.PLAIN_F64).solve(gd, phi, 1e-10)
     ctx = ofd.SCF(w.rho.shape, w.cell.h, to_dev(w.b), to_dev(np.sqrt(w.rho)), w.cell.n_electrons,
-                  lam=1.0, u_tol=1e-8)
+                  lam=1.0, u_tol=1e-8, u_precond=precond)
     ud = to_dev(np.sqrt(w.rho))
     it, res, eta = ctx.density_update(phi, ud)
     announce("density update 320^3 iterations", it, res)
