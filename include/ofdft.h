@@ -49,7 +49,9 @@ typedef enum {
     OFDFT_LEARNED = 2,         /* network initial guess + flexible CG with the network as
                                   preconditioner, FP64 vectors; plain CG as fallback      */
     OFDFT_MULTIGRID = 3,       /* CG preconditioned by a geometric multigrid V-cycle of
-                                  the second-order operator, FP64 vectors                 */
+                                  the second-order operator, FP64 vectors; the cycle's
+                                  level arrays in FP32                                    */
+    OFDFT_MULTIGRID_F64 = 4,   /* the same with the cycle in FP64 throughout              */
 } ofdft_mode;
 
 typedef struct {
@@ -102,8 +104,9 @@ int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
  * and reported in stats->removed_mean.
  *
  * ofdft_poisson_create allocates the workspace for one grid and one mode.
- *   mode  OFDFT_PLAIN_F64, OFDFT_REFINED_F32, OFDFT_MULTIGRID (every axis must
- *         halve evenly down to at most 16 points; INVALID_ARG otherwise) or
+ *   mode  OFDFT_PLAIN_F64, OFDFT_REFINED_F32, OFDFT_MULTIGRID or
+ *         OFDFT_MULTIGRID_F64 (every axis must halve evenly down to at most
+ *         16 points; INVALID_ARG otherwise) or
  *         OFDFT_LEARNED (needs a network, see ofdft_poisson_set_network).
  *         Multigrid: M = one V(2,2) cycle of the periodic 7-point operator
  *         (damped Jacobi, omega 0.8; full weighting; trilinear
@@ -169,7 +172,12 @@ int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inne
  *   grid (about 1.3 fine-grid vectors).  INVALID_ARG (nothing changed) or
  *   NO_MEMORY.
  * ------------------------------------------------------------------------ */
-typedef enum { OFDFT_PRECOND_NONE = 0, OFDFT_PRECOND_MULTIGRID = 1 } ofdft_precond;
+typedef enum {
+    OFDFT_PRECOND_NONE = 0,
+    OFDFT_PRECOND_MULTIGRID = 1,      /* cycle with FP32 / complex64 level arrays (reads r and
+                                         writes z in FP64 / complex128)                      */
+    OFDFT_PRECOND_MULTIGRID_F64 = 2   /* cycle in FP64 / complex128 throughout                */
+} ofdft_precond;
 typedef struct ofdft_batch ofdft_batch;
 int ofdft_batch_create(int nsys, const ofdft_grid *grids, int radius, ofdft_dtype dtype,
                        ofdft_batch **out);
@@ -230,14 +238,14 @@ typedef struct {
     int n_restart;             /* Polak-Ribiere restart period                            */
     int u_max_iter;
     double poisson_tol;        /* relative residual of the Poisson solve                  */
-    int poisson_mode;          /* OFDFT_PLAIN_F64, OFDFT_REFINED_F32 or OFDFT_MULTIGRID   */
+    int poisson_mode;          /* OFDFT_PLAIN_F64, OFDFT_REFINED_F32, OFDFT_MULTIGRID(_F64) */
     double helmholtz_tol;      /* relative residual of each shifted solve                 */
     ofdft_dtype helmholtz_dtype; /* OFDFT_C128 or OFDFT_C64                               */
     int max_iter;              /* Krylov iteration cap per solve                          */
     double line_tol;           /* line search: relative tolerance on the step, 0 = 1e-8  */
-    int helmholtz_precond;     /* OFDFT_PRECOND_NONE or OFDFT_PRECOND_MULTIGRID (C128)   */
+    int helmholtz_precond;     /* OFDFT_PRECOND_NONE or OFDFT_PRECOND_MULTIGRID(_F64), C128 */
     int u_precond;             /* density update: OFDFT_PRECOND_NONE (Algorithm 1 as
-                                  printed) or OFDFT_PRECOND_MULTIGRID (lambda > 0): the
+                                  printed) or OFDFT_PRECOND_MULTIGRID(_F64) (lambda > 0): the
                                   steepest-descent direction r becomes z = M r projected
                                   on <u, z> = 0, M one multigrid cycle of -Delta +
                                   2 sigma / lambda with sigma = V_TF(N_e / volume);
@@ -325,9 +333,9 @@ int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const double *g, c
                        double *loss, void *stream);
 int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const double *g, const double *phi,
                         double lr, double *loss, void *stream);
-/* z = M r with the multigrid preconditioner of an OFDFT_MULTIGRID solver
- * (device FP64 arrays of the solver's grid, z != r); INVALID_ARG for other
- * modes. */
+/* z = M r with the multigrid preconditioner of an OFDFT_MULTIGRID or
+ * OFDFT_MULTIGRID_F64 solver (device FP64 arrays of the solver's grid, z != r);
+ * INVALID_ARG for other modes. */
 int ofdft_poisson_apply_preconditioner(ofdft_poisson *s, const double *r, double *z, void *stream);
 int ofdft_poisson_set_learned_mode(ofdft_poisson *s, int precondition);
 int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);

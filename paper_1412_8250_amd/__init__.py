@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(HERE, "libofdft.so")
 
 OK, NOT_CONVERGED, INVALID_ARG, NONFINITE, BREAKDOWN, HIP_ERROR, NO_MEMORY = 0, 1, -1, -2, -3, -4, -5
 F64, F32, C128, C64 = 0, 1, 2, 3
-PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_MULTIGRID = 0, 1
+PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID, MULTIGRID_F64 = 0, 1, 2, 3, 4
+PRECOND_NONE, PRECOND_MULTIGRID, PRECOND_MULTIGRID_F64 = 0, 1, 2
 
 
 class OfdftError(RuntimeError):

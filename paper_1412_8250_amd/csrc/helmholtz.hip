@@ -624,11 +624,16 @@ extern "C" int ofdft_batch_set_config(ofdft_batch *b, int shape, int P) {
 }
 
 extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
-    if (!b || (kind != OFDFT_PRECOND_NONE && kind != OFDFT_PRECOND_MULTIGRID)) {
+    if (!b || (kind != OFDFT_PRECOND_NONE && kind != OFDFT_PRECOND_MULTIGRID &&
+               kind != OFDFT_PRECOND_MULTIGRID_F64)) {
         set_error("ofdft_batch_set_preconditioner: unknown kind %d", kind);
         return OFDFT_INVALID_ARG;
     }
     if (kind == b->precond) return OFDFT_OK;
+    if (b->precond != OFDFT_PRECOND_NONE && kind != OFDFT_PRECOND_NONE) {     // switch precision
+        const int st = ofdft_batch_set_preconditioner(b, OFDFT_PRECOND_NONE);
+        if (st != OFDFT_OK) return st;
+    }
     if (kind == OFDFT_PRECOND_NONE) {
         OFDFT_CHECK_HIP(hipDeviceSynchronize());
         precond_free(b);
@@ -668,7 +673,7 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
             Multigrid *mg = new (std::nothrow) Multigrid();
             if (!mg) return undo(OFDFT_NO_MEMORY);
             own.push_back(mg);
-            const int st = mg_create(*mg, g, 16);
+            const int st = mg_create(*mg, g, 16, kind == OFDFT_PRECOND_MULTIGRID);
             if (st != OFDFT_OK) return undo(st);
             of[j] = mg;
         }

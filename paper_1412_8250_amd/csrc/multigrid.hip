@@ -45,20 +45,57 @@ __device__ inline bool mg_point(int nx, int ny, MgPt &p) {
     return p.x < nx && p.y < ny;
 }
 
-// Element arithmetic for real (Poisson) and complex (shifted) levels.
+// Element types: the cycle's input f and output z are FP64 (real or complex);
+// the levels' arrays are stored, and their arithmetic done, in S (FP64 or
+// FP32, real or complex).  R is S's real type, C the complex scalar of that
+// precision (the Jacobi factor and the shift).
+template <typename S> struct MgT;
+template <> struct MgT<double> { using R = double; using C = double2; };
+template <> struct MgT<float> { using R = float; using C = float2; };
+template <> struct MgT<double2> { using R = double; using C = double2; };
+template <> struct MgT<float2> { using R = float; using C = float2; };
+
+template <typename To> __device__ inline To cv(double v);
+template <typename To> __device__ inline To cv(float v);
+template <typename To> __device__ inline To cv(double2 v);
+template <typename To> __device__ inline To cv(float2 v);
+template <> __device__ inline double cv<double>(double v) { return v; }
+template <> __device__ inline float cv<float>(double v) { return (float)v; }
+template <> __device__ inline double cv<double>(float v) { return (double)v; }
+template <> __device__ inline float cv<float>(float v) { return v; }
+template <> __device__ inline double2 cv<double2>(double2 v) { return v; }
+template <> __device__ inline float2 cv<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+template <> __device__ inline double2 cv<double2>(float2 v) { return make_double2(v.x, v.y); }
+template <> __device__ inline float2 cv<float2>(float2 v) { return v; }
+
 __device__ inline double mg_scale(double2 s, double v) { return s.x * v; }
+__device__ inline float mg_scale(float2 s, float v) { return s.x * v; }
 __device__ inline double2 mg_scale(double2 s, double2 v) {
     return make_double2(s.x * v.x - s.y * v.y, s.x * v.y + s.y * v.x);
 }
+__device__ inline float2 mg_scale(float2 s, float2 v) {
+    return make_float2(s.x * v.x - s.y * v.y, s.x * v.y + s.y * v.x);
+}
 __device__ inline double mg_axpy(double a, double x, double y) { return ::fma(a, x, y); }
+__device__ inline float mg_axpy(float a, float x, float y) { return fmaf(a, x, y); }
 __device__ inline double2 mg_axpy(double a, double2 x, double2 y) {
     return make_double2(::fma(a, x.x, y.x), ::fma(a, x.y, y.y));
 }
+__device__ inline float2 mg_axpy(float a, float2 x, float2 y) {
+    return make_float2(fmaf(a, x.x, y.x), fmaf(a, x.y, y.y));
+}
 
-// (A u) at p for the periodic 7-point operator A = -Delta_h + kappa (second order).
-template <typename T>
-__device__ inline T apply7(const T *__restrict__ u, const MgDims &d, const MgPt &p) {
-    using V = VT<T>;
+template <typename C> __device__ inline C mk_c(double a, double b);
+template <> __device__ inline double2 mk_c<double2>(double a, double b) { return make_double2(a, b); }
+template <> __device__ inline float2 mk_c<float2>(double a, double b) { return make_float2((float)a, (float)b); }
+
+// (A u) at p for the periodic 7-point operator A = -Delta_h + kappa (second
+// order), u of element type TI, computed in S.
+template <typename S, typename TI>
+__device__ inline S apply7(const TI *__restrict__ u, const MgDims &d, const MgPt &p) {
+    using V = VT<S>;
+    using R = typename MgT<S>::R;
+    using C = typename MgT<S>::C;
     const int64_t i = p.i, nxy = (int64_t)d.nx * d.ny;
     const int64_t xp = p.x + 1 == d.nx ? i - p.x : i + 1;
     const int64_t xm = p.x == 0 ? i + d.nx - 1 : i - 1;
@@ -66,12 +103,12 @@ __device__ inline T apply7(const T *__restrict__ u, const MgDims &d, const MgPt 
     const int64_t ym = p.y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
     const int64_t zp = p.z + 1 == d.nz ? i - (int64_t)p.z * nxy : i + nxy;
     const int64_t zm = p.z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
-    const T c = u[i];
-    T a = V::mul(d.diag, c);
-    a = mg_axpy(-d.cx, V::add(u[xp], u[xm]), a);
-    a = mg_axpy(-d.cy, V::add(u[yp], u[ym]), a);
-    a = mg_axpy(-d.cz, V::add(u[zp], u[zm]), a);
-    return V::add(a, mg_scale(make_double2(d.kre, d.kim), c));
+    const S c = cv<S>(u[i]);
+    S a = V::mul((R)d.diag, c);
+    a = mg_axpy((R)-d.cx, V::add(cv<S>(u[xp]), cv<S>(u[xm])), a);
+    a = mg_axpy((R)-d.cy, V::add(cv<S>(u[yp]), cv<S>(u[ym])), a);
+    a = mg_axpy((R)-d.cz, V::add(cv<S>(u[zp]), cv<S>(u[zm])), a);
+    return V::add(a, mg_scale(mk_c<C>(d.kre, d.kim), c));
 }
 
 // Per-launch shift source: when `kap` is given, kappa is read from device
@@ -94,59 +131,62 @@ __device__ inline bool take_shift(const MgShift &sh, MgDims &d) {
 }
 
 // omega / (diag + kappa)
-__device__ inline double2 jacobi_factor(const MgDims &d, double w) {
+template <typename C>
+__device__ inline C jacobi_factor(const MgDims &d, double w) {
     const double re = d.diag + d.kre, im = d.kim, den = re * re + im * im;
-    return make_double2(w * re / den, -w * im / den);
+    return mk_c<C>(w * re / den, -w * im / den);
 }
 
 // The two pre-smoothing sweeps from u = 0 in one pass: with the Jacobi factor
 // s = omega / (diag + kappa), u1 = s f and u2 = u1 + s (f - A u1) = s (2 f - s A f).
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const T *__restrict__ f,
-                                                      T *__restrict__ u, MgShift sh) {
+template <typename TF, typename S>
+__global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const TF *__restrict__ f,
+                                                      S *__restrict__ u, MgShift sh) {
     if (!take_shift(sh, d)) return;
     MgPt p;
     if (!mg_point(d.nx, d.ny, p)) return;
-    using V = VT<T>;
-    const double2 s = jacobi_factor(d, w);
-    const T af = apply7(f, d, p);
-    const T two_f = V::add(f[p.i], f[p.i]);
-    u[p.i] = mg_scale(s, V::sub(two_f, mg_scale(s, af)));
+    using V = VT<S>;
+    const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
+    const S af = apply7<S>(f, d, p);
+    const S fi = cv<S>(f[p.i]);
+    u[p.i] = mg_scale(s, V::sub(V::add(fi, fi), mg_scale(s, af)));
 }
 
-// t = u + omega (f - A u) / (diag + kappa)
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const T *__restrict__ f,
-                                                        const T *__restrict__ u, T *__restrict__ t,
+// t = u + omega (f - A u) / (diag + kappa), computed in S, stored as TO
+template <typename TF, typename S, typename TO>
+__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const TF *__restrict__ f,
+                                                        const S *__restrict__ u, TO *__restrict__ t,
                                                         MgShift sh) {
     if (!take_shift(sh, d)) return;
     MgPt p;
     if (!mg_point(d.nx, d.ny, p)) return;
-    using V = VT<T>;
-    const double2 s = jacobi_factor(d, w);
-    t[p.i] = V::add(u[p.i], mg_scale(s, V::sub(f[p.i], apply7(u, d, p))));
+    using V = VT<S>;
+    const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
+    const S r = V::sub(cv<S>(f[p.i]), apply7<S>(u, d, p));
+    t[p.i] = cv<TO>(V::add(u[p.i], mg_scale(s, r)));
 }
 
 // r = f - A u
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const T *__restrict__ f,
-                                                          const T *__restrict__ u, T *__restrict__ r,
+template <typename TF, typename S>
+__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const TF *__restrict__ f,
+                                                          const S *__restrict__ u, S *__restrict__ r,
                                                           MgShift sh) {
     if (!take_shift(sh, d)) return;
     MgPt p;
     if (!mg_point(d.nx, d.ny, p)) return;
-    r[p.i] = VT<T>::sub(f[p.i], apply7(u, d, p));
+    r[p.i] = VT<S>::sub(cv<S>(f[p.i]), apply7<S>(u, d, p));
 }
 
 // Full weighting: fc[I] = sum over the 27 fine points around 2I of
 // (1/8) w(dx) w(dy) w(dz) r, w(0) = 1, w(+-1) = 1/2 (= P^T / 8).
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const T *__restrict__ r,
-                                                          T *__restrict__ fc, MgShift sh) {
+template <typename S>
+__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const S *__restrict__ r,
+                                                          S *__restrict__ fc, MgShift sh) {
     if (sh.run && *sh.run != 0) return;
     MgPt P;
     if (!mg_point(cd.nx, cd.ny, P)) return;
-    using V = VT<T>;
+    using V = VT<S>;
+    using R = typename MgT<S>::R;
     const int64_t fnxy = (int64_t)fd.nx * fd.ny;
     int xs[3], ys[3], zs[3];
     xs[0] = P.x == 0 ? fd.nx - 1 : 2 * P.x - 1;
@@ -158,29 +198,31 @@ __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, 
     zs[0] = P.z == 0 ? fd.nz - 1 : 2 * P.z - 1;
     zs[1] = 2 * P.z;
     zs[2] = 2 * P.z + 1;
-    T acc = V::zero();
+    S acc = V::zero();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double wz = c == 1 ? 1.0 : 0.5;
+        const R wz = c == 1 ? (R)1 : (R)0.5;
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const double wy = b == 1 ? wz : 0.5 * wz;
+            const R wy = b == 1 ? wz : (R)0.5 * wz;
             const int64_t row = (int64_t)zs[c] * fnxy + (int64_t)ys[b] * fd.nx;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) acc = mg_axpy(a == 1 ? wy : 0.5 * wy, r[row + xs[a]], acc);
+            for (int a = 0; a < 3; ++a) acc = mg_axpy(a == 1 ? wy : (R)0.5 * wy, r[row + xs[a]], acc);
         }
     }
-    fc[P.i] = V::mul(0.125, acc);
+    fc[P.i] = V::mul((R)0.125, acc);
 }
 
 // Trilinear prolongation added to u: fine index i takes coarse i/2 (even i)
 // or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const T *__restrict__ uc,
-                                                             T *__restrict__ u, MgShift sh) {
+template <typename S>
+__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const S *__restrict__ uc,
+                                                             S *__restrict__ u, MgShift sh) {
     if (sh.run && *sh.run != 0) return;
     MgPt p;
     if (!mg_point(fd.nx, fd.ny, p)) return;
+    using V = VT<S>;
+    using R = typename MgT<S>::R;
     const int64_t cnxy = (int64_t)cd.nx * cd.ny;
     const int x0 = p.x >> 1, y0 = p.y >> 1, z0 = p.z >> 1;
     const int x1 = (p.x & 1) ? (x0 + 1 == cd.nx ? 0 : x0 + 1) : x0;
@@ -190,16 +232,15 @@ __global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims c
     const int64_t r10 = (int64_t)z1 * cnxy + (int64_t)y0 * cd.nx, r11 = (int64_t)z1 * cnxy + (int64_t)y1 * cd.nx;
     // the 8 corner weights are 1/8 each; duplicated corners (even indices)
     // add up to the weights 1, 1/2, 1/4 of fewer distinct points
-    using V = VT<T>;
-    T acc = V::zero();
+    S acc = V::zero();
     acc = V::add(acc, V::add(uc[r00 + x0], uc[r00 + x1]));
     acc = V::add(acc, V::add(uc[r01 + x0], uc[r01 + x1]));
     acc = V::add(acc, V::add(uc[r10 + x0], uc[r10 + x1]));
     acc = V::add(acc, V::add(uc[r11 + x0], uc[r11 + x1]));
-    u[p.i] = mg_axpy(0.125, acc, u[p.i]);
+    u[p.i] = mg_axpy((R)0.125, acc, u[p.i]);
 }
 
-// Exact solve on the coarsest grid (at most 16^3 points, one workgroup):
+// Exact solve on the coarsest grid (at most 16^3 points, one workgroup, FP64):
 // A is diagonalised by the DFT, eigenvalue sum_a c_a (2 - 2 cos(2 pi k_a / n_a))
 // + kappa; with kappa = 0 the k = 0 (constant) component is set to zero.
 __device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz, int axis, double sign) {
@@ -224,13 +265,17 @@ __device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz
 }
 
 __device__ inline double2 mg_to_c(double v) { return make_double2(v, 0.0); }
+__device__ inline double2 mg_to_c(float v) { return make_double2(v, 0.0); }
 __device__ inline double2 mg_to_c(double2 v) { return v; }
+__device__ inline double2 mg_to_c(float2 v) { return make_double2(v.x, v.y); }
 __device__ inline void mg_from_c(double2 v, double &o) { o = v.x; }
+__device__ inline void mg_from_c(double2 v, float &o) { o = (float)v.x; }
 __device__ inline void mg_from_c(double2 v, double2 &o) { o = v; }
+__device__ inline void mg_from_c(double2 v, float2 &o) { o = make_float2((float)v.x, (float)v.y); }
 
-template <typename T>
-__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const T *__restrict__ f,
-                                                              T *__restrict__ u, MgShift sh) {
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const TI *__restrict__ f,
+                                                              TO *__restrict__ u, MgShift sh) {
     if (!take_shift(sh, d)) return;
     __shared__ double2 a[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     __shared__ double2 b[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
@@ -268,38 +313,65 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const T 
     for (int i = threadIdx.x; i < n; i += blockDim.x) mg_from_c(a[i], u[i]);
 }
 
-template <typename T>
-int vcycle(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
+// V(2,2) cycle on level l >= 1 (arrays of S): f -> u.
+template <typename S>
+int vcycle_coarse(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
     MgLevel &L = mg.lv[l];
     const MgDims d = dims_of(L, kappa);
-    T *f = (T *)L.f;
+    S *f = (S *)L.f, *u = (S *)L.u, *t = (S *)L.t;
     if (l + 1 == (int)mg.lv.size()) {
-        hipLaunchKernelGGL(mg_coarse_solve<T>, dim3(1), dim3(kMgThreads), 0, s, d, f, (T *)L.u, sh);
+        hipLaunchKernelGGL((mg_coarse_solve<S, S>), dim3(1), dim3(kMgThreads), 0, s, d, (const S *)f, u, sh);
         OFDFT_CHECK_HIP(hipGetLastError());
         return OFDFT_OK;
     }
     const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
-    // V(2,2): both pre-sweeps in one pass into u, residual, coarse
-    // correction added to u, two post-sweeps (u -> t -> u)
-    T *u = (T *)L.u, *t = (T *)L.t;
-    hipLaunchKernelGGL(mg_pre2<T>, grid, block, 0, s, d, mg.omega, f, u, sh);
-    hipLaunchKernelGGL(mg_residual<T>, grid, block, 0, s, d, f, u, (T *)L.r, sh);
     MgLevel &C = mg.lv[l + 1];
     const MgDims cd = dims_of(C, kappa);
-    hipLaunchKernelGGL(mg_restrict<T>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const T *)L.r,
-                       (T *)C.f, sh);
+    hipLaunchKernelGGL((mg_pre2<S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, u, sh);
+    hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, (const S *)f, (const S *)u, (S *)L.r, sh);
+    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
+                       (S *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
-    OFDFT_TRY(vcycle<T>(mg, l + 1, kappa, sh, s));
-    hipLaunchKernelGGL(mg_prolong_add<T>, grid, block, 0, s, d, cd, (const T *)C.u, u, sh);
-    hipLaunchKernelGGL(mg_smooth<T>, grid, block, 0, s, d, mg.omega, f, u, t, sh);
-    hipLaunchKernelGGL(mg_smooth<T>, grid, block, 0, s, d, mg.omega, f, t, u, sh);
+    OFDFT_TRY(vcycle_coarse<S>(mg, l + 1, kappa, sh, s));
+    hipLaunchKernelGGL(mg_prolong_add<S>, grid, block, 0, s, d, cd, (const S *)C.u, u, sh);
+    hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, (const S *)u, t, sh);
+    hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, (const S *)t, u, sh);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+// The whole cycle z = M f: level 0 reads f and writes z in FP64 (TIO), its
+// work arrays are S.  V(2,2): both pre-sweeps in one pass into u, residual,
+// coarse correction added to u, post-sweeps u -> t -> z.
+template <typename TIO, typename S>
+int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipStream_t s) {
+    MgLevel &L = mg.lv[0];
+    const MgDims d = dims_of(L, kappa);
+    if (mg.lv.size() == 1) {
+        hipLaunchKernelGGL((mg_coarse_solve<TIO, TIO>), dim3(1), dim3(kMgThreads), 0, s, d, f, z, sh);
+        OFDFT_CHECK_HIP(hipGetLastError());
+        return OFDFT_OK;
+    }
+    const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
+    S *u = (S *)L.u, *t = (S *)L.t;
+    MgLevel &C = mg.lv[1];
+    const MgDims cd = dims_of(C, kappa);
+    hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, sh);
+    hipLaunchKernelGGL((mg_residual<TIO, S>), grid, block, 0, s, d, f, (const S *)u, (S *)L.r, sh);
+    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
+                       (S *)C.f, sh);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    OFDFT_TRY(vcycle_coarse<S>(mg, 1, kappa, sh, s));
+    hipLaunchKernelGGL(mg_prolong_add<S>, grid, block, 0, s, d, cd, (const S *)C.u, u, sh);
+    hipLaunchKernelGGL((mg_smooth<TIO, S, S>), grid, block, 0, s, d, mg.omega, f, (const S *)u, t, sh);
+    hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, (const S *)t, z, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
 
 }  // namespace
 
-int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes) {
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32) {
     mg_free(mg);
     if (elem_bytes != 8 && elem_bytes != 16) return OFDFT_INVALID_ARG;
     if (g.nz > 65535) {             // one z plane per grid row of the launches
@@ -307,6 +379,7 @@ int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes) {
         return OFDFT_INVALID_ARG;
     }
     mg.elem = elem_bytes;
+    mg.fp32 = fp32;
     MgLevel L;
     L.nx = g.nx;
     L.ny = g.ny;
@@ -332,11 +405,14 @@ int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes) {
         L.cy /= 4.0;
         L.cz /= 4.0;
     }
-    for (size_t l = 0; l < mg.lv.size(); ++l) {
+    const size_t es = fp32 ? (size_t)elem_bytes / 2 : (size_t)elem_bytes;
+    const int nlev = (int)mg.lv.size();
+    for (int l = 0; l < nlev; ++l) {
         MgLevel &M = mg.lv[l];
-        const size_t b = (size_t)elem_bytes * (size_t)M.n;
+        const size_t b = es * (size_t)M.n;
         void **own[4] = {&M.t, &M.r, &M.u, &M.f};
-        const int count = l == 0 ? 2 : 4;          // level 0 uses the caller's r and z
+        // level 0 reads the caller's f; a one-level hierarchy needs nothing
+        const int count = nlev == 1 ? 0 : (l == 0 ? 3 : 4);
         for (int k = 0; k < count; ++k) {
             void *p = nullptr;
             if (hipMalloc(&p, b) != hipSuccess) {
@@ -359,30 +435,33 @@ void mg_free(Multigrid &mg) {
 
 int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa) {
     if (mg.lv.empty() || mg.elem != 8) return OFDFT_INVALID_ARG;
-    MgLevel &L0 = mg.lv[0];
-    L0.f = const_cast<double *>(r);
-    L0.u = z;
     ProfScope ps(K_MULTIGRID, mg_cycle_bytes(mg), s);
-    return vcycle<double>(mg, 0, make_double2(kappa, 0.0), MgShift{nullptr, nullptr}, s);
+    const double2 k = make_double2(kappa, 0.0);
+    const MgShift sh{nullptr, nullptr};
+    return mg.fp32 ? vcycle<double, float>(mg, r, z, k, sh, s) : vcycle<double, double>(mg, r, z, k, sh, s);
 }
 
 int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
                      hipStream_t s) {
     if (mg.lv.empty() || mg.elem != 16 || !kappa) return OFDFT_INVALID_ARG;
-    MgLevel &L0 = mg.lv[0];
-    L0.f = const_cast<double2 *>(r);
-    L0.u = z;
-    return vcycle<double2>(mg, 0, make_double2(0.0, 0.0), MgShift{kappa, run}, s);
+    const double2 k = make_double2(0.0, 0.0);
+    const MgShift sh{kappa, run};
+    return mg.fp32 ? vcycle<double2, float2>(mg, r, z, k, sh, s) : vcycle<double2, double2>(mg, r, z, k, sh, s);
 }
 
-// Algorithmic bytes of one cycle on the fine level (the coarser levels add
-// about 1/7): pre-smoothing reads f and writes u, the residual and each
-// post-sweep read f, u and write one array, restriction reads r and writes
-// an eighth, prolongation reads and writes u.
+// Algorithmic bytes of one cycle.  Fine level: f (FP64) is read by the
+// pre-smoothing, the residual and both post-sweeps, z (FP64) written once;
+// work arrays (FP32 or FP64): u written, residual reads u and writes r,
+// restriction reads r and writes an eighth, prolongation reads an eighth and
+// reads and writes u, the post-sweeps read u / t and write t.  Each coarser
+// level moves 14.25 work-array elements per point, and they hold 1/7 of the
+// fine points in all.
 double mg_cycle_bytes(const Multigrid &mg) {
     if (mg.lv.empty()) return 0.0;
-    const double e = (double)mg.elem;
-    return (double)mg.lv[0].n * e * (2.0 + 3.0 * 3 + 1.125 + 2.0) * 8.0 / 7.0;
+    const double E = (double)mg.elem, e = mg.fp32 ? E / 2 : E;
+    const double n = (double)mg.lv[0].n;
+    if (mg.lv.size() == 1) return 2.0 * n * E;
+    return n * (5.0 * E + 9.25 * e) + n / 7.0 * 14.25 * e;
 }
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible
@@ -461,7 +540,7 @@ using namespace ofdft;
 // their own Krylov loop around the preconditioner).
 extern "C" int ofdft_poisson_apply_preconditioner(ofdft_poisson *s, const double *r, double *z,
                                                   void *stream) {
-    if (!s || !r || !z || r == z || s->mode != OFDFT_MULTIGRID || !s->mg) {
+    if (!s || !r || !z || r == z || !s->mg) {
         set_error("ofdft_poisson_apply_preconditioner: multigrid solver and distinct r, z required");
         return OFDFT_INVALID_ARG;
     }

@@ -29,16 +29,21 @@ struct Multigrid {
     std::vector<MgLevel> lv;
     static constexpr int nu = 2; // Jacobi sweeps before and after the coarse correction
     double omega = 0.8;          // Jacobi damping
-    int elem = 8;                // element bytes: 8 (FP64) or 16 (complex128)
+    int elem = 8;                // input / output element bytes: 8 (FP64) or 16 (complex128)
+    bool fp32 = true;            // level arrays and their arithmetic in FP32 (else FP64)
     std::vector<void *> allocs;
 };
 
 constexpr int kMgCoarseMax = 16;     // coarsest grid: at most this many points per axis
 
-// Hierarchy for grid g with FP64 (elem_bytes 8) or complex128 (16) levels:
-// halve every axis while all are even and one exceeds kMgCoarseMax.
-// INVALID_ARG if the coarsest grid would be larger than that.
-int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes);
+// Hierarchy for grid g, applied to FP64 (elem_bytes 8) or complex128 (16)
+// vectors; the level arrays (and the arithmetic on them) are FP32 / complex64
+// when fp32 is set: the cycle then reads r and writes z in FP64 but is a fixed
+// linear operator only to FP32 rounding, which the flexible and preconditioned
+// Krylov loops here tolerate without extra iterations.  Every axis is halved
+// while all are even and one exceeds kMgCoarseMax; INVALID_ARG if the
+// coarsest grid would be larger than that.
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32);
 void mg_free(Multigrid &mg);
 // z = M r for -Delta + kappa, kappa >= 0 real (device FP64 arrays of the fine
 // grid; z must not alias r).

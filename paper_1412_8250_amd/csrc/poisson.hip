@@ -390,7 +390,8 @@ int poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol
     int status;
     if (s->mode == OFDFT_REFINED_F32) status = solve_refined(s, x, rel_tol, max_iter, stats, st);
     else if (s->mode == OFDFT_LEARNED) status = poisson_solve_learned(s, x, rel_tol, max_iter, stats, st);
-    else if (s->mode == OFDFT_MULTIGRID) status = poisson_solve_mg(s, x, rel_tol, max_iter, stats, st);
+    else if (s->mode == OFDFT_MULTIGRID || s->mode == OFDFT_MULTIGRID_F64)
+        status = poisson_solve_mg(s, x, rel_tol, max_iter, stats, st);
     else status = solve_plain(s, x, rel_tol, max_iter, stats, st);
     if (status < 0 && status != OFDFT_BREAKDOWN && status != OFDFT_NONFINITE) return status;
     OFDFT_TRY(finalize_solution(s, x, st));
@@ -419,7 +420,7 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
         return OFDFT_INVALID_ARG;
     }
     if (mode != OFDFT_PLAIN_F64 && mode != OFDFT_REFINED_F32 && mode != OFDFT_LEARNED &&
-        mode != OFDFT_MULTIGRID) {
+        mode != OFDFT_MULTIGRID && mode != OFDFT_MULTIGRID_F64) {
         set_error("ofdft_poisson_create: unknown mode %d", mode);
         return OFDFT_INVALID_ARG;
     }
@@ -431,10 +432,10 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
     s->coef = make_coef(*grid, radius);
     s->coef32 = to_float(s->coef);
     int st = poisson_alloc(s);
-    if (st == OFDFT_OK && mode == OFDFT_MULTIGRID) {
+    if (st == OFDFT_OK && (mode == OFDFT_MULTIGRID || mode == OFDFT_MULTIGRID_F64)) {
         s->mg = new (std::nothrow) Multigrid();
         if (!s->mg) st = OFDFT_NO_MEMORY;
-        else st = mg_create(*s->mg, *grid, 8);
+        else st = mg_create(*s->mg, *grid, 8, mode == OFDFT_MULTIGRID);
         if (st == OFDFT_OK && hipMalloc(&s->z, sizeof(double) * npoints(*grid)) != hipSuccess) {
             set_error("ofdft_poisson_create: out of device memory");
             st = OFDFT_NO_MEMORY;

@@ -255,16 +255,17 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
                        &s->rA, &s->rB, &s->dA, &s->dB};
     for (double **q : vecs)
         if ((rc = salloc(s, q, b8))) return fail(rc);
-    if (p->u_precond == OFDFT_PRECOND_MULTIGRID && p->lambda > 0) {
+    const bool u_mg = p->u_precond == OFDFT_PRECOND_MULTIGRID || p->u_precond == OFDFT_PRECOND_MULTIGRID_F64;
+    if (u_mg && p->lambda > 0) {
         // preconditioner of the density update: -Delta + 2 sigma / lambda,
         // sigma = V_TF(mean density)
         if ((rc = salloc(s, &s->z, b8))) return fail(rc);
         s->umg = new (std::nothrow) Multigrid();
         if (!s->umg) return fail(OFDFT_NO_MEMORY);
-        if ((rc = mg_create(*s->umg, p->grid, 8))) return fail(rc);
+        if ((rc = mg_create(*s->umg, p->grid, 8, p->u_precond == OFDFT_PRECOND_MULTIGRID))) return fail(rc);
         const double rho_bar = p->n_electrons / ((double)s->n * s->dv);
         s->u_kappa = 2.0 * (5.0 / 3.0) * kCF * std::cbrt(rho_bar * rho_bar) / p->lambda;
-    } else if (p->u_precond != OFDFT_PRECOND_NONE && p->u_precond != OFDFT_PRECOND_MULTIGRID) {
+    } else if (p->u_precond != OFDFT_PRECOND_NONE && !u_mg) {
         set_error("ofdft_scf_create: unknown u_precond %d", p->u_precond);
         return fail(OFDFT_INVALID_ARG);
     }
@@ -296,7 +297,8 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         for (int j = 0; j < 8; ++j)
             if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     }
-    const int pmode = (p->poisson_mode == OFDFT_REFINED_F32 || p->poisson_mode == OFDFT_MULTIGRID)
+    const int pmode = (p->poisson_mode == OFDFT_REFINED_F32 || p->poisson_mode == OFDFT_MULTIGRID ||
+                       p->poisson_mode == OFDFT_MULTIGRID_F64)
                           ? p->poisson_mode
                           : OFDFT_PLAIN_F64;
     if ((rc = ofdft_poisson_create(&p->grid, p->radius, pmode, &s->pois))) return fail(rc);
