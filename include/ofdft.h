@@ -360,7 +360,9 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   passes, 4 COCG stencil phases (the whole solve when persistent),
  *   5 density-update stencil passes, 6 density-update vector passes,
  *   7 Anderson, 8 other vector passes, 9 network kernels, 10 COCG vector
- *   phase (stepped schedule), 11 multigrid V-cycles.
+ *   phase (stepped schedule), 11 multigrid cycles on FP64 vectors (Poisson,
+ *   density update), 12 multigrid cycles on complex128 vectors (shifted
+ *   systems).
  * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
  *   each result written once), timed launches and their summed milliseconds
  *   for one class since the last reset (synchronises on pending events).

@@ -185,7 +185,7 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
 
 KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
                   "anderson", "pointwise", "nn", "cocg_update",
-                  "multigrid")
+                  "multigrid", "multigrid_c")
 
 
 def profile_reset(timed=()):

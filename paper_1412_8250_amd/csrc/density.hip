@@ -92,20 +92,16 @@ struct ResidOp {        // r = -2 (Hu - eta u); totals {<r,r>, <r,r_prev>}
     }
 };
 
-// d = r + xi d_prev (xi = 0: steepest descent, with d_prev := r); with the
-// preconditioner r is z and the projection -cu u is added (u given).
+// d' = r + xi d_prev (xi = 0: steepest descent, with d_prev := r); with the
+// preconditioner r is z, and the stored direction is d = d' - cu u (EpiLd).
 struct LoadDir {
     const double *__restrict__ r;
-    const double *__restrict__ u;
     const double *__restrict__ d_prev;
-    double cu, xi;
+    double xi;
     __device__ void prepare() {
         if (xi == 0.0) d_prev = r;
     }
-    __device__ double operator()(int64_t i) const {
-        const double base = u ? ::fma(-cu, u[i], r[i]) : r[i];
-        return ::fma(xi, d_prev[i], base);
-    }
+    __device__ double operator()(int64_t i) const { return ::fma(xi, d_prev[i], r[i]); }
 };
 
 struct DotsOp {         // totals {<u,z>, <r,z>, <r_prev,z>, <u,r>, <u,r_prev>}
@@ -128,7 +124,9 @@ struct DotsOp {         // totals {<u,z>, <r,z>, <r_prev,z>, <u,r>, <u,r_prev>}
     }
 };
 
-// d (from the loader), L d; totals {<u,d>, <d,d>, <u,L d>, <d,L d>, <H u,d>}.
+// Stores d = d' - cu u (d' from the loader); totals of the loaded d':
+// {<u,d'>, <d',d'>, <u,L d'>, <d',L d'>, <H u,d'>} (the host corrects them
+// for the -cu u term with <u,u>, <u,L u>, <u,H u>, L being symmetric).
 // The last gives the line-search slope at s = 0 without an evaluation pass:
 // with u normalised, (V_loc + v) u = H u + (lambda/2) L u, and the lambda
 // terms of dE/ds cancel, leaving dE/ds(0) ~ <H u, d> - t <u, H u>.
@@ -139,6 +137,7 @@ struct EpiLd {
     double *totals;
     double *partials;
     unsigned int *counter;
+    double cu;
     double a0, a1, a2, a3, a4;
     double uv[4], hv[4];
     __device__ bool skip() const { return false; }
@@ -148,7 +147,7 @@ struct EpiLd {
     }
     __device__ void point(int q, int64_t i, double c, double s) {
         const double ui = uv[q];
-        d[i] = c;
+        d[i] = ::fma(-cu, ui, c);
         a0 = ::fma(ui, c, a0);
         a1 = ::fma(c, c, a1);
         a2 = ::fma(ui, s, a2);
@@ -317,16 +316,26 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         if (q % nres == 0 || !(xi > 0.0)) xi = 0.0;
         // Kd: d = r + xi d_prev (or z~ + xi d_prev), L d
         auto make_dir = [&](double xiv) -> int {
-            OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{base, pre ? u : nullptr, d_prev, cu, xiv},
-                                   EpiLd{u, s->Hu, d_cur, tot, s->rb.partials, s->rb.counter, 0, 0, 0, 0, 0},
+            OFDFT_TRY(stencil_pass(g, s->coef, LoadDir{base, d_prev, xiv},
+                                   EpiLd{u, s->Hu, d_cur, tot, s->rb.partials, s->rb.counter, cu, 0, 0, 0, 0, 0},
                                    st, 40));
             OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 16, tot, sizeof(double) * 5, hipMemcpyDeviceToHost, st));
             OFDFT_CHECK_HIP(hipStreamSynchronize(st));
             return OFDFT_OK;
         };
-        OFDFT_TRY(make_dir(xi));
-        double ud = s->hsc[16], dd = s->hsc[17], uLd = s->hsc[18], dLd = s->hsc[19], dHu = s->hsc[20];
         const double uLu = h[S_ULU], uHu = h[S_UHU];
+        double ud, dd, uLd, dLd, dHu;
+        // totals of d = d' - cu u from those of the loaded d'
+        auto read_dir = [&]() {
+            const double *t = s->hsc + 16;
+            ud = t[0] - cu * uu;
+            dd = t[1] - 2.0 * cu * t[0] + cu * cu * uu;
+            uLd = t[2] - cu * uLu;
+            dLd = t[3] - 2.0 * cu * t[2] + cu * cu * uLu;
+            dHu = t[4] - cu * uHu;
+        };
+        OFDFT_TRY(make_dir(xi));
+        read_dir();
         // slope at s = 0 from the direction pass (u is normalised, so c2 = N_e / (h^3 <u,u>))
         auto slope0 = [&]() { return ne / (dv * uu) * (dHu - ud / uu * uHu); };
         if (!(dd > 0.0)) break;
@@ -346,7 +355,7 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         if (!(f0 < 0.0) && xi != 0.0) {          // not a descent direction: restart along r
             xi = 0.0;
             OFDFT_TRY(make_dir(0.0));
-            ud = s->hsc[16]; dd = s->hsc[17]; uLd = s->hsc[18]; dLd = s->hsc[19]; dHu = s->hsc[20];
+            read_dir();
             f0 = slope0();
         }
         if (!(f0 < 0.0)) break;                  // no descent possible at this precision

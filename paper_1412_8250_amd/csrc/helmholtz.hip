@@ -748,9 +748,9 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
                 if (b->precond) {
                     // one cycle and one dot phase (read r, z) after the init
                     // phase and after each iteration but the last
-                    const int cycles = std::max(1, it_pass[j]);
+                    const int cycles = it_pass[j];
                     bu += n * e * 2.0 * cycles;
-                    prof_add(K_MULTIGRID, mg_cycle_bytes(*b->mg_of[j]) * cycles, 0);
+                    prof_add(K_MULTIGRID_C, mg_cycle_bytes(*b->mg_of[j]) * cycles, 0);
                 }
             }
             prof_add(K_COCG, bs, 0);

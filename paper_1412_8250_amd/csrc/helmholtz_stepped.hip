@@ -298,17 +298,22 @@ int launch_update(ofdft_batch *b, hipStream_t s) {
 }
 
 // z = M r of every preconditioned system, then rho = r^T z (and beta).
-// Systems that are not running skip both inside the kernels.  Timed: each
-// cycle and the dot launch are timed; otherwise the caller accounts them.
+// Systems that are not running skip both inside the kernels.  Timed: the
+// host reads the statuses first and launches (and times) only the cycles of
+// running systems; otherwise the caller accounts them.
 int precondition(ofdft_batch *b, hipStream_t s, bool timed) {
+    if (timed) {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * b->nsys, hipMemcpyDeviceToHost, s));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+    }
     for (int j = 0; j < b->nsys; ++j) {
         Multigrid *mg = b->mg_of[j];
         const double *kap = &b->d_sys[j].kre;      // {kre, kim} of system j (device)
         const int *run = &b->d_step[j].done;
         if (timed) {
-            // bytes are added after the pass from the iteration counts (a
-            // converged system's cycle launches return at once)
-            ProfScope ps(K_MULTIGRID, 0.0, s);
+            if (b->h_step[j].done != H_RUNNING) continue;
+            // bytes are added after the pass from the iteration counts
+            ProfScope ps(K_MULTIGRID_C, 0.0, s);
             OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
         } else {
             OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
@@ -418,7 +423,7 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
     for (int j : which) b->h_step[j].done = H_RUNNING;
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_step, b->h_step, sizeof(StepState) * nsys, hipMemcpyHostToDevice, s));
     const bool timed = prof_timed(K_COCG) || prof_timed(K_COCG_UPDATE) ||
-                       (b->precond && prof_timed(K_MULTIGRID));
+                       (b->precond && prof_timed(K_MULTIGRID_C));
     {
         ProfScope ps(K_COCG, 0.0, s);
         OFDFT_TRY(launch_stencil_phase<T>(b, shape, PH_INIT, tol, s));
@@ -427,16 +432,39 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
         OFDFT_TRY(precondition(b, s, timed));
         if (!timed) {
             prof_add(K_COCG_UPDATE, 0.0, 1);
-            prof_add(K_MULTIGRID, 0.0, nsys);
+            prof_add(K_MULTIGRID_C, 0.0, nsys);
         }
     }
     int reps = 1;
+    std::vector<double> rn2_0(nsys, 0.0);     // residual after the init phase
+    bool first = true;
     for (;;) {
         OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * nsys, hipMemcpyDeviceToHost, s));
         OFDFT_CHECK_HIP(hipStreamSynchronize(s));
         bool running = false;
         for (int j : which) running = running || b->h_step[j].done == H_RUNNING;
         if (!running) break;
+        if (first) {
+            for (int j : which) rn2_0[j] = b->h_step[j].rn2;
+            first = false;
+        } else {
+            // replays until the slowest running system is predicted to converge,
+            // from its mean residual reduction per iteration so far
+            double need = 0.0;
+            bool known = true;
+            for (int j : which) {
+                const StepState &q = b->h_step[j];
+                if (q.done != H_RUNNING) continue;
+                const double rate = q.iter > 0 && rn2_0[j] > 0 ? std::log(q.rn2 / rn2_0[j]) / q.iter : 0.0;
+                if (!(rate < -1e-3) || !std::isfinite(rate)) {
+                    known = false;
+                    break;
+                }
+                need = std::max(need, std::log(q.tol2 / q.rn2) / rate);
+            }
+            reps = known ? (int)std::ceil(std::max(need, 1.0) / kStepIters) : reps * 2;
+            reps = std::max(1, std::min(reps, 32));
+        }
         if (timed) {
             OFDFT_TRY(step_iterations<T>(b, shape, reps * kStepIters, s, true));
         } else {
@@ -444,9 +472,8 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
             for (int k = 0; k < reps; ++k) OFDFT_CHECK_HIP(hipGraphLaunch(b->step_graph, s));
             prof_add(K_COCG, 0.0, reps * kStepIters);
             prof_add(K_COCG_UPDATE, 0.0, reps * kStepIters * (b->precond ? 2 : 1));
-            if (b->precond) prof_add(K_MULTIGRID, 0.0, (int64_t)reps * kStepIters * nsys);
+            if (b->precond) prof_add(K_MULTIGRID_C, 0.0, (int64_t)reps * kStepIters * nsys);
         }
-        reps = std::min(reps * 2, 32);
     }
     for (int j = 0; j < nsys; ++j) {
         iters[j] = b->h_step[j].iter;

@@ -25,22 +25,26 @@ MgDims dims_of(const MgLevel &L, double2 kappa) {
     return MgDims{L.nx, L.ny, L.nz, L.cx, L.cy, L.cz, 2.0 * (L.cx + L.cy + L.cz), kappa.x, kappa.y, L.n};
 }
 
-// Launch geometry: 64 x 4 threads over (x, y), one z plane per block row of
-// the grid, so point coordinates come from the launch indices (no divisions).
-constexpr int kMgBX = 64, kMgBY = 4;
+// Launch geometry: 64 x 4 threads over (x, y); each thread runs down a
+// column of kMgKZ consecutive z planes (grid z = chunks), keeping the column's
+// values in registers so that the z neighbours are loaded once.  Point
+// coordinates come from the launch indices (no divisions).
+constexpr int kMgBX = 64, kMgBY = 4, kMgKZ = 4;
 static_assert(kMgBX * kMgBY == kMgThreads, "block shape");
 
-dim3 mg_grid(int nx, int ny, int nz) { return dim3((nx + kMgBX - 1) / kMgBX, (ny + kMgBY - 1) / kMgBY, nz); }
+dim3 mg_grid(int nx, int ny, int nz) {
+    return dim3((nx + kMgBX - 1) / kMgBX, (ny + kMgBY - 1) / kMgBY, (nz + kMgKZ - 1) / kMgKZ);
+}
 
 struct MgPt {
-    int x, y, z;
-    int64_t i;
+    int x, y, z;     // z: first plane of the thread's column chunk
+    int64_t i;       // index of (x, y, z)
 };
 
 __device__ inline bool mg_point(int nx, int ny, MgPt &p) {
     p.x = blockIdx.x * kMgBX + threadIdx.x;
     p.y = blockIdx.y * kMgBY + threadIdx.y;
-    p.z = blockIdx.z;
+    p.z = blockIdx.z * kMgKZ;
     p.i = ((int64_t)p.z * ny + p.y) * nx + p.x;
     return p.x < nx && p.y < ny;
 }
@@ -89,26 +93,43 @@ template <typename C> __device__ inline C mk_c(double a, double b);
 template <> __device__ inline double2 mk_c<double2>(double a, double b) { return make_double2(a, b); }
 template <> __device__ inline float2 mk_c<float2>(double a, double b) { return make_float2((float)a, (float)b); }
 
-// (A u) at p for the periodic 7-point operator A = -Delta_h + kappa (second
-// order), u of element type TI, computed in S.
+// A u on the thread's column chunk for the periodic 7-point operator
+// A = -Delta_h + kappa (second order), u of element type TI, computed in S:
+// au[k] and the centre values cen[k] for planes p.z + k, k < kMgKZ (planes
+// at or beyond nz are left unset).
 template <typename S, typename TI>
-__device__ inline S apply7(const TI *__restrict__ u, const MgDims &d, const MgPt &p) {
+__device__ inline void apply7_col(const TI *__restrict__ u, const MgDims &d, const MgPt &p, S (&cen)[kMgKZ],
+                                  S (&au)[kMgKZ]) {
     using V = VT<S>;
     using R = typename MgT<S>::R;
     using C = typename MgT<S>::C;
-    const int64_t i = p.i, nxy = (int64_t)d.nx * d.ny;
-    const int64_t xp = p.x + 1 == d.nx ? i - p.x : i + 1;
-    const int64_t xm = p.x == 0 ? i + d.nx - 1 : i - 1;
-    const int64_t yp = p.y + 1 == d.ny ? i - (int64_t)p.y * d.nx : i + d.nx;
-    const int64_t ym = p.y == 0 ? i + (int64_t)(d.ny - 1) * d.nx : i - d.nx;
-    const int64_t zp = p.z + 1 == d.nz ? i - (int64_t)p.z * nxy : i + nxy;
-    const int64_t zm = p.z == 0 ? i + (int64_t)(d.nz - 1) * nxy : i - nxy;
-    const S c = cv<S>(u[i]);
-    S a = V::mul((R)d.diag, c);
-    a = mg_axpy((R)-d.cx, V::add(cv<S>(u[xp]), cv<S>(u[xm])), a);
-    a = mg_axpy((R)-d.cy, V::add(cv<S>(u[yp]), cv<S>(u[ym])), a);
-    a = mg_axpy((R)-d.cz, V::add(cv<S>(u[zp]), cv<S>(u[zm])), a);
-    return V::add(a, mg_scale(mk_c<C>(d.kre, d.kim), c));
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+    const int64_t row = (int64_t)p.y * d.nx + p.x;
+    const int dxp = p.x + 1 == d.nx ? -p.x : 1, dxm = p.x == 0 ? d.nx - 1 : -1;
+    const int64_t dyp = p.y + 1 == d.ny ? -(int64_t)p.y * d.nx : d.nx;
+    const int64_t dym = p.y == 0 ? (int64_t)(d.ny - 1) * d.nx : -(int64_t)d.nx;
+    S col[kMgKZ + 2];
+#pragma unroll
+    for (int k = 0; k < kMgKZ + 2; ++k) {
+        int z = p.z - 1 + k;
+        z = z < 0 ? z + d.nz : (z >= d.nz ? z - d.nz : z);
+        z = z >= d.nz ? d.nz - 1 : z;        // chunk tail past nz: any valid plane
+        col[k] = cv<S>(u[(int64_t)z * nxy + row]);
+    }
+    const C kap = mk_c<C>(d.kre, d.kim);
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k) {
+        if (p.z + k < d.nz) {
+            const int64_t i = (int64_t)(p.z + k) * nxy + row;
+            const S c = col[k + 1];
+            S a = V::mul((R)d.diag, c);
+            a = mg_axpy((R)-d.cx, V::add(cv<S>(u[i + dxp]), cv<S>(u[i + dxm])), a);
+            a = mg_axpy((R)-d.cy, V::add(cv<S>(u[i + dyp]), cv<S>(u[i + dym])), a);
+            a = mg_axpy((R)-d.cz, V::add(col[k], col[k + 2]), a);
+            cen[k] = c;
+            au[k] = V::add(a, mg_scale(kap, c));
+        }
+    }
 }
 
 // Per-launch shift source: when `kap` is given, kappa is read from device
@@ -139,17 +160,26 @@ __device__ inline C jacobi_factor(const MgDims &d, double w) {
 
 // The two pre-smoothing sweeps from u = 0 in one pass: with the Jacobi factor
 // s = omega / (diag + kappa), u1 = s f and u2 = u1 + s (f - A u1) = s (2 f - s A f).
+// When fl is given, f is also stored there in S (the fine level's later
+// passes then read the narrower copy).
 template <typename TF, typename S>
 __global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const TF *__restrict__ f,
-                                                      S *__restrict__ u, MgShift sh) {
+                                                      S *__restrict__ u, S *__restrict__ fl, MgShift sh) {
     if (!take_shift(sh, d)) return;
     MgPt p;
     if (!mg_point(d.nx, d.ny, p)) return;
     using V = VT<S>;
     const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
-    const S af = apply7<S>(f, d, p);
-    const S fi = cv<S>(f[p.i]);
-    u[p.i] = mg_scale(s, V::sub(V::add(fi, fi), mg_scale(s, af)));
+    S fc[kMgKZ], af[kMgKZ];
+    apply7_col(f, d, p, fc, af);
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k)
+        if (p.z + k < d.nz) {
+            const int64_t i = p.i + k * nxy;
+            u[i] = mg_scale(s, V::sub(V::add(fc[k], fc[k]), mg_scale(s, af[k])));
+            if (fl) fl[i] = fc[k];
+        }
 }
 
 // t = u + omega (f - A u) / (diag + kappa), computed in S, stored as TO
@@ -162,8 +192,15 @@ __global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, cons
     if (!mg_point(d.nx, d.ny, p)) return;
     using V = VT<S>;
     const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
-    const S r = V::sub(cv<S>(f[p.i]), apply7<S>(u, d, p));
-    t[p.i] = cv<TO>(V::add(u[p.i], mg_scale(s, r)));
+    S uc[kMgKZ], au[kMgKZ];
+    apply7_col(u, d, p, uc, au);
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k)
+        if (p.z + k < d.nz) {
+            const int64_t i = p.i + k * nxy;
+            t[i] = cv<TO>(V::add(uc[k], mg_scale(s, V::sub(cv<S>(f[i]), au[k]))));
+        }
 }
 
 // r = f - A u
@@ -174,11 +211,21 @@ __global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const TF *__
     if (!take_shift(sh, d)) return;
     MgPt p;
     if (!mg_point(d.nx, d.ny, p)) return;
-    r[p.i] = VT<S>::sub(cv<S>(f[p.i]), apply7<S>(u, d, p));
+    S uc[kMgKZ], au[kMgKZ];
+    apply7_col(u, d, p, uc, au);
+    const int64_t nxy = (int64_t)d.nx * d.ny;
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k)
+        if (p.z + k < d.nz) {
+            const int64_t i = p.i + k * nxy;
+            r[i] = VT<S>::sub(cv<S>(f[i]), au[k]);
+        }
 }
 
 // Full weighting: fc[I] = sum over the 27 fine points around 2I of
-// (1/8) w(dx) w(dy) w(dz) r, w(0) = 1, w(+-1) = 1/2 (= P^T / 8).
+// (1/8) w(dx) w(dy) w(dz) r, w(0) = 1, w(+-1) = 1/2 (= P^T / 8).  A thread
+// runs down kMgKZ coarse planes; each fine plane's 9-point (x, y) sum is
+// formed once and shared by the coarse planes it touches.
 template <typename S>
 __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const S *__restrict__ r,
                                                           S *__restrict__ fc, MgShift sh) {
@@ -187,34 +234,44 @@ __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, 
     if (!mg_point(cd.nx, cd.ny, P)) return;
     using V = VT<S>;
     using R = typename MgT<S>::R;
-    const int64_t fnxy = (int64_t)fd.nx * fd.ny;
-    int xs[3], ys[3], zs[3];
+    const int64_t fnxy = (int64_t)fd.nx * fd.ny, cnxy = (int64_t)cd.nx * cd.ny;
+    int xs[3];
+    int64_t ys[3];
     xs[0] = P.x == 0 ? fd.nx - 1 : 2 * P.x - 1;
     xs[1] = 2 * P.x;
     xs[2] = 2 * P.x + 1;         // fine axes are even, so 2X + 1 < n
-    ys[0] = P.y == 0 ? fd.ny - 1 : 2 * P.y - 1;
-    ys[1] = 2 * P.y;
-    ys[2] = 2 * P.y + 1;
-    zs[0] = P.z == 0 ? fd.nz - 1 : 2 * P.z - 1;
-    zs[1] = 2 * P.z;
-    zs[2] = 2 * P.z + 1;
-    S acc = V::zero();
+    ys[0] = (int64_t)(P.y == 0 ? fd.ny - 1 : 2 * P.y - 1) * fd.nx;
+    ys[1] = (int64_t)(2 * P.y) * fd.nx;
+    ys[2] = (int64_t)(2 * P.y + 1) * fd.nx;
+    // plane sums q[j] for fine planes 2 Z0 - 1 + j, j = 0 .. 2 kMgKZ
+    S q[2 * kMgKZ + 1];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const R wz = c == 1 ? (R)1 : (R)0.5;
+    for (int j = 0; j < 2 * kMgKZ + 1; ++j) {
+        int z = 2 * P.z - 1 + j;
+        z = z < 0 ? z + fd.nz : (z >= fd.nz ? fd.nz - 1 : z);    // past the end: unused, any valid plane
+        const int64_t base = (int64_t)z * fnxy;
+        S acc = V::zero();
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            const R wy = b == 1 ? wz : (R)0.5 * wz;
-            const int64_t row = (int64_t)zs[c] * fnxy + (int64_t)ys[b] * fd.nx;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) acc = mg_axpy(a == 1 ? wy : (R)0.5 * wy, r[row + xs[a]], acc);
+            const R wy = b == 1 ? (R)1 : (R)0.5;
+            const S rowsum = V::add(mg_axpy((R)0.5, V::add(r[base + ys[b] + xs[0]], r[base + ys[b] + xs[2]]),
+                                            V::zero()),
+                                    r[base + ys[b] + xs[1]]);
+            acc = mg_axpy(wy, rowsum, acc);
         }
+        q[j] = acc;
     }
-    fc[P.i] = V::mul((R)0.125, acc);
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k)
+        if (P.z + k < cd.nz) {
+            const S sz = V::add(mg_axpy((R)0.5, V::add(q[2 * k], q[2 * k + 2]), V::zero()), q[2 * k + 1]);
+            fc[P.i + k * cnxy] = V::mul((R)0.125, sz);
+        }
 }
 
 // Trilinear prolongation added to u: fine index i takes coarse i/2 (even i)
-// or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.
+// or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.  A thread runs
+// down kMgKZ fine planes (kMgKZ / 2 + 1 coarse planes, loaded once).
 template <typename S>
 __global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const S *__restrict__ uc,
                                                              S *__restrict__ u, MgShift sh) {
@@ -223,21 +280,33 @@ __global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims c
     if (!mg_point(fd.nx, fd.ny, p)) return;
     using V = VT<S>;
     using R = typename MgT<S>::R;
-    const int64_t cnxy = (int64_t)cd.nx * cd.ny;
-    const int x0 = p.x >> 1, y0 = p.y >> 1, z0 = p.z >> 1;
+    static_assert(kMgKZ % 2 == 0, "chunks start on even planes");
+    const int64_t cnxy = (int64_t)cd.nx * cd.ny, fnxy = (int64_t)fd.nx * fd.ny;
+    const int x0 = p.x >> 1, y0 = p.y >> 1;
     const int x1 = (p.x & 1) ? (x0 + 1 == cd.nx ? 0 : x0 + 1) : x0;
     const int y1 = (p.y & 1) ? (y0 + 1 == cd.ny ? 0 : y0 + 1) : y0;
-    const int z1 = (p.z & 1) ? (z0 + 1 == cd.nz ? 0 : z0 + 1) : z0;
-    const int64_t r00 = (int64_t)z0 * cnxy + (int64_t)y0 * cd.nx, r01 = (int64_t)z0 * cnxy + (int64_t)y1 * cd.nx;
-    const int64_t r10 = (int64_t)z1 * cnxy + (int64_t)y0 * cd.nx, r11 = (int64_t)z1 * cnxy + (int64_t)y1 * cd.nx;
-    // the 8 corner weights are 1/8 each; duplicated corners (even indices)
-    // add up to the weights 1, 1/2, 1/4 of fewer distinct points
-    S acc = V::zero();
-    acc = V::add(acc, V::add(uc[r00 + x0], uc[r00 + x1]));
-    acc = V::add(acc, V::add(uc[r01 + x0], uc[r01 + x1]));
-    acc = V::add(acc, V::add(uc[r10 + x0], uc[r10 + x1]));
-    acc = V::add(acc, V::add(uc[r11 + x0], uc[r11 + x1]));
-    u[p.i] = mg_axpy((R)0.125, acc, u[p.i]);
+    const int64_t o00 = (int64_t)y0 * cd.nx + x0, o01 = (int64_t)y0 * cd.nx + x1;
+    const int64_t o10 = (int64_t)y1 * cd.nx + x0, o11 = (int64_t)y1 * cd.nx + x1;
+    // (x, y) interpolation (sum of the 4 corners, weight 1/4 each) on coarse
+    // planes Z0 .. Z0 + kMgKZ / 2 (periodic)
+    S cp[kMgKZ / 2 + 1];
+#pragma unroll
+    for (int j = 0; j < kMgKZ / 2 + 1; ++j) {
+        int Z = (p.z >> 1) + j;
+        Z = Z >= cd.nz ? Z - cd.nz : Z;
+        Z = Z >= cd.nz ? cd.nz - 1 : Z;      // past the end: unused, any valid plane
+        const int64_t b = (int64_t)Z * cnxy;
+        cp[j] = V::add(V::add(uc[b + o00], uc[b + o01]), V::add(uc[b + o10], uc[b + o11]));
+    }
+#pragma unroll
+    for (int k = 0; k < kMgKZ; ++k)
+        if (p.z + k < fd.nz) {
+            // even plane: coarse plane k/2 (weight 1); odd: mean of k/2 and k/2 + 1
+            const S e = (k & 1) ? mg_axpy((R)0.125, V::add(cp[k >> 1], cp[(k >> 1) + 1]), V::zero())
+                                : V::mul((R)0.25, cp[k >> 1]);
+            const int64_t i = p.i + k * fnxy;
+            u[i] = V::add(u[i], e);
+        }
 }
 
 // Exact solve on the coarsest grid (at most 16^3 points, one workgroup, FP64):
@@ -327,7 +396,7 @@ int vcycle_coarse(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s
     const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
     MgLevel &C = mg.lv[l + 1];
     const MgDims cd = dims_of(C, kappa);
-    hipLaunchKernelGGL((mg_pre2<S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, u, sh);
+    hipLaunchKernelGGL((mg_pre2<S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, u, (S *)nullptr, sh);
     hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, (const S *)f, (const S *)u, (S *)L.r, sh);
     hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
                        (S *)C.f, sh);
@@ -342,7 +411,9 @@ int vcycle_coarse(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s
 
 // The whole cycle z = M f: level 0 reads f and writes z in FP64 (TIO), its
 // work arrays are S.  V(2,2): both pre-sweeps in one pass into u, residual,
-// coarse correction added to u, post-sweeps u -> t -> z.
+// coarse correction added to u, post-sweeps u -> t -> z.  With S narrower
+// than TIO the pre-sweep pass also stores f in S (level 0's f array), which
+// the residual and the post-sweeps read instead of the FP64 input.
 template <typename TIO, typename S>
 int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipStream_t s) {
     MgLevel &L = mg.lv[0];
@@ -356,15 +427,27 @@ int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipSt
     S *u = (S *)L.u, *t = (S *)L.t;
     MgLevel &C = mg.lv[1];
     const MgDims cd = dims_of(C, kappa);
-    hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, sh);
-    hipLaunchKernelGGL((mg_residual<TIO, S>), grid, block, 0, s, d, f, (const S *)u, (S *)L.r, sh);
+    if constexpr (sizeof(S) < sizeof(TIO)) {
+        S *fl = (S *)L.f;
+        hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, fl, sh);
+        hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, (const S *)fl, (const S *)u, (S *)L.r, sh);
+    } else {
+        hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, (S *)nullptr, sh);
+        hipLaunchKernelGGL((mg_residual<TIO, S>), grid, block, 0, s, d, f, (const S *)u, (S *)L.r, sh);
+    }
     hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
                        (S *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     OFDFT_TRY(vcycle_coarse<S>(mg, 1, kappa, sh, s));
     hipLaunchKernelGGL(mg_prolong_add<S>, grid, block, 0, s, d, cd, (const S *)C.u, u, sh);
-    hipLaunchKernelGGL((mg_smooth<TIO, S, S>), grid, block, 0, s, d, mg.omega, f, (const S *)u, t, sh);
-    hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, (const S *)t, z, sh);
+    if constexpr (sizeof(S) < sizeof(TIO)) {
+        const S *fl = (const S *)L.f;
+        hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, fl, (const S *)u, t, sh);
+        hipLaunchKernelGGL((mg_smooth<S, S, TIO>), grid, block, 0, s, d, mg.omega, fl, (const S *)t, z, sh);
+    } else {
+        hipLaunchKernelGGL((mg_smooth<TIO, S, S>), grid, block, 0, s, d, mg.omega, f, (const S *)u, t, sh);
+        hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, (const S *)t, z, sh);
+    }
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
@@ -411,8 +494,9 @@ int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32) {
         MgLevel &M = mg.lv[l];
         const size_t b = es * (size_t)M.n;
         void **own[4] = {&M.t, &M.r, &M.u, &M.f};
-        // level 0 reads the caller's f; a one-level hierarchy needs nothing
-        const int count = nlev == 1 ? 0 : (l == 0 ? 3 : 4);
+        // level 0 reads the caller's f (and keeps an FP32 copy of it when the
+        // levels are FP32); a one-level hierarchy needs nothing
+        const int count = nlev == 1 ? 0 : (l == 0 && !fp32 ? 3 : 4);
         for (int k = 0; k < count; ++k) {
             void *p = nullptr;
             if (hipMalloc(&p, b) != hipSuccess) {
@@ -449,19 +533,21 @@ int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *
     return mg.fp32 ? vcycle<double2, float2>(mg, r, z, k, sh, s) : vcycle<double2, double2>(mg, r, z, k, sh, s);
 }
 
-// Algorithmic bytes of one cycle.  Fine level: f (FP64) is read by the
-// pre-smoothing, the residual and both post-sweeps, z (FP64) written once;
-// work arrays (FP32 or FP64): u written, residual reads u and writes r,
-// restriction reads r and writes an eighth, prolongation reads an eighth and
-// reads and writes u, the post-sweeps read u / t and write t.  Each coarser
-// level moves 14.25 work-array elements per point, and they hold 1/7 of the
-// fine points in all.
+// Algorithmic bytes of one cycle.  Fine level, FP64 levels: f is read by the
+// pre-smoothing, the residual and both post-sweeps, z written once, and the
+// work arrays move 9.25 elements per point (u written; residual reads u and
+// writes r; restriction reads r and writes an eighth; prolongation reads an
+// eighth and reads and writes u; the post-sweeps read u / t and write t).
+// FP32 levels: f (FP64) is read once and stored as FP32, which the other
+// three passes read (4 more FP32 moves).  Each coarser level moves 14.25
+// elements per point, and they hold 1/7 of the fine points in all.
 double mg_cycle_bytes(const Multigrid &mg) {
     if (mg.lv.empty()) return 0.0;
     const double E = (double)mg.elem, e = mg.fp32 ? E / 2 : E;
     const double n = (double)mg.lv[0].n;
     if (mg.lv.size() == 1) return 2.0 * n * E;
-    return n * (5.0 * E + 9.25 * e) + n / 7.0 * 14.25 * e;
+    const double fine = mg.fp32 ? 2.0 * E + 13.25 * e : 5.0 * E + 9.25 * e;
+    return n * fine + n / 7.0 * 14.25 * e;
 }
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible

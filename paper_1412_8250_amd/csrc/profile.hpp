@@ -22,7 +22,8 @@ enum KClass {
     K_POINTWISE,       // other vector passes (projections, casts, assembly)
     K_NN,              // network convolutions and their gradients
     K_COCG_UPDATE,     // batched COCG (stepped): x, r update + r.r
-    K_MULTIGRID,       // multigrid V-cycles (Poisson preconditioner)
+    K_MULTIGRID,       // multigrid cycles on FP64 vectors (Poisson, density update)
+    K_MULTIGRID_C,     // multigrid cycles on complex128 vectors (shifted systems)
     K_CLASSES
 };
 

@@ -200,3 +200,24 @@ def test_kernel_batch_workload():
         assert helmholtz.residual(xs[j], f, kap, h) <= 1e-8
     assert max(s["rel_res"] for s in st) <= 1e-8
     assert max(s["iters"] for s in st) <= 30
+
+
+def test_profiled_path_equals_graph_path():
+    """With per-launch timing of the cycles the iterations run eagerly (no
+    graph) and skip the cycles of converged systems; results are bitwise the
+    same and the timed launches are exactly the cycles run."""
+    announce("mg-cocg timed path")
+    rng = np.random.default_rng(12)
+    cells = [((32, 32, 32), (0.45,) * 3, k, rng.normal(size=(32, 32, 32)) + 1j * rng.normal(size=(32, 32, 32)))
+             for k in (-1.7 - 1.7j, 0.24 - 0.93j, 2.0 + 0.3j)]
+    xa, sa = _solve(cells, 1e-9)
+    ofd.profile_reset(timed=("multigrid_c",))
+    try:
+        xb, sb = _solve(cells, 1e-9)
+        prof = ofd.profile_read()["multigrid_c"]
+    finally:
+        ofd.profile_reset()
+    for a, b in zip(xa, xb):
+        assert np.array_equal(a, b)
+    assert [s["iters"] for s in sa] == [s["iters"] for s in sb]
+    assert prof["timed"] == prof["launches"] == sum(s["iters"] for s in sb)
