@@ -462,6 +462,12 @@ void precond_free(ofdft_batch *b) {
         if (p) (void)hipFree(p);
     if (b->d_kap) (void)hipFree(b->d_kap);
     b->d_kap = nullptr;
+    for (hipStream_t q : b->mg_lane) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : b->mg_join) (void)hipEventDestroy(e);
+    if (b->mg_fork) (void)hipEventDestroy(b->mg_fork);
+    b->mg_lane.clear();
+    b->mg_join.clear();
+    b->mg_fork = nullptr;
     b->mg_own.clear();
     b->mg_of.clear();
     b->z.clear();
@@ -647,6 +653,10 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
     std::vector<Multigrid *> own, of(b->nsys, nullptr);
     std::vector<void *> z(b->nsys, nullptr);
     double *kap = nullptr;
+    const int lanes = std::min(b->nsys, kMgLanes);
+    std::vector<hipStream_t> lane;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
     auto undo = [&](int st) {
         for (Multigrid *mg : own) {
             mg_free(*mg);
@@ -655,8 +665,20 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
         for (void *p : z)
             if (p) (void)hipFree(p);
         if (kap) (void)hipFree(kap);
+        for (hipStream_t q : lane) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
         return st;
     };
+    for (int k = 0; k < lanes; ++k) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) return undo(OFDFT_HIP_ERROR);
+        lane.push_back(q);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return undo(OFDFT_HIP_ERROR);
+        join.push_back(e);
+    }
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return undo(OFDFT_HIP_ERROR);
     if (hipMalloc(&kap, 2 * sizeof(double)) != hipSuccess) {
         kap = nullptr;
         set_error("ofdft_batch_set_preconditioner: out of device memory");
@@ -664,7 +686,7 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
     }
     for (int j = 0; j < b->nsys; ++j) {
         const ofdft_grid &g = b->grids[j];
-        for (int i = 0; i < j && !of[j]; ++i) {
+        for (int i = j % lanes; i < j && !of[j]; i += lanes) {      // same lane only
             const ofdft_grid &q = b->grids[i];
             if (q.nx == g.nx && q.ny == g.ny && q.nz == g.nz && q.hx == g.hx && q.hy == g.hy && q.hz == g.hz)
                 of[j] = of[i];
@@ -689,6 +711,9 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
     b->mg_of = of;
     b->z = z;
     b->d_kap = kap;
+    b->mg_lane = lane;
+    b->mg_join = join;
+    b->mg_fork = fork;
     b->precond = kind;
     return OFDFT_OK;
 }

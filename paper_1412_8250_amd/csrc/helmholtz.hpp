@@ -122,9 +122,18 @@ struct ofdft_batch {
     double *d_kap = nullptr;      // {Re, Im} for ofdft_batch_apply_preconditioner
     std::vector<void *> z;
     std::vector<ofdft::Multigrid *> mg_of, mg_own;
+    // the systems' cycles run on kMgLanes side streams (system j on lane
+    // j % lanes), forked from and joined back into the solve's stream, so
+    // the latency-bound coarse levels of different systems overlap; systems
+    // share a hierarchy only within a lane
+    std::vector<hipStream_t> mg_lane;
+    std::vector<hipEvent_t> mg_join;
+    hipEvent_t mg_fork = nullptr;
 };
 
 namespace ofdft {
+
+constexpr int kMgLanes = 4;
 
 // Stepped schedule: run COCG on the systems in `which` (system table `hs`
 // already uploaded; maxit[j] per system) to relative residual tol.  On return

@@ -298,26 +298,37 @@ int launch_update(ofdft_batch *b, hipStream_t s) {
 }
 
 // z = M r of every preconditioned system, then rho = r^T z (and beta).
-// Systems that are not running skip both inside the kernels.  Timed: the
-// host reads the statuses first and launches (and times) only the cycles of
-// running systems; otherwise the caller accounts them.
+// Systems that are not running skip both inside the kernels.  The cycles run
+// on the batch's side streams (forked from s and joined back; inside a graph
+// capture this makes parallel branches).  Timed: the host reads the
+// statuses first and launches (and times) only the cycles of running
+// systems, one after another on s, so each cycle's duration is its own;
+// otherwise the caller accounts them.
 int precondition(ofdft_batch *b, hipStream_t s, bool timed) {
     if (timed) {
         OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * b->nsys, hipMemcpyDeviceToHost, s));
         OFDFT_CHECK_HIP(hipStreamSynchronize(s));
     }
+    const int lanes = timed ? 0 : (int)b->mg_lane.size();
+    if (lanes) OFDFT_CHECK_HIP(hipEventRecord(b->mg_fork, s));
+    for (int k = 0; k < lanes; ++k) OFDFT_CHECK_HIP(hipStreamWaitEvent(b->mg_lane[k], b->mg_fork, 0));
     for (int j = 0; j < b->nsys; ++j) {
         Multigrid *mg = b->mg_of[j];
         const double *kap = &b->d_sys[j].kre;      // {kre, kim} of system j (device)
         const int *run = &b->d_step[j].done;
+        hipStream_t q = lanes ? b->mg_lane[j % lanes] : s;
         if (timed) {
             if (b->h_step[j].done != H_RUNNING) continue;
             // bytes are added after the pass from the iteration counts
-            ProfScope ps(K_MULTIGRID_C, 0.0, s);
-            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
+            ProfScope ps(K_MULTIGRID_C, 0.0, q);
+            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, q));
         } else {
-            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, s));
+            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, q));
         }
+    }
+    for (int k = 0; k < lanes; ++k) {
+        OFDFT_CHECK_HIP(hipEventRecord(b->mg_join[k], b->mg_lane[k]));
+        OFDFT_CHECK_HIP(hipStreamWaitEvent(s, b->mg_join[k], 0));
     }
     ProfScope ps(K_COCG_UPDATE, 0.0, s, timed);
     hipLaunchKernelGGL(step_dot<double2>, dim3(b->step_vblocks), dim3(kVecThreadsStep), 0, s, b->d_sys,
