@@ -1,0 +1,99 @@
+"""Pins of the order-2 kernel-term oracle (Section 2 linearised kernel energy
+and C_mnpq; Section 3.1 local reformulation; Appendix A table): the
+potential is the derivative of the energy (central differences), the L = 0
+case reduces to the K_00 oracle, each kernel operator is real and symmetric,
+a uniform density gives a uniform potential."""
+import numpy as np
+import pytest
+
+from oracle import kernel, wgc
+
+
+def _density(shape, seed, volume_per_point=0.4 ** 3):
+    rng = np.random.default_rng(seed)
+    z, y, x = np.meshgrid(*[np.arange(s) / s for s in shape], indexing="ij")
+    g = np.zeros(shape)
+    for _ in range(6):
+        k = rng.integers(0, 3, size=3)
+        g += rng.normal() * np.cos(2 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + rng.uniform(0, 2 * np.pi))
+    rho_bar = 0.0284
+    rho = rho_bar * (1.0 + 0.05 * g / np.abs(g).max())
+    return rho, rho_bar
+
+
+def test_potential_is_the_energy_derivative():
+    shape, h = (10, 8, 12), (0.41, 0.47, 0.39)
+    rho, _ = _density(shape, 3)
+    dv = float(np.prod(h))
+    vol = dv * rho.size
+    ne = float(rho.sum() * dv)
+    v = wgc.potential(rho, h, ne, vol)
+    for idx in [(0, 0, 0), (3, 5, 7), (9, 2, 11), (5, 7, 1)]:
+        eps = 1e-4 * rho[idx]
+        rp, rm = rho.copy(), rho.copy()
+        rp[idx] += eps
+        rm[idx] -= eps
+        # N_e and the volume (hence kF and rho_bar) stay those of rho: the
+        # derivative is taken at fixed expansion point
+        d = (wgc.energy(rp, h, ne, vol) - wgc.energy(rm, h, ne, vol)) / (2 * eps * dv)
+        assert abs(d - v[idx]) <= 1e-6 * abs(v[idx]), (idx, d, v[idx])
+
+
+def test_order_zero_is_the_k00_oracle():
+    shape, h = (8, 10, 9), (0.45, 0.4, 0.5)
+    rho, rho_bar = _density(shape, 5)
+    dv = float(np.prod(h))
+    vol, ne = dv * rho.size, float(rho.sum() * dv)
+    V = kernel.solve_all(rho, h, ne, vol)
+    ref = kernel.potential(rho, V, 1e-12 * ne / vol)
+    got = wgc.potential(rho, h, ne, vol, L=0)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mn", [(0, 0), (1, 0), (2, 0), (1, 1)])
+def test_kernel_operators_are_real_and_symmetric(mn):
+    rng = np.random.default_rng(7)
+    shape, h = (8, 9, 10), (0.4, 0.45, 0.5)
+    a, b = rng.normal(size=shape), rng.normal(size=shape)
+    vol = float(np.prod(h)) * a.size
+    Ka = wgc.apply_kernel(*mn, a, h, 10.0, vol)
+    Kb = wgc.apply_kernel(*mn, b, h, 10.0, vol)
+    assert abs(np.sum(Ka * b) - np.sum(a * Kb)) <= 1e-12 * np.abs(Ka).sum() * np.abs(b).max()
+    # a constant is scaled by K_mn(0): sum_r P_r / Q_r (zero for K_00, whose
+    # right-hand side is a Laplacian)
+    P, Q = wgc.coefficients(*mn)
+    k0 = 0.0 if mn == (0, 0) else float(np.real(sum(P[r] / Q[r] for r in range(4))))
+    Kc = wgc.apply_kernel(*mn, np.ones(shape), h, 10.0, vol)
+    assert np.abs(Kc - k0).max() <= 1e-12 * max(1.0, abs(k0))
+
+
+def test_uniform_density_gives_uniform_potential_and_table_symmetry():
+    shape, h = (8, 8, 8), (0.5,) * 3
+    rho = np.full(shape, 0.03)
+    vol = 0.125 * rho.size
+    v = wgc.potential(rho, h, float(rho.sum() * 0.125), vol)
+    assert np.ptp(v) <= 1e-12 * np.abs(v).max()
+    for mn in wgc.TABLE:
+        P, Q = wgc.coefficients(*mn)
+        assert P[1] == np.conj(P[0]) and Q[3] == np.conj(Q[2])
+
+
+def test_system_list():
+    s = wgc.systems(2)
+    assert len(s) == 32                       # 16 distinct convolutions x r = 1, 3
+    convs = {(m, n, round(a, 12)) for m, n, a, _ in s}
+    assert len(convs) == 16
+    assert len(wgc.systems(0)) == 4
+
+
+@pytest.mark.parametrize("m,n", [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)])
+def test_c_mnpq_is_the_taylor_expansion(m, n):
+    """sum_pq C_mnpq x^(m-p) y^(n-q) = (x - r)^m (y - r)^n / (m! n! r^(m+n)):
+    the coefficients expand the kernel in powers of (rho - rho_bar)."""
+    import math
+    r = 0.0284
+    for x, y in ((0.03, 0.025), (0.02, 0.041), (r, 0.05)):
+        lhs = sum(wgc.c_mnpq(m, n, p, q, r) * x ** (m - p) * y ** (n - q)
+                  for p in range(m + 1) for q in range(n + 1))
+        rhs = (x - r) ** m * (y - r) ** n / (math.factorial(m) * math.factorial(n) * r ** (m + n))
+        assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(rhs))
