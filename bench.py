@@ -322,6 +322,22 @@ def main():
                 extras[f"poisson_{name}_nn_applies"] = st["nn_applies"]
                 extras[f"poisson_{name}_fell_back"] = st["fell_back"]
             s.close()
+        # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)
+        # on the same cell: one step from the initial state
+        t0 = time.perf_counter()
+        scf2 = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3,
+                       u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8, poisson_mode=ofd.MULTIGRID,
+                       helmholtz_precond=ofd.PRECOND_MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID, lr_order=2)
+        torch.cuda.synchronize()
+        create_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        scf2.step()
+        torch.cuda.synchronize()
+        extras["scf_step_order2_kernel_terms"] = {"seconds": time.perf_counter() - t0,
+                                                  "context_and_v0_seconds": create_s,
+                                                  "stats": scf2.stats()}
+        scf2.close()
+        del scf2
         log("extras", extras)
 
     cpu = None

@@ -252,6 +252,12 @@ typedef struct {
                                   Polak-Ribiere xi = <r - r_prev, z> / <r_prev, z_prev>.
                                   Same minimiser, several times fewer iterations; every
                                   axis must halve evenly down to at most 16 points     */
+    int lr_order;              /* kernel terms (mu = 1): 0 = K_00 only (8 shifted systems,
+                                  4 solved); 2 = the order-2 expansion of Section 2 with
+                                  the K_00, K_10, K_20, K_11 rows of Appendix A (pairs
+                                  m + n <= 2): 16 distinct convolutions K_mn rho^a, 64
+                                  shifted systems, 32 solved (r = 2, 4 conjugates),
+                                  batched 8 at a time                                  */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;
@@ -263,11 +269,15 @@ int ofdft_scf_destroy(ofdft_scf *s);
 int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream);
 
 /* State access for checkpointing and inspection.  which: 0 = v, 1 = u, 2 = phi,
- * 3 = V_LR (device FP64 arrays of nx*ny*nz values); 4..11 = the solution of
- * shifted system which-4, kept as its next warm start (device complex128
- * arrays, 2*nx*ny*nz doubles; mu = 1 only; the odd systems are the
- * conjugates of the even ones and are rewritten from them after each
- * step).  INVALID_ARG for other values. */
+ * 3 = V_LR (device FP64 arrays of nx*ny*nz values); 4.. = the solutions of
+ * the shifted systems, kept as their next warm starts (device complex128
+ * arrays, 2*nx*ny*nz doubles; mu = 1 only): lr_order 0: 4..11 = system
+ * which-4 of the K_00 set (the odd systems are the conjugates of the even
+ * ones and are rewritten from them after each step); lr_order 2: 4..35 =
+ * solved system which-4, convolution (which-4)/2 with r = 1 (even) or 3 (odd),
+ * convolutions ordered by kernel pair (m, n) = (0,0), (0,1), (0,2), (1,0),
+ * (1,1), (2,0), then p, q, then the beta-side power before the alpha-side
+ * one, each (kernel, power) once.  INVALID_ARG for other values. */
 int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream);
 int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
 /* Forget the Anderson history and the line-search step memory, so that the

@@ -50,7 +50,7 @@ class ScfParams(ctypes.Structure):
                 ("u_max_iter", ctypes.c_int), ("poisson_tol", ctypes.c_double),
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
-                ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int)]
+                ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int)]
 
 
 _lib = None
@@ -367,7 +367,7 @@ class SCF:
                  u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
-                 u_precond: int = PRECOND_NONE, stream=None):
+                 u_precond: int = PRECOND_NONE, lr_order: int = 0, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -378,6 +378,7 @@ class SCF:
         p.line_tol = float(line_tol)
         p.helmholtz_precond = int(helmholtz_precond)
         p.u_precond = int(u_precond)
+        p.lr_order = int(lr_order)
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),
@@ -389,7 +390,8 @@ class SCF:
         return res.value
 
     def get(self, which: int, out, stream=None):
-        """Copy state vector `which` into `out` (float64 for 0..3, complex128 for 4..11)."""
+        """Copy state vector `which` into `out` (float64 for 0..3, complex128 for the
+        shifted-system solutions 4..11 (lr_order 0) or 4..35 (lr_order 2))."""
         _check(lib().ofdft_scf_get(self._h, int(which), _dev(out, self.shape), _stream(stream)))
         return out
 
@@ -403,7 +405,8 @@ class SCF:
         """Device copies of every state vector (restorable with restore())."""
         import torch
         snap = {}
-        for which in range(12 if self.params.mu else 4):
+        nsol = (8 if self.params.lr_order == 0 else 32) if self.params.mu else 0
+        for which in range(4 + nsol):
             dt = torch.float64 if which < 4 else torch.complex128
             t = torch.empty(self.shape, dtype=dt, device="cuda")
             self.get(which, t)

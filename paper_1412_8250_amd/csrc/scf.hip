@@ -111,6 +111,200 @@ struct VlrOp {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Order-2 kernel terms (Section 2, the Taylor expansion of the density-
+// dependent kernel about rho_bar with C_mnpq = (-1)^(p+q) / (m! n!)
+// binom(m,p) binom(n,q) rho_bar^(p+q-m-n); Section 3.1, the local form;
+// Appendix A, P and Q of K_00, K_10, K_20, K_11 for r = 1, 3, with
+// P_mn = P_nm, Q_mn = Q_nm and r = 2, 4 the conjugates).  The pairs with
+// m + n <= 2 are the ones the table covers.  Q_11 for r = 1 is printed with an
+// imaginary part of -0.0266195, one digit more than every other entry; it is
+// read as -0.266195, next to K_20's -0.233840 (the smaller value would place
+// the shift almost on the real axis inside the spectrum of -L_h).
+// K_mn rho^a = sum_r V_r with (-L_h + kappa_r) V_r = (2 kF)^2 P_r rho^a for
+// m + n > 0 and P_r (-L_h rho^a) for K_00, kappa_r = (2 kF)^2 Q_r; with a
+// real rho the r = 2, 4 solutions are conjugates of r = 1, 3, so the sum is
+// W = 2 Re(V_1 + V_3).
+//   V_LR = C_F sum_{m,n,p,q} C_mnpq [ (m-p+alpha) rho^(m-p+alpha-1) K_mn rho^(n-q+beta)
+//                                   + (n-q+beta) rho^(n-q+beta-1) K_mn rho^(m-p+alpha) ].
+struct LrKernel {
+    int m, n;
+    double P[2][2], Q[2][2];     // r = 1, 3: {re, im}
+};
+const LrKernel kLrTable[4] = {
+    {0, 0, {{0.108403, 0.079657}, {-0.908403, 0.439708}}, {{-0.470923, -0.465392}, {0.066051, -0.259678}}},
+    {1, 0, {{-0.030515, 0.015027}, {0.028915, -0.008817}}, {{-0.597793, -0.294130}, {-0.087917, -0.164937}}},
+    {2, 0, {{0.008907, -0.032841}, {-0.034974, 0.009116}}, {{-0.537986, -0.233840}, {-0.041565, -0.196662}}},
+    {1, 1, {{0.012423, -0.034421}, {-0.031907, 0.007392}}, {{-0.511699, -0.266195}, {-0.034031, -0.188927}}},
+};
+
+double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
+
+// The distinct convolutions and the V_LR terms of the order-L expansion
+// (L = 0 or 2), in the documented order.
+void lr_setup(int L, double rho_bar, std::vector<LrConv> &conv, std::vector<LrTerm> &terms) {
+    conv.clear();
+    terms.clear();
+    auto conv_index = [&](int m, int n, double a) {
+        const int km = std::max(m, n), kn = std::min(m, n);
+        for (size_t c = 0; c < conv.size(); ++c)
+            if (conv[c].m == km && conv[c].n == kn && std::fabs(conv[c].a - a) < 1e-12) return (int)c;
+        LrConv e{km, kn, a, {}, {}};
+        for (const LrKernel &k : kLrTable)
+            if (k.m == km && k.n == kn)
+                for (int r = 0; r < 2; ++r) {
+                    e.P[r] = make_double2(k.P[r][0], k.P[r][1]);
+                    e.Q[r] = make_double2(k.Q[r][0], k.Q[r][1]);
+                }
+        conv.push_back(e);
+        return (int)conv.size() - 1;
+    };
+    for (int m = 0; m <= L; ++m)
+        for (int n = 0; n <= L; ++n) {
+            if (m + n > L) continue;
+            for (int p = 0; p <= m; ++p)
+                for (int q = 0; q <= n; ++q) {
+                    const double a = m - p + kAlpha, b = n - q + kBeta;
+                    const int cb = conv_index(m, n, b), ca = conv_index(m, n, a);
+                    const double c = ((p + q) % 2 ? -1.0 : 1.0) / (fact(m) * fact(n)) * binom(m, p) * binom(n, q) *
+                                     std::pow(rho_bar, p + q - m - n);
+                    terms.push_back(LrTerm{kCF * c * a, a - 1.0, cb});
+                    terms.push_back(LrTerm{kCF * c * b, b - 1.0, ca});
+                }
+        }
+}
+
+// Right-hand sides of one round of solved systems: F_k = c_k g_k with g the
+// power rho^a (or -L_h rho^a for K_00, from the precomputed fa / fb).
+struct LrRhsOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 8 + 16 * kLrRound;
+    const double *u, *fa, *fb;
+    double2 *F[kLrRound];
+    double cre[kLrRound], cim[kLrRound], a[kLrRound];
+    int lap[kLrRound];          // 0: rho^a; 1: fa (-L_h rho^alpha); 2: fb (-L_h rho^beta)
+    int count;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double rho = u[i] * u[i];
+        const double lr = rho > 0.0 ? log(rho) : 0.0;
+        for (int k = 0; k < count; ++k) {
+            const double g = lap[k] == 1 ? fa[i] : (lap[k] == 2 ? fb[i] : (rho > 0.0 ? exp(a[k] * lr) : 0.0));
+            F[k][i] = make_double2(cre[k] * g, cim[k] * g);
+        }
+    }
+};
+
+// W_c = 2 Re(V_{2c} + V_{2c+1}) for the convolutions of one round
+struct LrSumOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16 * kLrRound + 8 * kLrRound / 2;
+    const double2 *V[kLrRound];
+    double *W[kLrRound / 2];
+    int count;                  // convolutions in the round
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        for (int c = 0; c < count; ++c) W[c][i] = 2.0 * (V[2 * c][i].x + V[2 * c + 1][i].x);
+    }
+};
+
+// V_LR = sum_t coef_t max(rho, floor)^e_t W_{conv_t}
+struct LrVlrOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 16 + 8 * kLrMaxConv;
+    const double *u;
+    const double *W[kLrMaxConv];
+    double *vlr;
+    double coef[kLrMaxTerms], e[kLrMaxTerms];
+    int conv[kLrMaxTerms];
+    int nterms;
+    double floor_rho;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double lr = log(fmax(u[i] * u[i], floor_rho));
+        double v = 0.0;
+        for (int t = 0; t < nterms; ++t) v = ::fma(coef[t] * exp(e[t] * lr), W[conv[t]][i], v);
+        vlr[i] = v;
+    }
+};
+
+// The order-2 kernel potential: rounds of kLrRound solved systems.
+int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) {
+    const int64_t n = s->n;
+    OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
+    OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
+    OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
+    const double volume = (double)n * s->dv;
+    const double kf = std::cbrt(3.0 * kPi * kPi * s->p.n_electrons / volume);
+    const double k2 = 4.0 * kf * kf;
+    const int nsys = 2 * (int)s->lr_conv.size();
+    for (int j0 = 0; j0 < nsys; j0 += kLrRound) {
+        const int cnt = std::min(kLrRound, nsys - j0);
+        LrRhsOp ro{};
+        ro.u = s->u;
+        ro.fa = s->f_a;
+        ro.fb = s->f_b;
+        ro.count = cnt;
+        const void *rhs[kLrRound];
+        void *xs[kLrRound];
+        double kap[2 * kLrRound];
+        for (int k = 0; k < cnt; ++k) {
+            const int j = j0 + k;
+            const LrConv &c = s->lr_conv[j / 2];
+            const int r = j % 2;
+            const bool k00 = c.m == 0 && c.n == 0;
+            const double sc = k00 ? 1.0 : k2;
+            ro.F[k] = s->lr_F[k];
+            ro.cre[k] = sc * c.P[r].x;
+            ro.cim[k] = sc * c.P[r].y;
+            ro.a[k] = c.a;
+            ro.lap[k] = !k00 ? 0 : (std::fabs(c.a - kAlpha) < 1e-12 ? 1 : 2);
+            rhs[k] = s->lr_F[k];
+            xs[k] = s->lr_V[j];
+            kap[2 * k] = k2 * c.Q[r].x;
+            kap[2 * k + 1] = k2 * c.Q[r].y;
+        }
+        if (cnt < kLrRound) {        // lr_setup gives 32 systems for L = 2
+            set_error("kernel terms: the number of solved systems must be a multiple of %d", kLrRound);
+            return OFDFT_INVALID_ARG;
+        }
+        OFDFT_TRY((launch_reduce<1>(n, ro, NoFin{}, s->rb, st)));
+        ofdft_solve_stats hs[kLrRound];
+        int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol, s->p.max_iter, hs, st);
+        if (hst < 0) return hst;
+        for (int k = 0; k < cnt; ++k) {
+            helm_it += hs[k].iters;
+            helm_res = std::max(helm_res, hs[k].rel_res);
+        }
+        LrSumOp so{};
+        so.count = cnt / 2;
+        for (int k = 0; k < cnt; ++k) so.V[k] = s->lr_V[j0 + k];
+        for (int c = 0; c < cnt / 2; ++c) so.W[c] = s->lr_W[j0 / 2 + c];
+        OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+    }
+    LrVlrOp vo{};
+    vo.u = s->u;
+    vo.vlr = s->vlr;
+    for (size_t c = 0; c < s->lr_W.size(); ++c) vo.W[c] = s->lr_W[c];
+    vo.nterms = (int)s->lr_terms.size();
+    for (int t = 0; t < vo.nterms; ++t) {
+        vo.coef[t] = s->lr_terms[t].coef;
+        vo.e[t] = s->lr_terms[t].e;
+        vo.conv[t] = s->lr_terms[t].conv;
+    }
+    vo.floor_rho = 1e-12 * s->p.n_electrons / volume;
+    OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+    return OFDFT_OK;
+}
+
 struct MixResidOp {     // vhat = phi + mu vlr; f = vhat - v; totals {|f|^2, |v|^2}
     static constexpr int kClass = K_POINTWISE;
     static constexpr int kBytes = 32;
@@ -179,6 +373,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
     pois_it = ps.iters;
     helm_it = 0;
     helm_res = 0.0;
+    if (s->p.mu && s->p.lr_order == 2) return lr2_potential(s, st, helm_it, helm_res);
     if (s->p.mu) {
         OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
@@ -231,7 +426,8 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     }
     OFDFT_TRY(check_grid(&p->grid, p->radius));
     if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
-        !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0))) {
+        !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
+        (p->lr_order != 0 && p->lr_order != 2)) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }
@@ -272,7 +468,36 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     if ((rc = salloc(s, &s->dsc, sizeof(double) * 64))) return fail(rc);
     if (hipHostMalloc(&s->hsc, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess) return fail(OFDFT_NO_MEMORY);
     if ((rc = redbuf_alloc(s->rb))) return fail(rc);
-    if (p->mu) {
+    if (p->mu && p->lr_order == 2) {
+        if ((rc = salloc(s, &s->rho_a, b8)) || (rc = salloc(s, &s->rho_b, b8)) ||
+            (rc = salloc(s, &s->f_a, b8)) || (rc = salloc(s, &s->f_b, b8)))
+            return fail(rc);
+        const double rho_bar = p->n_electrons / ((double)s->n * s->dv);
+        lr_setup(2, rho_bar, s->lr_conv, s->lr_terms);
+        if ((int)s->lr_conv.size() > kLrMaxConv || (int)s->lr_terms.size() > kLrMaxTerms ||
+            (2 * s->lr_conv.size()) % kLrRound) {
+            set_error("ofdft_scf_create: kernel-term tables exceed their limits");
+            return fail(OFDFT_INVALID_ARG);
+        }
+        s->lr_V.assign(2 * s->lr_conv.size(), nullptr);
+        s->lr_W.assign(s->lr_conv.size(), nullptr);
+        for (double2 *&q : s->lr_V) {
+            if ((rc = salloc(s, &q, 2 * b8))) return fail(rc);
+            if (hipMemsetAsync(q, 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
+        }
+        for (double *&q : s->lr_W)
+            if ((rc = salloc(s, &q, b8))) return fail(rc);
+        for (double2 *&q : s->lr_F)
+            if ((rc = salloc(s, &q, 2 * b8))) return fail(rc);
+        ofdft_grid grids[kLrRound];
+        for (int q = 0; q < kLrRound; ++q) grids[q] = p->grid;
+        if ((rc = ofdft_batch_create(kLrRound, grids, p->radius,
+                                     p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
+            return fail(rc);
+        if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
+            (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
+            return fail(rc);
+    } else if (p->mu) {
         if ((rc = salloc(s, &s->rho_a, b8)) || (rc = salloc(s, &s->rho_b, b8)) ||
             (rc = salloc(s, &s->f_a, b8)) || (rc = salloc(s, &s->f_b, b8)))
             return fail(rc);
@@ -359,8 +584,9 @@ extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
     return std::isfinite(res) ? OFDFT_OK : OFDFT_NONFINITE;
 }
 
-// State vectors: 0 v, 1 u, 2 phi, 3 V_LR (n doubles); 4..11 the shifted-solve
-// solutions V_j, j = which - 4 (complex128, 2n doubles; mu = 1 only).
+// State vectors: 0 v, 1 u, 2 phi, 3 V_LR (n doubles); 4.. the shifted-solve
+// solutions (complex128, 2n doubles; mu = 1 only): 4..11 the K_00 systems,
+// or 4..35 the solved systems of the order-2 terms.
 static double *state_ptr(ofdft_scf *s, int which, size_t &count) {
     count = (size_t)s->n;
     switch (which) {
@@ -369,6 +595,10 @@ static double *state_ptr(ofdft_scf *s, int which, size_t &count) {
         case 2: return s->phi;
         case 3: return s->vlr;
         default:
+            if (which >= 4 && which - 4 < (int)s->lr_V.size()) {
+                count = 2 * (size_t)s->n;
+                return (double *)s->lr_V[which - 4];
+            }
             if (which >= 4 && which < 12 && s->Vr[which - 4]) {
                 count = 2 * (size_t)s->n;
                 return (double *)s->Vr[which - 4];

@@ -7,6 +7,28 @@
 struct ofdft_batch;
 struct ofdft_anderson;
 
+namespace ofdft {
+
+// One distinct convolution K_mn rho^a of the order-2 kernel terms (solved as
+// the shifted systems r = 1, 3; r = 2, 4 are their conjugates).
+struct LrConv {
+    int m, n;                // kernel, m >= n
+    double a;                // power of rho
+    double2 P[2], Q[2];      // r = 1, 3
+};
+
+// One term of V_LR: coef rho^e (K rho^a of convolution conv).
+struct LrTerm {
+    double coef, e;
+    int conv;
+};
+
+constexpr int kLrMaxConv = 16;
+constexpr int kLrMaxTerms = 32;
+constexpr int kLrRound = 8;        // shifted systems per batched solve
+
+}  // namespace ofdft
+
 struct ofdft_scf {
     ofdft_scf_params p{};
     ofdft_grid g{};
@@ -20,6 +42,14 @@ struct ofdft_scf {
     double *rho_a = nullptr, *rho_b = nullptr, *f_a = nullptr, *f_b = nullptr;
     double2 *Fr[8] = {}, *Vr[8] = {};
     double kappa[16] = {};
+    // order-2 kernel terms (lr_order 2): distinct convolutions, V_LR terms,
+    // the solved systems' solutions (2 per convolution, kept as warm starts),
+    // each convolution's real sum W = 2 Re(V_1 + V_3), a round's right-hand sides
+    std::vector<ofdft::LrConv> lr_conv;
+    std::vector<ofdft::LrTerm> lr_terms;
+    std::vector<double2 *> lr_V;
+    std::vector<double *> lr_W;
+    double2 *lr_F[ofdft::kLrRound] = {};
     // density update workspace; with the preconditioner, z = M r and the
     // multigrid hierarchy of -Delta + u_kappa
     double *Hu = nullptr, *rA = nullptr, *rB = nullptr, *dA = nullptr, *dB = nullptr, *z = nullptr;

@@ -142,3 +142,40 @@ def test_lr_kernel_step_matches_oracle(pmode, hpre):
         vj = torch.empty(w.rho.shape, dtype=torch.complex128, device="cuda")
         ctx.get(4 + j, vj)
         assert helmholtz.residual(to_host(vj), fs[j], ks[j], w.cell.h) <= 1.05e-10, j
+
+
+@pytest.mark.parametrize("which,hpre", [("small", ofd.PRECOND_NONE), ("small", ofd.PRECOND_MULTIGRID),
+                                        ("supercell", ofd.PRECOND_MULTIGRID)])
+def test_order2_kernel_terms_match_oracle(which, hpre):
+    """The order-2 kernel terms (K_00, K_10, K_20, K_11; 32 solved systems):
+    V_LR of the initial density against the oracle, and every solved system
+    against its own equation (oracle residual)."""
+    torch = torch_cuda()
+    from oracle import fd, helmholtz, kernel, wgc
+    announce("scf order-2 kernel terms", which, hpre)
+    w = inputs.small_cell() if which == "small" else inputs.supercell_500()
+    tol = 1e-10 if which == "small" else 1e-8
+    ctx = _ctx(w, lam=1.0, mu=1, lr_order=2, helmholtz_tol=tol, poisson_tol=tol, helmholtz_precond=hpre,
+               poisson_mode=ofd.MULTIGRID if hpre else ofd.PLAIN_F64)
+    h, ne, vol = w.cell.h, w.cell.n_electrons, w.cell.volume
+    ud = torch.empty(w.rho.shape, dtype=torch.float64, device="cuda")
+    ctx.get(ofd.SCF.U, ud)
+    rho = to_host(ud) ** 2
+    vd = torch.empty_like(ud)
+    ctx.get(ofd.SCF.VLR, vd)
+    ref = wgc.potential(rho, h, ne, vol)
+    err = np.abs(to_host(vd) - ref).max() / np.abs(ref).max()
+    announce("V_LR relative error", err)
+    # the second-order terms are differences of nearly equal products
+    # (C_mnpq carries rho_bar^-(m+n)), so V_LR's relative error is ~100x the
+    # solves' relative residual
+    assert err <= 200 * tol
+    k2 = (2.0 * kernel.fermi_wavevector(ne, vol)) ** 2
+    sol = torch.empty(w.rho.shape, dtype=torch.complex128, device="cuda")
+    for j, (m, n, a, r) in enumerate(wgc.systems(2)):
+        ctx.get(4 + j, sol)
+        P, Q = wgc.coefficients(m, n)
+        f = P[r] * (-fd.laplacian(rho ** a, h)) if (m, n) == (0, 0) else k2 * P[r] * rho ** a
+        assert helmholtz.residual(to_host(sol), f, k2 * Q[r], h) <= 1.05 * tol, j
+    assert np.isfinite(ctx.step())
+    assert ctx.stats()["helmholtz_res"] <= tol
