@@ -289,6 +289,33 @@ int ofdft_scf_reset_history(ofdft_scf *s);
  * residual, [4] Poisson residual, [5] worst shifted-solve residual, [6] eta. */
 int ofdft_scf_stats(ofdft_scf *s, double *out7);
 
+/* Ground-state energy terms and forces on the nuclei (Section 3.3 energy
+ * expression and forces; Section 3.2 local electrostatics; Appendix B overlap
+ * correction), from the context's current u, phi and kernel solutions (call
+ * after ofdft_scf_create or a step).  Pseudocharges are the Gaussians of the
+ * stand-in inputs: b_J = charge (2 pi sigma^2)^-3/2 exp(-|x - R_J|^2 / (2
+ * sigma^2)) with images, V_J = charge erf(r / (sqrt 2 sigma)) / r; the self
+ * term and the forces sum over each atom's grid points within `cutoff`
+ * (e.g. 8.5 sigma); the overlap correction is the closed form for Gaussians,
+ * E_c = 1/2 sum_{I != J, images} charge^2 erfc(d / (2 sigma)) / d.
+ * ofdft_scf_energy: terms (host, 8 doubles, hartree): Thomas-Fermi,
+ *   von Weizsacker (-(lambda/2) h^3 <u, L_h u>), exchange-correlation,
+ *   electrostatic (1/2 h^3 sum (rho + b) phi), nuclear self energy (-1/2 sum_J
+ *   int b_J V_J), overlap correction, kernel energy (mu T_LR of the expansion
+ *   in use), total.
+ * ofdft_scf_forces: forces (host, 3 doubles per atom, hartree/bohr)
+ *   f_J = sum_images h^3 sum grad b_J (phi - V_J) + f^c_J.
+ * Both synchronise the stream; INVALID_ARG for a bad context or atoms. */
+typedef struct {
+    int count;                 /* atoms                                                  */
+    const double *pos;         /* host, 3*count (x, y, z) in bohr                        */
+    double charge;             /* pseudocharge per atom (-3 for the Al stand-in)         */
+    double sigma;              /* Gaussian width (bohr)                                  */
+    double cutoff;             /* radius of the per-atom grid sums (bohr)                */
+} ofdft_gauss_atoms;
+int ofdft_scf_energy(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double *terms, void *stream);
+int ofdft_scf_forces(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double *forces, void *stream);
+
 /* The density update U(v) alone (Algorithm 1), using the context's parameters:
  * v, u device FP64; u holds the starting guess on entry and U(v) on exit.
  * iters/residual/eta (host, optional) receive the iteration count, the final

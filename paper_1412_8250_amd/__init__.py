@@ -53,6 +53,11 @@ class ScfParams(ctypes.Structure):
                 ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int)]
 
 
+class GaussAtoms(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int), ("pos", ctypes.POINTER(ctypes.c_double)), ("charge", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("cutoff", ctypes.c_double)]
+
+
 _lib = None
 _V = ctypes.c_void_p
 _I = ctypes.c_int
@@ -89,6 +94,8 @@ def _declare(l):
         "ofdft_stencil_set_config": (_I, [_I, _I, _I, _I, _I, _I]),
         "ofdft_batch_set_config": (_I, [_V, _I, _I]),
         "ofdft_batch_set_preconditioner": (_I, [_V, _I]),
+        "ofdft_scf_energy": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
+        "ofdft_scf_forces": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
         "ofdft_batch_apply_preconditioner": (_I, [_V, _I, ctypes.POINTER(_D), _V, _V, _V]),
         "ofdft_nn_create": (_I, [ctypes.c_uint64, ctypes.POINTER(_V)]),
         "ofdft_nn_destroy": (_I, [_V]),
@@ -424,6 +431,32 @@ class SCF:
         keys = ("u_iters", "poisson_iters", "helmholtz_iters", "u_res", "poisson_res",
                 "helmholtz_res", "eta")
         return dict(zip(keys, list(out)))
+
+    ENERGY_TERMS = ("tf", "vw", "xc", "electrostatic", "self", "overlap", "kernel", "total")
+
+    @staticmethod
+    def _atoms(pos, charge, sigma, cutoff):
+        import numpy as _np
+        p = _np.ascontiguousarray(_np.asarray(pos, dtype=_np.float64).reshape(-1, 3))
+        a = GaussAtoms(len(p), p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(charge), float(sigma),
+                       float(8.5 * sigma if cutoff is None else cutoff))
+        return a, p
+
+    def energy(self, pos, charge: float = -3.0, sigma: float = 0.8, cutoff=None, stream=None) -> dict:
+        """Energy terms (hartree) of the current state for Gaussian pseudocharges at pos (M x 3, bohr)."""
+        a, keep = self._atoms(pos, charge, sigma, cutoff)
+        out = (ctypes.c_double * 8)()
+        _check(lib().ofdft_scf_energy(self._h, ctypes.byref(a), out, _stream(stream)))
+        return dict(zip(self.ENERGY_TERMS, list(out)))
+
+    def forces(self, pos, charge: float = -3.0, sigma: float = 0.8, cutoff=None, stream=None):
+        """Forces on the nuclei (M x 3, hartree/bohr) from the current state."""
+        import numpy as _np
+        a, keep = self._atoms(pos, charge, sigma, cutoff)
+        out = _np.zeros((a.count, 3))
+        _check(lib().ofdft_scf_forces(self._h, ctypes.byref(a), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _stream(stream)))
+        return out
 
     def density_update(self, v, u, stream=None, allow_not_converged=False):
         it, res, eta = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()

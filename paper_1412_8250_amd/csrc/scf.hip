@@ -147,9 +147,13 @@ double fact(int n) { return n <= 1 ? 1.0 : n * fact(n - 1); }
 
 // The distinct convolutions and the V_LR terms of the order-L expansion
 // (L = 0 or 2), in the documented order.
-void lr_setup(int L, double rho_bar, std::vector<LrConv> &conv, std::vector<LrTerm> &terms) {
+// eterms: the kernel energy C_F sum C_mnpq <rho^(m-p+alpha), K_mn rho^(n-q+beta)>
+// as coef <rho^e, W_conv> terms.
+void lr_setup(int L, double rho_bar, std::vector<LrConv> &conv, std::vector<LrTerm> &terms,
+              std::vector<LrTerm> &eterms) {
     conv.clear();
     terms.clear();
+    eterms.clear();
     auto conv_index = [&](int m, int n, double a) {
         const int km = std::max(m, n), kn = std::min(m, n);
         for (size_t c = 0; c < conv.size(); ++c)
@@ -175,6 +179,7 @@ void lr_setup(int L, double rho_bar, std::vector<LrConv> &conv, std::vector<LrTe
                                      std::pow(rho_bar, p + q - m - n);
                     terms.push_back(LrTerm{kCF * c * a, a - 1.0, cb});
                     terms.push_back(LrTerm{kCF * c * b, b - 1.0, ca});
+                    eterms.push_back(LrTerm{kCF * c, a, cb});
                 }
         }
 }
@@ -473,7 +478,7 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
             (rc = salloc(s, &s->f_a, b8)) || (rc = salloc(s, &s->f_b, b8)))
             return fail(rc);
         const double rho_bar = p->n_electrons / ((double)s->n * s->dv);
-        lr_setup(2, rho_bar, s->lr_conv, s->lr_terms);
+        lr_setup(2, rho_bar, s->lr_conv, s->lr_terms, s->lr_eterms);
         if ((int)s->lr_conv.size() > kLrMaxConv || (int)s->lr_terms.size() > kLrMaxTerms ||
             (2 * s->lr_conv.size()) % kLrRound) {
             set_error("ofdft_scf_create: kernel-term tables exceed their limits");

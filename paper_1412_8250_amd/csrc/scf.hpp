@@ -46,7 +46,7 @@ struct ofdft_scf {
     // the solved systems' solutions (2 per convolution, kept as warm starts),
     // each convolution's real sum W = 2 Re(V_1 + V_3), a round's right-hand sides
     std::vector<ofdft::LrConv> lr_conv;
-    std::vector<ofdft::LrTerm> lr_terms;
+    std::vector<ofdft::LrTerm> lr_terms, lr_eterms;
     std::vector<double2 *> lr_V;
     std::vector<double *> lr_W;
     double2 *lr_F[ofdft::kLrRound] = {};
