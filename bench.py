@@ -322,6 +322,19 @@ def main():
                 extras[f"poisson_{name}_nn_applies"] = st["nn_applies"]
                 extras[f"poisson_{name}_fell_back"] = st["fell_back"]
             s.close()
+        # energy terms and forces on the 16384 nuclei from the step's state
+        scf.restore(snap)
+        scf.step()
+        torch.cuda.synchronize()
+        atoms = np.array(w.cell.atoms, dtype=float)
+        t0 = time.perf_counter()
+        et = scf.energy(atoms)
+        t_e = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fo = scf.forces(atoms)
+        t_f = time.perf_counter() - t0
+        extras["energy_and_forces"] = {"energy_seconds": t_e, "forces_seconds": t_f, "terms": et,
+                                       "max_force": float(np.abs(fo).max()), "atoms": len(atoms)}
         # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)
         # on the same cell: one step from the initial state
         t0 = time.perf_counter()

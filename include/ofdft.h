@@ -248,7 +248,7 @@ typedef struct {
                                   printed) or OFDFT_PRECOND_MULTIGRID(_F64) (lambda > 0): the
                                   steepest-descent direction r becomes z = M r projected
                                   on <u, z> = 0, M one multigrid cycle of -Delta +
-                                  2 sigma / lambda with sigma = V_TF(N_e / volume);
+                                  2 sigma / lambda (sigma: u_precond_sigma);
                                   Polak-Ribiere xi = <r - r_prev, z> / <r_prev, z_prev>.
                                   Same minimiser, several times fewer iterations; every
                                   axis must halve evenly down to at most 16 points     */
@@ -258,6 +258,8 @@ typedef struct {
                                   m + n <= 2): 16 distinct convolutions K_mn rho^a, 64
                                   shifted systems, 32 solved (r = 2, 4 conjugates),
                                   batched 8 at a time                                  */
+    double u_precond_sigma;    /* sigma of the density update's preconditioner (hartree);
+                                  0 = V_TF(N_e / volume)                               */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

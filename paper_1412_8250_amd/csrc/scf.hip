@@ -465,7 +465,9 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         if (!s->umg) return fail(OFDFT_NO_MEMORY);
         if ((rc = mg_create(*s->umg, p->grid, 8, p->u_precond == OFDFT_PRECOND_MULTIGRID))) return fail(rc);
         const double rho_bar = p->n_electrons / ((double)s->n * s->dv);
-        s->u_kappa = 2.0 * (5.0 / 3.0) * kCF * std::cbrt(rho_bar * rho_bar) / p->lambda;
+        const double sigma = p->u_precond_sigma > 0.0 ? p->u_precond_sigma
+                                                       : (5.0 / 3.0) * kCF * std::cbrt(rho_bar * rho_bar);
+        s->u_kappa = 2.0 * sigma / p->lambda;
     } else if (p->u_precond != OFDFT_PRECOND_NONE && !u_mg) {
         set_error("ofdft_scf_create: unknown u_precond %d", p->u_precond);
         return fail(OFDFT_INVALID_ARG);
