@@ -1,20 +1,6 @@
-// fd_laplacian_apply: y = alpha L_h x + beta y for f64 / f32 / c128 / c64.
-#include "stencil_launch.hpp"
-
-namespace ofdft {
-
-template <typename T>
-static int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x, void *y,
-                   double alpha, double beta, hipStream_t s) {
-    using S = typename VT<T>::S;
-    LoadPlain<T> ld{(const T *)x};
-    ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
-    if (beta != 0.0)
-        return launch_stencil<T>(g, c, ld, EpiAxpby<T, true>{(T *)y, (S)alpha, (S)beta, {}}, s);
-    return launch_stencil<T>(g, c, ld, EpiAxpby<T, false>{(T *)y, (S)alpha, (S)beta, {}}, s);
-}
-
-}  // namespace ofdft
+// fd_laplacian_apply: y = alpha L_h x + beta y for f64 / f32 / c128 / c64 (the
+// kernels of each type are built in stencil_<type>.hip).
+#include "stencil_apply.hpp"
 
 using namespace ofdft;
 

@@ -5,9 +5,15 @@
 //  * A workgroup owns a TX x (TYT*RY) tile of an xy-plane and marches along z
 //    over a chunk of planes.  Each thread owns one x column and RY
 //    consecutive y rows.
-//  * z-neighbours come from a per-thread register queue of 13 planes, filled
-//    by one coalesced load per point per plane (the queue front, fetched
-//    R + 3 planes ahead of the output plane).
+//  * z-neighbours come from a per-thread register ring of A + R + 1 planes,
+//    filled by one coalesced load per point per plane (the queue front,
+//    fetched A = R + 3 planes ahead of the output plane: 16 slots).  The z
+//    loop is unrolled by the ring's period, so every ring index is a
+//    constant: loads land in the register that holds the plane until it is
+//    consumed, with no register copies, and the compiler waits only for the
+//    plane being used, never for the younger prefetches (a shifting queue
+//    makes it copy fresh loads at the loop latch, which drains every load in
+//    flight).
 //  * x- and y-neighbours come from an LDS copy of the current plane with a
 //    6-wide halo: the tile centre is written from the queue, only the halo
 //    ring is fetched from global memory.  The ring of a plane is fetched at
@@ -24,6 +30,8 @@
 
 #include "common.hpp"
 #include "profile.hpp"
+
+#include <type_traits>
 
 namespace ofdft {
 
@@ -134,12 +142,12 @@ struct TileCtx {
 };
 
 // Stencil arithmetic of one plane from an LDS plane buffer (centre + halo)
-// and the register z queue; calls the epilogue for the valid owned points.
-template <typename T, int TX, int TYT, int RY, class Epi>
-__device__ inline void stencil_plane_compute(const Coef<typename VT<T>::S> &w, const T *buf,
-                                             const T (&q)[2 * kMaxRadius + 1][RY],
-                                             const TileCtx<TX, TYT, RY> &tc, bool active,
-                                             int64_t pk, Epi &ep) {
+// and the register z ring; calls the epilogue for the valid owned points.
+// Ring slot (J + R + d) mod NB holds plane k + d of output plane k.
+template <typename T, int TX, int TYT, int RY, int NB, int J, class Epi>
+__device__ __forceinline__ void stencil_plane_compute(const Coef<typename VT<T>::S> &w, const T *buf,
+                                                      const T (&q)[NB][RY], const TileCtx<TX, TYT, RY> &tc,
+                                                      int64_t pk, Epi &ep) {
     using V = VT<T>;
     using TS = TileShape<TX, TYT, RY>;
     constexpr int R = TS::R, W = TS::W;
@@ -150,22 +158,38 @@ __device__ inline void stencil_plane_compute(const Coef<typename VT<T>::S> &w, c
     for (int j = 0; j < RY + 2 * R; ++j) col[j] = buf[(ty * RY + j) * W + tx + R];
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-        const T c = q[R][r];
+        const T c = q[(J + R) % NB][r];
         T sacc = V::mul(w.c0, c);
         const T *row = buf + (ty * RY + r + R) * W + tx + R;
 #pragma unroll
         for (int p = 1; p <= R; ++p) {
             sacc = V::fma(w.wx[p], V::add(row[p], row[-p]), sacc);
             sacc = V::fma(w.wy[p], V::add(col[r + R + p], col[r + R - p]), sacc);
-            sacc = V::fma(w.wz[p], V::add(q[R + p][r], q[R - p][r]), sacc);
+            sacc = V::fma(w.wz[p], V::add(q[(J + R + p) % NB][r], q[(J + R - p + NB) % NB][r]), sacc);
         }
-        if (active && tc.xvalid && tc.yvalid[r]) ep.point(r, pk + tc.own[r], c, sacc);
+        if (tc.xvalid && tc.yvalid[r]) ep.point(r, pk + tc.own[r], c, sacc);
+    }
+}
+
+// Compile-time loops: f(std::integral_constant<int, I>) for I = B .. E - 1;
+// the _while form stops at the first call that returns false.
+template <int I, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < E) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, E>(f);
+    }
+}
+template <int I, int E, class F>
+__device__ __forceinline__ void static_for_while(F &&f) {
+    if constexpr (I < E) {
+        if (f(std::integral_constant<int, I>{})) static_for_while<I + 1, E>(f);
     }
 }
 
 // LDS plan of a tile shape and element type.  The halo ring of plane P is
 // fetched L planes before P is computed and parked in one of L plane buffers
-// (slot (P - zb) mod L) until then; the centre is written from the z queue at
+// (slot (P - zb) mod L) until then; the centre is written from the z ring at
 // P.  L = R + 3 fetches the ring together with the queue front of plane P,
 // i.e. when the tiles around this one fetch P's centre, so that the halo
 // reads hit in L2.  L is the largest value up to R + 3 whose buffers fit in
@@ -173,7 +197,7 @@ __device__ inline void stencil_plane_compute(const Coef<typename VT<T>::S> &w, c
 //
 // Ring fetches wait in kRingDepth register buffers before going to LDS, so
 // the ring of plane P is fetched L - 2 + kRingDepth planes ahead and the
-// queue front (two register buffers) R + 3 planes ahead: a depth of
+// queue front R + 3 planes ahead: a depth of
 // R + 5 - L (2..4) keeps the two fetches of a plane close together when
 // fewer than R + 3 LDS slots fit.
 template <typename T, int TX, int TYT, int RY>
@@ -192,39 +216,49 @@ struct StencilLds {
 // `lds` holds L plane buffers of W*H + 1 elements (the last element of each
 // is a dummy target for spare ring slots).
 //
-// Timeline of output plane k: write q[R] (plane k) into slot(k) and the ring
-// fetched PR planes ago (plane k + L - 2) into slot(k + L - 2); issue the
-// epilogue's loads for plane k, then the fetches of ring k + L - 2 + PR and
-// of queue front k + R + 3; barrier; compute plane k.  A slot is rewritten
-// two planes after its last reader, so one barrier per plane suffices.
-// In-flight fetches land in fixed registers (the loop is unrolled by U), so
-// waiting for one plane's data never waits for younger loads.  Ring fetches
-// past the chunk end are clamped to its last plane (never used, an L2 hit).
+// Timeline of output plane k: write the ring slot of plane k into LDS slot(k)
+// and the halo ring fetched PR planes ago (plane k + L - 2) into
+// slot(k + L - 2); issue the epilogue's loads for plane k, then the fetches
+// of halo ring k + L - 2 + PR and of queue front k + A (into the register
+// slot that plane k - R - 1 has just left); barrier; compute plane k.  An LDS
+// slot is rewritten two planes after its last reader, so one barrier per
+// plane suffices.  The z ring has NB = A + R + 1 register slots and the loop
+// is unrolled by lcm(NB, PR) planes, so that all register slots are
+// constants; the last, partial step of a chunk stops at its end.  A queue
+// front is first used A - R planes after its fetch, a halo ring PR planes
+// after.  Halo fetches past the chunk end are clamped to its last plane
+// (never used, an L2 hit).
+constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
+
 template <typename T, int TX, int TYT, int RY, class Load, class Epi,
-          int L = StencilLds<T, TX, TYT, RY>::kLead, int PR = StencilLds<T, TX, TYT, RY>::kRingDepth>
+          int L = StencilLds<T, TX, TYT, RY>::kLead, int PR = StencilLds<T, TX, TYT, RY>::kRingDepth,
+          int A = kMaxRadius + 3>
 __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>::S> &w,
                                     const Load &ld, Epi &ep, int logical_block, T *lds) {
     using TS = TileShape<TX, TYT, RY>;
     constexpr int R = TS::R, W = TS::W, H = TS::H;
     constexpr int SL = W * H + 1;
-    constexpr int U = PR == 2 ? 2 : 4;     // planes per unrolled step (multiple of PR and of 2)
+    // queue lead A: plane k + A is fetched at output plane k
+    constexpr int NB = A + R + 1;           // register slots of the z ring
+    constexpr int U = NB / gcd_i(NB, PR) * PR;   // unrolled planes: cycles ring and halo buffers
     static_assert(L >= 2 && L <= R + 3, "ring lead out of range");
-    static_assert(PR == 2 || PR == 4, "ring depth 2 or 4");
+    static_assert(PR >= 2 && PR <= 8, "halo register depth");
+    static_assert(A > R, "the queue front must lead the stencil reach");
     const TileCtx<TX, TYT, RY> tc(g, logical_block);
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int zb = tc.zb, ze = tc.ze;
     const int zlast = ze - 1;
     const int64_t nxy = (int64_t)g.nx * g.ny;
 
-    // z queue: q[j][r] holds plane (k - R + j) for output plane k.
-    T q[2 * R + 1][RY];
+    // z ring: slot (P - zb + R) mod NB holds plane P; planes zb - R .. zb + A - 1 first
+    T q[NB][RY];
 #pragma unroll
-    for (int j = 0; j < 2 * R + 1; ++j) {
+    for (int j = 0; j < A + R; ++j) {
         const int64_t pb = (int64_t)wrapi(zb - R + j, g.nz) * nxy;
 #pragma unroll
         for (int r = 0; r < RY; ++r) q[j][r] = ld(pb + tc.own[r]);
     }
-    // rings of planes zb .. zb + L - 3 go straight to their slots
+    // halo rings of planes zb .. zb + L - 3 go straight to their slots
 #pragma unroll
     for (int j = 0; j < L - 2; ++j) {
         const int64_t pb = (int64_t)min(zb + j, zlast) * nxy;
@@ -232,66 +266,55 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) slot[tc.ring_lds[i]] = ld(pb + tc.ring_glb[i]);
     }
-    // rings of planes zb + L - 2 .. zb + L - 3 + PR and queue fronts R + 1, R + 2 in flight
+    // halo rings of planes zb + L - 2 .. zb + L - 3 + PR in flight
     T ring[PR][TS::RING_PER_T];
-    T qn[2][RY];
 #pragma unroll
     for (int j = 0; j < PR; ++j) {
         const int64_t rp = (int64_t)min(zb + L - 2 + j, zlast) * nxy;
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) ring[j][i] = ld(rp + tc.ring_glb[i]);
     }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int64_t fp = (int64_t)wrapi(zb + R + 1 + j, g.nz) * nxy;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) qn[j][r] = ld(fp + tc.own[r]);
-    }
-    int kr = zb + L - 2 + PR;              // plane of the next ring fetch (clamped at use)
-    int kf = wrapi(zb + R + 3, g.nz);      // plane of the next queue-front fetch
-    int sc = 0;                            // slot of the output plane
+    int kr = zb + L - 2 + PR;              // plane of the next halo fetch (clamped at use)
+    int kf = wrapi(zb + A, g.nz);          // plane of the next queue-front fetch
+    int sc = 0;                            // LDS slot of the output plane
 
-    // `active` is false for the padding planes past the chunk end: they
-    // still load (in bounds) but store nothing.
-    auto plane = [&](int k, T (&rb)[TS::RING_PER_T], T (&qb)[RY], bool active) {
-        const int kk = active ? k : zb;
-        const int64_t pk = (int64_t)kk * nxy;
+    auto plane = [&](int k, auto jc) __attribute__((always_inline)) {
+        constexpr int J = decltype(jc)::value;
+        const int64_t pk = (int64_t)k * nxy;
         T *buf = lds + sc * SL;
         const int sr = sc + L - 2 >= L ? sc - 2 : sc + L - 2;
         T *rbuf = lds + sr * SL;
+        T (&rb)[TS::RING_PER_T] = ring[J % PR];
 #pragma unroll
-        for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[R][r];
+        for (int r = 0; r < RY; ++r) buf[(ty * RY + r + R) * W + tx + R] = q[(J + R) % NB][r];
 #pragma unroll
         for (int i = 0; i < TS::RING_PER_T; ++i) rbuf[tc.ring_lds[i]] = rb[i];
 #pragma unroll
         for (int r = 0; r < RY; ++r) ep.pre(r, pk + tc.own[r]);
-        T nxt[RY];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) nxt[r] = qb[r];
         {
             const int64_t pr = (int64_t)min(kr, zlast) * nxy, pf = (int64_t)kf * nxy;
 #pragma unroll
             for (int i = 0; i < TS::RING_PER_T; ++i) rb[i] = ld(pr + tc.ring_glb[i]);
 #pragma unroll
-            for (int r = 0; r < RY; ++r) qb[r] = ld(pf + tc.own[r]);
+            for (int r = 0; r < RY; ++r) q[(J + NB - 1) % NB][r] = ld(pf + tc.own[r]);
         }
         __syncthreads();
-        stencil_plane_compute<T, TX, TYT, RY>(w, buf, q, tc, active, pk, ep);
-#pragma unroll
-        for (int j = 0; j < 2 * R; ++j)
-#pragma unroll
-            for (int r = 0; r < RY; ++r) q[j][r] = q[j + 1][r];
-#pragma unroll
-        for (int r = 0; r < RY; ++r) q[2 * R][r] = nxt[r];
+        stencil_plane_compute<T, TX, TYT, RY, NB, J>(w, buf, q, tc, pk, ep);
         ++kr;
         kf = (kf + 1 == g.nz) ? 0 : kf + 1;
         sc = (sc + 1 == L) ? 0 : sc + 1;
     };
 
-    for (int k = zb; k < ze; k += U) {
-#pragma unroll
-        for (int j = 0; j < U; ++j) plane(k + j, ring[j % PR], qn[j % 2], k + j < ze);
-    }
+    int k0 = zb;
+    for (; k0 + U <= ze; k0 += U)
+        static_for<0, U>([&](auto jc) __attribute__((always_inline)) { plane(k0 + decltype(jc)::value, jc); });
+    if (k0 < ze)
+        static_for_while<0, U>([&](auto jc) __attribute__((always_inline)) {
+            const int k = k0 + decltype(jc)::value;
+            if (k >= ze) return false;
+            plane(k, jc);
+            return true;
+        });
     // the LDS buffers are reused by the next tile of a persistent caller
     __syncthreads();
 }

@@ -1,0 +1,6 @@
+// fd_laplacian_apply kernels for double elements.
+#include "stencil_apply.hpp"
+
+namespace ofdft {
+template int apply_t<double>(const ofdft_grid &, const Coef<double> &, const void *, void *, double, double, hipStream_t);
+}  // namespace ofdft

@@ -179,3 +179,22 @@ def test_order2_kernel_terms_match_oracle(which, hpre):
         assert helmholtz.residual(to_host(sol), f, k2 * Q[r], h) <= 1.05 * tol, j
     assert np.isfinite(ctx.step())
     assert ctx.stats()["helmholtz_res"] <= tol
+
+
+def test_kernel_term_and_preconditioner_option_errors():
+    """Refused combinations: lr_order other than 0 or 2; the multigrid
+    preconditioner with complex64 shifted solves; bad atoms for the energy."""
+    torch_cuda()
+    w = inputs.small_cell()
+    with pytest.raises(ofd.OfdftError):
+        _ctx(w, lam=1.0, mu=1, lr_order=1)
+    with pytest.raises(ofd.OfdftError):
+        _ctx(w, lam=1.0, mu=1, lr_order=2, helmholtz_dtype=ofd.C64, helmholtz_precond=ofd.PRECOND_MULTIGRID)
+    ctx = _ctx(w, lam=1.0, mu=1, lr_order=2, helmholtz_dtype=ofd.C64, helmholtz_tol=1e-8)
+    assert np.isfinite(ctx.step())
+    assert ctx.stats()["helmholtz_res"] <= 1e-8
+    with pytest.raises(ofd.OfdftError):
+        ctx.energy(np.zeros((0, 3)))
+    with pytest.raises(ofd.OfdftError):
+        ctx.energy(np.zeros((4, 3)), sigma=0.0)
+    ctx.close()
