@@ -4,6 +4,8 @@
 // parallel.
 #pragma once
 
+#include <type_traits>
+
 #include "stencil_launch.hpp"
 
 namespace ofdft {
@@ -14,9 +16,15 @@ int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x
     using S = typename VT<T>::S;
     LoadPlain<T> ld{(const T *)x};
     ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
-    if (beta != 0.0)
-        return launch_stencil<T>(g, c, ld, EpiAxpby<T, true>{(T *)y, (S)alpha, (S)beta, {}}, s);
-    return launch_stencil<T>(g, c, ld, EpiAxpby<T, false>{(T *)y, (S)alpha, (S)beta, {}}, s);
+    auto go = [&](const auto &ep) {
+        if constexpr (std::is_same_v<T, double>) {
+            const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T), true);
+            if (cfg.shape == SHAPE_64x8x4) return launch_stencil_shape<T, 64, 8, 4>(g, cfg.zlen, c, ld, ep, s);
+        }
+        return launch_stencil<T>(g, c, ld, ep, s);
+    };
+    if (beta != 0.0) return go(EpiAxpby<T, true>{(T *)y, (S)alpha, (S)beta, {}});
+    return go(EpiAxpby<T, false>{(T *)y, (S)alpha, (S)beta, {}});
 }
 
 extern template int apply_t<double>(const ofdft_grid &, const Coef<double> &, const void *, void *, double,

@@ -46,7 +46,7 @@ int zlen_auto(const ofdft_grid &g, int tx, int ty, int resident) {
     return best;
 }
 
-StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes) {
+StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes, bool plain_f64) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_table.find(std::make_tuple(g.nx, g.ny, g.nz, elem_bytes));
@@ -54,11 +54,14 @@ StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes) {
     }
     StencilCfg c;
     // Measured at 320^3 on MI355X: real types run fastest with 64 x 16 tiles
-    // of 512 threads (two rows each), complex128 with 32 x 16 tiles.
-    if (elem_bytes >= 16) c.shape = SHAPE_32x8x2;
-    else if (g.nx <= 40 || (g.nx % 64 != 0 && g.nx % 64 <= 32 && g.nx < 256))
+    // of 512 threads (two rows each), complex128 with 64 x 8 tiles of 512
+    // threads (one row each: two rows of complex128 need too many registers).
+    if (g.nx <= 40 || (g.nx % 64 != 0 && g.nx % 64 <= 32 && g.nx < 256))
         c.shape = SHAPE_32x8x2;                          // avoid a mostly idle last x tile
-    else c.shape = SHAPE_64x8x2;
+    else c.shape = elem_bytes >= 16 ? SHAPE_64x8x1 : SHAPE_64x8x2;
+    // the plain FP64 apply on wide grids: 64 x 32 tiles (four rows per
+    // thread) halve the halo fetched per point and cut the LDS reads
+    if (plain_f64 && g.nx % 64 == 0 && g.ny >= 128) c.shape = SHAPE_64x8x4;
     c.zlen = 0;
     return c;
 }

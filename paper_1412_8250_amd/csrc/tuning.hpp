@@ -14,7 +14,9 @@ enum StencilShape {
     SHAPE_32x8x2 = 2,    // 32 x 16 tile, 256 threads
     SHAPE_64x8x2 = 3,    // 64 x 16 tile, 512 threads
     SHAPE_64x8x1 = 4,    // 64 x 8 tile, 512 threads
-    SHAPE_COUNT = 5
+    SHAPE_64x8x4 = 5,    // 64 x 32 tile, 512 threads: the plain FP64 apply only
+                         // (fused kernels given this id run 64 x 8 x 2)
+    SHAPE_COUNT = 6
 };
 
 template <int TX_, int TYT_, int RY_>
@@ -28,7 +30,8 @@ inline int dispatch_shape(int shape, F &&f) {
     switch (shape) {
         case SHAPE_64x4x4: return f(ShapeTag<64, 4, 4>{});
         case SHAPE_32x8x2: return f(ShapeTag<32, 8, 2>{});
-        case SHAPE_64x8x2: return f(ShapeTag<64, 8, 2>{});
+        case SHAPE_64x8x2:
+        case SHAPE_64x8x4: return f(ShapeTag<64, 8, 2>{});
         case SHAPE_64x8x1: return f(ShapeTag<64, 8, 1>{});
         default: return f(ShapeTag<64, 4, 2>{});
     }
@@ -47,11 +50,13 @@ inline void shape_extent(int shape, int &tx, int &ty) {
         case SHAPE_64x4x4: tx = 64; ty = 16; break;
         case SHAPE_32x8x2: tx = 32; ty = 16; break;
         case SHAPE_64x8x2: tx = 64; ty = 16; break;
+        case SHAPE_64x8x4: tx = 64; ty = 32; break;
         default: tx = 64; ty = 8; break;
     }
 }
 
-StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes);
+// plain_f64: the caller is the plain FP64 apply, which also has 64 x 32 tiles.
+StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes, bool plain_f64 = false);
 int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks);
 // z-chunk length minimising (waves of workgroups) x (chunk planes + warm-up)
 // for `resident` workgroups in flight; tiles of tx x ty points.

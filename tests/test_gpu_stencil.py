@@ -12,7 +12,8 @@ SHAPES = [((16, 16, 16), (0.46875,) * 3),
           ((9, 7, 5), (0.31, 0.42, 0.53)),          # smaller than the stencil: repeated wrap
           ((20, 37, 70), (0.4, 0.45, 0.5)),         # ragged tiles in x and y
           ((33, 18, 130), (0.35, 0.39, 0.41)),
-          ((96, 96, 96), (0.390625,) * 3)]
+          ((96, 96, 96), (0.390625,) * 3),
+          ((20, 150, 128), (0.4, 0.45, 0.5))]      # wide: the 64 x 32 tiles of the FP64 apply
 
 
 def _ref_scale(x, h, N):
@@ -41,6 +42,36 @@ def test_apply_matches_oracle(shape, h, dtype):
     ref = fd.laplacian(xin, h, 6)
     tol = (1e-14 if dtype in ("f64", "c128") else 2e-6) * _ref_scale(xin, h, 6)
     assert np.abs(to_host(yd) - ref).max() <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "c128"])
+def test_every_launch_shape(dtype):
+    """Each tile shape the launch table can hold (set by hand, as the tuner
+    does), on a grid with ragged tiles in x and y and short z chunks."""
+    torch = torch_cuda()
+    import paper_1412_8250_amd as ofd
+    shape, h = (26, 70, 136), (0.4, 0.45, 0.5)
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=shape)
+    if dtype == "c128":
+        x = x + 1j * rng.normal(size=shape)
+    tdt = {"f64": torch.float64, "f32": torch.float32, "c128": torch.complex128}[dtype]
+    eb = {"f64": 8, "f32": 4, "c128": 16}[dtype]
+    xd = to_dev(x, tdt)
+    xin = to_host(xd).astype(np.complex128 if dtype == "c128" else np.float64)
+    ref = fd.laplacian(xin, h, 6)
+    tol = (1e-14 if dtype != "f32" else 2e-6) * _ref_scale(xin, h, 6)
+    try:
+        for sid in range(6):
+            for zlen in (0, 7):
+                announce("stencil shape", dtype, sid, zlen)
+                ofd.set_stencil_config(shape, eb, sid, zlen)
+                yd = torch.full_like(xd, float("nan"))
+                ofd.fd_laplacian_apply(xd, yd, h, 6)
+                torch.cuda.synchronize()
+                assert np.abs(to_host(yd) - ref).max() <= tol, (sid, zlen)
+    finally:
+        ofd.set_stencil_config(shape, eb, -1)
 
 
 @pytest.mark.parametrize("radius", [1, 2, 3, 4, 5, 6])
