@@ -182,6 +182,51 @@ def profile_kernel(which, shape, h, reps=5):
     print(f"profiled {which} x{reps}", flush=True)
 
 
+def batch_extra(dev):
+    """Time to 1e-8 of the uneven 32-cell x 8-shift batch (Re kappa > 0):
+    complex128 COCG, complex64 COCG in complex128 refinement, and complex128
+    with the multigrid preconditioner; the second of two identical solves."""
+    import torch
+    import paper_1412_8250_amd as ofd
+    from paper_1412_8250_amd import inputs
+    a_pow, b_pow = 5.0 / 6.0 + 5.0 ** 0.5 / 6.0, 5.0 / 6.0 - 5.0 ** 0.5 / 6.0
+    shapes, hs, kaps, rhs = [], [], [], []
+    points = 0
+    for wl, kappa, c in inputs.batched_workloads():
+        h = wl.cell.h
+        rho = torch.from_numpy(wl.rho).to(dev)
+        fab = []
+        for pw in (a_pow, b_pow):
+            src = rho ** pw
+            f = torch.empty_like(src)
+            ofd.fd_laplacian_apply(src, f, h, 6, alpha=-1.0)
+            fab.append(f.to(torch.complex128))
+        for j in range(8):
+            shapes.append(tuple(rho.shape))
+            hs.append(h)
+            kaps.append(complex(kappa[j]))
+            rhs.append(complex(c[j]) * fab[0 if j < 4 else 1])
+            points += rho.numel()
+    out = {"systems": len(rhs), "points": points}
+    for name, dt, pre in (("c128", ofd.C128, None), ("c64_refined", ofd.C64, None),
+                          ("c128_multigrid", ofd.C128, ofd.PRECOND_MULTIGRID)):
+        bt = ofd.HelmholtzBatch(shapes, hs, 6, dt)
+        if pre is not None:
+            bt.set_preconditioner(pre)
+        for rep in range(2):
+            xs = [torch.zeros_like(f) for f in rhs]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, st = bt.solve(kaps, rhs, xs, 1e-8)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+        out[name] = {"seconds": sec, "max_iters": max(s["iters"] for s in st),
+                     "max_rel_res": max(s["rel_res"] for s in st)}
+        bt.close()
+        del xs
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -335,6 +380,9 @@ def main():
         t_f = time.perf_counter() - t0
         extras["energy_and_forces"] = {"energy_seconds": t_e, "forces_seconds": t_f, "terms": et,
                                        "max_force": float(np.abs(fo).max()), "atoms": len(atoms)}
+        # the uneven batch: 32 cells (24^3 .. 96^3) x 8 shifts = 256 systems,
+        # right-hand sides -L_h rho^alpha, -L_h rho^beta built with the library
+        extras["batched_256_systems"] = batch_extra(dev)
         # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)
         # on the same cell: one step from the initial state
         t0 = time.perf_counter()

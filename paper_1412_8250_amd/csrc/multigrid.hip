@@ -269,50 +269,127 @@ __global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, 
         }
 }
 
-// Trilinear prolongation added to u: fine index i takes coarse i/2 (even i)
-// or the mean of coarse (i-1)/2 and (i+1)/2 (odd i), per axis.  A thread runs
-// down kMgKZ fine planes (kMgKZ / 2 + 1 coarse planes, loaded once).
-template <typename S>
-__global__ void __launch_bounds__(kMgThreads) mg_prolong_add(MgDims fd, MgDims cd, const S *__restrict__ uc,
-                                                             S *__restrict__ u, MgShift sh) {
-    if (sh.run && *sh.run != 0) return;
-    MgPt p;
-    if (!mg_point(fd.nx, fd.ny, p)) return;
+// Coarse correction (P uc) on fine plane z + K (K = -1 .. kMgKZ) from the
+// corner sums cs[j][c] of coarse block plane j (coarse plane z / 2 - 1 + j)
+// for the fine column c: 1/4 of one plane's sum (even fine plane) or 1/8 of
+// two (odd fine plane).
+template <int K, int CI, typename S, int NZC>
+__device__ __forceinline__ S mg_corr(const S (&cs)[NZC][5]) {
     using V = VT<S>;
     using R = typename MgT<S>::R;
+    constexpr int J = (K + 2) >> 1;              // block plane of coarse plane (z + K) >> 1
+    if constexpr (K & 1)
+        return mg_axpy((R)0.125, V::add(cs[J][CI], cs[J + 1][CI]), V::zero());
+    else
+        return V::mul((R)0.25, cs[J][CI]);
+}
+
+// The first post-smoothing sweep with the coarse correction folded in:
+// t = v + omega (f - A v) / (diag + kappa), v = u + P uc, with P the
+// trilinear prolongation (per axis, fine index i takes coarse i/2 when i is
+// even and the mean of coarse (i-1)/2 and (i+1)/2 when odd), formed in
+// registers; v is never stored: it is the corrected u that the two
+// post-sweeps start from.  The thread's column needs v on planes z - 1 ..
+// z + kMgKZ at (x, y) and on planes z .. z + kMgKZ - 1 at the four (x, y)
+// neighbours; their coarse corners lie in a 3 x 3 block of coarse columns
+// around (x / 2, y / 2) on coarse planes z / 2 - 1 .. z / 2 + kMgKZ / 2, each
+// loaded once.
+template <typename TF, typename S>
+__global__ void __launch_bounds__(kMgThreads) mg_prolong_smooth(MgDims d, MgDims cd, double w,
+                                                                const TF *__restrict__ f,
+                                                                const S *__restrict__ u,
+                                                                const S *__restrict__ uc,
+                                                                S *__restrict__ t, MgShift sh) {
+    if (!take_shift(sh, d)) return;
+    MgPt p;
+    if (!mg_point(d.nx, d.ny, p)) return;
+    using V = VT<S>;
+    using R = typename MgT<S>::R;
+    using C = typename MgT<S>::C;
     static_assert(kMgKZ % 2 == 0, "chunks start on even planes");
-    const int64_t cnxy = (int64_t)cd.nx * cd.ny, fnxy = (int64_t)fd.nx * fd.ny;
-    const int x0 = p.x >> 1, y0 = p.y >> 1;
-    const int x1 = (p.x & 1) ? (x0 + 1 == cd.nx ? 0 : x0 + 1) : x0;
-    const int y1 = (p.y & 1) ? (y0 + 1 == cd.ny ? 0 : y0 + 1) : y0;
-    const int64_t o00 = (int64_t)y0 * cd.nx + x0, o01 = (int64_t)y0 * cd.nx + x1;
-    const int64_t o10 = (int64_t)y1 * cd.nx + x0, o11 = (int64_t)y1 * cd.nx + x1;
-    // (x, y) interpolation (sum of the 4 corners, weight 1/4 each) on coarse
-    // planes Z0 .. Z0 + kMgKZ / 2 (periodic)
-    S cp[kMgKZ / 2 + 1];
+    constexpr int NZC = kMgKZ / 2 + 2;             // coarse planes z/2 - 1 .. z/2 + kMgKZ/2
+    const int64_t nxy = (int64_t)d.nx * d.ny, cnxy = (int64_t)cd.nx * cd.ny;
+    const int cx0 = p.x >> 1, cy0 = p.y >> 1;
+    int64_t cxo[3], cyo[3];                        // block columns cx0 - 1 .. cx0 + 1, likewise y
 #pragma unroll
-    for (int j = 0; j < kMgKZ / 2 + 1; ++j) {
-        int Z = (p.z >> 1) + j;
-        Z = Z >= cd.nz ? Z - cd.nz : Z;
-        Z = Z >= cd.nz ? cd.nz - 1 : Z;      // past the end: unused, any valid plane
-        const int64_t b = (int64_t)Z * cnxy;
-        cp[j] = V::add(V::add(uc[b + o00], uc[b + o01]), V::add(uc[b + o10], uc[b + o11]));
+    for (int m = 0; m < 3; ++m) {
+        int X = cx0 - 1 + m, Y = cy0 - 1 + m;
+        X = X < 0 ? X + cd.nx : (X >= cd.nx ? X - cd.nx : X);
+        Y = Y < 0 ? Y + cd.ny : (Y >= cd.ny ? Y - cd.ny : Y);
+        cxo[m] = X;
+        cyo[m] = (int64_t)Y * cd.nx;
     }
+    // Corner sums of the fine columns c = 0: (x, y), 1: (x + 1, y), 2: (x - 1, y),
+    // 3: (x, y + 1), 4: (x, y - 1) on each block plane j.  Per axis the fine
+    // column at x + dx takes block columns (x0, x1) = (0, 1), (1, 1), (1, 2)
+    // for dx = -1, 0, 1 when x is even and (1, 1), (1, 2), (2, 2) when odd
+    // (grids are even, so the parity survives the periodic wrap); a corner sum
+    // is (x0 + x1 on row y0) + (x0 + x1 on row y1).  The row sums are formed
+    // for every candidate pair and the parity selects among the values.
+    const bool px = p.x & 1, py = p.y & 1;
+    S cs[NZC][5];
 #pragma unroll
-    for (int k = 0; k < kMgKZ; ++k)
-        if (p.z + k < fd.nz) {
-            // even plane: coarse plane k/2 (weight 1); odd: mean of k/2 and k/2 + 1
-            const S e = (k & 1) ? mg_axpy((R)0.125, V::add(cp[k >> 1], cp[(k >> 1) + 1]), V::zero())
-                                : V::mul((R)0.25, cp[k >> 1]);
-            const int64_t i = p.i + k * fnxy;
-            u[i] = V::add(u[i], e);
+    for (int j = 0; j < NZC; ++j) {
+        int Z = (p.z >> 1) - 1 + j;
+        Z = Z < 0 ? Z + cd.nz : (Z >= cd.nz ? Z - cd.nz : Z);
+        Z = Z >= cd.nz ? cd.nz - 1 : Z;            // chunk tail past the end: unused, any valid plane
+        const int64_t b = (int64_t)Z * cnxy;
+        S rm[3], r0[3], rp[3];                     // row sums for dx = -1, 0, +1 on block rows 0..2
+#pragma unroll
+        for (int my = 0; my < 3; ++my) {
+            const S c0 = uc[b + cyo[my] + cxo[0]], c1 = uc[b + cyo[my] + cxo[1]], c2 = uc[b + cyo[my] + cxo[2]];
+            const S s01 = V::add(c0, c1), s11 = V::add(c1, c1), s12 = V::add(c1, c2), s22 = V::add(c2, c2);
+            rm[my] = px ? s11 : s01;
+            r0[my] = px ? s12 : s11;
+            rp[my] = px ? s22 : s12;
         }
+        // rows (y0, y1): dy = 0 -> (1, 1) even / (1, 2) odd; +1 -> (1, 2) / (2, 2); -1 -> (0, 1) / (1, 1)
+        cs[j][0] = py ? V::add(r0[1], r0[2]) : V::add(r0[1], r0[1]);
+        cs[j][1] = py ? V::add(rp[1], rp[2]) : V::add(rp[1], rp[1]);
+        cs[j][2] = py ? V::add(rm[1], rm[2]) : V::add(rm[1], rm[1]);
+        cs[j][3] = py ? V::add(r0[2], r0[2]) : V::add(r0[1], r0[2]);
+        cs[j][4] = py ? V::add(r0[1], r0[1]) : V::add(r0[0], r0[1]);
+    }
+    const int64_t row = (int64_t)p.y * d.nx + p.x;
+    const int dxp = p.x + 1 == d.nx ? -p.x : 1, dxm = p.x == 0 ? d.nx - 1 : -1;
+    const int64_t dyp = p.y + 1 == d.ny ? -(int64_t)p.y * d.nx : d.nx;
+    const int64_t dym = p.y == 0 ? (int64_t)(d.ny - 1) * d.nx : -(int64_t)d.nx;
+    // v on the centre column, planes z - 1 .. z + kMgKZ
+    S col[kMgKZ + 2];
+    static_for<0, kMgKZ + 2>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        int z = p.z - 1 + k;
+        z = z < 0 ? z + d.nz : (z >= d.nz ? z - d.nz : z);
+        z = z >= d.nz ? d.nz - 1 : z;              // chunk tail past nz: any valid plane
+        col[k] = V::add(u[(int64_t)z * nxy + row], mg_corr<k - 1, 0>(cs));
+    });
+    const C kap = mk_c<C>(d.kre, d.kim);
+    const auto s = jacobi_factor<C>(d, w);
+    static_for<0, kMgKZ>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value;
+        if (p.z + k < d.nz) {
+            const int64_t i = (int64_t)(p.z + k) * nxy + row;
+            const S c = col[k + 1];
+            const S vxp = V::add(u[i + dxp], mg_corr<k, 1>(cs));
+            const S vxm = V::add(u[i + dxm], mg_corr<k, 2>(cs));
+            const S vyp = V::add(u[i + dyp], mg_corr<k, 3>(cs));
+            const S vym = V::add(u[i + dym], mg_corr<k, 4>(cs));
+            S a = V::mul((R)d.diag, c);
+            a = mg_axpy((R)-d.cx, V::add(vxp, vxm), a);
+            a = mg_axpy((R)-d.cy, V::add(vyp, vym), a);
+            a = mg_axpy((R)-d.cz, V::add(col[k], col[k + 2]), a);
+            const S av = V::add(a, mg_scale(kap, c));
+            t[i] = V::add(c, mg_scale(s, V::sub(cv<S>(f[i]), av)));
+        }
+    });
 }
 
 // Exact solve on the coarsest grid (at most 16^3 points, one workgroup, FP64):
 // A is diagonalised by the DFT, eigenvalue sum_a c_a (2 - 2 cos(2 pi k_a / n_a))
 // + kappa; with kappa = 0 the k = 0 (constant) component is set to zero.
-__device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz, int axis, double sign) {
+// tw[m] = (cos, sin)(2 pi m / len) for m < len, one table per axis.
+__device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz, int axis, double sign,
+                         const double2 *tw) {
     const int n = nx * ny * nz;
     const int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
     const int stride = axis == 0 ? 1 : (axis == 1 ? nx : nx * ny);
@@ -321,13 +398,14 @@ __device__ void dft_axis(const double2 *in, double2 *out, int nx, int ny, int nz
         const int k = axis == 0 ? x : (axis == 1 ? y : z);
         const int base = o - k * stride;
         double re = 0.0, im = 0.0;
+        int m = 0;                                 // (j k) mod len
         for (int j = 0; j < len; ++j) {
-            double sn, cs;
-            sincospi(2.0 * (double)((j * k) % len) / (double)len, &sn, &cs);
-            sn *= sign;
+            const double cs = tw[m].x, sn = sign * tw[m].y;
             const double2 v = in[base + j * stride];
             re += v.x * cs - v.y * sn;
             im += v.x * sn + v.y * cs;
+            m += k;
+            if (m >= len) m -= len;
         }
         out[o] = make_double2(re, im);
     }
@@ -348,20 +426,27 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const TI
     if (!take_shift(sh, d)) return;
     __shared__ double2 a[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     __shared__ double2 b[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
+    __shared__ double2 tw[3][kMgCoarseMax];
     const int n = (int)d.n;
     for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = mg_to_c(f[i]);
+    for (int i = threadIdx.x; i < 3 * kMgCoarseMax; i += blockDim.x) {
+        const int ax = i / kMgCoarseMax, m = i % kMgCoarseMax;
+        const int len = ax == 0 ? d.nx : (ax == 1 ? d.ny : d.nz);
+        double sn = 0.0, cs = 1.0;
+        if (m < len) sincospi(2.0 * (double)m / (double)len, &sn, &cs);
+        tw[ax][m] = make_double2(cs, sn);
+    }
     __syncthreads();
-    dft_axis(a, b, d.nx, d.ny, d.nz, 0, -1.0);
+    dft_axis(a, b, d.nx, d.ny, d.nz, 0, -1.0, tw[0]);
     __syncthreads();
-    dft_axis(b, a, d.nx, d.ny, d.nz, 1, -1.0);
+    dft_axis(b, a, d.nx, d.ny, d.nz, 1, -1.0, tw[1]);
     __syncthreads();
-    dft_axis(a, b, d.nx, d.ny, d.nz, 2, -1.0);
+    dft_axis(a, b, d.nx, d.ny, d.nz, 2, -1.0, tw[2]);
     __syncthreads();
     for (int o = threadIdx.x; o < n; o += blockDim.x) {
         const int x = o % d.nx, y = (o / d.nx) % d.ny, z = o / (d.nx * d.ny);
-        const double lr = d.cx * (2.0 - 2.0 * cospi(2.0 * x / d.nx)) +
-                          d.cy * (2.0 - 2.0 * cospi(2.0 * y / d.ny)) +
-                          d.cz * (2.0 - 2.0 * cospi(2.0 * z / d.nz)) + d.kre;
+        const double lr = d.cx * (2.0 - 2.0 * tw[0][x].x) + d.cy * (2.0 - 2.0 * tw[1][y].x) +
+                          d.cz * (2.0 - 2.0 * tw[2][z].x) + d.kre;
         const double li = d.kim, den = lr * lr + li * li;
         double2 v = b[o];
         if (den == 0.0) {
@@ -373,11 +458,11 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const TI
         b[o] = v;
     }
     __syncthreads();
-    dft_axis(b, a, d.nx, d.ny, d.nz, 0, 1.0);
+    dft_axis(b, a, d.nx, d.ny, d.nz, 0, 1.0, tw[0]);
     __syncthreads();
-    dft_axis(a, b, d.nx, d.ny, d.nz, 1, 1.0);
+    dft_axis(a, b, d.nx, d.ny, d.nz, 1, 1.0, tw[1]);
     __syncthreads();
-    dft_axis(b, a, d.nx, d.ny, d.nz, 2, 1.0);
+    dft_axis(b, a, d.nx, d.ny, d.nz, 2, 1.0, tw[2]);
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += blockDim.x) mg_from_c(a[i], u[i]);
 }
@@ -402,8 +487,8 @@ int vcycle_coarse(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s
                        (S *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     OFDFT_TRY(vcycle_coarse<S>(mg, l + 1, kappa, sh, s));
-    hipLaunchKernelGGL(mg_prolong_add<S>, grid, block, 0, s, d, cd, (const S *)C.u, u, sh);
-    hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, (const S *)u, t, sh);
+    hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, (const S *)f,
+                       (const S *)u, (const S *)C.u, t, sh);
     hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, (const S *)t, u, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
@@ -439,13 +524,14 @@ int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipSt
                        (S *)C.f, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     OFDFT_TRY(vcycle_coarse<S>(mg, 1, kappa, sh, s));
-    hipLaunchKernelGGL(mg_prolong_add<S>, grid, block, 0, s, d, cd, (const S *)C.u, u, sh);
     if constexpr (sizeof(S) < sizeof(TIO)) {
         const S *fl = (const S *)L.f;
-        hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, fl, (const S *)u, t, sh);
+        hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, fl, (const S *)u,
+                           (const S *)C.u, t, sh);
         hipLaunchKernelGGL((mg_smooth<S, S, TIO>), grid, block, 0, s, d, mg.omega, fl, (const S *)t, z, sh);
     } else {
-        hipLaunchKernelGGL((mg_smooth<TIO, S, S>), grid, block, 0, s, d, mg.omega, f, (const S *)u, t, sh);
+        hipLaunchKernelGGL((mg_prolong_smooth<TIO, S>), grid, block, 0, s, d, cd, mg.omega, f, (const S *)u,
+                           (const S *)C.u, t, sh);
         hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, (const S *)t, z, sh);
     }
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -535,19 +621,19 @@ int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *
 
 // Algorithmic bytes of one cycle.  Fine level, FP64 levels: f is read by the
 // pre-smoothing, the residual and both post-sweeps, z written once, and the
-// work arrays move 9.25 elements per point (u written; residual reads u and
-// writes r; restriction reads r and writes an eighth; prolongation reads an
-// eighth and reads and writes u; the post-sweeps read u / t and write t).
-// FP32 levels: f (FP64) is read once and stored as FP32, which the other
-// three passes read (4 more FP32 moves).  Each coarser level moves 14.25
-// elements per point, and they hold 1/7 of the fine points in all.
+// work arrays move 7.25 elements per point (u written; residual reads u and
+// writes r; restriction reads r and writes an eighth; the first post-sweep
+// reads u and an eighth (the coarse correction) and writes t; the second
+// reads t).  FP32 levels: f (FP64) is read once and stored as FP32, which the
+// other three passes read (4 more FP32 moves).  Each coarser level moves
+// 12.25 elements per point, and they hold 1/7 of the fine points in all.
 double mg_cycle_bytes(const Multigrid &mg) {
     if (mg.lv.empty()) return 0.0;
     const double E = (double)mg.elem, e = mg.fp32 ? E / 2 : E;
     const double n = (double)mg.lv[0].n;
     if (mg.lv.size() == 1) return 2.0 * n * E;
-    const double fine = mg.fp32 ? 2.0 * E + 13.25 * e : 5.0 * E + 9.25 * e;
-    return n * fine + n / 7.0 * 14.25 * e;
+    const double fine = mg.fp32 ? 2.0 * E + 11.25 * e : 5.0 * E + 7.25 * e;
+    return n * fine + n / 7.0 * 12.25 * e;
 }
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible
