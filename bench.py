@@ -182,6 +182,13 @@ def profile_kernel(which, shape, h, reps=5):
     print(f"profiled {which} x{reps}", flush=True)
 
 
+# The density update's line search accepts a step once |dE/ds| is 1/100 of
+# its value at s = 0 (the library's default is a million-fold reduction, an
+# exact line search); measured on this step: 65 instead of 66 iterations and
+# 348 instead of 418 vector passes, the same minimiser to the 1e-8 tolerance.
+LINE_SLOPE_TOL = 1e-2
+
+
 def batch_extra(dev):
     """Time to 1e-8 of the uneven 32-cell x 8-shift batch (Re kappa > 0):
     complex128 COCG, complex64 COCG in complex128 refinement, and complex128
@@ -257,7 +264,8 @@ def main():
                   u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8,
                   poisson_mode=ofd.PLAIN_F64 if args.plain_poisson else ofd.MULTIGRID,
                   helmholtz_precond=ofd.PRECOND_NONE if args.plain_helmholtz else ofd.PRECOND_MULTIGRID,
-                  u_precond=ofd.PRECOND_NONE if args.plain_density else ofd.PRECOND_MULTIGRID)
+                  u_precond=ofd.PRECOND_NONE if args.plain_density else ofd.PRECOND_MULTIGRID,
+                  line_slope_tol=LINE_SLOPE_TOL)
     torch.cuda.synchronize()
     log(f"context + v0 in {time.perf_counter() - t0:.1f}s")
 

@@ -260,6 +260,9 @@ typedef struct {
                                   batched 8 at a time                                  */
     double u_precond_sigma;    /* sigma of the density update's preconditioner (hartree);
                                   0 = V_TF(N_e / volume)                               */
+    double line_slope_tol;     /* line search: a step is accepted once |dE/ds| is at most
+                                  this fraction of its value at s = 0 (or the bracket is
+                                  below line_tol); 0 = 1e-6 (an exact line search)      */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

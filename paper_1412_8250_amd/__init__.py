@@ -51,7 +51,7 @@ class ScfParams(ctypes.Structure):
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
                 ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int),
-                ("u_precond_sigma", ctypes.c_double)]
+                ("u_precond_sigma", ctypes.c_double), ("line_slope_tol", ctypes.c_double)]
 
 
 class GaussAtoms(ctypes.Structure):
@@ -375,7 +375,8 @@ class SCF:
                  u_max_iter: int = 20000, poisson_tol: float = 1e-10, poisson_mode: int = PLAIN_F64,
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
-                 u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0, stream=None):
+                 u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0,
+                 line_slope_tol: float = 0.0, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -388,6 +389,7 @@ class SCF:
         p.u_precond = int(u_precond)
         p.lr_order = int(lr_order)
         p.u_precond_sigma = float(u_precond_sigma)
+        p.line_slope_tol = float(line_slope_tol)
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

@@ -278,6 +278,7 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     res = INFINITY;
     eta = 0.0;
     double s_prev = s->s_prev;
+    double f0_prev = 0.0;                        // slope at s = 0 of the previous iteration
     const int maxit = s->p.u_max_iter > 0 ? s->p.u_max_iter : 20000;
     const int nres = s->p.n_restart > 0 ? s->p.n_restart : 50;
     for (;;) {
@@ -360,14 +361,23 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         }
         if (!(f0 < 0.0)) break;                  // no descent possible at this precision
         double lo = 0.0, flo = f0;
+        // first probe: the previous step scaled by the ratio of the slopes at
+        // s = 0 (the first-order decrease of the last step, repeated), kept
+        // within 0.1x..10x of that step; with no history, the previous step
+        // or a step of the size of u
         double hi = s_prev > 0 ? s_prev : 1.0 / std::sqrt(std::max(dd * dv / ne, 1e-300));
+        if (s_prev > 0 && f0_prev < 0.0) hi = s_prev * std::min(std::max(f0_prev / f0, 0.1), 10.0);
+        const double ltol = s->p.line_tol > 0.0 ? s->p.line_tol : 1e-8;
+        const double stol = s->p.line_slope_tol > 0.0 ? s->p.line_slope_tol : 1e-6;
+        const double ftol = stol * std::fabs(f0);
         double fhi;
         OFDFT_TRY(slope(hi, fhi));
         // Bracket the root of dE/ds: while the slope is still negative, step
         // just past the secant estimate of its zero (at least 1.1x, at most
         // 8x further), which the nearly linear slope usually brackets at once.
+        // A probe whose slope is already within ftol is the accepted step.
         int grow = 0;
-        while (fhi < 0.0 && grow < 80) {
+        while (fhi < 0.0 && std::fabs(fhi) > ftol && grow < 80) {
             double next = 2.0 * hi;
             if (fhi > flo) {
                 const double sec = hi + (hi - lo) * (-fhi) / (fhi - flo);
@@ -381,15 +391,17 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
         }
         if (!std::isfinite(fhi)) return OFDFT_NONFINITE;
         double sstar = hi;
-        const double ltol = s->p.line_tol > 0.0 ? s->p.line_tol : 1e-8;
-        // the slope is reduced a million-fold at the accepted step (an exact
-        // line search for NLCG purposes), or the bracket is below ltol
-        OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, ltol * hi, 1e-6 * std::fabs(f0), 200, sstar));
+        // the slope is reduced by stol at the accepted step (by default a
+        // million-fold: an exact line search for NLCG purposes), or the
+        // bracket is below ltol
+        if (std::fabs(fhi) > ftol)
+            OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, ltol * hi, ftol, 200, sstar));
         const double ww = uu + sstar * (2.0 * ud + sstar * dd);
         const double c = sqn / std::sqrt(dv * ww);
         StepOp so{u, d_cur, sstar, c};
         OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
         s_prev = std::fabs(sstar);
+        f0_prev = f0;
         rr_prev = rr;
         rz_prev = rz;
         std::swap(r_cur, r_prev);

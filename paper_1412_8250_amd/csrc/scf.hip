@@ -432,7 +432,7 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     OFDFT_TRY(check_grid(&p->grid, p->radius));
     if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
         !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
-        (p->lr_order != 0 && p->lr_order != 2)) {
+        (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0)) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }

@@ -198,3 +198,25 @@ def test_kernel_term_and_preconditioner_option_errors():
     with pytest.raises(ofd.OfdftError):
         ctx.energy(np.zeros((4, 3)), sigma=0.0)
     ctx.close()
+
+
+def test_density_update_inexact_line_search():
+    """A line search that stops once |dE/ds| is 1/100 of its starting value
+    reaches the same minimiser as the oracle's exact Brent search."""
+    torch_cuda()
+    announce("density update, line_slope_tol 1e-2")
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    for precond in (ofd.PRECOND_NONE, ofd.PRECOND_MULTIGRID):
+        ctx = _ctx(w, lam=1.0, u_precond=precond, line_slope_tol=1e-2)
+        ud = to_dev(np.sqrt(w.rho))
+        it, res, eta = ctx.density_update(to_dev(phi), ud)
+        u_ref, _, _, eta_ref = density.update(np.sqrt(w.rho), phi, w.cell.h, 1.0, w.cell.n_electrons, tol=1e-10)
+        u = to_host(ud)
+        assert res <= 1e-10
+        assert abs(eta - eta_ref) < 1e-9
+        assert np.abs(u - u_ref).max() < 1e-7 * np.abs(u_ref).max()
+        ctx.close()
+    with pytest.raises(ofd.OfdftError):
+        _ctx(w, lam=1.0, line_slope_tol=1.0)
