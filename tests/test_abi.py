@@ -58,3 +58,62 @@ def test_invalid_arguments_are_rejected_without_gpu_work():
     g = m.Grid(4, 4, 4, -0.5, 0.5, 0.5)
     assert l.fd_laplacian_apply(ctypes.byref(g), 6, m.F64, ctypes.c_void_p(8), ctypes.c_void_p(16),
                                 1.0, 0.0, None) == m.INVALID_ARG
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the parameter structs have the header's size and
+    field offsets (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    import paper_1412_8250_amd as m
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    checks = {"ofdft_scf_params": m.ScfParams, "ofdft_grid": m.Grid, "ofdft_gauss_atoms": m.GaussAtoms}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ofdft.h"', "int main(void) {"]
+    for cname, cls in checks.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            cf = {"lam": "lambda"}.get(fname, fname)
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in checks.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_scf_parameters_are_checked_before_gpu_work():
+    """An out-of-range line-search slope tolerance (and other bad parameters)
+    is rejected by the argument checks, before any device allocation."""
+    import paper_1412_8250_amd as m
+    l = m.lib()
+    p = m.ScfParams()
+    p.grid = m.Grid(16, 16, 16, 0.5, 0.5, 0.5)
+    p.radius, p.lam, p.mu, p.n_electrons = 6, 0.2, 0, 12.0
+    p.history, p.zeta, p.u_tol, p.poisson_tol, p.helmholtz_tol = 7, 0.3, 1e-8, 1e-8, 1e-8
+    out = ctypes.c_void_p()
+    for field, bad in (("line_slope_tol", 1.0), ("line_slope_tol", -0.1), ("line_slope_tol", float("nan")),
+                       ("lr_order", 1), ("u_tol", 0.0)):
+        q = m.ScfParams.from_buffer_copy(p)
+        setattr(q, field, bad)
+        st = l.ofdft_scf_create(ctypes.byref(q), ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.byref(out), None)
+        assert st == m.INVALID_ARG, (field, bad)
+        assert "invalid parameters" in m.last_error()
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with a message
+    before anything touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
