@@ -134,7 +134,7 @@ int cg_poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_
  * this off for the solver (results are bitwise identical either way). */
 int ofdft_poisson_set_graphs(ofdft_poisson *s, int enable);
 /* Refined form: each FP32 inner solve targets 0.3 x (remaining reduction),
- * clamped to [inner_min, inner_max] (defaults 1e-5, 1e-2).  INVALID_ARG unless
+ * clamped to [inner_min, inner_max] (defaults 1e-5, 1e-1).  INVALID_ARG unless
  * 0 < inner_min <= inner_max < 1. */
 int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inner_max);
 

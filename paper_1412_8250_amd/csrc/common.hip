@@ -106,4 +106,4 @@ extern "C" int ofdft_last_error(char *buf, size_t len) {
     return (int)e.size();
 }
 
-extern "C" const char *ofdft_version(void) { return "ofdft-gfx950 0.1"; }
+extern "C" const char *ofdft_version(void) { return "ofdft-gfx950 0.2"; }

@@ -457,7 +457,7 @@ extern "C" int ofdft_poisson_destroy(ofdft_poisson *s) {
     return OFDFT_OK;
 }
 
-// Bounds of the FP32 inner tolerance of the refined form (defaults 1e-5, 1e-2).
+// Bounds of the FP32 inner tolerance of the refined form (defaults 1e-5, 1e-1).
 extern "C" int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inner_max) {
     if (!s || !(inner_min > 0) || !(inner_max >= inner_min) || !(inner_max < 1)) {
         set_error("ofdft_poisson_set_refinement: need 0 < inner_min <= inner_max < 1");

@@ -24,7 +24,7 @@ struct ofdft_poisson {
     // captured iteration blocks (FP64 and FP32 loops)
     ofdft::CgGraph *graph64 = nullptr, *graph32 = nullptr;
     bool use_graphs = true;
-    double inner_min = 1e-5, inner_max = 1e-2;    // FP32 inner tolerance bounds (refined form)
+    double inner_min = 1e-5, inner_max = 1e-1;    // FP32 inner tolerance bounds (refined form)
     // learned form
     ofdft_nn *net = nullptr;
     double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
