@@ -358,11 +358,13 @@ def main():
         forms = [("plain_f64", ofd.PLAIN_F64, None), ("refined_f32", ofd.REFINED_F32, None),
                  ("multigrid", ofd.MULTIGRID, None)]
         if net is not None:
-            forms += [("learned", ofd.LEARNED, False), ("learned_fcg", ofd.LEARNED, True)]
+            forms += [("learned", ofd.LEARNED, False), ("learned_fcg", ofd.LEARNED, True),
+                      ("learned_refined", ofd.LEARNED_REFINED, False)]
         for name, mode, fcg in forms:
             s = ofd.PoissonSolver(shape, h, 6, mode)
-            if mode == ofd.LEARNED:
+            if mode in (ofd.LEARNED, ofd.LEARNED_REFINED):
                 s.set_network(net)
+            if mode == ofd.LEARNED:
                 s.set_learned_mode(fcg)
             x = torch.zeros_like(g)
             s.solve(g, x, 1e-8, allow_not_converged=True)      # warm-up (graphs, workspaces)
@@ -371,7 +373,7 @@ def main():
             extras[f"poisson_{name}_time_to_1e-8_s"] = st["seconds"]
             extras[f"poisson_{name}_iters"] = st["iters"]
             extras[f"poisson_{name}_rel_res"] = st["rel_res"]
-            if mode == ofd.LEARNED:
+            if mode in (ofd.LEARNED, ofd.LEARNED_REFINED):
                 extras[f"poisson_{name}_nn_applies"] = st["nn_applies"]
                 extras[f"poisson_{name}_fell_back"] = st["fell_back"]
             s.close()

@@ -52,6 +52,9 @@ typedef enum {
                                   the second-order operator, FP64 vectors; the cycle's
                                   level arrays in FP32                                    */
     OFDFT_MULTIGRID_F64 = 4,   /* the same with the cycle in FP64 throughout              */
+    OFDFT_LEARNED_REFINED = 5, /* the learned form's network correction of the starting
+                                  guess, then the refined form (FP32 CG inside FP64
+                                  residual refinement) to the tolerance                  */
 } ofdft_mode;
 
 typedef struct {
@@ -107,7 +110,8 @@ int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
  *   mode  OFDFT_PLAIN_F64, OFDFT_REFINED_F32, OFDFT_MULTIGRID or
  *         OFDFT_MULTIGRID_F64 (every axis must halve evenly down to at most
  *         16 points; INVALID_ARG otherwise) or
- *         OFDFT_LEARNED (needs a network, see ofdft_poisson_set_network).
+ *         OFDFT_LEARNED or OFDFT_LEARNED_REFINED (need a network, see
+ *         ofdft_poisson_set_network).
  *         Multigrid: M = one V(2,2) cycle of the periodic 7-point operator
  *         (damped Jacobi, omega 0.8; full weighting; trilinear
  *         prolongation; exact DFT solve on the coarsest grid), a fixed
@@ -352,14 +356,16 @@ int ofdft_density_update(ofdft_scf *s, const double *v, double *u, int *iters,
  *   order); train_step also applies Adam (beta 0.9/0.999, eps 1e-8) with
  *   learning rate lr.  loss (host) may be NULL.
  * ofdft_nn_set_loss: choose the loss kind (0 default, 1, 2); INVALID_ARG else.
- * ofdft_poisson_set_network: attach a network to an OFDFT_LEARNED solver
- *   (the solver keeps the pointer; the network must outlive its use).
+ * ofdft_poisson_set_network: attach a network to an OFDFT_LEARNED or
+ *   OFDFT_LEARNED_REFINED solver (the solver keeps the pointer; the network
+ *   must outlive its use).
  * ofdft_poisson_set_learned_mode: what the learned form does after the
  *   network's correction of the starting guess (x += a N(r) with the step a
  *   minimising the energy-norm error): precondition 0 (default) = plain FP64
  *   CG to the tolerance; 1 = flexible CG preconditioned by the network,
  *   falling back to plain CG from the best iterate when it stalls (less than
- *   10x residual reduction in 20 iterations) or breaks down.
+ *   10x residual reduction in 20 iterations) or breaks down.  OFDFT_LEARNED
+ *   only (OFDFT_LEARNED_REFINED always continues with the refined form).
  * ------------------------------------------------------------------------ */
 typedef struct ofdft_nn ofdft_nn;
 int ofdft_nn_create(uint64_t seed, ofdft_nn **out);

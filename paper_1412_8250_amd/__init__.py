@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libofdft.so")
 
 OK, NOT_CONVERGED, INVALID_ARG, NONFINITE, BREAKDOWN, HIP_ERROR, NO_MEMORY = 0, 1, -1, -2, -3, -4, -5
 F64, F32, C128, C64 = 0, 1, 2, 3
-PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID, MULTIGRID_F64 = 0, 1, 2, 3, 4
+PLAIN_F64, REFINED_F32, LEARNED, MULTIGRID, MULTIGRID_F64, LEARNED_REFINED = 0, 1, 2, 3, 4, 5
 PRECOND_NONE, PRECOND_MULTIGRID, PRECOND_MULTIGRID_F64 = 0, 1, 2
 
 

@@ -240,7 +240,7 @@ int poisson_alloc(ofdft_poisson *s) {
     OFDFT_CHECK_HIP(hipMalloc(&s->pA, b8));
     OFDFT_CHECK_HIP(hipMalloc(&s->pB, b8));
     OFDFT_CHECK_HIP(hipMalloc(&s->Ap, b8));
-    if (s->mode == OFDFT_REFINED_F32) {
+    if (s->mode == OFDFT_REFINED_F32 || s->mode == OFDFT_LEARNED_REFINED) {
         OFDFT_CHECK_HIP(hipMalloc(&s->r32, b4));
         OFDFT_CHECK_HIP(hipMalloc(&s->d32, b4));
         OFDFT_CHECK_HIP(hipMalloc(&s->qA, b4));
@@ -331,7 +331,7 @@ int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
     return status_from_done(done);
 }
 
-static int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
                          ofdft_solve_stats &stats, hipStream_t st) {
     const int64_t n = npoints(s->g);
     // Each FP32 inner solve targets the reduction still needed (with margin),
@@ -389,7 +389,8 @@ int poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol
     OFDFT_TRY(project_rhs(s, rhs, st));
     int status;
     if (s->mode == OFDFT_REFINED_F32) status = solve_refined(s, x, rel_tol, max_iter, stats, st);
-    else if (s->mode == OFDFT_LEARNED) status = poisson_solve_learned(s, x, rel_tol, max_iter, stats, st);
+    else if (s->mode == OFDFT_LEARNED || s->mode == OFDFT_LEARNED_REFINED)
+        status = poisson_solve_learned(s, x, rel_tol, max_iter, stats, st);
     else if (s->mode == OFDFT_MULTIGRID || s->mode == OFDFT_MULTIGRID_F64)
         status = poisson_solve_mg(s, x, rel_tol, max_iter, stats, st);
     else status = solve_plain(s, x, rel_tol, max_iter, stats, st);
@@ -420,7 +421,7 @@ extern "C" int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode
         return OFDFT_INVALID_ARG;
     }
     if (mode != OFDFT_PLAIN_F64 && mode != OFDFT_REFINED_F32 && mode != OFDFT_LEARNED &&
-        mode != OFDFT_MULTIGRID && mode != OFDFT_MULTIGRID_F64) {
+        mode != OFDFT_MULTIGRID && mode != OFDFT_MULTIGRID_F64 && mode != OFDFT_LEARNED_REFINED) {
         set_error("ofdft_poisson_create: unknown mode %d", mode);
         return OFDFT_INVALID_ARG;
     }

@@ -42,6 +42,10 @@ int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
 // Plain FP64 CG from the iterate x (residual recomputed first); stats.iters set.
 int solve_plain(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
                 ofdft_solve_stats &stats, hipStream_t st);
+// FP32 CG inside FP64 residual refinement from the current x (needs the FP32
+// workspace of the refined forms).
+int solve_refined(ofdft_poisson *s, double *x, double rel_tol, int max_iter,
+                ofdft_solve_stats &stats, hipStream_t st);
 
 template <typename T>
 int cg_k1(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const T *r, const T *p_old,

@@ -1,6 +1,8 @@
 // Learned form of the Poisson solve: a network initial guess and flexible CG
 // with the network as preconditioner (the paper calls for real-space
 // preconditioners to make iteration counts size-independent, Section 5.5).
+// The learned-refined form continues from the corrected guess with FP32 CG
+// inside FP64 residual refinement instead.
 //
 //   M(r) = h^2 rms(r) N(r / rms(r)), projected to zero mean
 //   x_0 = x + M(g - A x);  r_0 = g - A x_0;  z_0 = M(r_0);  p_0 = z_0
@@ -64,6 +66,14 @@ int poisson_solve_learned(ofdft_poisson *s, double *x, double rel_tol, int max_i
         OFDFT_TRY(residual(r2));
     }
     stats.nn_applies = applies;
+    if (s->mode == OFDFT_LEARNED_REFINED) {      // the refined form from the corrected guess
+        ofdft_solve_stats rest{};
+        const int status = solve_refined(s, x, rel_tol, max_iter, rest, st);
+        stats.iters = rest.iters;
+        stats.outer_iters = rest.outer_iters;
+        stats.fell_back = 0;
+        return status;
+    }
     if (!s->learned_fcg) {
         ofdft_solve_stats rest{};
         const int status = solve_plain(s, x, rel_tol, max_iter, rest, st);
@@ -147,8 +157,8 @@ extern "C" int ofdft_poisson_set_learned_mode(ofdft_poisson *s, int precondition
 }
 
 extern "C" int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net) {
-    if (!s || s->mode != OFDFT_LEARNED) {
-        set_error("ofdft_poisson_set_network: solver must be created with OFDFT_LEARNED");
+    if (!s || (s->mode != OFDFT_LEARNED && s->mode != OFDFT_LEARNED_REFINED)) {
+        set_error("ofdft_poisson_set_network: solver must be created with OFDFT_LEARNED(_REFINED)");
         return OFDFT_INVALID_ARG;
     }
     if (!net) {

@@ -134,6 +134,35 @@ def test_learned_poisson_solve_reaches_tolerance(precondition):
     assert poisson.residual(to_host(x2), g, w.cell.h) <= 1e-8
 
 
+@pytest.mark.parametrize("trained", [True, False])
+def test_learned_refined_poisson_solve(trained):
+    """The learned-refined form: the network's correction of the zero guess,
+    then FP32 CG inside FP64 residual refinement, to 1e-8 against the oracle's
+    exact solution; an untrained network changes the path, not the answer."""
+    torch = torch_cuda()
+    announce("learned-refined poisson", trained)
+    net = ofd.Network(13)
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    gd, pd = to_dev(g), to_dev(phi)
+    if trained:
+        for _ in range(40):
+            net.train_step(gd, pd, w.cell.h, 1e-3)
+    s = ofd.PoissonSolver(g.shape, w.cell.h, 6, ofd.LEARNED_REFINED)
+    with pytest.raises(ofd.OfdftError):
+        st = s.solve(gd, torch.zeros_like(gd), 1e-8)        # no network attached yet
+    s.set_network(net)
+    with pytest.raises(ofd.OfdftError):
+        s.set_learned_mode(True)                             # flexible CG is the learned form's option
+    x = torch.zeros_like(gd)
+    st = s.solve(gd, x, 1e-8)
+    assert st["nn_applies"] == 1 and st["outer_iters"] >= 1
+    assert poisson.residual(to_host(x), g, w.cell.h) <= 1e-8
+    assert np.abs(to_host(x) - phi).max() <= 1e-6 * np.abs(phi).max()
+    s.close()
+
+
 def test_trained_network_gain():
     """What the trained network gains over the method without it.  Trained on
     solver-generated pairs of small perturbed cells (energy-norm loss), its
