@@ -325,6 +325,9 @@ def main():
                 "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                 "avg_launch_ms": dom["ms"] / max(dom["timed"], 1),
                 "measured_on": "one extra step after the timed region, events around each launch of the class"}
+    # the extras run untimed: per-launch events would force the eager paths
+    # (the batched solver's per-system cycles, no graph replays)
+    ofd.profile_reset(timed=())
 
     extras = {}
     if not args.no_extras and args.workload == "large":

@@ -462,6 +462,11 @@ void precond_free(ofdft_batch *b) {
         if (p) (void)hipFree(p);
     if (b->d_kap) (void)hipFree(b->d_kap);
     b->d_kap = nullptr;
+    if (b->d_rtab) (void)hipFree(b->d_rtab);
+    if (b->d_ztab) (void)hipFree(b->d_ztab);
+    b->d_rtab = b->d_ztab = nullptr;
+    b->mg_q.clear();
+    b->mg_groups.clear();
     for (hipStream_t q : b->mg_lane) (void)hipStreamDestroy(q);
     for (hipEvent_t e : b->mg_join) (void)hipEventDestroy(e);
     if (b->mg_fork) (void)hipEventDestroy(b->mg_fork);
@@ -652,7 +657,10 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
     // build everything first, so a failure leaves the batch unchanged
     std::vector<Multigrid *> own, of(b->nsys, nullptr);
     std::vector<void *> z(b->nsys, nullptr);
+    std::vector<int> qidx(b->nsys, 0);
+    std::vector<std::pair<int, int>> groups;
     double *kap = nullptr;
+    void **rtab = nullptr, **ztab = nullptr;
     const int lanes = std::min(b->nsys, kMgLanes);
     std::vector<hipStream_t> lane;
     std::vector<hipEvent_t> join;
@@ -665,6 +673,8 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
         for (void *p : z)
             if (p) (void)hipFree(p);
         if (kap) (void)hipFree(kap);
+        if (rtab) (void)hipFree(rtab);
+        if (ztab) (void)hipFree(ztab);
         for (hipStream_t q : lane) (void)hipStreamDestroy(q);
         for (hipEvent_t e : join) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
@@ -684,31 +694,56 @@ extern "C" int ofdft_batch_set_preconditioner(ofdft_batch *b, int kind) {
         set_error("ofdft_batch_set_preconditioner: out of device memory");
         return undo(OFDFT_NO_MEMORY);
     }
+    auto same = [](const ofdft_grid &p, const ofdft_grid &q) {
+        return q.nx == p.nx && q.ny == p.ny && q.nz == p.nz && q.hx == p.hx && q.hy == p.hy && q.hz == p.hz;
+    };
+    for (int j = 0; j < b->nsys;) {
+        int k = j + 1;
+        while (k < b->nsys && k - j < kMgGroupMax && same(b->grids[k], b->grids[j])) ++k;
+        Multigrid *mg = new (std::nothrow) Multigrid();
+        if (!mg) return undo(OFDFT_NO_MEMORY);
+        own.push_back(mg);
+        const int st = mg_create(*mg, b->grids[j], 16, kind == OFDFT_PRECOND_MULTIGRID, k - j);
+        if (st != OFDFT_OK) return undo(st);
+        for (int i = j; i < k; ++i) {
+            of[i] = mg;
+            qidx[i] = i - j;
+        }
+        groups.push_back({j, k - j});
+        j = k;
+    }
     for (int j = 0; j < b->nsys; ++j) {
         const ofdft_grid &g = b->grids[j];
-        for (int i = j % lanes; i < j && !of[j]; i += lanes) {      // same lane only
-            const ofdft_grid &q = b->grids[i];
-            if (q.nx == g.nx && q.ny == g.ny && q.nz == g.nz && q.hx == g.hx && q.hy == g.hy && q.hz == g.hz)
-                of[j] = of[i];
-        }
-        if (!of[j]) {
-            Multigrid *mg = new (std::nothrow) Multigrid();
-            if (!mg) return undo(OFDFT_NO_MEMORY);
-            own.push_back(mg);
-            const int st = mg_create(*mg, g, 16, kind == OFDFT_PRECOND_MULTIGRID);
-            if (st != OFDFT_OK) return undo(st);
-            of[j] = mg;
-        }
         if (hipMalloc(&z[j], sizeof(double2) * (size_t)npoints(g)) != hipSuccess) {
             z[j] = nullptr;
             set_error("ofdft_batch_set_preconditioner: out of device memory");
             return undo(OFDFT_NO_MEMORY);
         }
     }
+    {
+        std::vector<void *> rt(b->r.begin(), b->r.begin() + b->nsys);
+        if (hipMalloc(&rtab, sizeof(void *) * b->nsys) != hipSuccess) {
+            rtab = nullptr;
+            set_error("ofdft_batch_set_preconditioner: out of device memory");
+            return undo(OFDFT_NO_MEMORY);
+        }
+        if (hipMalloc(&ztab, sizeof(void *) * b->nsys) != hipSuccess) {
+            ztab = nullptr;
+            set_error("ofdft_batch_set_preconditioner: out of device memory");
+            return undo(OFDFT_NO_MEMORY);
+        }
+        if (hipMemcpy(rtab, rt.data(), sizeof(void *) * b->nsys, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ztab, z.data(), sizeof(void *) * b->nsys, hipMemcpyHostToDevice) != hipSuccess)
+            return undo(OFDFT_HIP_ERROR);
+    }
     OFDFT_CHECK_HIP(hipDeviceSynchronize());
     precond_free(b);
     b->mg_own = own;
     b->mg_of = of;
+    b->mg_q = qidx;
+    b->mg_groups = groups;
+    b->d_rtab = rtab;
+    b->d_ztab = ztab;
     b->z = z;
     b->d_kap = kap;
     b->mg_lane = lane;
@@ -726,7 +761,7 @@ extern "C" int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const dou
     }
     hipStream_t s = (hipStream_t)stream;
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_kap, kappa, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-    OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], (const double2 *)r, (double2 *)z, b->d_kap, nullptr, s));
+    OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], b->mg_q[j], (const double2 *)r, (double2 *)z, b->d_kap, nullptr, s));
     OFDFT_CHECK_HIP(hipStreamSynchronize(s));
     return OFDFT_OK;
 }

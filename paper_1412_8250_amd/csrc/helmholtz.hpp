@@ -116,16 +116,20 @@ struct ofdft_batch {
     hipGraphExec_t step_graph = nullptr;
     hipStream_t step_cap = nullptr;
     int step_graph_key[4] = {-1, -1, -1, -1};
-    // preconditioner (OFDFT_PRECOND_*): z = M r per system; systems on equal
-    // grids share one multigrid hierarchy (their cycles run one after another)
+    // preconditioner (OFDFT_PRECOND_*): z = M r per system
     int precond = 0;
     double *d_kap = nullptr;      // {Re, Im} for ofdft_batch_apply_preconditioner
     std::vector<void *> z;
     std::vector<ofdft::Multigrid *> mg_of, mg_own;
-    // the systems' cycles run on kMgLanes side streams (system j on lane
-    // j % lanes), forked from and joined back into the solve's stream, so
-    // the latency-bound coarse levels of different systems overlap; systems
-    // share a hierarchy only within a lane
+    // consecutive systems on one grid form a group: one hierarchy holds their
+    // level arrays (system j is member mg_q[j]) and one launch per kernel runs
+    // their cycles; groups as (first system, count)
+    std::vector<int> mg_q;
+    std::vector<std::pair<int, int>> mg_groups;
+    void **d_rtab = nullptr, **d_ztab = nullptr;   // r[j], z[j] (device tables)
+    // the groups' cycles run on kMgLanes side streams (group g on lane
+    // g % lanes), forked from and joined back into the solve's stream, so
+    // the latency-bound coarse levels of different groups overlap
     std::vector<hipStream_t> mg_lane;
     std::vector<hipEvent_t> mg_join;
     hipEvent_t mg_fork = nullptr;
@@ -134,6 +138,7 @@ struct ofdft_batch {
 namespace ofdft {
 
 constexpr int kMgLanes = 4;
+constexpr int kMgGroupMax = 64;     // systems per grouped cycle
 
 // Stepped schedule: run COCG on the systems in `which` (system table `hs`
 // already uploaded; maxit[j] per system) to relative residual tol.  On return

@@ -309,21 +309,30 @@ int precondition(ofdft_batch *b, hipStream_t s, bool timed) {
         OFDFT_CHECK_HIP(hipMemcpyAsync(b->h_step, b->d_step, sizeof(StepState) * b->nsys, hipMemcpyDeviceToHost, s));
         OFDFT_CHECK_HIP(hipStreamSynchronize(s));
     }
+    static_assert(sizeof(HSys) % sizeof(double) == 0 && sizeof(StepState) % sizeof(int) == 0,
+                  "per-system shift and status strides");
     const int lanes = timed ? 0 : (int)b->mg_lane.size();
     if (lanes) OFDFT_CHECK_HIP(hipEventRecord(b->mg_fork, s));
     for (int k = 0; k < lanes; ++k) OFDFT_CHECK_HIP(hipStreamWaitEvent(b->mg_lane[k], b->mg_fork, 0));
-    for (int j = 0; j < b->nsys; ++j) {
-        Multigrid *mg = b->mg_of[j];
-        const double *kap = &b->d_sys[j].kre;      // {kre, kim} of system j (device)
-        const int *run = &b->d_step[j].done;
-        hipStream_t q = lanes ? b->mg_lane[j % lanes] : s;
-        if (timed) {
+    if (timed) {
+        // one cycle per running system, one after another on s, each timed
+        for (int j = 0; j < b->nsys; ++j) {
             if (b->h_step[j].done != H_RUNNING) continue;
             // bytes are added after the pass from the iteration counts
-            ProfScope ps(K_MULTIGRID_C, 0.0, q);
-            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, q));
-        } else {
-            OFDFT_TRY(mg_apply_shifted(*mg, (const double2 *)b->r[j], (double2 *)b->z[j], kap, run, q));
+            ProfScope ps(K_MULTIGRID_C, 0.0, s);
+            OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], b->mg_q[j], (const double2 *)b->r[j], (double2 *)b->z[j],
+                                       &b->d_sys[j].kre, &b->d_step[j].done, s));
+        }
+    } else {
+        // one grouped cycle per group: shift {kre, kim} and status of system j
+        // at d_sys[j] and d_step[j]; converged systems' workgroups return at once
+        for (size_t g = 0; g < b->mg_groups.size(); ++g) {
+            const int j0 = b->mg_groups[g].first, cnt = b->mg_groups[g].second;
+            hipStream_t q = lanes ? b->mg_lane[g % lanes] : s;
+            OFDFT_TRY(mg_apply_shifted_group(*b->mg_of[j0], cnt, (const double2 *const *)(b->d_rtab + j0),
+                                             (double2 *const *)(b->d_ztab + j0), &b->d_sys[j0].kre,
+                                             (int)(sizeof(HSys) / sizeof(double)), &b->d_step[j0].done,
+                                             (int)(sizeof(StepState) / sizeof(int)), q));
         }
     }
     for (int k = 0; k < lanes; ++k) {

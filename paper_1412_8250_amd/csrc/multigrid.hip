@@ -32,8 +32,11 @@ MgDims dims_of(const MgLevel &L, double2 kappa) {
 constexpr int kMgBX = 64, kMgBY = 4, kMgKZ = 4;
 static_assert(kMgBX * kMgBY == kMgThreads, "block shape");
 
-dim3 mg_grid(int nx, int ny, int nz) {
-    return dim3((nx + kMgBX - 1) / kMgBX, (ny + kMgBY - 1) / kMgBY, (nz + kMgKZ - 1) / kMgKZ);
+// z chunks of one system; the systems of a launch are stacked along grid z
+__host__ __device__ inline int mg_zch(int nz) { return (nz + kMgKZ - 1) / kMgKZ; }
+
+dim3 mg_grid(int nx, int ny, int nz, int count = 1) {
+    return dim3((nx + kMgBX - 1) / kMgBX, (ny + kMgBY - 1) / kMgBY, mg_zch(nz) * count);
 }
 
 struct MgPt {
@@ -41,10 +44,13 @@ struct MgPt {
     int64_t i;       // index of (x, y, z)
 };
 
-__device__ inline bool mg_point(int nx, int ny, MgPt &p) {
+// System of the workgroup within its launch (grid z = system * chunks + chunk).
+__device__ inline int mg_sys(int nz) { return blockIdx.z / mg_zch(nz); }
+
+__device__ inline bool mg_point(int nx, int ny, int nz, MgPt &p) {
     p.x = blockIdx.x * kMgBX + threadIdx.x;
     p.y = blockIdx.y * kMgBY + threadIdx.y;
-    p.z = blockIdx.z * kMgKZ;
+    p.z = (blockIdx.z - mg_sys(nz) * mg_zch(nz)) * kMgKZ;
     p.i = ((int64_t)p.z * ny + p.y) * nx + p.x;
     return p.x < nx && p.y < ny;
 }
@@ -135,18 +141,30 @@ __device__ inline void apply7_col(const TI *__restrict__ u, const MgDims &d, con
 // Per-launch shift source: when `kap` is given, kappa is read from device
 // memory (so a captured launch follows the current shift); when `run` is
 // given the kernel returns at once unless *run == 0 (a converged system of a
-// batch).
+// batch).  System q of a launch reads kap + q kstride and run + q rstride.
 struct MgShift {
     const double *kap;
     const int *run;
+    int kstride, rstride;
+    __device__ bool skip(int q) const { return run && run[(int64_t)q * rstride] != 0; }
 };
 
-// Returns false when the launch is to be skipped; otherwise sets d's shift.
-__device__ inline bool take_shift(const MgShift &sh, MgDims &d) {
-    if (sh.run && *sh.run != 0) return false;
+// An array of every system of a launch: system q's part starts at
+// base + q stride, or at tab[q] (a device table of the callers' arrays).
+template <typename P>
+struct MgArr {
+    P *base;
+    int64_t stride;
+    P *const *tab;
+    __device__ P *at(int q) const { return tab ? tab[q] : (base ? base + (int64_t)q * stride : nullptr); }
+};
+
+// Returns false when system q is to be skipped; otherwise sets d's shift.
+__device__ inline bool take_shift(const MgShift &sh, MgDims &d, int q) {
+    if (sh.skip(q)) return false;
     if (sh.kap) {
-        d.kre = sh.kap[0];
-        d.kim = sh.kap[1];
+        d.kre = sh.kap[(int64_t)q * sh.kstride];
+        d.kim = sh.kap[(int64_t)q * sh.kstride + 1];
     }
     return true;
 }
@@ -163,11 +181,15 @@ __device__ inline C jacobi_factor(const MgDims &d, double w) {
 // When fl is given, f is also stored there in S (the fine level's later
 // passes then read the narrower copy).
 template <typename TF, typename S>
-__global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const TF *__restrict__ f,
-                                                      S *__restrict__ u, S *__restrict__ fl, MgShift sh) {
-    if (!take_shift(sh, d)) return;
+__global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, MgArr<const TF> fa, MgArr<S> ua,
+                                                      MgArr<S> fla, MgShift sh) {
+    const int q = mg_sys(d.nz);
+    if (!take_shift(sh, d, q)) return;
     MgPt p;
-    if (!mg_point(d.nx, d.ny, p)) return;
+    if (!mg_point(d.nx, d.ny, d.nz, p)) return;
+    const TF *__restrict__ f = fa.at(q);
+    S *__restrict__ u = ua.at(q);
+    S *__restrict__ fl = fla.at(q);
     using V = VT<S>;
     const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
     S fc[kMgKZ], af[kMgKZ];
@@ -184,12 +206,15 @@ __global__ void __launch_bounds__(kMgThreads) mg_pre2(MgDims d, double w, const 
 
 // t = u + omega (f - A u) / (diag + kappa), computed in S, stored as TO
 template <typename TF, typename S, typename TO>
-__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, const TF *__restrict__ f,
-                                                        const S *__restrict__ u, TO *__restrict__ t,
-                                                        MgShift sh) {
-    if (!take_shift(sh, d)) return;
+__global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, MgArr<const TF> fa,
+                                                        MgArr<const S> ua, MgArr<TO> ta, MgShift sh) {
+    const int q = mg_sys(d.nz);
+    if (!take_shift(sh, d, q)) return;
     MgPt p;
-    if (!mg_point(d.nx, d.ny, p)) return;
+    if (!mg_point(d.nx, d.ny, d.nz, p)) return;
+    const TF *__restrict__ f = fa.at(q);
+    const S *__restrict__ u = ua.at(q);
+    TO *__restrict__ t = ta.at(q);
     using V = VT<S>;
     const auto s = jacobi_factor<typename MgT<S>::C>(d, w);
     S uc[kMgKZ], au[kMgKZ];
@@ -205,12 +230,15 @@ __global__ void __launch_bounds__(kMgThreads) mg_smooth(MgDims d, double w, cons
 
 // r = f - A u
 template <typename TF, typename S>
-__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const TF *__restrict__ f,
-                                                          const S *__restrict__ u, S *__restrict__ r,
-                                                          MgShift sh) {
-    if (!take_shift(sh, d)) return;
+__global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, MgArr<const TF> fa, MgArr<const S> ua,
+                                                          MgArr<S> ra, MgShift sh) {
+    const int q = mg_sys(d.nz);
+    if (!take_shift(sh, d, q)) return;
     MgPt p;
-    if (!mg_point(d.nx, d.ny, p)) return;
+    if (!mg_point(d.nx, d.ny, d.nz, p)) return;
+    const TF *__restrict__ f = fa.at(q);
+    const S *__restrict__ u = ua.at(q);
+    S *__restrict__ r = ra.at(q);
     S uc[kMgKZ], au[kMgKZ];
     apply7_col(u, d, p, uc, au);
     const int64_t nxy = (int64_t)d.nx * d.ny;
@@ -227,11 +255,14 @@ __global__ void __launch_bounds__(kMgThreads) mg_residual(MgDims d, const TF *__
 // runs down kMgKZ coarse planes; each fine plane's 9-point (x, y) sum is
 // formed once and shared by the coarse planes it touches.
 template <typename S>
-__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, const S *__restrict__ r,
-                                                          S *__restrict__ fc, MgShift sh) {
-    if (sh.run && *sh.run != 0) return;
+__global__ void __launch_bounds__(kMgThreads) mg_restrict(MgDims fd, MgDims cd, MgArr<const S> ra,
+                                                          MgArr<S> fca, MgShift sh) {
+    const int qs = mg_sys(cd.nz);
+    if (sh.skip(qs)) return;
     MgPt P;
-    if (!mg_point(cd.nx, cd.ny, P)) return;
+    if (!mg_point(cd.nx, cd.ny, cd.nz, P)) return;
+    const S *__restrict__ r = ra.at(qs);
+    S *__restrict__ fc = fca.at(qs);
     using V = VT<S>;
     using R = typename MgT<S>::R;
     const int64_t fnxy = (int64_t)fd.nx * fd.ny, cnxy = (int64_t)cd.nx * cd.ny;
@@ -296,13 +327,16 @@ __device__ __forceinline__ S mg_corr(const S (&cs)[NZC][5]) {
 // loaded once.
 template <typename TF, typename S>
 __global__ void __launch_bounds__(kMgThreads) mg_prolong_smooth(MgDims d, MgDims cd, double w,
-                                                                const TF *__restrict__ f,
-                                                                const S *__restrict__ u,
-                                                                const S *__restrict__ uc,
-                                                                S *__restrict__ t, MgShift sh) {
-    if (!take_shift(sh, d)) return;
+                                                                MgArr<const TF> fa, MgArr<const S> ua,
+                                                                MgArr<const S> uca, MgArr<S> ta, MgShift sh) {
+    const int q = mg_sys(d.nz);
+    if (!take_shift(sh, d, q)) return;
     MgPt p;
-    if (!mg_point(d.nx, d.ny, p)) return;
+    if (!mg_point(d.nx, d.ny, d.nz, p)) return;
+    const TF *__restrict__ f = fa.at(q);
+    const S *__restrict__ u = ua.at(q);
+    const S *__restrict__ uc = uca.at(q);
+    S *__restrict__ t = ta.at(q);
     using V = VT<S>;
     using R = typename MgT<S>::R;
     using C = typename MgT<S>::C;
@@ -421,9 +455,12 @@ __device__ inline void mg_from_c(double2 v, double2 &o) { o = v; }
 __device__ inline void mg_from_c(double2 v, float2 &o) { o = make_float2((float)v.x, (float)v.y); }
 
 template <typename TI, typename TO>
-__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const TI *__restrict__ f,
-                                                              TO *__restrict__ u, MgShift sh) {
-    if (!take_shift(sh, d)) return;
+__global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, MgArr<const TI> fa, MgArr<TO> ua,
+                                                              MgShift sh) {
+    const int q = blockIdx.x;                  // one workgroup per system
+    if (!take_shift(sh, d, q)) return;
+    const TI *__restrict__ f = fa.at(q);
+    TO *__restrict__ u = ua.at(q);
     __shared__ double2 a[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     __shared__ double2 b[kMgCoarseMax * kMgCoarseMax * kMgCoarseMax];
     __shared__ double2 tw[3][kMgCoarseMax];
@@ -467,72 +504,87 @@ __global__ void __launch_bounds__(kMgThreads) mg_coarse_solve(MgDims d, const TI
     for (int i = threadIdx.x; i < n; i += blockDim.x) mg_from_c(a[i], u[i]);
 }
 
-// V(2,2) cycle on level l >= 1 (arrays of S): f -> u.
+// Level array of systems q0 .. q0 + count - 1 of a hierarchy.
 template <typename S>
-int vcycle_coarse(Multigrid &mg, int l, double2 kappa, MgShift sh, hipStream_t s) {
+MgArr<S> lvl(void *base, const MgLevel &L, int q0) {
+    return MgArr<S>{base ? (S *)base + (int64_t)q0 * L.n : nullptr, L.n, nullptr};
+}
+
+// V(2,2) cycle on level l >= 1 (arrays of S) of `count` systems from q0: f -> u.
+template <typename S>
+int vcycle_coarse(Multigrid &mg, int l, int q0, int count, double2 kappa, MgShift sh, hipStream_t s) {
     MgLevel &L = mg.lv[l];
     const MgDims d = dims_of(L, kappa);
-    S *f = (S *)L.f, *u = (S *)L.u, *t = (S *)L.t;
+    const MgArr<S> f = lvl<S>(L.f, L, q0), u = lvl<S>(L.u, L, q0), t = lvl<S>(L.t, L, q0), r = lvl<S>(L.r, L, q0);
+    const MgArr<const S> fc{f.base, f.stride, nullptr}, uc_{u.base, u.stride, nullptr},
+        tc{t.base, t.stride, nullptr}, rc{r.base, r.stride, nullptr};
     if (l + 1 == (int)mg.lv.size()) {
-        hipLaunchKernelGGL((mg_coarse_solve<S, S>), dim3(1), dim3(kMgThreads), 0, s, d, (const S *)f, u, sh);
+        hipLaunchKernelGGL((mg_coarse_solve<S, S>), dim3(count), dim3(kMgThreads), 0, s, d, fc, u, sh);
         OFDFT_CHECK_HIP(hipGetLastError());
         return OFDFT_OK;
     }
-    const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
+    const dim3 grid = mg_grid(L.nx, L.ny, L.nz, count), block(kMgBX, kMgBY);
     MgLevel &C = mg.lv[l + 1];
     const MgDims cd = dims_of(C, kappa);
-    hipLaunchKernelGGL((mg_pre2<S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, u, (S *)nullptr, sh);
-    hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, (const S *)f, (const S *)u, (S *)L.r, sh);
-    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
-                       (S *)C.f, sh);
+    const MgArr<S> cf = lvl<S>(C.f, C, q0);
+    const MgArr<const S> cu{(const S *)C.u + (int64_t)q0 * C.n, C.n, nullptr};
+    const MgArr<S> none{nullptr, 0, nullptr};
+    hipLaunchKernelGGL((mg_pre2<S, S>), grid, block, 0, s, d, mg.omega, fc, u, none, sh);
+    hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, fc, uc_, r, sh);
+    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz, count), block, 0, s, d, cd, rc, cf, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
-    OFDFT_TRY(vcycle_coarse<S>(mg, l + 1, kappa, sh, s));
-    hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, (const S *)f,
-                       (const S *)u, (const S *)C.u, t, sh);
-    hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, (const S *)f, (const S *)t, u, sh);
+    OFDFT_TRY(vcycle_coarse<S>(mg, l + 1, q0, count, kappa, sh, s));
+    hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, fc, uc_, cu, t, sh);
+    hipLaunchKernelGGL((mg_smooth<S, S, S>), grid, block, 0, s, d, mg.omega, fc, tc, u, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
 
-// The whole cycle z = M f: level 0 reads f and writes z in FP64 (TIO), its
-// work arrays are S.  V(2,2): both pre-sweeps in one pass into u, residual,
-// coarse correction added to u, post-sweeps u -> t -> z.  With S narrower
-// than TIO the pre-sweep pass also stores f in S (level 0's f array), which
-// the residual and the post-sweeps read instead of the FP64 input.
+// The whole cycle z = M f for `count` systems from q0 of the hierarchy: level
+// 0 reads f and writes z in FP64 (TIO), its work arrays are S.  V(2,2): both
+// pre-sweeps in one pass into u, residual, coarse correction folded into the
+// first post-sweep u -> t, second post-sweep t -> z.  With S narrower than
+// TIO the pre-sweep pass also stores f in S (level 0's f array), which the
+// residual and the post-sweeps read instead of the FP64 input.  f, z and sh
+// address system q0 first.
 template <typename TIO, typename S>
-int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipStream_t s) {
+int vcycle(Multigrid &mg, int q0, int count, MgArr<const TIO> f, MgArr<TIO> z, double2 kappa, MgShift sh,
+           hipStream_t s) {
     MgLevel &L = mg.lv[0];
     const MgDims d = dims_of(L, kappa);
     if (mg.lv.size() == 1) {
-        hipLaunchKernelGGL((mg_coarse_solve<TIO, TIO>), dim3(1), dim3(kMgThreads), 0, s, d, f, z, sh);
+        hipLaunchKernelGGL((mg_coarse_solve<TIO, TIO>), dim3(count), dim3(kMgThreads), 0, s, d, f, z, sh);
         OFDFT_CHECK_HIP(hipGetLastError());
         return OFDFT_OK;
     }
-    const dim3 grid = mg_grid(L.nx, L.ny, L.nz), block(kMgBX, kMgBY);
-    S *u = (S *)L.u, *t = (S *)L.t;
+    const dim3 grid = mg_grid(L.nx, L.ny, L.nz, count), block(kMgBX, kMgBY);
+    const MgArr<S> u = lvl<S>(L.u, L, q0), t = lvl<S>(L.t, L, q0), r = lvl<S>(L.r, L, q0);
+    const MgArr<const S> uc_{u.base, u.stride, nullptr}, tc{t.base, t.stride, nullptr},
+        rc{r.base, r.stride, nullptr};
     MgLevel &C = mg.lv[1];
     const MgDims cd = dims_of(C, kappa);
+    const MgArr<S> cf = lvl<S>(C.f, C, q0);
+    const MgArr<const S> cu{(const S *)C.u + (int64_t)q0 * C.n, C.n, nullptr};
     if constexpr (sizeof(S) < sizeof(TIO)) {
-        S *fl = (S *)L.f;
+        const MgArr<S> fl = lvl<S>(L.f, L, q0);
+        const MgArr<const S> flc{fl.base, fl.stride, nullptr};
         hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, fl, sh);
-        hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, (const S *)fl, (const S *)u, (S *)L.r, sh);
+        hipLaunchKernelGGL((mg_residual<S, S>), grid, block, 0, s, d, flc, uc_, r, sh);
     } else {
-        hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, (S *)nullptr, sh);
-        hipLaunchKernelGGL((mg_residual<TIO, S>), grid, block, 0, s, d, f, (const S *)u, (S *)L.r, sh);
+        const MgArr<S> none{nullptr, 0, nullptr};
+        hipLaunchKernelGGL((mg_pre2<TIO, S>), grid, block, 0, s, d, mg.omega, f, u, none, sh);
+        hipLaunchKernelGGL((mg_residual<TIO, S>), grid, block, 0, s, d, f, uc_, r, sh);
     }
-    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz), block, 0, s, d, cd, (const S *)L.r,
-                       (S *)C.f, sh);
+    hipLaunchKernelGGL(mg_restrict<S>, mg_grid(C.nx, C.ny, C.nz, count), block, 0, s, d, cd, rc, cf, sh);
     OFDFT_CHECK_HIP(hipGetLastError());
-    OFDFT_TRY(vcycle_coarse<S>(mg, 1, kappa, sh, s));
+    OFDFT_TRY(vcycle_coarse<S>(mg, 1, q0, count, kappa, sh, s));
     if constexpr (sizeof(S) < sizeof(TIO)) {
-        const S *fl = (const S *)L.f;
-        hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, fl, (const S *)u,
-                           (const S *)C.u, t, sh);
-        hipLaunchKernelGGL((mg_smooth<S, S, TIO>), grid, block, 0, s, d, mg.omega, fl, (const S *)t, z, sh);
+        const MgArr<const S> flc{(const S *)L.f + (int64_t)q0 * L.n, L.n, nullptr};
+        hipLaunchKernelGGL((mg_prolong_smooth<S, S>), grid, block, 0, s, d, cd, mg.omega, flc, uc_, cu, t, sh);
+        hipLaunchKernelGGL((mg_smooth<S, S, TIO>), grid, block, 0, s, d, mg.omega, flc, tc, z, sh);
     } else {
-        hipLaunchKernelGGL((mg_prolong_smooth<TIO, S>), grid, block, 0, s, d, cd, mg.omega, f, (const S *)u,
-                           (const S *)C.u, t, sh);
-        hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, (const S *)t, z, sh);
+        hipLaunchKernelGGL((mg_prolong_smooth<TIO, S>), grid, block, 0, s, d, cd, mg.omega, f, uc_, cu, t, sh);
+        hipLaunchKernelGGL((mg_smooth<TIO, S, TIO>), grid, block, 0, s, d, mg.omega, f, tc, z, sh);
     }
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
@@ -540,15 +592,20 @@ int vcycle(Multigrid &mg, const TIO *f, TIO *z, double2 kappa, MgShift sh, hipSt
 
 }  // namespace
 
-int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32) {
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32, int groups) {
     mg_free(mg);
-    if (elem_bytes != 8 && elem_bytes != 16) return OFDFT_INVALID_ARG;
+    if ((elem_bytes != 8 && elem_bytes != 16) || groups < 1) return OFDFT_INVALID_ARG;
+    if ((int64_t)mg_zch(g.nz) * groups > 65535) {     // grid z = systems x z chunks
+        set_error("multigrid: %d systems of %d planes exceed one launch", groups, g.nz);
+        return OFDFT_INVALID_ARG;
+    }
     if (g.nz > 65535) {             // one z plane per grid row of the launches
         set_error("multigrid: nz = %d exceeds 65535", g.nz);
         return OFDFT_INVALID_ARG;
     }
     mg.elem = elem_bytes;
     mg.fp32 = fp32;
+    mg.groups = groups;
     MgLevel L;
     L.nx = g.nx;
     L.ny = g.ny;
@@ -578,7 +635,7 @@ int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32) {
     const int nlev = (int)mg.lv.size();
     for (int l = 0; l < nlev; ++l) {
         MgLevel &M = mg.lv[l];
-        const size_t b = es * (size_t)M.n;
+        const size_t b = es * (size_t)M.n * (size_t)groups;
         void **own[4] = {&M.t, &M.r, &M.u, &M.f};
         // level 0 reads the caller's f (and keeps an FP32 copy of it when the
         // levels are FP32); a one-level hierarchy needs nothing
@@ -607,16 +664,34 @@ int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double ka
     if (mg.lv.empty() || mg.elem != 8) return OFDFT_INVALID_ARG;
     ProfScope ps(K_MULTIGRID, mg_cycle_bytes(mg), s);
     const double2 k = make_double2(kappa, 0.0);
-    const MgShift sh{nullptr, nullptr};
-    return mg.fp32 ? vcycle<double, float>(mg, r, z, k, sh, s) : vcycle<double, double>(mg, r, z, k, sh, s);
+    const MgShift sh{nullptr, nullptr, 0, 0};
+    const MgArr<const double> f{r, 0, nullptr};
+    const MgArr<double> o{z, 0, nullptr};
+    return mg.fp32 ? vcycle<double, float>(mg, 0, 1, f, o, k, sh, s)
+                   : vcycle<double, double>(mg, 0, 1, f, o, k, sh, s);
 }
 
-int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
+int mg_apply_shifted(Multigrid &mg, int q, const double2 *r, double2 *z, const double *kappa, const int *run,
                      hipStream_t s) {
-    if (mg.lv.empty() || mg.elem != 16 || !kappa) return OFDFT_INVALID_ARG;
+    if (mg.lv.empty() || mg.elem != 16 || !kappa || q < 0 || q >= mg.groups) return OFDFT_INVALID_ARG;
     const double2 k = make_double2(0.0, 0.0);
-    const MgShift sh{kappa, run};
-    return mg.fp32 ? vcycle<double2, float2>(mg, r, z, k, sh, s) : vcycle<double2, double2>(mg, r, z, k, sh, s);
+    const MgShift sh{kappa, run, 0, 0};
+    const MgArr<const double2> f{r, 0, nullptr};
+    const MgArr<double2> o{z, 0, nullptr};
+    return mg.fp32 ? vcycle<double2, float2>(mg, q, 1, f, o, k, sh, s)
+                   : vcycle<double2, double2>(mg, q, 1, f, o, k, sh, s);
+}
+
+int mg_apply_shifted_group(Multigrid &mg, int count, const double2 *const *r, double2 *const *z,
+                           const double *kappa, int kstride, const int *run, int rstride, hipStream_t s) {
+    if (mg.lv.empty() || mg.elem != 16 || !kappa || !r || !z || count < 1 || count > mg.groups)
+        return OFDFT_INVALID_ARG;
+    const double2 k = make_double2(0.0, 0.0);
+    const MgShift sh{kappa, run, kstride, rstride};
+    const MgArr<const double2> f{nullptr, 0, r};
+    const MgArr<double2> o{nullptr, 0, z};
+    return mg.fp32 ? vcycle<double2, float2>(mg, 0, count, f, o, k, sh, s)
+                   : vcycle<double2, double2>(mg, 0, count, f, o, k, sh, s);
 }
 
 // Algorithmic bytes of one cycle.  Fine level, FP64 levels: f is read by the

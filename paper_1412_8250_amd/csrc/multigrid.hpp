@@ -31,6 +31,7 @@ struct Multigrid {
     double omega = 0.8;          // Jacobi damping
     int elem = 8;                // input / output element bytes: 8 (FP64) or 16 (complex128)
     bool fp32 = true;            // level arrays and their arithmetic in FP32 (else FP64)
+    int groups = 1;              // systems whose level arrays the hierarchy holds (same grid)
     std::vector<void *> allocs;
 };
 
@@ -43,7 +44,10 @@ constexpr int kMgCoarseMax = 16;     // coarsest grid: at most this many points 
 // Krylov loops here tolerate without extra iterations.  Every axis is halved
 // while all are even and one exceeds kMgCoarseMax; INVALID_ARG if the
 // coarsest grid would be larger than that.
-int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32);
+// `groups` systems of this grid get level arrays of their own (system q's
+// part of a level array starts q * n elements in), so that one launch per
+// kernel can run the cycles of all of them.
+int mg_create(Multigrid &mg, const ofdft_grid &g, int elem_bytes, bool fp32, int groups = 1);
 void mg_free(Multigrid &mg);
 // z = M r for -Delta + kappa, kappa >= 0 real (device FP64 arrays of the fine
 // grid; z must not alias r).
@@ -53,8 +57,15 @@ int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double ka
 // sequence follows later changes of the shift; if `run` is given, every
 // kernel returns at once unless *run == 0 (a converged system of a batch).
 // Not accounted in the profile (the caller accounts cycles).
-int mg_apply_shifted(Multigrid &mg, const double2 *r, double2 *z, const double *kappa, const int *run,
+// System q of the hierarchy's group does the cycle.
+int mg_apply_shifted(Multigrid &mg, int q, const double2 *r, double2 *z, const double *kappa, const int *run,
                      hipStream_t s);
+// The cycles of systems 0 .. count-1 of the group in one launch per kernel:
+// system q reads r[q], writes z[q] (device tables of device pointers), its
+// shift at kappa + q kstride and its run flag at run + q rstride (run may be
+// null).  Not accounted in the profile.
+int mg_apply_shifted_group(Multigrid &mg, int count, const double2 *const *r, double2 *const *z,
+                           const double *kappa, int kstride, const int *run, int rstride, hipStream_t s);
 // Algorithmic HBM bytes of one cycle.
 double mg_cycle_bytes(const Multigrid &mg);
 
