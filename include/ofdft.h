@@ -172,9 +172,10 @@ int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, double inne
  *   keeps the bilinear form r^T z.  Requires dtype C128 and the stepped
  *   schedule (group 0 at solve time, else the solve returns INVALID_ARG);
  *   every axis of every grid must halve evenly down to at most 16 points.
- *   Allocates one complex128 vector per system and one hierarchy per distinct
- *   grid (about 1.3 fine-grid vectors).  INVALID_ARG (nothing changed) or
- *   NO_MEMORY.
+ *   Allocates one complex128 vector per system and multigrid level arrays
+ *   per system (about 1.3 fine-grid vectors); consecutive systems on one
+ *   grid (up to 64) form a group whose cycles run as one launch per kernel.
+ *   INVALID_ARG (nothing changed) or NO_MEMORY.
  * ------------------------------------------------------------------------ */
 typedef enum {
     OFDFT_PRECOND_NONE = 0,
