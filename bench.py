@@ -406,7 +406,8 @@ def main():
         t0 = time.perf_counter()
         scf2 = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3,
                        u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8, poisson_mode=ofd.MULTIGRID,
-                       helmholtz_precond=ofd.PRECOND_MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID, lr_order=2)
+                       helmholtz_precond=ofd.PRECOND_MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID, lr_order=2,
+                       line_slope_tol=LINE_SLOPE_TOL)
         torch.cuda.synchronize()
         create_s = time.perf_counter() - t0
         t0 = time.perf_counter()
