@@ -18,6 +18,7 @@ Modules:
   fd        weights, exact discrete symbol, stencil apply (C)
   poisson   right-hand side, exact spectral solve, textbook CG (C)
   helmholtz exact spectral shifted solve, textbook COCG (C)
+  multishift multi-shift COCG: one Krylov sequence for the shifts of one right-hand side
   xc        Thomas-Fermi and Perdew-Zunger LDA energy densities / potentials
   kernel    K_00 shifts/weights table and kernel-potential assembly
   anderson  Anderson mixing
