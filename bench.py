@@ -22,8 +22,10 @@ Extras: stand-alone stencil GB/s at 320^3 (f64, f32, c128); Poisson
 time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined, the
 multigrid-preconditioned and the learned forms (the network trained here
 first, on 16 small perturbed cells, about 20 s); the uneven batch of 256
-shifted systems to 1e-8; energy terms and forces of the large cell; one SCF
-step with the order-2 kernel terms.
+shifted systems to 1e-8; the four K_00 shifts of one right-hand side at
+320^3 by multi-shift COCG against the batched COCG (plain and multigrid-
+preconditioned); energy terms and forces of the large cell; one SCF step
+with the order-2 kernel terms.
 cpu_baseline: the oracle (C, OpenMP) running textbook CG iterations of the
 same 320^3 Poisson problem, counted with the same per-iteration bytes.
 """
@@ -53,7 +55,7 @@ def parse():
     ap.add_argument("--plain-density", action="store_true",
                     help="density update by Algorithm 1 as printed instead of the multigrid-preconditioned NLCG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
-    ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy", "mgc", "mg", "density"],
+    ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy", "mgc", "mg", "density", "msc"],
                     default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
                          "(for rocprofv3 counter runs) and exit")
@@ -155,6 +157,15 @@ def profile_kernel(which, shape, h, reps=5):
             ps.apply_preconditioner(r, z)
         counts = ofd.profile_read()
         ps.close()
+    elif which == "msc":       # multi-shift COCG, the four paper shifts, 8 iterations (one status poll)
+        kappas = [complex(-1.68, -1.66), complex(-1.68, 1.66), complex(0.236, -0.926), complex(0.236, 0.926)]
+        f = torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen)
+        xs = [torch.empty_like(f) for _ in kappas]
+        ms = ofd.MultiShift(shape, h, 6, max_shifts=4)
+        ofd.profile_reset()
+        ms.solve(kappas, f, xs, 1e-30, max_iter=8, seed=0, allow_not_converged=True)
+        counts = ofd.profile_read()
+        ms.close()
     elif which == "density":   # preconditioned density update, `reps` iterations
         ne = 3.0 * 4 * 16 ** 3                      # the large cell's electrons
         vol = float(np.prod([n * hh for n, hh in zip(shape, h)]))
@@ -177,7 +188,7 @@ def profile_kernel(which, shape, h, reps=5):
         bt.solve(kappas, rhs, xs, 1e-30, max_iter=reps, allow_not_converged=True)
         bt.close()
     torch.cuda.synchronize()
-    if which in ("mgc", "mg", "density"):
+    if which in ("mgc", "mg", "density", "msc"):
         # the library's own launch and byte counts of the profiled work, for
         # turning per-dispatch counters into per-launch figures
         print("profile_counts " + json.dumps({k: v for k, v in counts.items() if v["launches"]}), flush=True)
@@ -233,6 +244,70 @@ def batch_extra(dev):
             if rep:
                 secs.append(time.perf_counter() - t0)
         out[name] = {"seconds": sorted(secs)[1], "seconds_all": secs, "max_iters": max(s["iters"] for s in st),
+                     "max_rel_res": max(s["rel_res"] for s in st)}
+        bt.close()
+        del xs
+    return out
+
+
+def multishift_extra(dev, rho_np, h, kappas):
+    """The K_00 systems of the large cell for the base right-hand side
+    f = -L_h rho^beta at 320^3 (the other base, rho^alpha, is the same work):
+    the four shifts by multi-shift COCG (one Krylov sequence, one stencil per
+    iteration), by the batched plain COCG (four systems) and by the batched
+    multigrid-preconditioned COCG, to 1e-8; the median of three identical
+    solves after a first one.  Then one more multi-shift solve with HIP events
+    around each launch: the algorithmic bandwidth of its two phases."""
+    import torch
+    import paper_1412_8250_amd as ofd
+    b_pow = 5.0 / 6.0 - 5.0 ** 0.5 / 6.0
+    rho = torch.from_numpy(rho_np).to(dev)
+    src = rho ** b_pow
+    fr = torch.empty_like(src)
+    ofd.fd_laplacian_apply(src, fr, h, 6, alpha=-1.0)
+    f = fr.to(torch.complex128)
+    del rho, src, fr
+    shape = tuple(f.shape)
+    out = {"shifts": [[k.real, k.imag] for k in kappas]}
+
+    def timed(solve):
+        secs = []
+        for rep in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = solve()
+            torch.cuda.synchronize()
+            if rep:
+                secs.append(time.perf_counter() - t0)
+        return sorted(secs)[1], secs, res
+
+    ms = ofd.MultiShift(shape, h, 6, max_shifts=len(kappas))
+    xs = [torch.empty_like(f) for _ in kappas]
+    sec, secs, (_, st, seed) = timed(lambda: ms.solve(kappas, f, xs, 1e-8))
+    out["multishift_c128"] = {"seconds": sec, "seconds_all": secs, "seed": seed,
+                              "iters": [s["iters"] for s in st], "max_rel_res": max(s["rel_res"] for s in st)}
+    ofd.profile_reset(timed=("ms_stencil", "ms_update"))
+    ms.solve(kappas, f, xs, 1e-8)
+    prof = ofd.profile_read()
+    ofd.profile_reset(timed=())
+    for c in ("ms_stencil", "ms_update"):
+        p = prof[c]
+        out[f"{c}_GBps"] = p["bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else None
+        out[f"{c}_launches"] = p["launches"]
+        out[f"{c}_ms"] = p["ms"]
+    ms.close()
+    del xs
+    for name, pre in (("batched_c128", ofd.PRECOND_NONE), ("batched_c128_multigrid", ofd.PRECOND_MULTIGRID)):
+        bt = ofd.HelmholtzBatch([shape] * len(kappas), [h] * len(kappas), 6, ofd.C128)
+        bt.set_preconditioner(pre)
+        xs = [torch.zeros_like(f) for _ in kappas]
+
+        def solve():
+            for x in xs:
+                x.zero_()
+            return bt.solve(kappas, [f] * len(kappas), xs, 1e-8)
+        sec, secs, (_, st) = timed(solve)
+        out[name] = {"seconds": sec, "seconds_all": secs, "iters": [s["iters"] for s in st],
                      "max_rel_res": max(s["rel_res"] for s in st)}
         bt.close()
         del xs
@@ -401,6 +476,8 @@ def main():
         # the uneven batch: 32 cells (24^3 .. 96^3) x 8 shifts = 256 systems,
         # right-hand sides -L_h rho^alpha, -L_h rho^beta built with the library
         extras["batched_256_systems"] = batch_extra(dev)
+        # the K_00 shifts of one right-hand side at 320^3: multi-shift against batched COCG
+        extras["multishift_320_4_shifts"] = multishift_extra(dev, w.rho, h, scf.kernel_shifts()[0])
         # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)
         # on the same cell: one step from the initial state
         t0 = time.perf_counter()

@@ -198,6 +198,43 @@ int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa,
                                      void *stream);
 
 /* ------------------------------------------------------------------------
+ * Multi-shift COCG: the shifted systems (-L_h + kappa_r) u_r = f, r = 0 ..
+ * nshift-1, of ONE right-hand side (the kernel convolutions of Section 3.1
+ * and the order-2 terms of Section 2 apply several shifts to the same f).
+ * The Krylov space does not depend on the shift, so one COCG sequence of a
+ * seed system serves every shift (shifted COCG: r_k^(r) = r_k / pi_k^(r) with
+ * a scalar recurrence for pi), one stencil application per iteration.  All
+ * iterates start at zero; a shift is frozen once |r_k| / |pi_k^(r)| <=
+ * rel_tol |f|.  No preconditioner (a shift-dependent preconditioner breaks the
+ * shared Krylov space: use ofdft_batch_set_preconditioner for that).
+ * ofdft_multishift_create: one grid, radius 1..6, up to max_shifts (1..16)
+ *   shifts per solve.  Allocates 4 + (max_shifts - 1) complex128 vectors of
+ *   the grid.  INVALID_ARG or NO_MEMORY.
+ * cocg_multishift_solve:
+ *   kappa    host array of 2*nshift doubles (re, im); each kappa_r != 0
+ *   seed     index of the seed system, or -1: the shift expected to converge
+ *            slowest (Re kappa < 0, putting -kappa inside the spectrum of
+ *            -L_h, with the smallest |Im kappa|; else the smallest |kappa|)
+ *   rhs      device complex128 array f of the grid (not modified)
+ *   x        host array of nshift distinct device complex128 arrays of the
+ *            grid, none equal to rhs: the solutions on exit (overwritten,
+ *            no initial guess)
+ *   stats    optional host array of nshift records: iters = steps after
+ *            which the shift froze, outer_iters = seed steps taken, rel_res =
+ *            true relative residual recomputed in complex128, status, seconds
+ *   seed_used optional: the seed index used
+ * Returns OK, NOT_CONVERGED (a shift missed max_iter or its true residual is
+ * above 2 rel_tol), BREAKDOWN, NONFINITE, INVALID_ARG, HIP_ERROR.
+ * Synchronises the stream.
+ * ------------------------------------------------------------------------ */
+typedef struct ofdft_multishift ofdft_multishift;
+int ofdft_multishift_create(const ofdft_grid *grid, int radius, int max_shifts, ofdft_multishift **out);
+int ofdft_multishift_destroy(ofdft_multishift *m);
+int cocg_multishift_solve(ofdft_multishift *m, int nshift, const double *kappa, int seed, const void *rhs,
+                          void *const *x, double rel_tol, int max_iter, ofdft_solve_stats *stats,
+                          int *seed_used, void *stream);
+
+/* ------------------------------------------------------------------------
  * Anderson mixing (Appendix D):
  *   v_{k+1} = v_k + zeta f_k - (S_k + zeta Y_k)(Y_k^T Y_k)^{-1} Y_k^T f_k,
  * S_k, Y_k the last m differences of iterates and of residuals f = vhat - v.
@@ -293,6 +330,12 @@ int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
 /* Forget the Anderson history and the line-search step memory, so that the
  * next step behaves like the first step from the current state. */
 int ofdft_scf_reset_history(ofdft_scf *s);
+/* The four K_00 shifts kappa_r = (2 kF)^2 Q_r (host, 8 doubles re, im) and the
+ * factors P_r (8 doubles, may be NULL) of the Appendix A table for the
+ * context's cell, kF = (3 pi^2 N_e / |Omega|)^(1/3) (Section 3.1): the
+ * shifted systems (-L_h + kappa_r) V_r = P_r (-L_h rho^p) the kernel term
+ * solves.  INVALID_ARG for NULL. */
+int ofdft_scf_kernel_shifts(ofdft_scf *s, double *kappa8, double *factor8);
 /* Statistics of the last step: [0] U iterations, [1] Poisson iterations,
  * [2] total shifted-solve iterations (of the 4 systems solved: r = 1, 3 for
  * both powers; r = 2, 4 are their complex conjugates, Appendix A), [3] U
@@ -411,7 +454,8 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   7 Anderson, 8 other vector passes, 9 network kernels, 10 COCG vector
  *   phase (stepped schedule), 11 multigrid cycles on FP64 vectors (Poisson,
  *   density update), 12 multigrid cycles on complex128 vectors (shifted
- *   systems).
+ *   systems), 13 multi-shift COCG stencil phase, 14 multi-shift COCG vector
+ *   phase.
  * ofdft_profile_read: launches, algorithmic bytes (each operand read once and
  *   each result written once), timed launches and their summed milliseconds
  *   for one class since the last reset (synchronises on pending events).

@@ -89,6 +89,7 @@ def _declare(l):
         "ofdft_scf_get": (_I, [_V, _I, _V, _V]),
         "ofdft_scf_set": (_I, [_V, _I, _V, _V]),
         "ofdft_scf_stats": (_I, [_V, ctypes.POINTER(_D)]),
+        "ofdft_scf_kernel_shifts": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
         "ofdft_scf_reset_history": (_I, [_V]),
         "ofdft_density_update": (_I, [_V, _V, _V, ctypes.POINTER(_I), ctypes.POINTER(_D),
                                       ctypes.POINTER(_D), _V]),
@@ -98,6 +99,10 @@ def _declare(l):
         "ofdft_scf_energy": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
         "ofdft_scf_forces": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
         "ofdft_batch_apply_preconditioner": (_I, [_V, _I, ctypes.POINTER(_D), _V, _V, _V]),
+        "ofdft_multishift_create": (_I, [ctypes.POINTER(Grid), _I, _I, ctypes.POINTER(_V)]),
+        "ofdft_multishift_destroy": (_I, [_V]),
+        "cocg_multishift_solve": (_I, [_V, _I, ctypes.POINTER(_D), _I, _V, ctypes.POINTER(_V), _D, _I,
+                                       _SP, ctypes.POINTER(_I), _V]),
         "ofdft_nn_create": (_I, [ctypes.c_uint64, ctypes.POINTER(_V)]),
         "ofdft_nn_destroy": (_I, [_V]),
         "ofdft_nn_param_count": (ctypes.c_size_t, []),
@@ -193,7 +198,7 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
 
 KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
                   "anderson", "pointwise", "nn", "cocg_update",
-                  "multigrid", "multigrid_c")
+                  "multigrid", "multigrid_c", "ms_stencil", "ms_update")
 
 
 def profile_reset(timed=()):
@@ -338,6 +343,54 @@ class HelmholtzBatch:
             pass
 
 
+class MultiShift:
+    """Multi-shift COCG: (-L_h + kappa_r) u_r = f for several shifts of one f,
+    one Krylov sequence (one stencil per iteration) for all of them."""
+
+    def __init__(self, shape_zyx, h_xyz, radius: int = 6, max_shifts: int = 4):
+        self.shape = tuple(shape_zyx)
+        self.max_shifts = int(max_shifts)
+        self._grid = grid_of(self.shape, h_xyz)
+        self._h = ctypes.c_void_p()
+        _check(lib().ofdft_multishift_create(ctypes.byref(self._grid), int(radius), self.max_shifts,
+                                             ctypes.byref(self._h)))
+
+    def solve(self, kappas, rhs, xs, rel_tol: float = 1e-8, max_iter: int = 100000, seed: int = -1,
+              stream=None, allow_not_converged: bool = False):
+        """kappas: sequence of complex; rhs and xs: complex128 CUDA tensors of the grid
+        (xs overwritten with the solutions).  Returns (status, stats per shift, seed used)."""
+        S = len(kappas)
+        if len(xs) != S:
+            raise ValueError("one solution array per shift")
+        for t in [rhs, *xs]:
+            if str(t.dtype) != "torch.complex128":
+                raise TypeError("multi-shift COCG takes complex128 arrays")
+            _dev(t, self.shape)
+        k = (ctypes.c_double * (2 * S))()
+        for j, kj in enumerate(kappas):
+            k[2 * j], k[2 * j + 1] = float(complex(kj).real), float(complex(kj).imag)
+        xp = (ctypes.c_void_p * S)(*[t.data_ptr() for t in xs])
+        st = (SolveStats * S)()
+        used = ctypes.c_int(-1)
+        status = lib().cocg_multishift_solve(self._h, S, k, int(seed), _dev(rhs, self.shape), xp,
+                                             float(rel_tol), int(max_iter), st, ctypes.byref(used),
+                                             _stream(stream))
+        ok = (OK, NOT_CONVERGED) if allow_not_converged else (OK,)
+        _check(status, ok)
+        return status, [s.as_dict() for s in st], used.value
+
+    def close(self):
+        if self._h:
+            lib().ofdft_multishift_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Anderson:
     """Anderson mixing state (history m, parameter zeta) for vectors of n values."""
 
@@ -428,6 +481,13 @@ class SCF:
         for which, t in snap.items():
             self.set(which, t)
         self.reset_history()
+
+    def kernel_shifts(self):
+        """The four K_00 shifts kappa_r and factors P_r of this cell (lists of complex)."""
+        k, f = (ctypes.c_double * 8)(), (ctypes.c_double * 8)()
+        _check(lib().ofdft_scf_kernel_shifts(self._h, k, f))
+        return ([complex(k[2 * r], k[2 * r + 1]) for r in range(4)],
+                [complex(f[2 * r], f[2 * r + 1]) for r in range(4)])
 
     def stats(self) -> dict:
         out = (ctypes.c_double * 7)()

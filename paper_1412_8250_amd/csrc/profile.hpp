@@ -24,6 +24,8 @@ enum KClass {
     K_COCG_UPDATE,     // batched COCG (stepped): x, r update + r.r
     K_MULTIGRID,       // multigrid cycles on FP64 vectors (Poisson, density update)
     K_MULTIGRID_C,     // multigrid cycles on complex128 vectors (shifted systems)
+    K_MS_STENCIL,      // multi-shift COCG: seed direction + stencil + p.q
+    K_MS_UPDATE,       // multi-shift COCG: every shift's p, x update; r update + r.r
     K_CLASSES
 };
 

@@ -645,6 +645,25 @@ extern "C" int ofdft_scf_reset_history(ofdft_scf *s) {
     return ofdft_anderson_reset(s->mix);
 }
 
+extern "C" int ofdft_scf_kernel_shifts(ofdft_scf *s, double *kappa8, double *factor8) {
+    if (!s || !kappa8) {
+        set_error("ofdft_scf_kernel_shifts: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    const double volume = (double)s->n * s->dv;
+    const double kf = std::cbrt(3.0 * kPi * kPi * s->p.n_electrons / volume);
+    const double k2 = 4.0 * kf * kf;
+    for (int r = 0; r < 4; ++r) {
+        kappa8[2 * r] = k2 * kQ00[r][0];
+        kappa8[2 * r + 1] = k2 * kQ00[r][1];
+        if (factor8) {
+            factor8[2 * r] = kP00[r][0];
+            factor8[2 * r + 1] = kP00[r][1];
+        }
+    }
+    return OFDFT_OK;
+}
+
 extern "C" int ofdft_scf_stats(ofdft_scf *s, double *out7) {
     if (!s || !out7) return OFDFT_INVALID_ARG;
     for (int k = 0; k < 7; ++k) out7[k] = s->last[k];
