@@ -52,6 +52,9 @@ def parse():
                     help="SCF Poisson solve by plain FP64 CG instead of multigrid-preconditioned CG")
     ap.add_argument("--plain-helmholtz", action="store_true",
                     help="shifted solves by plain COCG instead of multigrid-preconditioned COCG")
+    ap.add_argument("--multishift-helmholtz", action="store_true",
+                    help="kernel solves by one multi-shift COCG solve per power (from zero) instead of "
+                         "the batched multigrid-preconditioned COCG")
     ap.add_argument("--plain-density", action="store_true",
                     help="density update by Algorithm 1 as printed instead of the multigrid-preconditioned NLCG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
@@ -343,7 +346,9 @@ def main():
     scf = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3,
                   u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8,
                   poisson_mode=ofd.PLAIN_F64 if args.plain_poisson else ofd.MULTIGRID,
-                  helmholtz_precond=ofd.PRECOND_NONE if args.plain_helmholtz else ofd.PRECOND_MULTIGRID,
+                  helmholtz_precond=(ofd.PRECOND_NONE if args.plain_helmholtz or args.multishift_helmholtz
+                                     else ofd.PRECOND_MULTIGRID),
+                  helmholtz_multishift=args.multishift_helmholtz,
                   u_precond=ofd.PRECOND_NONE if args.plain_density else ofd.PRECOND_MULTIGRID,
                   line_slope_tol=LINE_SLOPE_TOL)
     torch.cuda.synchronize()
@@ -512,7 +517,8 @@ def main():
                                "120 bohr, 320^3 grid, 12th-order FD, TFW + K_00 kernel, "
                                "Poisson + 8 shifted solves to 1e-8, Anderson m=7; "
                                + ("plain" if args.plain_poisson else "multigrid-preconditioned") + " CG, "
-                               + ("plain" if args.plain_helmholtz else "multigrid-preconditioned") + " COCG, "
+                               + ("multi-shift" if args.multishift_helmholtz
+                                  else "plain" if args.plain_helmholtz else "multigrid-preconditioned") + " COCG, "
                                + ("plain" if args.plain_density else "multigrid-preconditioned") + " NLCG"
                    if args.workload == "large"
                    else "small cell SCF step: 4-atom FCC cell, 16^3 grid",

@@ -51,7 +51,8 @@ class ScfParams(ctypes.Structure):
                 ("poisson_mode", ctypes.c_int), ("helmholtz_tol", ctypes.c_double),
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
                 ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int),
-                ("u_precond_sigma", ctypes.c_double), ("line_slope_tol", ctypes.c_double)]
+                ("u_precond_sigma", ctypes.c_double), ("line_slope_tol", ctypes.c_double),
+                ("helmholtz_multishift", ctypes.c_int)]
 
 
 class GaussAtoms(ctypes.Structure):
@@ -429,7 +430,7 @@ class SCF:
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
                  u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0,
-                 line_slope_tol: float = 0.0, stream=None):
+                 line_slope_tol: float = 0.0, helmholtz_multishift: bool = False, stream=None):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -443,6 +444,7 @@ class SCF:
         p.lr_order = int(lr_order)
         p.u_precond_sigma = float(u_precond_sigma)
         p.line_slope_tol = float(line_slope_tol)
+        p.helmholtz_multishift = int(bool(helmholtz_multishift))
         self.params = p
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

@@ -76,6 +76,40 @@ struct ShiftRhsOp {     // F_j = P_r f_beta (j = 0, 2), P_r f_alpha (j = 4, 6), 
     }
 };
 
+struct BaseRhsOp {      // complex128 copies of the base right-hand sides f_beta, f_alpha
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 48;
+    const double *fa, *fb;
+    double2 *Fb, *Fa;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        Fb[i] = make_double2(fb[i], 0.0);
+        Fa[i] = make_double2(fa[i], 0.0);
+    }
+};
+
+struct ScaleConjOp {    // V_j = P_r U_j in place (r = j % 4), V_{j+1} = conj(V_j), j = 0, 2, 4, 6
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 192;
+    double2 *V0, *V2, *V4, *V6;
+    double2 *V1, *V3, *V5, *V7;
+    double2 P0, P2;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double2 a = cmul(P0, V0[i]), b = cmul(P2, V2[i]), c = cmul(P0, V4[i]), d = cmul(P2, V6[i]);
+        V0[i] = a;
+        V2[i] = b;
+        V4[i] = c;
+        V6[i] = d;
+        V1[i] = make_double2(a.x, -a.y);
+        V3[i] = make_double2(b.x, -b.y);
+        V5[i] = make_double2(c.x, -c.y);
+        V7[i] = make_double2(d.x, -d.y);
+    }
+};
+
 struct ConjOp {         // V_{j+1} = conj(V_j), j = 0, 2, 4, 6
     static constexpr int kClass = K_POINTWISE;
     static constexpr int kBytes = 128;
@@ -353,6 +387,7 @@ int salloc(ofdft_scf *s, P_ **p, size_t bytes) {
 void scf_free(ofdft_scf *s) {
     if (s->pois) ofdft_poisson_destroy(s->pois);
     if (s->batch) ofdft_batch_destroy(s->batch);
+    if (s->ms) ofdft_multishift_destroy(s->ms);
     if (s->mix) ofdft_anderson_destroy(s->mix);
     if (s->umg) {
         mg_free(*s->umg);
@@ -379,7 +414,35 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
     helm_it = 0;
     helm_res = 0.0;
     if (s->p.mu && s->p.lr_order == 2) return lr2_potential(s, st, helm_it, helm_res);
-    if (s->p.mu) {
+    if (s->p.mu && s->ms) {
+        // The systems of one power share the right-hand side up to P_r: one
+        // multi-shift solve of (-L_h + kappa_r) U_r = f per power for r = 1, 3
+        // (from zero), then V_r = P_r U_r and the conjugate partners.
+        OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
+        OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
+        OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
+        OFDFT_TRY((launch_reduce<1>(n, BaseRhsOp{s->f_a, s->f_b, (double2 *)s->Fr[0], (double2 *)s->Fr[4]},
+                                    NoFin{}, s->rb, st)));
+        const double kap[4] = {s->kappa[0], s->kappa[1], s->kappa[4], s->kappa[5]};
+        for (int q = 0; q < 2; ++q) {          // q = 0: f_beta (V_0, V_2), q = 1: f_alpha (V_4, V_6)
+            void *xs[2] = {s->Vr[4 * q], s->Vr[4 * q + 2]};
+            ofdft_solve_stats hs[2];
+            const int hst = cocg_multishift_solve(s->ms, 2, kap, -1, s->Fr[4 * q], xs, s->p.helmholtz_tol,
+                                                  s->p.max_iter, hs, nullptr, st);
+            if (hst < 0) return hst;
+            for (int k = 0; k < 2; ++k) {
+                helm_it += hs[k].iters;
+                helm_res = std::max(helm_res, hs[k].rel_res);
+            }
+        }
+        ScaleConjOp sc{(double2 *)s->Vr[0], (double2 *)s->Vr[2], (double2 *)s->Vr[4], (double2 *)s->Vr[6],
+                       (double2 *)s->Vr[1], (double2 *)s->Vr[3], (double2 *)s->Vr[5], (double2 *)s->Vr[7],
+                       make_double2(kP00[0][0], kP00[0][1]), make_double2(kP00[2][0], kP00[2][1])};
+        OFDFT_TRY((launch_reduce<1>(n, sc, NoFin{}, s->rb, st)));
+        const double rho_bar = s->p.n_electrons / ((double)n * s->dv);
+        VlrOp vo{s->u, s->Vr[0], s->Vr[2], s->Vr[4], s->Vr[6], s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
+        OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+    } else if (s->p.mu) {
         OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
@@ -432,7 +495,10 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     OFDFT_TRY(check_grid(&p->grid, p->radius));
     if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
         !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
-        (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0)) {
+        (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0) ||
+        (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1) ||
+        (p->helmholtz_multishift && (p->lr_order == 2 || p->helmholtz_dtype == OFDFT_C64 ||
+                                     p->helmholtz_precond != OFDFT_PRECOND_NONE))) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }
@@ -520,12 +586,16 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         }
         ofdft_grid grids[4];
         for (int q = 0; q < 4; ++q) grids[q] = p->grid;
-        if ((rc = ofdft_batch_create(4, grids, p->radius,
-                                     p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
-            return fail(rc);
-        if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
-            (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
-            return fail(rc);
+        if (p->helmholtz_multishift) {
+            if ((rc = ofdft_multishift_create(&p->grid, p->radius, 2, &s->ms))) return fail(rc);
+        } else {
+            if ((rc = ofdft_batch_create(4, grids, p->radius,
+                                         p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
+                return fail(rc);
+            if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
+                (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
+                return fail(rc);
+        }
         for (int j = 0; j < 8; ++j)
             if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     }

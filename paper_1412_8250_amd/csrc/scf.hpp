@@ -5,6 +5,7 @@
 #include "poisson.hpp"
 
 struct ofdft_batch;
+struct ofdft_multishift;
 struct ofdft_anderson;
 
 namespace ofdft {
@@ -59,6 +60,7 @@ struct ofdft_scf {
     // solver contexts
     ofdft_poisson *pois = nullptr;
     ofdft_batch *batch = nullptr;
+    ofdft_multishift *ms = nullptr;   // multi-shift solver of the K_00 term (helmholtz_multishift)
     ofdft_anderson *mix = nullptr;
     ofdft::RedBuf rb{};
     double *dsc = nullptr, *hsc = nullptr;   // device / pinned host scalars
