@@ -209,7 +209,9 @@ int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa,
  * shared Krylov space: use ofdft_batch_set_preconditioner for that).
  * ofdft_multishift_create: one grid, radius 1..6, up to max_shifts (1..16)
  *   shifts per solve.  Allocates 4 + (max_shifts - 1) complex128 vectors of
- *   the grid.  INVALID_ARG or NO_MEMORY.
+ *   the grid and the solve's device scalars, so a context serves one solve
+ *   at a time (solves on one context must not overlap on different streams).
+ *   INVALID_ARG or NO_MEMORY.
  * cocg_multishift_solve:
  *   kappa    host array of 2*nshift doubles (re, im); each kappa_r != 0
  *   seed     index of the seed system, or -1: the shift expected to converge
