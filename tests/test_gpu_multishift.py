@@ -151,3 +151,43 @@ def test_scf_kernel_shifts_match_oracle_table():
     for r in range(4):
         assert abs(ks[r] - ref[r]) <= 1e-12 * abs(ref[r])
         assert ps[r] == kernel.P00[r]
+
+
+@pytest.mark.parametrize("shape,h,nshift", [((3, 5, 7), (0.5, 0.45, 0.4), 3),      # smaller than the stencil reach
+                                            ((9, 12, 66), (0.42, 0.4, 0.37), 16)])  # the maximum shift count
+def test_edge_grids_and_maximum_shifts(shape, h, nshift):
+    """Every axis shorter than the radius-6 reach (periodic images wrap several
+    times), and 16 shifts at once: 9 steps element by element against the oracle."""
+    announce("multishift edge", shape, nshift)
+    rng = np.random.default_rng(34)
+    f = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    mags = np.exp(rng.uniform(np.log(0.2), np.log(6.0), nshift))
+    args = rng.uniform(-0.9 * np.pi, 0.9 * np.pi, nshift)
+    kaps = [complex(m * np.exp(1j * a)) for m, a in zip(mags, args)]
+    status, xs, st, used = _run(shape, h, kaps, f, 1e-300, 9, seed=-1, allow=True)
+    ref, _, _ = multishift.solve(f, kaps, h, seed=used, tol=0.0, maxit=9)
+    for j, (x, r) in enumerate(zip(xs, ref)):
+        assert np.abs(x - r).max() <= 1e-10 * np.abs(r).max(), j
+
+
+def test_context_reuse_with_fewer_shifts():
+    """Two solves in a row on one context (the second with fewer shifts and a
+    different right-hand side) give the same results as fresh contexts."""
+    torch = torch_cuda()
+    shape, h = GRIDS[0]
+    announce("multishift reuse")
+    rng = np.random.default_rng(35)
+    f1 = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    f2 = rng.normal(size=shape) + 0j
+    kaps = _shifts()
+    ms = ofd.MultiShift(shape, h, 6, max_shifts=5)
+    xs = [torch.empty(shape, dtype=torch.complex128, device="cuda") for _ in kaps]
+    ms.solve(kaps, to_dev(f1), xs, 1e-9)
+    ys = xs[:2]
+    _, st, _ = ms.solve(kaps[2:4], to_dev(f2), ys, 1e-9)
+    got = [to_host(y) for y in ys]
+    ms.close()
+    _, fresh, st2, _ = _run(shape, h, kaps[2:4], f2, 1e-9)
+    for a, b, s1, s2 in zip(got, fresh, st, st2):
+        assert s1["iters"] == s2["iters"]
+        assert np.array_equal(a, b)
