@@ -307,11 +307,16 @@ typedef struct {
     double line_slope_tol;     /* line search: a step is accepted once |dE/ds| is at most
                                   this fraction of its value at s = 0 (or the bracket is
                                   below line_tol); 0 = 1e-6 (an exact line search)      */
-    int helmholtz_multishift;  /* K_00 term (lr_order 0): 1 = one multi-shift COCG solve per
-                                  power rho^alpha, rho^beta for the shifts r = 1, 3 (see
-                                  cocg_multishift_solve; from zero, complex128, needs
-                                  helmholtz_precond NONE), V_r = P_r U_r; 0 = the batched
-                                  solver (warm-started from the previous solutions)       */
+    int helmholtz_multishift;  /* 1 = the kernel solves without a warm start (the
+                                  context's first kernel potential) by multi-shift COCG
+                                  (see cocg_multishift_solve; from zero, complex128): the
+                                  systems sharing a right-hand side g (-L_h rho^a for
+                                  K_00; rho^a, the same power in several kernels, for the
+                                  order-2 terms) in one solve, up to 16 shifts, then
+                                  V = c_r U with the system's factor; later kernel
+                                  potentials by the batched solver (helmholtz_precond,
+                                  helmholtz_dtype) warm-started from the previous
+                                  solutions.  0 = the batched solver throughout.         */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;

@@ -240,6 +240,39 @@ struct LrRhsOp {
     }
 };
 
+struct LrBaseOp {        // F = g (complex128), the shared right-hand side of one group
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *u, *fa, *fb;
+    double2 *F;
+    double a;
+    int lap;                    // 0: rho^a; 1: fa (-L_h rho^alpha); 2: fb (-L_h rho^beta)
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        double g;
+        if (lap == 1) {
+            g = fa[i];
+        } else if (lap == 2) {
+            g = fb[i];
+        } else {
+            const double rho = u[i] * u[i];
+            g = rho > 0.0 ? exp(a * log(rho)) : 0.0;
+        }
+        F[i] = make_double2(g, 0.0);
+    }
+};
+
+struct LrScaleOp {       // V *= c (the factor (2 kF)^2 P_r of the system's right-hand side)
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 32;
+    double2 *V;
+    double2 c;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { V[i] = cmul(c, V[i]); }
+};
+
 // W_c = 2 Re(V_{2c} + V_{2c+1}) for the convolutions of one round
 struct LrSumOp {
     static constexpr int kClass = K_POINTWISE;
@@ -285,7 +318,51 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
     const double kf = std::cbrt(3.0 * kPi * kPi * s->p.n_electrons / volume);
     const double k2 = 4.0 * kf * kf;
     const int nsys = 2 * (int)s->lr_conv.size();
+    const bool ms = s->ms && !s->kernel_warm;
+    if (ms) {
+        // no warm start: one multi-shift solve of (-L_h + kappa_r) U = g per group
+        // of systems sharing g (from zero), then V = c_r U with the system's factor
+        // c_r = P_r (K_00, g = -L_h rho^a) or (2 kF)^2 P_r (g = rho^a)
+        for (const std::vector<int> &grp : s->lr_groups) {
+            const int cnt = (int)grp.size();
+            const LrConv &c0 = s->lr_conv[grp[0] / 2];
+            const bool k00 = c0.m == 0 && c0.n == 0;
+            const int lap = !k00 ? 0 : (std::fabs(c0.a - kAlpha) < 1e-12 ? 1 : 2);
+            OFDFT_TRY((launch_reduce<1>(n, LrBaseOp{s->u, s->f_a, s->f_b, s->lr_F[0], c0.a, lap}, NoFin{}, s->rb,
+                                        st)));
+            void *xs[kMsGroupMax];
+            double kap[2 * kMsGroupMax];
+            for (int k = 0; k < cnt; ++k) {
+                const LrConv &c = s->lr_conv[grp[k] / 2];
+                const int r = grp[k] % 2;
+                xs[k] = s->lr_V[grp[k]];
+                kap[2 * k] = k2 * c.Q[r].x;
+                kap[2 * k + 1] = k2 * c.Q[r].y;
+            }
+            ofdft_solve_stats hs[kMsGroupMax];
+            const int hst = cocg_multishift_solve(s->ms, cnt, kap, -1, s->lr_F[0], xs, s->p.helmholtz_tol,
+                                                  s->p.max_iter, hs, nullptr, st);
+            if (hst < 0) return hst;
+            const double sc = k00 ? 1.0 : k2;
+            for (int k = 0; k < cnt; ++k) {
+                helm_it += hs[k].iters;
+                helm_res = std::max(helm_res, hs[k].rel_res);
+                const LrConv &c = s->lr_conv[grp[k] / 2];
+                const int r = grp[k] % 2;
+                LrScaleOp so{s->lr_V[grp[k]], make_double2(sc * c.P[r].x, sc * c.P[r].y)};
+                OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+            }
+        }
+    }
     for (int j0 = 0; j0 < nsys; j0 += kLrRound) {
+        if (ms) {               // solved above: only the round's sums
+            LrSumOp so{};
+            so.count = kLrRound / 2;
+            for (int k = 0; k < kLrRound; ++k) so.V[k] = s->lr_V[j0 + k];
+            for (int c = 0; c < kLrRound / 2; ++c) so.W[c] = s->lr_W[j0 / 2 + c];
+            OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+            continue;
+        }
         const int cnt = std::min(kLrRound, nsys - j0);
         LrRhsOp ro{};
         ro.u = s->u;
@@ -341,6 +418,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
     }
     vo.floor_rho = 1e-12 * s->p.n_electrons / volume;
     OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+    s->kernel_warm = true;
     return OFDFT_OK;
 }
 
@@ -414,10 +492,10 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
     helm_it = 0;
     helm_res = 0.0;
     if (s->p.mu && s->p.lr_order == 2) return lr2_potential(s, st, helm_it, helm_res);
-    if (s->p.mu && s->ms) {
-        // The systems of one power share the right-hand side up to P_r: one
-        // multi-shift solve of (-L_h + kappa_r) U_r = f per power for r = 1, 3
-        // (from zero), then V_r = P_r U_r and the conjugate partners.
+    if (s->p.mu && s->ms && !s->kernel_warm) {
+        // No warm start yet: the systems of one power share the right-hand side
+        // up to P_r, so one multi-shift solve of (-L_h + kappa_r) U_r = f per
+        // power for r = 1, 3 (from zero), then V_r = P_r U_r and the conjugates.
         OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_b, s->f_b, -1.0, 0.0, st));
@@ -442,6 +520,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
         const double rho_bar = s->p.n_electrons / ((double)n * s->dv);
         VlrOp vo{s->u, s->Vr[0], s->Vr[2], s->Vr[4], s->Vr[6], s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
         OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+        s->kernel_warm = true;
     } else if (s->p.mu) {
         OFDFT_TRY((launch_reduce<1>(n, PowersOp{s->u, s->rho_a, s->rho_b, kAlpha, kBeta}, NoFin{}, s->rb, st)));
         OFDFT_TRY(fd_laplacian_apply(&s->g, s->p.radius, OFDFT_F64, s->rho_a, s->f_a, -1.0, 0.0, st));
@@ -476,6 +555,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
         const double rho_bar = s->p.n_electrons / ((double)n * s->dv);
         VlrOp vo{s->u, s->Vr[0], s->Vr[2], s->Vr[4], s->Vr[6], s->vlr, 1e-12 * rho_bar, kAlpha, kBeta};
         OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
+        s->kernel_warm = true;
     }
     return OFDFT_OK;
 }
@@ -496,9 +576,7 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
         !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
         (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0) ||
-        (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1) ||
-        (p->helmholtz_multishift && (p->lr_order == 2 || p->helmholtz_dtype == OFDFT_C64 ||
-                                     p->helmholtz_precond != OFDFT_PRECOND_NONE))) {
+        (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1)) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }
@@ -564,6 +642,27 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
             if ((rc = salloc(s, &q, 2 * b8))) return fail(rc);
         ofdft_grid grids[kLrRound];
         for (int q = 0; q < kLrRound; ++q) grids[q] = p->grid;
+        if (p->helmholtz_multishift) {
+            // group the systems by their shared right-hand side: rho^a (the same
+            // power in several kernels) or -L_h rho^a (K_00), up to kMsGroupMax
+            std::vector<std::pair<double, bool>> keys;
+            int gmax = 0;
+            for (int j = 0; j < 2 * (int)s->lr_conv.size(); ++j) {
+                const LrConv &c = s->lr_conv[j / 2];
+                const bool k00 = c.m == 0 && c.n == 0;
+                size_t g = 0;
+                while (g < keys.size() && !(std::fabs(keys[g].first - c.a) < 1e-12 && keys[g].second == k00 &&
+                                            (int)s->lr_groups[g].size() < kMsGroupMax))
+                    ++g;
+                if (g == keys.size()) {
+                    keys.emplace_back(c.a, k00);
+                    s->lr_groups.emplace_back();
+                }
+                s->lr_groups[g].push_back(j);
+                gmax = std::max(gmax, (int)s->lr_groups[g].size());
+            }
+            if ((rc = ofdft_multishift_create(&p->grid, p->radius, gmax, &s->ms))) return fail(rc);
+        }
         if ((rc = ofdft_batch_create(kLrRound, grids, p->radius,
                                      p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
             return fail(rc);
@@ -586,16 +685,14 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         }
         ofdft_grid grids[4];
         for (int q = 0; q < 4; ++q) grids[q] = p->grid;
-        if (p->helmholtz_multishift) {
-            if ((rc = ofdft_multishift_create(&p->grid, p->radius, 2, &s->ms))) return fail(rc);
-        } else {
-            if ((rc = ofdft_batch_create(4, grids, p->radius,
-                                         p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
-                return fail(rc);
-            if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
-                (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
-                return fail(rc);
-        }
+        if (p->helmholtz_multishift && (rc = ofdft_multishift_create(&p->grid, p->radius, 2, &s->ms)))
+            return fail(rc);
+        if ((rc = ofdft_batch_create(4, grids, p->radius,
+                                     p->helmholtz_dtype == OFDFT_C64 ? OFDFT_C64 : OFDFT_C128, &s->batch)))
+            return fail(rc);
+        if (p->helmholtz_precond != OFDFT_PRECOND_NONE &&
+            (rc = ofdft_batch_set_preconditioner(s->batch, p->helmholtz_precond)))
+            return fail(rc);
         for (int j = 0; j < 8; ++j)
             if (hipMemsetAsync(s->Vr[j], 0, 2 * b8, st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     }

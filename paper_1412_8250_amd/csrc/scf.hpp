@@ -27,6 +27,7 @@ struct LrTerm {
 constexpr int kLrMaxConv = 16;
 constexpr int kLrMaxTerms = 32;
 constexpr int kLrRound = 8;        // shifted systems per batched solve
+constexpr int kMsGroupMax = 16;    // shifts per multi-shift solve (the solver's maximum)
 
 }  // namespace ofdft
 
@@ -47,6 +48,12 @@ struct ofdft_scf {
     // the solved systems' solutions (2 per convolution, kept as warm starts),
     // each convolution's real sum W = 2 Re(V_1 + V_3), a round's right-hand sides
     std::vector<ofdft::LrConv> lr_conv;
+    // multi-shift form (helmholtz_multishift): the kernel potential without a
+    // warm start (the context's first) solves the systems grouped by their
+    // shared right-hand side, one multi-shift solve per group; later ones use
+    // the batched solver warm-started from the previous solutions
+    std::vector<std::vector<int>> lr_groups;
+    bool kernel_warm = false;
     std::vector<ofdft::LrTerm> lr_terms, lr_eterms;
     std::vector<double2 *> lr_V;
     std::vector<double *> lr_W;

@@ -106,10 +106,8 @@ def test_scf_parameters_are_checked_before_gpu_work():
         st = l.ofdft_scf_create(ctypes.byref(q), ctypes.c_void_p(8), ctypes.c_void_p(16), ctypes.byref(out), None)
         assert st == m.INVALID_ARG, (field, bad)
         assert "invalid parameters" in m.last_error()
-    # the multi-shift kernel solver: K_00 only, complex128, no preconditioner
-    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": 1, "lr_order": 2},
-                  {"helmholtz_multishift": 1, "helmholtz_dtype": m.C64},
-                  {"helmholtz_multishift": 1, "helmholtz_precond": m.PRECOND_MULTIGRID}):
+    # the multi-shift switch is 0 or 1
+    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": -1}):
         q = m.ScfParams.from_buffer_copy(p)
         q.mu = 1
         for k, v in extra.items():

@@ -110,11 +110,12 @@ def test_jellium_fixed_point():
 
 @pytest.mark.parametrize("pmode,hpre,ms", [(ofd.PLAIN_F64, ofd.PRECOND_NONE, False),
                                            (ofd.MULTIGRID, ofd.PRECOND_MULTIGRID, False),
-                                           (ofd.MULTIGRID, ofd.PRECOND_NONE, True)])
+                                           (ofd.MULTIGRID, ofd.PRECOND_MULTIGRID, True)])
 def test_lr_kernel_step_matches_oracle(pmode, hpre, ms):
     """TFW + K_00 kernel term (lambda = 1, mu = 1): the paper's shifts, two
     steps, with plain or multigrid-preconditioned Poisson and shifted solves,
-    or the shifted solves by one multi-shift solve per power."""
+    or the first kernel potential's shifted solves by one multi-shift solve per
+    power (the steps then warm-start the batched solves from them)."""
     torch = torch_cuda()
     announce("scf lr kernel step", pmode, hpre, ms)
     w = inputs.small_cell()
@@ -148,19 +149,23 @@ def test_lr_kernel_step_matches_oracle(pmode, hpre, ms):
         assert helmholtz.residual(to_host(vj), fs[j], ks[j], w.cell.h) <= 1.05 * htol, j
 
 
-@pytest.mark.parametrize("which,hpre", [("small", ofd.PRECOND_NONE), ("small", ofd.PRECOND_MULTIGRID),
-                                        ("supercell", ofd.PRECOND_MULTIGRID)])
-def test_order2_kernel_terms_match_oracle(which, hpre):
+@pytest.mark.parametrize("which,hpre,ms", [("small", ofd.PRECOND_NONE, False), ("small", ofd.PRECOND_MULTIGRID, False),
+                                           ("supercell", ofd.PRECOND_MULTIGRID, False),
+                                           ("small", ofd.PRECOND_MULTIGRID, True),
+                                           ("supercell", ofd.PRECOND_MULTIGRID, True)])
+def test_order2_kernel_terms_match_oracle(which, hpre, ms):
     """The order-2 kernel terms (K_00, K_10, K_20, K_11; 32 solved systems):
     V_LR of the initial density against the oracle, and every solved system
     against its own equation (oracle residual)."""
     torch = torch_cuda()
     from oracle import fd, helmholtz, kernel, wgc
-    announce("scf order-2 kernel terms", which, hpre)
+    announce("scf order-2 kernel terms", which, hpre, ms)
     w = inputs.small_cell() if which == "small" else inputs.supercell_500()
     tol = 1e-10 if which == "small" else 1e-8
     ctx = _ctx(w, lam=1.0, mu=1, lr_order=2, helmholtz_tol=tol, poisson_tol=tol, helmholtz_precond=hpre,
-               poisson_mode=ofd.MULTIGRID if hpre else ofd.PLAIN_F64)
+               poisson_mode=ofd.MULTIGRID if hpre else ofd.PLAIN_F64, helmholtz_multishift=ms)
+    # multi-shift solves stop on their recurrence residual; the true one stays within a small factor
+    htol = 1.5 * tol if ms else tol
     h, ne, vol = w.cell.h, w.cell.n_electrons, w.cell.volume
     ud = torch.empty(w.rho.shape, dtype=torch.float64, device="cuda")
     ctx.get(ofd.SCF.U, ud)
@@ -180,9 +185,9 @@ def test_order2_kernel_terms_match_oracle(which, hpre):
         ctx.get(4 + j, sol)
         P, Q = wgc.coefficients(m, n)
         f = P[r] * (-fd.laplacian(rho ** a, h)) if (m, n) == (0, 0) else k2 * P[r] * rho ** a
-        assert helmholtz.residual(to_host(sol), f, k2 * Q[r], h) <= 1.05 * tol, j
+        assert helmholtz.residual(to_host(sol), f, k2 * Q[r], h) <= 1.05 * htol, j
     assert np.isfinite(ctx.step())
-    assert ctx.stats()["helmholtz_res"] <= tol
+    assert ctx.stats()["helmholtz_res"] <= htol
 
 
 def test_kernel_term_and_preconditioner_option_errors():
