@@ -20,7 +20,9 @@ the pairs with m + n <= L, the ones the table covers; the Q_11, r = 1 entry
 printed with an imaginary part of -0.0266195 (one digit more than every
 other entry) is read as -0.266195, in line with the neighbouring second-order
 kernel K_20 (-0.233840); the smaller value would put the shift almost on the
-real axis inside the spectrum of -L_h, a near-resonant kernel.
+real axis inside the spectrum of -L_h, a near-resonant kernel.  That entry
+is therefore parity unpinned: no printed number fixes it, and every result
+containing K_11 follows the reading.
 Convolutions with the same kernel and the same power of rho are computed once.
 """
 import math
