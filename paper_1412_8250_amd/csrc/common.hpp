@@ -157,12 +157,19 @@ __device__ inline void block_sum(double (&x)[K], double *scratch) {
 // it.  `partials` has K * gridDim slots laid out [k][block].
 //
 // Visibility without a device-wide cache flush: the partials are written
-// with agent-scope atomic stores (coherent at the device level), a
-// workgroup-scope release makes the thread wait until those stores have
-// completed, and only then is the arrival counted.  The last block reads the
-// partials with agent-scope atomic loads.  No other data crosses blocks
-// inside the kernel, so no agent-scope fence (which writes back and
-// invalidates the L2 of every XCD) is needed.
+// with agent-scope atomic stores, which the gfx9 cache policy makes coherent
+// at the device level (they write through the XCD's L2), and the arrival is
+// counted only after those stores have completed: `s_waitcnt vmcnt(0)`
+// stalls the wave until every vector-memory operation it issued, stores
+// included, has been acknowledged by the memory system, and the asm
+// statement's memory clobber keeps the compiler from moving the stores past
+// it.  The last block reads the partials with agent-scope atomic loads, which
+// do not hit a stale L2 line, issued after its counter RMW has returned.  No
+// other data crosses blocks inside the kernel, so no agent-scope release
+// fence (which writes back the L2 of the XCD and costs in proportion to the
+// dirty data the kernel has produced) is needed.
+__device__ inline void wait_vector_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 template <int K>
 __device__ inline bool publish_partial(const double (&x)[K], double *partials, int nblocks,
                                        int block, unsigned int *counter) {
@@ -172,7 +179,7 @@ __device__ inline bool publish_partial(const double (&x)[K], double *partials, i
         for (int k = 0; k < K; ++k)
             __hip_atomic_store(partials + (size_t)k * nblocks + block, x[k], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        wait_vector_memory();
         const unsigned int prev =
             __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == (unsigned int)nblocks - 1);
