@@ -208,7 +208,7 @@ int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa,
  * rel_tol |f|.  No preconditioner (a shift-dependent preconditioner breaks the
  * shared Krylov space: use ofdft_batch_set_preconditioner for that).
  * ofdft_multishift_create: one grid, radius 1..6, up to max_shifts (1..16)
- *   shifts per solve.  Allocates 4 + (max_shifts - 1) complex128 vectors of
+ *   shifts per solve.  Allocates 4 + max(max_shifts - 1, 1) complex128 vectors of
  *   the grid and the solve's device scalars, so a context serves one solve
  *   at a time (solves on one context must not overlap on different streams).
  *   INVALID_ARG or NO_MEMORY.
@@ -222,12 +222,17 @@ int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const double *kappa,
  *            grid, none equal to rhs: the solutions on exit (overwritten,
  *            no initial guess)
  *   stats    optional host array of nshift records: iters = steps after
- *            which the shift froze, outer_iters = seed steps taken, rel_res =
- *            true relative residual recomputed in complex128, status, seconds
+ *            which the shift froze plus the steps of its correction solves,
+ *            outer_iters = seed steps taken, rel_res = true relative residual
+ *            recomputed in complex128, status, seconds
  *   seed_used optional: the seed index used
- * Returns OK, NOT_CONVERGED (a shift missed max_iter or its true residual is
- * above 2 rel_tol), BREAKDOWN, NONFINITE, INVALID_ARG, HIP_ERROR.
- * Synchronises the stream.
+ * The recurred residual that freezes a shift and the true residual drift
+ * apart in floating point: a frozen shift whose true residual is above
+ * rel_tol gets correction solves (d = f - A x, A e = d by a one-shift
+ * sequence from zero, x += e; at most 4, within the max_iter budget left).
+ * Returns OK (every shift's true residual <= rel_tol), NOT_CONVERGED (a
+ * shift missed max_iter or its true residual is still above rel_tol),
+ * BREAKDOWN, NONFINITE, INVALID_ARG, HIP_ERROR.  Synchronises the stream.
  * ------------------------------------------------------------------------ */
 typedef struct ofdft_multishift ofdft_multishift;
 int ofdft_multishift_create(const ofdft_grid *grid, int radius, int max_shifts, ofdft_multishift **out);
@@ -316,12 +321,20 @@ typedef struct {
                                   V = c_r U with the system's factor; later kernel
                                   potentials by the batched solver (helmholtz_precond,
                                   helmholtz_dtype) warm-started from the previous
-                                  solutions.  0 = the batched solver throughout.         */
+                                  solutions (the multi-shift workspace is freed once
+                                  that first potential is formed).  0 = the batched
+                                  solver throughout.                                     */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;
 /* b: device FP64 nuclear charge density; u0: device FP64 initial sqrt-density.
- * Both are copied.  Computes v_0 = phi[u0] + mu V_LR[u0]. */
+ * Both are copied.  Computes v_0 = phi[u0] + mu V_LR[u0].
+ * Status of create and step: the worst of their parts.  NOT_CONVERGED (the
+ * context is still created, the step still taken and *fp_residual written)
+ * when U(v) stopped above u_tol (u_max_iter reached, or no descent direction
+ * left at FP64 precision) or a Poisson or shifted solve missed its tolerance
+ * within max_iter; errors of any part are returned at once (create then
+ * frees everything and leaves *out unset). */
 int ofdft_scf_create(const ofdft_scf_params *p, const double *b, const double *u0,
                      ofdft_scf **out, void *stream);
 int ofdft_scf_destroy(ofdft_scf *s);

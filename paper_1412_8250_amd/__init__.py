@@ -430,7 +430,8 @@ class SCF:
                  helmholtz_tol: float = 1e-10, helmholtz_dtype: int = C128, max_iter: int = 100000,
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
                  u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0,
-                 line_slope_tol: float = 0.0, helmholtz_multishift: bool = False, stream=None):
+                 line_slope_tol: float = 0.0, helmholtz_multishift: bool = False, stream=None,
+                 allow_not_converged: bool = False):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -447,12 +448,19 @@ class SCF:
         p.helmholtz_multishift = int(bool(helmholtz_multishift))
         self.params = p
         self._h = ctypes.c_void_p()
-        _check(lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),
-                                      ctypes.byref(self._h), _stream(stream)))
+        st = lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),
+                                    ctypes.byref(self._h), _stream(stream))
+        _check(st, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        self.status = st
 
-    def step(self, stream=None) -> float:
+    def step(self, stream=None, allow_not_converged: bool = False) -> float:
+        """One fixed-point step; returns ||vhat - v|| / ||v||.  self.status holds
+        the call's status (NOT_CONVERGED if U(v) or a solve missed its tolerance,
+        accepted only with allow_not_converged)."""
         res = ctypes.c_double()
-        _check(lib().ofdft_scf_step(self._h, ctypes.byref(res), _stream(stream)))
+        st = lib().ofdft_scf_step(self._h, ctypes.byref(res), _stream(stream))
+        _check(st, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        self.status = st
         return res.value
 
     def get(self, which: int, out, stream=None):

@@ -410,7 +410,9 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     }
     s->s_prev = s_prev;
     iters = q;
-    return OFDFT_OK;
+    // stopped by the iteration cap or by the lack of a descent direction
+    // before the tolerance: the result is written, the status says so
+    return res <= s->p.u_tol ? OFDFT_OK : OFDFT_NOT_CONVERGED;
 }
 
 }  // namespace ofdft

@@ -10,7 +10,12 @@
 //   alpha_k^(r) = alpha_k pi_k / pi_{k+1},  beta_{k-1}^(r) = (pi_{k-1} / pi_k)^2 beta_{k-1}.
 // One stencil application per iteration serves all shifts; iterates start at
 // zero.  A shift whose residual |r_k| / |pi_k| reaches the tolerance is
-// frozen; the seed sequence runs until every shift is frozen.
+// frozen; the seed sequence runs until every shift is frozen.  The recurred
+// residual and the true one drift apart in floating point, so each shift's
+// true residual is recomputed at the end, and a shift still above the
+// tolerance gets correction solves (iterative refinement): e from
+// (-L_h + kappa_r) e = f - (-L_h + kappa_r) x_r by a one-shift sequence from
+// zero, x_r += e, until the true residual meets the tolerance.
 //
 // Two launches per iteration:
 //  * stencil phase: the seed direction p = r + beta p_old is formed on the
@@ -318,6 +323,47 @@ ms_residual(TileGeom tg, Coef<double> coef, double kre, double kim, const double
     if (reduce_grid<1>(acc, part, total, lb, ctr, scratch, t)) *out = t[0];
 }
 
+struct MsEpiResVec {     // d = f - (-L x + kappa x) written; acc |d|^2
+    GPtr<double2> f, d;
+    double2 kappa;
+    double acc[1];
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, double2 c, double2 s) {
+        const double2 a = cfma(kappa, c, c2(-s.x, -s.y));
+        const double2 dv = csub(f[i], a);
+        d.st(i, dv);
+        acc[0] += dv.x * dv.x + dv.y * dv.y;
+    }
+};
+
+template <int TX, int TYT, int RY>
+__global__ void __launch_bounds__(TX * TYT)
+ms_resvec(TileGeom tg, Coef<double> coef, double kre, double kim, const double2 *x, const double2 *f,
+          double2 *d, double *part, unsigned int *ctr, double *out) {
+    using SLd = StencilLds<double2, TX, TYT, RY>;
+    __shared__ double2 lds[SLd::kElems];
+    __shared__ double scratch[TX * TYT / 64];
+    const int total = tg.nblocks;
+    const int lb = xcd_remap(blockIdx.x, total);
+    MsLoadX ld{GPtr<double2>(x)};
+    MsEpiResVec ep{GPtr<double2>(f), GPtr<double2>(d), c2(kre, kim), {0.0}};
+    stencil_tile<double2, TX, TYT, RY>(tg, coef, ld, ep, lb, lds);
+    double acc[1] = {ep.acc[0]};
+    block_sum<1>(acc, scratch);
+    double t[1];
+    if (reduce_grid<1>(acc, part, total, lb, ctr, scratch, t)) *out = t[0];
+}
+
+// x += e
+__global__ void __launch_bounds__(kMsThreads) ms_axpy(double2 *x, const double2 *e, int64_t n) {
+    const GPtr<double2> X(x), E(e);
+    const int64_t stride = (int64_t)gridDim.x * kMsThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kMsThreads + threadIdx.x; i < n; i += stride) {
+        const double2 a = X[i], b = E[i];
+        X.st(i, c2(a.x + b.x, a.y + b.y));
+    }
+}
+
 // Seed rank (smaller converges slower): a shift with Re kappa < 0 puts a
 // near-resonance -kappa inside the spectrum of -L_h (a subset of [0, inf)),
 // worst for the smallest |Im kappa|; otherwise the smallest |kappa| is the
@@ -343,7 +389,8 @@ struct ofdft_multishift {
     int64_t n = 0;
     int vblocks = 0;
     double2 *r = nullptr, *q = nullptr, *pA = nullptr, *pB = nullptr;
-    std::vector<double2 *> p;    // directions of non-seed shifts (max_shifts - 1)
+    std::vector<double2 *> p;    // directions of non-seed shifts (max_shifts - 1, at least
+                                 // one: p[0] holds the correction of the finishing solves)
     MsState *d_state = nullptr;
     MsShift *d_shift = nullptr;
     double *d_part = nullptr;
@@ -414,7 +461,7 @@ extern "C" int ofdft_multishift_create(const ofdft_grid *grid, int radius, int m
     m->vblocks = (int)std::min<int64_t>(kMsMaxVBlocks, (m->n + kMsThreads - 1) / kMsThreads);
     const size_t vb = sizeof(double2) * (size_t)m->n;
     const size_t nslots = (size_t)std::max(m->tg.nblocks, m->vblocks);
-    m->p.assign(max_shifts - 1, nullptr);
+    m->p.assign(std::max(max_shifts - 1, 1), nullptr);
     int st = OFDFT_OK;
     if ((st = ms_alloc(&m->r, vb)) || (st = ms_alloc(&m->q, vb)) || (st = ms_alloc(&m->pA, vb)) ||
         (st = ms_alloc(&m->pB, vb)) || (st = ms_alloc(&m->d_state, sizeof(MsState))) ||
@@ -443,16 +490,19 @@ extern "C" int ofdft_multishift_destroy(ofdft_multishift *m) {
 
 namespace {
 
-int ms_solve(ofdft_multishift *m, int S, const double *kappa, int seed, const double2 *f,
-             double2 *const *x, double tol, int maxit, ofdft_solve_stats *stats, hipStream_t s) {
+// The shifted COCG sequence of a seed system from zero: fills the final
+// device state and per-shift records (hst, hsh) and accounts the bytes.
+int ms_iterate(ofdft_multishift *m, int S, const double *kappa, int seed, const double2 *f,
+               double2 *const *x, double tol, int maxit, MsState &hst, std::vector<MsShift> &hsh,
+               hipStream_t s) {
     // host-side initial scalars: pi = pi_prev = 1, beta = 0, alpha_prev = 1
-    MsState hst{};
+    hst = MsState{};
     hst.alp_re = 1.0;
     hst.maxit = maxit;
     hst.nshift = S;
     hst.seed = seed;
     hst.done = H_RUNNING;
-    std::vector<MsShift> hsh(kMsMax, MsShift{});
+    hsh.assign(kMsMax, MsShift{});
     int pi = 0;
     for (int j = 0; j < S; ++j) {
         MsShift &h = hsh[j];
@@ -518,39 +568,91 @@ int ms_solve(ofdft_multishift *m, int S, const double *kappa, int seed, const do
         }
         prof_add(K_MS_UPDATE, n * e * upd, 0);
     }
-    // true residuals
-    for (int j = 0; j < S; ++j) {
-        int st = ms_dispatch(m->shape, [&](auto sh) {
-            using Sh = decltype(sh);
+    return OFDFT_OK;
+}
+
+// |f - (-L_h + kappa) x|^2 into *d_out (and the vector into d when d != NULL).
+int ms_true_residual(ofdft_multishift *m, const double *kap, const double2 *x, const double2 *f, double2 *d,
+                     double *d_out, hipStream_t s) {
+    const double e = sizeof(double2), n = (double)m->n;
+    return ms_dispatch(m->shape, [&](auto sh) {
+        using Sh = decltype(sh);
+        if (d) {
+            ProfScope ps(K_RESIDUAL, n * e * 3.0, s);
+            hipLaunchKernelGGL((ms_resvec<Sh::TX, Sh::TYT, Sh::RY>), dim3(m->tg.nblocks), dim3(Sh::TX, Sh::TYT),
+                               0, s, m->tg, m->coef, kap[0], kap[1], x, f, d, m->d_part, m->d_ctr, d_out);
+        } else {
             ProfScope ps(K_RESIDUAL, n * e * 2.0, s);
             hipLaunchKernelGGL((ms_residual<Sh::TX, Sh::TYT, Sh::RY>), dim3(m->tg.nblocks), dim3(Sh::TX, Sh::TYT),
-                               0, s, m->tg, m->coef, kappa[2 * j], kappa[2 * j + 1], x[j], f, m->d_part,
-                               m->d_ctr, m->d_res + j);
-            OFDFT_CHECK_HIP(hipGetLastError());
-            return OFDFT_OK;
-        });
-        OFDFT_TRY(st);
-    }
+                               0, s, m->tg, m->coef, kap[0], kap[1], x, f, m->d_part, m->d_ctr, d_out);
+        }
+        OFDFT_CHECK_HIP(hipGetLastError());
+        return OFDFT_OK;
+    });
+}
+
+constexpr int kMsFixRounds = 4;     // correction solves per shift at most
+
+int ms_solve(ofdft_multishift *m, int S, const double *kappa, int seed, const double2 *f,
+             double2 *const *x, double tol, int maxit, ofdft_solve_stats *stats, hipStream_t s) {
+    MsState hst{};
+    std::vector<MsShift> hsh;
+    OFDFT_TRY(ms_iterate(m, S, kappa, seed, f, x, tol, maxit, hst, hsh, s));
+    const int steps = hst.iter;
+    const double fn2 = hst.fn2;
+    const int done = hst.done;
+    // true residuals
+    for (int j = 0; j < S; ++j) OFDFT_TRY(ms_true_residual(m, kappa + 2 * j, x[j], f, nullptr, m->d_res + j, s));
     double res2[kMsMax];
     OFDFT_CHECK_HIP(hipMemcpyAsync(res2, m->d_res, sizeof(double) * S, hipMemcpyDeviceToHost, s));
     OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+    int extra_it[kMsMax] = {};
     int worst = OFDFT_OK;
     for (int j = 0; j < S; ++j) {
         const MsShift &h = hsh[j];
-        const double rel = hst.fn2 > 0.0 ? std::sqrt(res2[j] / hst.fn2) : 0.0;
+        double rel = fn2 > 0.0 ? std::sqrt(res2[j] / fn2) : 0.0;
         int code;
-        switch (hst.fn2 == 0.0 ? H_CONVERGED : h.stat) {
-            case H_CONVERGED: code = rel <= 2.0 * tol ? OFDFT_OK : OFDFT_NOT_CONVERGED; break;
+        switch (fn2 == 0.0 ? H_CONVERGED : h.stat) {
+            case H_CONVERGED: code = rel <= tol ? OFDFT_OK : OFDFT_NOT_CONVERGED; break;
             case H_BREAKDOWN: code = OFDFT_BREAKDOWN; break;
             case H_NONFINITE: code = OFDFT_NONFINITE; break;
             default: code = OFDFT_NOT_CONVERGED; break;
         }
-        if (hst.done == H_NONFINITE && code == OFDFT_NOT_CONVERGED) code = OFDFT_NONFINITE;
-        if (hst.done == H_BREAKDOWN && code == OFDFT_NOT_CONVERGED) code = OFDFT_BREAKDOWN;
+        // A converged shift whose true residual drifted above the tolerance:
+        // correction solves d = f - A x (into r), A e = d from zero (e in p[0],
+        // one-shift sequence, target tol |f| / |d| with a margin), x += e.
+        if (h.stat == H_CONVERGED && code == OFDFT_NOT_CONVERGED && std::isfinite(rel)) {
+            int budget = std::max(maxit - steps, 0);
+            for (int round = 0; round < kMsFixRounds && rel > tol && budget > 0; ++round) {
+                OFDFT_TRY(ms_true_residual(m, kappa + 2 * j, x[j], f, m->r, m->d_res + j, s));
+                double d2 = 0.0;
+                OFDFT_CHECK_HIP(hipMemcpyAsync(&d2, m->d_res + j, sizeof(double), hipMemcpyDeviceToHost, s));
+                OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+                if (!(d2 > 0.0) || !std::isfinite(d2)) break;
+                const double tc = std::min(0.5, 0.5 * tol * std::sqrt(fn2 / d2));
+                MsState cst{};
+                std::vector<MsShift> csh;
+                double2 *ex[1] = {m->p[0]};
+                OFDFT_TRY(ms_iterate(m, 1, kappa + 2 * j, 0, m->r, ex, tc, budget, cst, csh, s));
+                extra_it[j] += cst.iter;
+                budget -= cst.iter;
+                if (cst.done == H_NONFINITE || cst.done == H_BREAKDOWN) break;
+                hipLaunchKernelGGL(ms_axpy, dim3(m->vblocks), dim3(kMsThreads), 0, s, x[j], m->p[0], m->n);
+                OFDFT_CHECK_HIP(hipGetLastError());
+                prof_add(K_POINTWISE, (double)m->n * sizeof(double2) * 3.0, 1);
+                OFDFT_TRY(ms_true_residual(m, kappa + 2 * j, x[j], f, nullptr, m->d_res + j, s));
+                OFDFT_CHECK_HIP(hipMemcpyAsync(&d2, m->d_res + j, sizeof(double), hipMemcpyDeviceToHost, s));
+                OFDFT_CHECK_HIP(hipStreamSynchronize(s));
+                rel = std::sqrt(d2 / fn2);
+            }
+            code = rel <= tol ? OFDFT_OK : OFDFT_NOT_CONVERGED;
+        }
+        if (done == H_NONFINITE && code == OFDFT_NOT_CONVERGED) code = OFDFT_NONFINITE;
+        if (done == H_BREAKDOWN && code == OFDFT_NOT_CONVERGED) code = OFDFT_BREAKDOWN;
         if (!std::isfinite(rel)) code = OFDFT_NONFINITE;
         if (stats) {
             stats[j] = ofdft_solve_stats{};
-            stats[j].iters = h.stat == H_RUNNING ? steps : h.iters;
+            stats[j].iters = (h.stat == H_RUNNING ? steps : h.iters) + extra_it[j];
             stats[j].outer_iters = steps;
             stats[j].status = code;
             stats[j].rel_res = rel;

@@ -319,6 +319,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
     const double k2 = 4.0 * kf * kf;
     const int nsys = 2 * (int)s->lr_conv.size();
     const bool ms = s->ms && !s->kernel_warm;
+    int worst = OFDFT_OK;       // worst non-negative status of the solves
     if (ms) {
         // no warm start: one multi-shift solve of (-L_h + kappa_r) U = g per group
         // of systems sharing g (from zero), then V = c_r U with the system's factor
@@ -343,6 +344,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
             const int hst = cocg_multishift_solve(s->ms, cnt, kap, -1, s->lr_F[0], xs, s->p.helmholtz_tol,
                                                   s->p.max_iter, hs, nullptr, st);
             if (hst < 0) return hst;
+            worst = std::max(worst, hst);
             const double sc = k00 ? 1.0 : k2;
             for (int k = 0; k < cnt; ++k) {
                 helm_it += hs[k].iters;
@@ -396,6 +398,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
         ofdft_solve_stats hs[kLrRound];
         int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol, s->p.max_iter, hs, st);
         if (hst < 0) return hst;
+        worst = std::max(worst, hst);
         for (int k = 0; k < cnt; ++k) {
             helm_it += hs[k].iters;
             helm_res = std::max(helm_res, hs[k].rel_res);
@@ -419,7 +422,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
     vo.floor_rho = 1e-12 * s->p.n_electrons / volume;
     OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
     s->kernel_warm = true;
-    return OFDFT_OK;
+    return worst;
 }
 
 struct MixResidOp {     // vhat = phi + mu vlr; f = vhat - v; totals {|f|^2, |v|^2}
@@ -479,7 +482,9 @@ void scf_free(ofdft_scf *s) {
     redbuf_free(s->rb);
 }
 
-// vhat -> s->fres (phi and the shifted solutions are updated as warm starts)
+// vhat -> s->fres (phi and the shifted solutions are updated as warm starts).
+// Returns the worst status of the solves: an error (< 0) at once, else
+// NOT_CONVERGED if any solve missed its tolerance (the map is still formed).
 int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, int &helm_it,
                   double &helm_res) {
     const int64_t n = s->n;
@@ -487,11 +492,15 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
     ofdft_solve_stats ps{};
     int pst = poisson_solve(s->pois, s->g4, s->phi, s->p.poisson_tol, s->p.max_iter, ps, st);
     if (pst < 0) return pst;
+    int worst = pst;
     pois_res = ps.rel_res;
     pois_it = ps.iters;
     helm_it = 0;
     helm_res = 0.0;
-    if (s->p.mu && s->p.lr_order == 2) return lr2_potential(s, st, helm_it, helm_res);
+    if (s->p.mu && s->p.lr_order == 2) {
+        const int lst = lr2_potential(s, st, helm_it, helm_res);
+        return lst < 0 ? lst : std::max(worst, lst);
+    }
     if (s->p.mu && s->ms && !s->kernel_warm) {
         // No warm start yet: the systems of one power share the right-hand side
         // up to P_r, so one multi-shift solve of (-L_h + kappa_r) U_r = f per
@@ -508,6 +517,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
             const int hst = cocg_multishift_solve(s->ms, 2, kap, -1, s->Fr[4 * q], xs, s->p.helmholtz_tol,
                                                   s->p.max_iter, hs, nullptr, st);
             if (hst < 0) return hst;
+            worst = std::max(worst, hst);
             for (int k = 0; k < 2; ++k) {
                 helm_it += hs[k].iters;
                 helm_res = std::max(helm_res, hs[k].rel_res);
@@ -544,6 +554,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
         int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol,
                                              s->p.max_iter, hs, st);
         if (hst < 0) return hst;
+        worst = std::max(worst, hst);
         for (int q = 0; q < 4; ++q) {
             helm_it += hs[q].iters;
             helm_res = std::max(helm_res, hs[q].rel_res);
@@ -557,7 +568,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
         OFDFT_TRY((launch_reduce<1>(n, vo, NoFin{}, s->rb, st)));
         s->kernel_warm = true;
     }
-    return OFDFT_OK;
+    return worst;
 }
 
 }  // namespace
@@ -710,7 +721,14 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     // v_0 = phi[u_0] + mu V_LR[u_0]
     double pr, hr;
     int pit, hit;
-    if ((rc = potential_map(s, st, pr, pit, hit, hr)) < 0) return fail(rc);
+    const int mst = potential_map(s, st, pr, pit, hit, hr);
+    if (mst < 0) return fail(mst);
+    // the multi-shift context serves only this first kernel potential (the
+    // steps warm-start the batched solver): release its vectors
+    if (s->ms) {
+        ofdft_multishift_destroy(s->ms);
+        s->ms = nullptr;
+    }
     if ((rc = launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)p->mu},
                                NoFin{}, s->rb, st)) < 0)
         return fail(rc);
@@ -718,7 +736,7 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     if ((rc = launch_reduce<1>(s->n, CopyOp{s->fres, s->v}, NoFin{}, s->rb, st)) < 0) return fail(rc);
     if (hipStreamSynchronize(st) != hipSuccess) return fail(OFDFT_HIP_ERROR);
     *out = s;
-    return OFDFT_OK;
+    return mst;         // NOT_CONVERGED if a solve of v_0 missed its tolerance
 }
 
 extern "C" int ofdft_scf_destroy(ofdft_scf *s) {
@@ -736,10 +754,12 @@ extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     int uit = 0;
     double ures = 0, eta = 0;
-    OFDFT_TRY(density_update(s, s->v, s->u, uit, ures, eta, st));
+    const int ust = density_update(s, s->v, s->u, uit, ures, eta, st);
+    if (ust < 0) return ust;
     double pr = 0, hr = 0;
     int pit = 0, hit = 0;
-    OFDFT_TRY(potential_map(s, st, pr, pit, hit, hr));
+    const int mst = potential_map(s, st, pr, pit, hit, hr);
+    if (mst < 0) return mst;
     OFDFT_TRY((launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)s->p.mu},
                                 StoreTotals<2>{s->dsc + 40}, s->rb, st)));
     OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 40, s->dsc + 40, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -755,7 +775,8 @@ extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
     s->last[4] = pr;
     s->last[5] = hr;
     s->last[6] = eta;
-    return std::isfinite(res) ? OFDFT_OK : OFDFT_NONFINITE;
+    if (!std::isfinite(res)) return OFDFT_NONFINITE;
+    return std::max(ust, mst);      // NOT_CONVERGED if U(v) or a solve missed its tolerance
 }
 
 // State vectors: 0 v, 1 u, 2 phi, 3 V_LR (n doubles); 4.. the shifted-solve
@@ -845,9 +866,10 @@ extern "C" int ofdft_density_update(ofdft_scf *s, const double *v, double *u, in
     }
     int it = 0;
     double res = 0, e = 0;
-    OFDFT_TRY(density_update(s, v, u, it, res, e, (hipStream_t)stream));
+    const int ust = density_update(s, v, u, it, res, e, (hipStream_t)stream);
+    if (ust < 0) return ust;
     if (iters) *iters = it;
     if (residual) *residual = res;
     if (eta) *eta = e;
-    return res <= s->p.u_tol ? OFDFT_OK : OFDFT_NOT_CONVERGED;
+    return ust;
 }

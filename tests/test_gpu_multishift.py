@@ -68,17 +68,21 @@ def test_converged_shifts_match_oracle_and_spectral_solve(grid, seed):
     lam = fd.symbol(shape, h, 6)
     for j, kap in enumerate(kaps):
         res = helmholtz.residual(xs[j], f, kap, h)
-        assert res <= 2 * tol and abs(st[j]["rel_res"] - res) <= 1e-3 * res + 1e-15
+        # OK means the true residual meets the tolerance (a shift whose true
+        # residual drifted above it got correction solves)
+        assert res <= 1.0001 * tol and abs(st[j]["rel_res"] - res) <= 1e-3 * res + 1e-15
+        assert st[j]["rel_res"] <= tol
         # the step at which a shift freezes is a threshold decision on COCG's erratic
-        # residual: rounding moves it by a few steps (the solutions agree below)
-        assert abs(st[j]["iters"] - iters[j]) <= 3, (j, st[j]["iters"], iters[j])
+        # residual: rounding moves it by a few steps (the solutions agree below);
+        # correction solves add their steps
+        assert iters[j] - 3 <= st[j]["iters"] <= iters[j] + 3 + 30, (j, st[j]["iters"], iters[j])
         exact = helmholtz.solve_exact(f, kap, h)
         inv_norm = 1.0 / np.abs(-lam + kap).min()
         assert np.linalg.norm(xs[j] - exact) <= 1.01 * inv_norm * res * np.linalg.norm(f)
         # both iterations stop at (nearly) the same step: the iterates agree to the tolerance
         assert np.linalg.norm(xs[j] - ref[j]) <= 4 * inv_norm * tol * np.linalg.norm(f)
-    # the seed sequence ran exactly until the last shift froze
-    assert max(s["iters"] for s in st) == st[0]["outer_iters"] == k
+    # the seed sequence ran until the last shift froze, as the oracle's did
+    assert st[0]["outer_iters"] == k and max(s["iters"] for s in st) >= k
 
 
 def test_one_shift_and_zero_rhs_and_errors():
