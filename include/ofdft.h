@@ -133,6 +133,21 @@ int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode, ofdft_poi
 int ofdft_poisson_destroy(ofdft_poisson *s);
 int cg_poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol,
                      int max_iter, ofdft_solve_stats *stats, void *stream);
+/* cg_poisson_solve_noalloc -- for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the OFDFT_PLAIN_F64 form of cg_poisson_solve with the same
+ * arguments as a solver of that mode (rhs, x, rel_tol, max_iter, stats, stream
+ * as above; grid and radius as for ofdft_poisson_create), but no context:
+ * its workspace (five FP64 vectors, the device scalars and the reduction
+ * partials, about 40.5 MiB) is a static device array of the library that each
+ * GPU holds until the process ends.  The call allocates nothing (no device or
+ * pinned host memory, events or graphs) and synchronises the stream.
+ * Limit: nx*ny*nz <= 2^20 points (96^3 fits); larger grids return
+ * INVALID_ARG.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller.  Results equal cg_poisson_solve's (same kernels, same order). */
+int cg_poisson_solve_noalloc(const ofdft_grid *grid, int radius, const double *rhs, double *x,
+                             double rel_tol, int max_iter, ofdft_solve_stats *stats, void *stream);
 /* Blocks of 16 CG iterations are captured once as a HIP graph (on a private
  * stream) and replayed; kernels leave early once converged.  enable = 0 turns
  * this off for the solver (results are bitwise identical either way). */

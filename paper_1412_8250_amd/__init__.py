@@ -76,6 +76,7 @@ def _declare(l):
         "ofdft_poisson_create": (_I, [_GP, _I, _I, ctypes.POINTER(_V)]),
         "ofdft_poisson_destroy": (_I, [_V]),
         "cg_poisson_solve": (_I, [_V, _V, _V, _D, _I, _SP, _V]),
+        "cg_poisson_solve_noalloc": (_I, [_GP, _I, _V, _V, _D, _I, _SP, _V]),
         "ofdft_batch_create": (_I, [_I, _GP, _I, _I, ctypes.POINTER(_V)]),
         "ofdft_batch_destroy": (_I, [_V]),
         "cg_helmholtz_solve_batched": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_V),
@@ -225,6 +226,20 @@ def profile_read() -> dict:
 def set_stencil_config(shape_zyx, elem_bytes: int, shape_id: int, zlen: int = 0):
     nz, ny, nx = shape_zyx
     _check(lib().ofdft_stencil_set_config(nx, ny, nz, elem_bytes, shape_id, zlen))
+
+
+def poisson_solve_noalloc(rhs, x, h_xyz, rel_tol: float = 1e-10, max_iter: int = 100000, radius: int = 6,
+                          stream=None, allow_not_converged: bool = False) -> dict:
+    """Plain FP64 Poisson solve on the library's static workspace (no
+    allocation; grids up to 2^20 points; calls on one GPU must not overlap)."""
+    g = grid_of(x.shape, h_xyz)
+    st = SolveStats()
+    status = lib().cg_poisson_solve_noalloc(ctypes.byref(g), int(radius), _dev(rhs, x.shape), _dev(x),
+                                            float(rel_tol), int(max_iter), ctypes.byref(st), _stream(stream))
+    out = st.as_dict()
+    out["status"] = status
+    _check(status, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+    return out
 
 
 class PoissonSolver:

@@ -125,3 +125,22 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_noalloc_poisson_refuses_before_gpu_work():
+    """The allocation-free Poisson entry point checks its grid against the
+    static workspace (2^20 points) and its arguments on the host."""
+    import paper_1412_8250_amd as m
+    l = m.lib()
+    st = m.SolveStats()
+    g = m.Grid(128, 128, 65, 0.4, 0.4, 0.4)            # 2^20 + 16384 points
+    assert l.cg_poisson_solve_noalloc(ctypes.byref(g), 6, ctypes.c_void_p(256), ctypes.c_void_p(512), 1e-8, 10,
+                                      ctypes.byref(st), None) == m.INVALID_ARG
+    assert "static workspace" in m.last_error()
+    g = m.Grid(16, 16, 16, 0.4, 0.4, 0.4)
+    assert l.cg_poisson_solve_noalloc(ctypes.byref(g), 6, ctypes.c_void_p(256), ctypes.c_void_p(256), 1e-8, 10,
+                                      ctypes.byref(st), None) == m.INVALID_ARG
+    assert l.cg_poisson_solve_noalloc(ctypes.byref(g), 6, ctypes.c_void_p(256), ctypes.c_void_p(512), 0.0, 10,
+                                      ctypes.byref(st), None) == m.INVALID_ARG
+    assert l.cg_poisson_solve_noalloc(ctypes.byref(g), 7, ctypes.c_void_p(256), ctypes.c_void_p(512), 1e-8, 10,
+                                      ctypes.byref(st), None) == m.INVALID_ARG
