@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--plain-density", action="store_true",
                     help="density update by Algorithm 1 as printed instead of the multigrid-preconditioned NLCG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's untuned launch configuration (no autotuner run)")
     ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy", "mgc", "mg", "density", "msc"],
                     default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
@@ -204,8 +206,18 @@ def profile_kernel(which, shape, h, reps=5):
 # 348 instead of 418 vector passes, the same minimiser to the 1e-8 tolerance.
 LINE_SLOPE_TOL = 1e-2
 
+# Kernel classes whose every launch is one kernel (the multigrid cycles and
+# the density-update passes are several kernels each).
+SINGLE_KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "cocg", "ms_stencil", "ms_update")
+KERNEL_NAMES = {"cocg": "step_stencil (stepped COCG stencil phase, complex128)",
+                "cg_stencil": "stencil_kernel<LoadCgP, EpiCgAp> (CG stencil pass)",
+                "cg_update": "reduce_kernel<CgUpdate> (CG vector pass)",
+                "apply": "stencil_kernel<LoadPlain, EpiAxpby> (apply)",
+                "ms_stencil": "ms_stencil (multi-shift COCG stencil phase)",
+                "ms_update": "ms_update (multi-shift COCG vector phase)"}
 
-def batch_extra(dev):
+
+def batch_extra(dev, autotune=True):
     """Time to 1e-8 of the uneven 32-cell x 8-shift batch (Re kappa > 0):
     complex128 COCG, complex64 COCG in complex128 refinement, and complex128
     with the multigrid preconditioner; the median of three identical solves
@@ -237,6 +249,12 @@ def batch_extra(dev):
         bt = ofd.HelmholtzBatch(shapes, hs, 6, dt)
         if pre is not None:
             bt.set_preconditioner(pre)
+        tune = None
+        if autotune:
+            xs = [torch.zeros_like(f) for f in rhs]
+            tune = bt.tune(kaps, rhs, xs, iters=8)
+            tune["shape_name"] = ofd.SHAPE_NAMES[tune["shape"]]
+            del xs
         secs = []
         for rep in range(4):                    # the first solve captures graphs and builds hierarchies
             xs = [torch.zeros_like(f) for f in rhs]
@@ -247,7 +265,7 @@ def batch_extra(dev):
             if rep:
                 secs.append(time.perf_counter() - t0)
         out[name] = {"seconds": sorted(secs)[1], "seconds_all": secs, "max_iters": max(s["iters"] for s in st),
-                     "max_rel_res": max(s["rel_res"] for s in st)}
+                     "max_rel_res": max(s["rel_res"] for s in st), "autotune": tune}
         bt.close()
         del xs
     return out
@@ -349,9 +367,18 @@ def main():
                   helmholtz_precond=ofd.PRECOND_NONE if args.plain_helmholtz else ofd.PRECOND_MULTIGRID,
                   helmholtz_multishift=args.multishift_helmholtz,
                   u_precond=ofd.PRECOND_NONE if args.plain_density else ofd.PRECOND_MULTIGRID,
-                  line_slope_tol=LINE_SLOPE_TOL)
+                  line_slope_tol=LINE_SLOPE_TOL, autotune=not args.no_autotune)
     torch.cuda.synchronize()
     log(f"context + v0 in {time.perf_counter() - t0:.1f}s")
+    tuned = None
+    if not args.no_autotune:
+        # the context tuned its grid's fused passes, apply and batch at creation;
+        # re-running the stencil tuner reports what it chose (same table entries)
+        tuned = {fam: ofd.tune_stencil(shape, h, ofd.F64, code, reps=5)
+                 for fam, code in (("pass_f64", ofd.TUNE_PASS), ("apply_f64", ofd.TUNE_APPLY))}
+        for v in tuned.values():
+            v["shape_name"] = ofd.SHAPE_NAMES[v["shape"]]
+        log("autotuned launch configuration:", tuned)
 
     # Every step (warm-up and timed) is the first fixed-point step from the same
     # state: v_0, u_0 and the warm-start solutions of the Poisson and shifted
@@ -366,7 +393,10 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup step {k}: residual {r:.3e} in {time.perf_counter() - t0:.2f}s  {scf.stats()}")
     prof = ofd.profile_read()
-    dominant = max(prof, key=lambda c: prof[c]["ms"]) if args.warmup else "cocg"
+    # the roofline is reported for one kernel: the class, among those whose
+    # launches are each a single kernel, with the most time in the step
+    single = [c for c in SINGLE_KERNEL_CLASSES if prof[c]["launches"]]
+    dominant = max(single, key=lambda c: prof[c]["ms"]) if args.warmup and single else "cocg"
     warm_ms = {c: round(v["ms"] / max(args.warmup, 1), 2) for c, v in prof.items() if v["launches"]}
     log("warmup profile (ms per step):", warm_ms)
 
@@ -400,7 +430,8 @@ def main():
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "traffic_algorithmic_per_launch": tr["algorithmic_bytes_per_launch"] if tr else None,
                 "traffic_source": tr["source"] if tr else None,
-                "kernel": dominant, "launches": dom["launches"],
+                "kernel": dominant, "kernel_name": KERNEL_NAMES.get(dominant, dominant),
+                "launches": dom["launches"],
                 "bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
                 "avg_launch_ms": dom["ms"] / max(dom["timed"], 1),
                 "measured_on": "one extra step after the timed region, events around each launch of the class"}
@@ -409,7 +440,24 @@ def main():
     ofd.profile_reset(timed=())
 
     extras = {}
+    if tuned is not None:
+        extras["autotune_320"] = tuned
     if not args.no_extras and args.workload == "large":
+        if not args.no_autotune:
+            # the apply of each element type at 320^3 and the fused passes on
+            # the grids of the uneven batch and of the learned aid's cells
+            at = {}
+            for name, code in (("f32", ofd.F32), ("c128", ofd.C128)):
+                r = ofd.tune_stencil(shape, h, code, ofd.TUNE_APPLY, reps=5)
+                r["shape_name"] = ofd.SHAPE_NAMES[r["shape"]]
+                at[f"apply_{name}_320"] = r
+            for n in (24, 48, 64, 96, 112, 192):
+                hh = (0.4,) * 3
+                for fam, code in (("apply", ofd.TUNE_APPLY), ("pass", ofd.TUNE_PASS)):
+                    r = ofd.tune_stencil((n, n, n), hh, ofd.F64, code, reps=5)
+                    r["shape_name"] = ofd.SHAPE_NAMES[r["shape"]]
+                    at[f"{fam}_f64_{n}"] = r
+            extras["autotune_grids"] = at
         for dt, eb in ((torch.float64, 8), (torch.float32, 4), (torch.complex128, 16)):
             x = torch.randn(shape, dtype=dt, device=dev)
             y = torch.empty_like(x)
@@ -479,7 +527,7 @@ def main():
                                        "max_force": float(np.abs(fo).max()), "atoms": len(atoms)}
         # the uneven batch: 32 cells (24^3 .. 96^3) x 8 shifts = 256 systems,
         # right-hand sides -L_h rho^alpha, -L_h rho^beta built with the library
-        extras["batched_256_systems"] = batch_extra(dev)
+        extras["batched_256_systems"] = batch_extra(dev, autotune=not args.no_autotune)
         # the K_00 shifts of one right-hand side at 320^3: multi-shift against batched COCG
         extras["multishift_320_4_shifts"] = multishift_extra(dev, w.rho, h, scf.kernel_shifts()[0])
         # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)

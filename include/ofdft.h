@@ -339,6 +339,11 @@ typedef struct {
                                   solutions (the multi-shift workspace is freed once
                                   that first potential is formed).  0 = the batched
                                   solver throughout.                                     */
+    int autotune;              /* 1 = tune the launch configuration at creation: the
+                                  fused stencil passes and the apply on the grid
+                                  (ofdft_tune_stencil) and, for mu = 1, the shifted-
+                                  system batch on the first batched kernel solve
+                                  (ofdft_batch_tune, 8 iterations); 0 = untuned      */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;
@@ -477,9 +482,12 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  * tuner, the benchmark and the tests).
  *
  * ofdft_stencil_set_config: fix the stencil launch shape for one grid and
- *   element size (elem_bytes 4, 8 or 16): shape 0 = 64x16 tile (4 rows per
- *   thread), 1 = 64x8 tile, 2 = 32x16 tile; zlen = planes per z chunk (0 =
- *   automatic).  shape < 0 removes the entry.  INVALID_ARG for unknown shapes.
+ *   element size (elem_bytes 4, 8 or 16), for every kernel family (it
+ *   replaces the grid's tuned entries): shape 0 = 64x16 tile of 256 threads
+ *   (4 rows per thread), 1 = 64x8 tile of 256, 2 = 32x16 tile of 256, 3 =
+ *   64x16 tile of 512, 4 = 64x8 tile of 512, 5 = 64x32 tile of 512 (the plain
+ *   FP64 apply; 3 elsewhere); zlen = planes per z chunk (0 = automatic).
+ *   shape < 0 removes the grid's entries.  INVALID_ARG for unknown shapes.
  * ofdft_batch_set_config: schedule of the shifted-system solver.  group 0
  *   (default) = stepped schedule: one launch per COCG phase over all systems,
  *   replayed from a HIP graph; group P in 1..1024 = persistent schedule, one
@@ -501,6 +509,51 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   for one class since the last reset (synchronises on pending events).
  * ------------------------------------------------------------------------ */
 int ofdft_stencil_set_config(int nx, int ny, int nz, int elem_bytes, int shape, int zlen);
+
+/* ------------------------------------------------------------------------
+ * Autotuner of the launch configuration (not part of the method; it decides
+ * how the Laplacian of Section 4 is tiled on the chip).  Every candidate
+ * computes the same operator; the fused passes' reduction order follows the
+ * tiling, so tuned and untuned runs agree to rounding, and runs with one
+ * configuration are bitwise repeatable.
+ *
+ * ofdft_tune_stencil: times each legal (tile shape, z-chunk length) of one
+ *   kernel family on `grid` (scratch vectors allocated and freed inside;
+ *   `reps` timed launches after one warm-up, HIP events on `stream`) and
+ *   records the fastest in the launch table for (grid, element size,
+ *   family).  family OFDFT_TUNE_APPLY: fd_laplacian_apply, any dtype;
+ *   OFDFT_TUNE_PASS: the fused single-pass stencil kernels (CG, residual and
+ *   density-update passes), timed on the CG stencil pass, dtype F64 or F32.
+ *   The untuned configuration is a candidate and is kept unless another is
+ *   more than 2% faster.  Synchronises the stream.  INVALID_ARG, NO_MEMORY,
+ *   HIP_ERROR.
+ * ofdft_batch_tune: times `iters` COCG iterations of the batch's systems
+ *   (kappa, rhs as for cg_helmholtz_solve_batched; x = starting guesses, read
+ *   only: the runs use copies) for each stepped-schedule tile shape and
+ *   z-chunk target (40, 80, 160 planes) and, without a preconditioner, the
+ *   persistent schedule with 16 and 64 workgroups per group; sets the
+ *   fastest as the batch's configuration.
+ * out (optional): shape id, zlen (z-chunk length; for a batch the z-chunk
+ *   target, planes), group (batch: persistent group size, 0 = stepped),
+ *   candidates timed, best_ms and default_ms (per launch; per solve of
+ *   `iters` iterations for a batch) of the choice and of the untuned
+ *   configuration.
+ * ofdft_tune_save / ofdft_tune_load: the launch table as text (one entry per
+ *   line: family nx ny nz elem_bytes shape zlen; family -1 = set by hand for
+ *   every family); load adds entries (count in *entries, may be NULL).
+ * ------------------------------------------------------------------------ */
+#define OFDFT_TUNE_APPLY 0
+#define OFDFT_TUNE_PASS  1
+typedef struct {
+    int shape, zlen, group, candidates;
+    double best_ms, default_ms;
+} ofdft_tune_result;
+int ofdft_tune_stencil(const ofdft_grid *grid, int radius, ofdft_dtype dtype, int family, int reps,
+                       ofdft_tune_result *out, void *stream);
+int ofdft_batch_tune(ofdft_batch *b, const double *kappa, const void *const *rhs, const void *const *x,
+                     int iters, ofdft_tune_result *out, void *stream);
+int ofdft_tune_save(const char *path);
+int ofdft_tune_load(const char *path, int *entries);
 int ofdft_batch_set_config(ofdft_batch *b, int shape, int group);
 int ofdft_profile_reset(unsigned timed_mask);
 int ofdft_profile_read(int cls, int64_t *launches, double *bytes, int64_t *timed, double *ms);

@@ -52,7 +52,15 @@ class ScfParams(ctypes.Structure):
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
                 ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int),
                 ("u_precond_sigma", ctypes.c_double), ("line_slope_tol", ctypes.c_double),
-                ("helmholtz_multishift", ctypes.c_int)]
+                ("helmholtz_multishift", ctypes.c_int), ("autotune", ctypes.c_int)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int), ("zlen", ctypes.c_int), ("group", ctypes.c_int),
+                ("candidates", ctypes.c_int), ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class GaussAtoms(ctypes.Structure):
@@ -121,6 +129,11 @@ def _declare(l):
         "ofdft_poisson_apply_preconditioner": (_I, [_V, _V, _V, _V]),
         "ofdft_nn_set_loss": (_I, [_V, _I]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
+        "ofdft_tune_stencil": (_I, [_GP, _I, _I, _I, _I, ctypes.POINTER(TuneResult), _V]),
+        "ofdft_batch_tune": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_V), ctypes.POINTER(_V), _I,
+                                  ctypes.POINTER(TuneResult), _V]),
+        "ofdft_tune_save": (_I, [ctypes.c_char_p]),
+        "ofdft_tune_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
         "ofdft_profile_read": (_I, [_I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)]),
     }
@@ -228,6 +241,31 @@ def set_stencil_config(shape_zyx, elem_bytes: int, shape_id: int, zlen: int = 0)
     _check(lib().ofdft_stencil_set_config(nx, ny, nz, elem_bytes, shape_id, zlen))
 
 
+TUNE_APPLY, TUNE_PASS = 0, 1
+SHAPE_NAMES = ("64x16/256", "64x8/256", "32x16/256", "64x16/512", "64x8/512", "64x32/512")
+
+
+def tune_stencil(shape_zyx, h_xyz, dtype: int = F64, family: int = TUNE_APPLY, reps: int = 5,
+                 radius: int = 6, stream=None) -> dict:
+    """Time every legal launch shape / z chunk of one kernel family on the grid
+    and record the fastest (see ofdft_tune_stencil)."""
+    g = grid_of(shape_zyx, h_xyz)
+    r = TuneResult()
+    _check(lib().ofdft_tune_stencil(ctypes.byref(g), int(radius), int(dtype), int(family), int(reps),
+                                    ctypes.byref(r), _stream(stream)))
+    return r.as_dict()
+
+
+def tune_save(path: str):
+    _check(lib().ofdft_tune_save(str(path).encode()))
+
+
+def tune_load(path: str) -> int:
+    n = ctypes.c_int()
+    _check(lib().ofdft_tune_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
 def poisson_solve_noalloc(rhs, x, h_xyz, rel_tol: float = 1e-10, max_iter: int = 100000, radius: int = 6,
                           stream=None, allow_not_converged: bool = False) -> dict:
     """Plain FP64 Poisson solve on the library's static workspace (no
@@ -326,9 +364,7 @@ class HelmholtzBatch:
                                                       _dev(z, self.shapes[j]), _stream(stream)))
         return z
 
-    def solve(self, kappas, rhs, xs, rel_tol: float = 1e-8, max_iter: int = 100000, stream=None,
-              allow_not_converged: bool = False):
-        """kappas: sequence of complex; rhs, xs: complex128 CUDA tensors (x = guess in, solution out)."""
+    def _marshal(self, kappas, rhs, xs):
         if len(kappas) != self.n or len(rhs) != self.n or len(xs) != self.n:
             raise ValueError("one kappa, rhs and x per system")
         k = (ctypes.c_double * (2 * self.n))()
@@ -340,6 +376,20 @@ class HelmholtzBatch:
             _dev(t, s)
         fp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in rhs])
         xp = (ctypes.c_void_p * self.n)(*[t.data_ptr() for t in xs])
+        return k, fp, xp
+
+    def tune(self, kappas, rhs, xs, iters: int = 8, stream=None) -> dict:
+        """Time the schedules and tile shapes on these systems (x read only) and
+        keep the fastest (see ofdft_batch_tune)."""
+        k, fp, xp = self._marshal(kappas, rhs, xs)
+        r = TuneResult()
+        _check(lib().ofdft_batch_tune(self._h, k, fp, xp, int(iters), ctypes.byref(r), _stream(stream)))
+        return r.as_dict()
+
+    def solve(self, kappas, rhs, xs, rel_tol: float = 1e-8, max_iter: int = 100000, stream=None,
+              allow_not_converged: bool = False):
+        """kappas: sequence of complex; rhs, xs: complex128 CUDA tensors (x = guess in, solution out)."""
+        k, fp, xp = self._marshal(kappas, rhs, xs)
         st = (SolveStats * self.n)()
         status = lib().cg_helmholtz_solve_batched(self._h, k, fp, xp, float(rel_tol), int(max_iter),
                                                   st, _stream(stream))
@@ -446,7 +496,7 @@ class SCF:
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
                  u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0,
                  line_slope_tol: float = 0.0, helmholtz_multishift: bool = False, stream=None,
-                 allow_not_converged: bool = False):
+                 allow_not_converged: bool = False, autotune: bool = False):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -461,6 +511,7 @@ class SCF:
         p.u_precond_sigma = float(u_precond_sigma)
         p.line_slope_tol = float(line_slope_tol)
         p.helmholtz_multishift = int(bool(helmholtz_multishift))
+        p.autotune = int(bool(autotune))
         self.params = p
         self._h = ctypes.c_void_p()
         st = lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

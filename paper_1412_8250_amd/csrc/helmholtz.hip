@@ -515,7 +515,7 @@ int upload_systems(ofdft_batch *b, const double *kappa, const std::vector<const 
         h.ny = g.ny;
         h.nz = g.nz;
         const int eff = c64 ? cocg_shape<float2>(shape) : cocg_shape<double2>(shape);
-        const int zl = stepped ? stepped_zlen(g, c64, eff) : zlen_for_units(g, eff);
+        const int zl = stepped ? stepped_zlen(g, c64, eff, b->zplanes) : zlen_for_units(g, eff);
         dispatch_shape(eff, [&](auto sh) {
             using S = decltype(sh);
             h.tg = make_tile_geom<S::TX, S::TYT, S::RY>(g, zl);
@@ -631,6 +631,104 @@ extern "C" int ofdft_batch_set_config(ofdft_batch *b, int shape, int P) {
     }
     b->shape = shape;
     b->P = P;
+    return OFDFT_OK;
+}
+
+// Autotuner of a batch's schedule: times `iters` COCG iterations of the
+// given systems (from copies of x; tolerance out of reach, so every
+// candidate runs the same iterations) for each stepped tile shape and z-chunk
+// target and, without a preconditioner, the persistent schedule with two
+// group sizes, then keeps the fastest (the untuned configuration unless
+// beaten by more than 2%).
+extern "C" int ofdft_batch_tune(ofdft_batch *b, const double *kappa, const void *const *rhs,
+                                const void *const *x, int iters, ofdft_tune_result *out, void *stream) {
+    if (!b || !kappa || !rhs || !x || iters < 1 || iters > 10000) {
+        set_error("ofdft_batch_tune: bad arguments (1 <= iters <= 10000)");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int nsys = b->nsys;
+    std::vector<void *> tmp(nsys, nullptr);
+    auto release = [&]() {
+        for (void *p : tmp)
+            if (p) (void)hipFree(p);
+    };
+    for (int j = 0; j < nsys; ++j) {
+        if (!x[j] || !rhs[j]) {
+            release();
+            set_error("ofdft_batch_tune: NULL array for system %d", j);
+            return OFDFT_INVALID_ARG;
+        }
+        if (hipMalloc(&tmp[j], sizeof(double2) * npoints(b->grids[j])) != hipSuccess) {
+            (void)hipGetLastError();
+            release();
+            set_error("ofdft_batch_tune: out of device memory");
+            return OFDFT_NO_MEMORY;
+        }
+    }
+    struct Cand {
+        int shape, P, planes;
+    };
+    const bool c64 = b->dtype == OFDFT_C64;
+    const Cand def{default_shape(b), 0, kStepPlanes};
+    std::vector<Cand> cand;
+    const std::vector<int> shapes = c64 ? std::vector<int>{SHAPE_64x4x2, SHAPE_64x4x4, SHAPE_32x8x2, SHAPE_64x8x2,
+                                                           SHAPE_64x8x1}
+                                        : std::vector<int>{SHAPE_64x8x1, SHAPE_64x4x2, SHAPE_32x8x2};
+    for (int sh : shapes)
+        for (int planes : {40, kStepPlanes, 160}) cand.push_back({sh, 0, planes});
+    if (!b->precond)
+        for (int P : {16, 64}) cand.push_back({def.shape, P, kStepPlanes});
+    const int keep_shape = b->shape, keep_P = b->P, keep_planes = b->zplanes;
+    std::vector<ofdft_solve_stats> st(nsys);
+    double best = -1.0, def_ms = -1.0;
+    Cand pick = def;
+    int rc = OFDFT_OK;
+    for (const Cand &k : cand) {
+        b->shape = k.shape;
+        b->P = k.P;
+        b->zplanes = k.planes;
+        double t = 0.0;
+        for (int rep = 0; rep < 2 && rc >= 0; ++rep) {     // the first run captures graphs / lays out
+            for (int j = 0; j < nsys && rc >= 0; ++j)
+                if (hipMemcpyAsync(tmp[j], x[j], sizeof(double2) * npoints(b->grids[j]), hipMemcpyDeviceToDevice,
+                                   s) != hipSuccess)
+                    rc = OFDFT_HIP_ERROR;
+            if (rc < 0) break;
+            rc = cg_helmholtz_solve_batched(b, kappa, rhs, tmp.data(), 1e-300, iters, st.data(), stream);
+            t = st[0].seconds * 1e3;
+        }
+        if (rc < 0) break;
+        rc = OFDFT_OK;
+        if (k.shape == def.shape && k.P == def.P && k.planes == def.planes) def_ms = t;
+        if (best < 0.0 || t < best) {
+            best = t;
+            pick = k;
+        }
+    }
+    release();
+    if (rc < 0) {
+        b->shape = keep_shape;
+        b->P = keep_P;
+        b->zplanes = keep_planes;
+        return rc;
+    }
+    if (def_ms > 0.0 && best > 0.98 * def_ms) {
+        pick = def;
+        best = def_ms;
+    }
+    b->shape = pick.shape;
+    b->P = pick.P;
+    b->zplanes = pick.planes;
+    if (out) {
+        *out = ofdft_tune_result{};
+        out->shape = pick.shape;
+        out->zlen = pick.planes;
+        out->group = pick.P;
+        out->candidates = (int)cand.size();
+        out->best_ms = best;
+        out->default_ms = def_ms;
+    }
     return OFDFT_OK;
 }
 

@@ -85,6 +85,11 @@ inline int dispatch_cocg_shape(int shape, F &&f) {
 
 }  // namespace ofdft
 
+namespace ofdft {
+// Default z-chunk target of the stepped schedule (planes per chunk).
+constexpr int kStepPlanes = 80;
+}  // namespace ofdft
+
 struct ofdft_batch {
     int nsys = 0, radius = 6;
     ofdft_dtype dtype = OFDFT_C128;
@@ -102,9 +107,9 @@ struct ofdft_batch {
     double *d_totals = nullptr;   // 2 per system
     ofdft::RedBuf rb{};
     int groups_cap = 0;
-    // launch configuration: shape (< 0: default) and persistent group size
-    // (0: stepped schedule)
-    int shape = -1, P = 0;
+    // launch configuration: shape (< 0: default), persistent group size
+    // (0: stepped schedule) and the stepped schedule's z-chunk target (planes)
+    int shape = -1, P = 0, zplanes = ofdft::kStepPlanes;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // stepped schedule
     ofdft::StepState *d_step = nullptr, *h_step = nullptr;   // per system (host copy pinned)
@@ -147,9 +152,9 @@ int stepped_run(ofdft_batch *b, bool c64, int shape, const std::vector<HSys> &hs
                 const std::vector<int> &which, const std::vector<int> &maxit, double tol,
                 std::vector<int> &iters, std::vector<int> &done, hipStream_t s);
 void stepped_free(ofdft_batch *b);
-// z-chunk length of the stepped stencil phases on grid g (depends only on g,
-// the element type and the shape, so a system's reduction order does not
-// depend on the rest of the batch).
-int stepped_zlen(const ofdft_grid &g, bool c64, int shape);
+// z-chunk length of the stepped stencil phases on grid g for chunks of about
+// `planes` planes (depends only on g, the shape and the batch's setting, so a
+// system's reduction order does not depend on the rest of the batch).
+int stepped_zlen(const ofdft_grid &g, bool c64, int shape, int planes = kStepPlanes);
 
 }  // namespace ofdft

@@ -504,16 +504,17 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
 
 }  // namespace
 
-// Chunks of about 80 planes: long enough for little queue warm-up, short
-// enough that one or two systems still running (the tail of a batch) spread
-// over more workgroups than the chip's CUs (measured: 80 beat 160 and 40 at
-// 320^3); they shrink down to 8 planes while a system would have fewer than
-// 32 tiles.
-int stepped_zlen(const ofdft_grid &g, bool, int shape) {
+// Chunks of about `planes` planes (default 80): long enough for little
+// queue warm-up, short enough that one or two systems still running (the
+// tail of a batch) spread over more workgroups than the chip's CUs
+// (measured: 80 beat 160 and 40 at 320^3; the autotuner times others); they
+// shrink down to 8 planes while a system would have fewer than 32 tiles.
+int stepped_zlen(const ofdft_grid &g, bool, int shape, int planes) {
     int tx, ty;
     shape_extent(shape, tx, ty);
     const int64_t tiles = (int64_t)((g.nx + tx - 1) / tx) * ((g.ny + ty - 1) / ty);
-    int chunks = std::max(1, (g.nz + 79) / 80);
+    planes = std::max(planes, 8);
+    int chunks = std::max(1, (g.nz + planes - 1) / planes);
     while (tiles * chunks < 32 && g.nz / (chunks + 1) >= 8) ++chunks;
     return (g.nz + chunks - 1) / chunks;
 }

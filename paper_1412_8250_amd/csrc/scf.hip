@@ -308,6 +308,14 @@ struct LrVlrOp {
     }
 };
 
+// With autotune, the batch's schedule is timed on its first batched solve
+// (8 iterations from the current warm starts, on copies).
+int tune_batch_once(ofdft_scf *s, const double *kap, const void *const *rhs, void *const *xs, hipStream_t st) {
+    if (!s->p.autotune || s->batch_tuned) return OFDFT_OK;
+    s->batch_tuned = true;
+    return ofdft_batch_tune(s->batch, kap, rhs, (const void *const *)xs, 8, nullptr, st);
+}
+
 // The order-2 kernel potential: rounds of kLrRound solved systems.
 int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) {
     const int64_t n = s->n;
@@ -396,6 +404,7 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
         }
         OFDFT_TRY((launch_reduce<1>(n, ro, NoFin{}, s->rb, st)));
         ofdft_solve_stats hs[kLrRound];
+        OFDFT_TRY(tune_batch_once(s, kap, rhs, xs, st));
         int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol, s->p.max_iter, hs, st);
         if (hst < 0) return hst;
         worst = std::max(worst, hst);
@@ -551,6 +560,7 @@ int potential_map(ofdft_scf *s, hipStream_t st, double &pois_res, int &pois_it, 
             kap[2 * q + 1] = s->kappa[4 * q + 1];
         }
         ofdft_solve_stats hs[4];
+        OFDFT_TRY(tune_batch_once(s, kap, rhs, xs, st));
         int hst = cg_helmholtz_solve_batched(s->batch, kap, rhs, xs, s->p.helmholtz_tol,
                                              s->p.max_iter, hs, st);
         if (hst < 0) return hst;
@@ -587,7 +597,8 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
     if (!(p->n_electrons > 0) || p->lambda < 0 || (p->mu != 0 && p->mu != 1) || p->history < 0 ||
         !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
         (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0) ||
-        (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1)) {
+        (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1) ||
+        (p->autotune != 0 && p->autotune != 1)) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }
@@ -718,6 +729,13 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         hipMemsetAsync(s->phi, 0, b8, st) != hipSuccess || hipMemsetAsync(s->vlr, 0, b8, st) != hipSuccess ||
         hipMemsetAsync(s->v, 0, b8, st) != hipSuccess)
         return fail(OFDFT_HIP_ERROR);
+    if (p->autotune) {
+        // the fused stencil passes (density update, CG, residuals) and the
+        // apply (kernel right-hand sides) on this grid
+        if ((rc = ofdft_tune_stencil(&p->grid, p->radius, OFDFT_F64, OFDFT_TUNE_PASS, 5, nullptr, st)) ||
+            (rc = ofdft_tune_stencil(&p->grid, p->radius, OFDFT_F64, OFDFT_TUNE_APPLY, 5, nullptr, st)))
+            return fail(rc);
+    }
     // v_0 = phi[u_0] + mu V_LR[u_0]
     double pr, hr;
     int pit, hit;

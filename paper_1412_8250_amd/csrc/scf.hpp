@@ -54,6 +54,7 @@ struct ofdft_scf {
     // the batched solver warm-started from the previous solutions
     std::vector<std::vector<int>> lr_groups;
     bool kernel_warm = false;
+    bool batch_tuned = false;     // autotune: the batch's schedule has been timed
     std::vector<ofdft::LrTerm> lr_terms, lr_eterms;
     std::vector<double2 *> lr_V;
     std::vector<double *> lr_W;

@@ -43,8 +43,8 @@ inline int launch_stencil_shape(const ofdft_grid &g, int zlen, const Coef<typena
 
 template <typename T, class Load, class Epi>
 inline int launch_stencil(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const Load &ld,
-                          const Epi &ep, hipStream_t s) {
-    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T));
+                          const Epi &ep, hipStream_t s, int family = FAMILY_PASS) {
+    const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T), family);
     return dispatch_shape(cfg.shape, [&](auto sh) {
         using S = decltype(sh);
         return launch_stencil_shape<T, S::TX, S::TYT, S::RY>(g, cfg.zlen, c, ld, ep, s);

@@ -1,6 +1,9 @@
-// Launch-shape selection for the stencil kernels.  A small table keyed by
-// (grid size, element bytes) is consulted; entries are measured by the
-// library's own tuner (ofdft_tune_stencil) and can be overridden at run time.
+// Launch-shape selection for the stencil kernels.  A table keyed by (grid
+// size, element bytes, kernel family) is consulted first; its entries are
+// written by the library's autotuner (ofdft_tune_stencil, which times every
+// legal shape and z-chunk length of a family on the grid) or set by hand
+// (ofdft_stencil_set_config, for every family at once); without an entry a
+// fixed heuristic measured at 320^3 decides.
 #pragma once
 
 #include "common.hpp"
@@ -55,8 +58,17 @@ inline void shape_extent(int shape, int &tx, int &ty) {
     }
 }
 
-// plain_f64: the caller is the plain FP64 apply, which also has 64 x 32 tiles.
-StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes, bool plain_f64 = false);
+// Kernel families with entries of their own: the plain apply (which also has
+// 64 x 32 tiles for FP64) and the fused single-pass stencil kernels (CG,
+// residual, density-update passes).  FAMILY_ALL entries (set by hand) serve
+// every family without an entry of its own.
+enum TuneFamily { FAMILY_ALL = -1, FAMILY_APPLY = 0, FAMILY_PASS = 1, FAMILY_COUNT = 2 };
+
+StencilCfg pick_stencil_cfg(const ofdft_grid &g, int elem_bytes, int family);
+// The heuristic alone (no table).
+StencilCfg default_stencil_cfg(const ofdft_grid &g, int elem_bytes, int family);
+void record_stencil_cfg(const ofdft_grid &g, int elem_bytes, int family, StencilCfg c);
+void erase_stencil_cfg(const ofdft_grid &g, int elem_bytes, int family);
 int zlen_for_blocks(const ofdft_grid &g, int shape, int target_blocks);
 // z-chunk length minimising (waves of workgroups) x (chunk planes + warm-up)
 // for `resident` workgroups in flight; tiles of tx x ty points.

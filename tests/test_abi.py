@@ -69,7 +69,8 @@ def test_binding_structs_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    checks = {"ofdft_scf_params": m.ScfParams, "ofdft_grid": m.Grid, "ofdft_gauss_atoms": m.GaussAtoms}
+    checks = {"ofdft_scf_params": m.ScfParams, "ofdft_grid": m.Grid, "ofdft_gauss_atoms": m.GaussAtoms,
+              "ofdft_tune_result": m.TuneResult, "ofdft_solve_stats": m.SolveStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ofdft.h"', "int main(void) {"]
     for cname, cls in checks.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -107,7 +108,7 @@ def test_scf_parameters_are_checked_before_gpu_work():
         assert st == m.INVALID_ARG, (field, bad)
         assert "invalid parameters" in m.last_error()
     # the multi-shift switch is 0 or 1
-    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": -1}):
+    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": -1}, {"autotune": 2}):
         q = m.ScfParams.from_buffer_copy(p)
         q.mu = 1
         for k, v in extra.items():
@@ -144,3 +145,29 @@ def test_noalloc_poisson_refuses_before_gpu_work():
                                       ctypes.byref(st), None) == m.INVALID_ARG
     assert l.cg_poisson_solve_noalloc(ctypes.byref(g), 7, ctypes.c_void_p(256), ctypes.c_void_p(512), 1e-8, 10,
                                       ctypes.byref(st), None) == m.INVALID_ARG
+
+
+def test_launch_table_save_and_load(tmp_path):
+    """The autotuner's launch table round-trips through its text form (host
+    only: no kernel runs), malformed files are refused, and a hand-set entry
+    is written with family -1."""
+    import paper_1412_8250_amd as m
+    m.set_stencil_config((37, 41, 43), 8, 2, 9)
+    p1 = tmp_path / "table.txt"
+    m.tune_save(str(p1))
+    lines = [l.split() for l in p1.read_text().splitlines() if not l.startswith("#")]
+    assert ["-1", "43", "41", "37", "8", "2", "9"] in lines
+    m.set_stencil_config((37, 41, 43), 8, -1)
+    p2 = tmp_path / "table2.txt"
+    m.tune_save(str(p2))
+    assert ["-1", "43", "41", "37", "8", "2", "9"] not in [l.split() for l in p2.read_text().splitlines()]
+    assert m.tune_load(str(p1)) == len(lines)
+    m.tune_save(str(p2))
+    assert ["-1", "43", "41", "37", "8", "2", "9"] in [l.split() for l in p2.read_text().splitlines()]
+    m.set_stencil_config((37, 41, 43), 8, -1)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 10 10 10 8 9 0\n")           # unknown shape id
+    with pytest.raises(m.OfdftError):
+        m.tune_load(str(bad))
+    with pytest.raises(m.OfdftError):
+        m.tune_load(str(tmp_path / "missing.txt"))
