@@ -463,6 +463,13 @@ size_t ofdft_nn_param_count(void);
 int ofdft_nn_set_weights(ofdft_nn *net, const float *w, size_t count);
 int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int gradients);
 int ofdft_nn_set_loss(ofdft_nn *net, int kind);
+/* ofdft_nn_set_precision: activation storage of the same kernels: 0 = BF16
+ *   (default: BF16 activations, gradients and weight copies, FP32
+ *   accumulation on v_mfma_f32_16x16x16 bf16), 1 = FP32 (FP32 activations,
+ *   gradients and weight copies on v_mfma_f32_16x16x4 f32; for element-wise
+ *   checks of the kernels against an FP64 reference).  The workspace is
+ *   reallocated on the next forward / gradient call.  INVALID_ARG else. */
+int ofdft_nn_set_precision(ofdft_nn *net, int fp32);
 int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid);
 int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const double *in, double *out,
                      double scale, void *stream);

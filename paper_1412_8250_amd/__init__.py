@@ -128,6 +128,7 @@ def _declare(l):
         "ofdft_poisson_set_learned_mode": (_I, [_V, _I]),
         "ofdft_poisson_apply_preconditioner": (_I, [_V, _V, _V, _V]),
         "ofdft_nn_set_loss": (_I, [_V, _I]),
+        "ofdft_nn_set_precision": (_I, [_V, _I]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
         "ofdft_tune_stencil": (_I, [_GP, _I, _I, _I, _I, ctypes.POINTER(TuneResult), _V]),
         "ofdft_batch_tune": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_V), ctypes.POINTER(_V), _I,
@@ -668,6 +669,11 @@ class Network:
         """Training loss: Network.L2 (solution error), Network.ENERGY (A-norm
         error) or Network.RESIDUAL (norm of the residual the output leaves)."""
         _check(lib().ofdft_nn_set_loss(self._h, int(kind)))
+
+    def set_precision(self, fp32: bool):
+        """Activation storage of the kernels: BF16 (default) or FP32 (the FP32
+        mode of the same kernels)."""
+        _check(lib().ofdft_nn_set_precision(self._h, 1 if fp32 else 0))
 
     def gradients(self, g_rhs, phi, h_xyz, stream=None) -> float:
         g = grid_of(g_rhs.shape, h_xyz)

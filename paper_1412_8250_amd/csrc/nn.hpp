@@ -29,11 +29,15 @@ struct ofdft_nn {
     float *w[ofdft::nn::kLayers] = {}, *m[ofdft::nn::kLayers] = {}, *v[ofdft::nn::kLayers] = {},
           *gr[ofdft::nn::kLayers] = {};
     ofdft::nn::u16 *wf[ofdft::nn::kLayers] = {}, *wb[ofdft::nn::kLayers] = {};
+    float *wf32[ofdft::nn::kLayers] = {}, *wb32[ofdft::nn::kLayers] = {};   // FP32-mode copies
     int adam_t = 0;
-    // workspace for one grid
-    int nx = 0, ny = 0, nz = 0;
+    // activation storage: 0 = BF16 (default), 1 = FP32 (the FP32 mode of the
+    // same kernels, for element-wise checks against the FP64 reference)
+    int fp32 = 0;
+    // workspace for one grid (and one activation storage type)
+    int nx = 0, ny = 0, nz = 0, ws_fp32 = -1;
     std::vector<void *> ws;
-    ofdft::nn::u16 *buf[64] = {};
+    void *buf[64] = {};
     float *out = nullptr;
     float *part = nullptr;
     size_t part_cap = 0;

@@ -17,12 +17,22 @@ namespace nn {
 
 // ---------------------------------------------------------------------------
 // Convolution, C_in a multiple of 16.  Block = 4 waves, each 16 points.
-// Weights Wt: [27][NTILE*16][Cin] BF16 (zero rows for co >= Cout).
-// Output: BF16 (with or without ReLU) or FP32 (no ReLU), channels-last Cout.
-template <int NTILE>
+// Weights Wt: [27][NTILE*16][Cin] (BF16, or FP32 in the FP32 mode; zero rows
+// for co >= Cout).  Output: activation type A (with or without ReLU) or FP32
+// (no ReLU), channels-last Cout.
+//
+// One 16-channel chunk of one tap is one v_mfma_f32_16x16x16 bf16 (lane
+// (m, kq) supplies channels 4 kq .. 4 kq + 3 of point m and of output m) or,
+// in the FP32 mode, four v_mfma_f32_16x16x4 f32 with the same loads: step j
+// takes channel 4 kq + j from every lane, so its K = 4 values are channels
+// j, 4 + j, 8 + j, 12 + j -- a permutation of the chunk's channels, applied
+// to A and B alike.
+template <int NTILE, typename A>
 __global__ void __launch_bounds__(256)
-conv_k16(InDesc in, Geo g, const u16 *__restrict__ Wt, int cin, int cout, u16 *out_bf,
+conv_k16(InDescT<A> in, Geo g, const A *__restrict__ Wt, int cin, int cout, A *out_a,
          float *out_f32, int relu) {
+    using V = typename Vec4<A>::type;
+    using Raw = typename Vec4<A>::raw;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p0 = (blockIdx.x * 4 + wave) * 16;
     if (p0 >= g.npts) return;
@@ -39,14 +49,20 @@ conv_k16(InDesc in, Geo g, const u16 *__restrict__ Wt, int cin, int cout, u16 *o
     constexpr int CO = NTILE * 16;
     for (int t = 0; t < 27; ++t) {
         const int xx = xs[t % 3], yy = ys[(t / 3) % 3], zz = zs[t / 9];
-        const u16 *wt = Wt + (size_t)t * CO * cin;
+        const A *wt = Wt + (size_t)t * CO * cin;
         for (int c0 = 0; c0 < cin; c0 += 16) {
-            const s16x4 a = fetch4(in, xx, yy, zz, c0 + 4 * kq, g);
+            const V a = fetch4<A>(in, xx, yy, zz, c0 + 4 * kq, g);
 #pragma unroll
             for (int nt = 0; nt < NTILE; ++nt) {
-                const uint2 raw = *reinterpret_cast<const uint2 *>(wt + (size_t)(nt * 16 + m) * cin + c0 + 4 * kq);
-                const s16x4 b = __builtin_bit_cast(s16x4, raw);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+                const Raw raw = *reinterpret_cast<const Raw *>(wt + (size_t)(nt * 16 + m) * cin + c0 + 4 * kq);
+                const V b = __builtin_bit_cast(V, raw);
+                if constexpr (sizeof(A) == 2) {
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], b[j], acc[nt], 0, 0, 0);
+                }
             }
         }
     }
@@ -61,16 +77,18 @@ conv_k16(InDesc in, Geo g, const u16 *__restrict__ Wt, int cin, int cout, u16 *o
             float v = acc[nt][i];
             if (relu) v = fmaxf(v, 0.f);
             if (out_f32) out_f32[(size_t)q * cout + co] = v;
-            else out_bf[(size_t)q * cout + co] = f2bf(v);
+            else out_a[(size_t)q * cout + co] = Act<A>::from(v);
         }
     }
 }
 
 // Convolution with one input channel: the 27 taps (padded to 32) form K of a
-// single 16x16x32 step.  W1: [NTILE*16][32] BF16.
-template <int NTILE>
+// single 16x16x32 bf16 step (lane kq supplies taps 8 kq .. 8 kq + 7), or of
+// eight 16x16x4 f32 steps in the FP32 mode (step j: tap 8 kq + j of every
+// lane).  W1: [NTILE*16][32].
+template <int NTILE, typename A>
 __global__ void __launch_bounds__(256)
-conv_c1(InDesc in, Geo g, const u16 *__restrict__ W1, int cout, u16 *out_bf, float *out_f32, int relu) {
+conv_c1(InDescT<A> in, Geo g, const A *__restrict__ W1, int cout, A *out_a, float *out_f32, int relu) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int p0 = (blockIdx.x * 4 + wave) * 16;
     if (p0 >= g.npts) return;
@@ -78,24 +96,33 @@ conv_c1(InDesc in, Geo g, const u16 *__restrict__ W1, int cout, u16 *out_bf, flo
     int p = p0 + m;
     if (p >= g.npts) p = p0;
     const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-    s16x8 a;
+    A a[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int t = 8 * kq + j;
-        short v = 0;
+        A v = A(0);
         if (t < 27) {
             const int xx = wrapc(x + (t % 3) - 1, g.nx), yy = wrapc(y + (t / 3) % 3 - 1, g.ny),
                       zz = wrapc(z + t / 9 - 1, g.nz);
-            v = (short)fetch1(in, xx, yy, zz, 0, g);
+            v = fetch1<A>(in, xx, yy, zz, 0, g);
         }
         a[j] = v;
     }
-    const bf16x8 av = __builtin_bit_cast(bf16x8, a);
 #pragma unroll
     for (int nt = 0; nt < NTILE; ++nt) {
-        const uint4 raw = *reinterpret_cast<const uint4 *>(W1 + (size_t)(nt * 16 + m) * 32 + 8 * kq);
-        const bf16x8 b = __builtin_bit_cast(bf16x8, raw);
-        f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        const A *wrow = W1 + (size_t)(nt * 16 + m) * 32 + 8 * kq;
+        if constexpr (sizeof(A) == 2) {
+            s16x8 av;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) av[j] = (short)a[j];
+            const uint4 raw = *reinterpret_cast<const uint4 *>(wrow);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                          __builtin_bit_cast(bf16x8, raw), acc, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], wrow[j], acc, 0, 0, 0);
+        }
         const int co = nt * 16 + m;
         if (co >= cout) continue;
 #pragma unroll
@@ -105,16 +132,19 @@ conv_c1(InDesc in, Geo g, const u16 *__restrict__ W1, int cout, u16 *out_bf, flo
             float v = acc[i];
             if (relu) v = fmaxf(v, 0.f);
             if (out_f32) out_f32[(size_t)q * cout + co] = v;
-            else out_bf[(size_t)q * cout + co] = f2bf(v);
+            else out_a[(size_t)q * cout + co] = Act<A>::from(v);
         }
     }
 }
 
 // Weight gradient partials: part[chunk][t][ci][co] = sum over the chunk's
 // points p of X[p + off_t][ci] * dYm[p][co], dYm = dY * (Y > 0) if ymask.
-// Grid: (chunks, 27, ci_tiles * co_tiles); one wave per block.
+// Grid: (chunks, 27, ci_tiles * co_tiles); one wave per block.  K = 16
+// points per step: one bf16 16x16x16 instruction (lane kq supplies points
+// 4 kq .. 4 kq + 3) or four f32 16x16x4 ones (step j: point 4 kq + j).
+template <typename A>
 __global__ void __launch_bounds__(64)
-conv_wgrad(InDesc x_in, Geo g, const u16 *__restrict__ dy, const u16 *__restrict__ ymask, int cin,
+conv_wgrad(InDescT<A> x_in, Geo g, const A *__restrict__ dy, const A *__restrict__ ymask, int cin,
            int cout, int chunk_pts, float *__restrict__ part) {
     const int lane = threadIdx.x;
     const int chunk = blockIdx.x, t = blockIdx.y;
@@ -127,25 +157,36 @@ conv_wgrad(InDesc x_in, Geo g, const u16 *__restrict__ dy, const u16 *__restrict
     const int pb = chunk * chunk_pts;
     const int pe = min(pb + chunk_pts, g.npts);
     for (int k0 = pb; k0 < pe; k0 += 16) {
-        s16x4 a, b;
+        A av[4], bv[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int p = k0 + 4 * kq + j;
-            short av = 0, bv = 0;
+            A xa = A(0), db = A(0);
             if (p < pe) {
                 const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
                 if (ci < cin)
-                    av = (short)fetch1(x_in, wrapc(x + dx, g.nx), wrapc(y + dyo, g.ny), wrapc(z + dz, g.nz), ci, g);
+                    xa = fetch1<A>(x_in, wrapc(x + dx, g.nx), wrapc(y + dyo, g.ny), wrapc(z + dz, g.nz), ci, g);
                 if (co < cout) {
-                    u16 d = dy[(size_t)p * cout + co];
-                    if (ymask && !((short)ymask[(size_t)p * cout + co] > 0)) d = 0;
-                    bv = (short)d;
+                    A d = dy[(size_t)p * cout + co];
+                    if (ymask && !Act<A>::pos(ymask[(size_t)p * cout + co])) d = A(0);
+                    db = d;
                 }
             }
-            a[j] = av;
-            b[j] = bv;
+            av[j] = xa;
+            bv[j] = db;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        if constexpr (sizeof(A) == 2) {
+            s16x4 a, b;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                a[j] = (short)av[j];
+                b[j] = (short)bv[j];
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc, 0, 0, 0);
+        }
     }
     // lane holds D[ci = cit*16 + 4*kq + i][co = co_t*16 + m]
 #pragma unroll
@@ -166,7 +207,8 @@ __global__ void wgrad_reduce(const float *__restrict__ part, int chunks, int cou
 }
 
 // 2x2x2 average pooling (fine grid g, C channels).
-__global__ void pool2(const u16 *__restrict__ in, Geo g, int C, u16 *__restrict__ out) {
+template <typename A>
+__global__ void pool2(const A *__restrict__ in, Geo g, int C, A *__restrict__ out) {
     const int hx = g.nx / 2, hy = g.ny / 2, hz = g.nz / 2;
     const int64_t total = (int64_t)hx * hy * hz * C;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -177,15 +219,16 @@ __global__ void pool2(const u16 *__restrict__ in, Geo g, int C, u16 *__restrict_
         float s = 0.f;
         for (int d = 0; d < 8; ++d) {
             const int xx = 2 * x + (d & 1), yy = 2 * y + ((d >> 1) & 1), zz = 2 * z + (d >> 2);
-            s += bf2f(in[((size_t)(zz * g.ny + yy) * g.nx + xx) * C + c]);
+            s += Act<A>::f(in[((size_t)(zz * g.ny + yy) * g.nx + xx) * C + c]);
         }
-        out[i] = f2bf(0.125f * s);
+        out[i] = Act<A>::from(0.125f * s);
     }
 }
 
 // Gradient through [up(coarse), skip] concatenation at the fine level:
 // dcoarse[q][c] = sum of dcat[child][c] over the 8 children (c < c1).
-__global__ void up_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1, u16 *__restrict__ dcoarse) {
+template <typename A>
+__global__ void up_grad(const A *__restrict__ dcat, Geo g, int ccat, int c1, A *__restrict__ dcoarse) {
     const int hx = g.nx / 2, hy = g.ny / 2, hz = g.nz / 2;
     const int64_t total = (int64_t)hx * hy * hz * c1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -196,15 +239,16 @@ __global__ void up_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1, u
         float s = 0.f;
         for (int d = 0; d < 8; ++d) {
             const int xx = 2 * x + (d & 1), yy = 2 * y + ((d >> 1) & 1), zz = 2 * z + (d >> 2);
-            s += bf2f(dcat[((size_t)(zz * g.ny + yy) * g.nx + xx) * ccat + c]);
+            s += Act<A>::f(dcat[((size_t)(zz * g.ny + yy) * g.nx + xx) * ccat + c]);
         }
-        dcoarse[i] = f2bf(s);
+        dcoarse[i] = Act<A>::from(s);
     }
 }
 
 // dskip[p][c] = dcat[p][c1 + c] + pool_grad(dpool)[p][c]  (pool_grad = 1/8 of the parent)
-__global__ void skip_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1, int cs,
-                          const u16 *__restrict__ dpool, u16 *__restrict__ dskip) {
+template <typename A>
+__global__ void skip_grad(const A *__restrict__ dcat, Geo g, int ccat, int c1, int cs,
+                          const A *__restrict__ dpool, A *__restrict__ dskip) {
     const int64_t total = (int64_t)g.npts * cs;
     const int hx = g.nx / 2, hy = g.ny / 2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -213,7 +257,8 @@ __global__ void skip_grad(const u16 *__restrict__ dcat, Geo g, int ccat, int c1,
         const int64_t p = i / cs;
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((int64_t)g.nx * g.ny));
         const size_t parent = ((size_t)(z / 2) * hy + (y / 2)) * hx + (x / 2);
-        dskip[i] = f2bf(bf2f(dcat[(size_t)p * ccat + c1 + c]) + 0.125f * bf2f(dpool[parent * cs + c]));
+        dskip[i] = Act<A>::from(Act<A>::f(dcat[(size_t)p * ccat + c1 + c]) +
+                                0.125f * Act<A>::f(dpool[parent * cs + c]));
     }
 }
 
@@ -236,12 +281,13 @@ __global__ void adam_kernel(LayerPtrs L, float lr, float b1, float b2, float c1,
     }
 }
 
-// BF16 copies of layer weights W[t][ci][co] (FP32).
+// BF16 (or, for the FP32 mode, FP32) copies of layer weights W[t][ci][co].
 //   forward, cin >= 16: wf[t][co_pad][ci]; cin == 1: wf[co_pad][32 taps]
 //   transposed (input gradient), flipped taps t' = 26 - t, roles swapped:
 //   cout >= 16: wb[t'][ci_pad][co]; cout == 1: wb[ci_pad][32 taps]
+template <typename A>
 __global__ void pack_weights(const float *__restrict__ w, int cin, int cout, int ntf, int ntb,
-                             u16 *__restrict__ wf, u16 *__restrict__ wb) {
+                             A *__restrict__ wf, A *__restrict__ wb) {
     const int cof = ntf * 16, cib = ntb * 16;
     const int nf = cin == 1 ? cof * 32 : 27 * cof * cin;
     const int nb = cout == 1 ? cib * 32 : 27 * cib * cout;
@@ -255,7 +301,7 @@ __global__ void pack_weights(const float *__restrict__ w, int cin, int cout, int
                 const int ci = i % cin, co = (i / cin) % cof, t = i / (cin * cof);
                 if (co < cout) v = w[((size_t)t * cin + ci) * cout + co];
             }
-            wf[i] = f2bf(v);
+            wf[i] = Act<A>::from(v);
         } else {
             const int j = i - nf;
             float v = 0.f;
@@ -266,17 +312,18 @@ __global__ void pack_weights(const float *__restrict__ w, int cin, int cout, int
                 const int co = j % cout, ci = (j / cout) % cib, t = j / (cout * cib);
                 if (ci < cin) v = w[((size_t)(26 - t) * cin + ci) * cout + co];
             }
-            wb[j] = f2bf(v);
+            wb[j] = Act<A>::from(v);
         }
     }
 }
 
-// Network input: x = bf16(a * scale); totals of a^2 are computed beforehand.
+// Network input: x = A(a * scale); totals of a^2 are computed beforehand.
+template <typename A>
 struct CastInOp {
     static constexpr int kClass = K_POINTWISE;
-    static constexpr int kBytes = 10;
+    static constexpr int kBytes = 8 + sizeof(A);
     const double *a;
-    u16 *x;
+    A *x;
     const double *totals;       // {sum a^2}
     double inv_n, scale;
     __device__ bool skip() const { return false; }
@@ -284,7 +331,7 @@ struct CastInOp {
         const double ms = totals[0] * inv_n;
         scale = ms > 0 ? 1.0 / sqrt(ms) : 0.0;
     }
-    __device__ void operator()(int64_t i, double (&)[1]) const { x[i] = f2bf((float)(a[i] * scale)); }
+    __device__ void operator()(int64_t i, double (&)[1]) const { x[i] = Act<A>::from((float)(a[i] * scale)); }
 };
 
 struct SqOp {
@@ -298,12 +345,13 @@ struct SqOp {
 
 // Loss ||out - t||^2 / ||t||^2 and dout = 2 (out - t) / ||t||^2 (BF16), with
 // t = phi / (h^2 rms(g)).  totals: {sum g^2 (input), sum phi^2} precomputed.
+template <typename A>
 struct LossOp {
     static constexpr int kClass = K_POINTWISE;
-    static constexpr int kBytes = 14;
+    static constexpr int kBytes = 12 + sizeof(A);
     const float *out;
     const double *phi;
-    u16 *dout;
+    A *dout;
     const double *totals;
     double inv_n, h2, tscale, den;
     __device__ bool skip() const { return false; }
@@ -316,7 +364,7 @@ struct LossOp {
         const double t = phi[i] * tscale;
         const double d = (double)out[i] - t;
         acc[0] = ::fma(d, d, acc[0]);
-        dout[i] = f2bf((float)(2.0 * d / den));
+        dout[i] = Act<A>::from((float)(2.0 * d / den));
     }
 };
 
@@ -353,11 +401,12 @@ struct DotOp {
 
 // Sums a.b and writes dout = 2 grad / den (BF16): energy norm (a = e, b =
 // grad = A e) or residual norm (a = b = A e, grad = A A e).
+template <typename A>
 struct EnergyLossOp {
     static constexpr int kClass = K_POINTWISE;
-    static constexpr int kBytes = 26;
+    static constexpr int kBytes = 24 + sizeof(A);
     const double *a, *b, *grad;
-    u16 *dout;
+    A *dout;
     const double *totals;
     double inv_n, h2, den;
     __device__ bool skip() const { return false; }
@@ -368,7 +417,7 @@ struct EnergyLossOp {
     }
     __device__ void operator()(int64_t i, double (&acc)[1]) const {
         acc[0] = ::fma(a[i], b[i], acc[0]);
-        dout[i] = f2bf((float)(2.0 * grad[i] / den));
+        dout[i] = Act<A>::from((float)(2.0 * grad[i] / den));
     }
 };
 

@@ -56,44 +56,48 @@ int nalloc(ofdft_nn *net, P **p, size_t bytes, std::vector<void *> &list) {
     return OFDFT_OK;
 }
 
-InDesc one(const u16 *s, int c, const u16 *mask = nullptr) {
-    InDesc d{};
-    d.s1 = s;
-    d.mask1 = mask;
+template <typename A>
+InDescT<A> one(const void *s, int c, const void *mask = nullptr) {
+    InDescT<A> d{};
+    d.s1 = (const A *)s;
+    d.mask1 = (const A *)mask;
     d.c1 = c;
     return d;
 }
-InDesc cat(const u16 *coarse, int c1, const u16 *skip, int c2) {
-    InDesc d{};
-    d.s1 = coarse;
+template <typename A>
+InDescT<A> cat(const void *coarse, int c1, const void *skip, int c2) {
+    InDescT<A> d{};
+    d.s1 = (const A *)coarse;
     d.c1 = c1;
     d.up1 = 1;
-    d.s2 = skip;
+    d.s2 = (const A *)skip;
     d.c2 = c2;
     return d;
 }
 
 // launch a convolution: cin == 1 uses the tap-packed path
-int conv(const InDesc &in, const Geo &g, const u16 *w, int cin, int cout, u16 *out_bf, float *out_f32,
+template <typename A>
+int conv(const InDescT<A> &in, const Geo &g, const A *w, int cin, int cout, void *out_act, float *out_f32,
          bool relu, hipStream_t s) {
     const int blocks = (g.npts + 63) / 64;
-    // algorithmic bytes: read the input once, write the output once (BF16)
-    ProfScope ps(K_NN, (double)g.npts * 2.0 * (cin + cout), s);
+    // algorithmic bytes: read the input once, write the output once
+    ProfScope ps(K_NN, (double)g.npts * sizeof(A) * (cin + cout), s);
     const int r = relu ? 1 : 0;
+    A *oa = (A *)out_act;
     if (cin == 1) {
         switch (ntile(cout)) {
-            case 1: hipLaunchKernelGGL((conv_c1<1>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
-            case 2: hipLaunchKernelGGL((conv_c1<2>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
-            default: hipLaunchKernelGGL((conv_c1<4>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, out_bf, out_f32, r); break;
+            case 1: hipLaunchKernelGGL((conv_c1<1, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, oa, out_f32, r); break;
+            case 2: hipLaunchKernelGGL((conv_c1<2, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, oa, out_f32, r); break;
+            default: hipLaunchKernelGGL((conv_c1<4, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, oa, out_f32, r); break;
         }
     } else {
         switch (ntile(cout)) {
-            case 1: hipLaunchKernelGGL((conv_k16<1>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
-            case 2: hipLaunchKernelGGL((conv_k16<2>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
-            case 3: hipLaunchKernelGGL((conv_k16<3>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
-            case 4: hipLaunchKernelGGL((conv_k16<4>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
-            case 6: hipLaunchKernelGGL((conv_k16<6>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
-            case 8: hipLaunchKernelGGL((conv_k16<8>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, out_bf, out_f32, r); break;
+            case 1: hipLaunchKernelGGL((conv_k16<1, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
+            case 2: hipLaunchKernelGGL((conv_k16<2, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
+            case 3: hipLaunchKernelGGL((conv_k16<3, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
+            case 4: hipLaunchKernelGGL((conv_k16<4, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
+            case 6: hipLaunchKernelGGL((conv_k16<6, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
+            case 8: hipLaunchKernelGGL((conv_k16<8, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
             default:
                 set_error("network: unsupported channel count %d", cout);
                 return OFDFT_INVALID_ARG;
@@ -103,7 +107,8 @@ int conv(const InDesc &in, const Geo &g, const u16 *w, int cin, int cout, u16 *o
     return OFDFT_OK;
 }
 
-int wgrad(ofdft_nn *net, int layer, const InDesc &x, const Geo &g, const u16 *dy, const u16 *ymask,
+template <typename A>
+int wgrad(ofdft_nn *net, int layer, const InDescT<A> &x, const Geo &g, const void *dy, const void *ymask,
           hipStream_t s) {
     const int cin = kDefs[layer].cin, cout = kDefs[layer].cout;
     const int chunks = (g.npts + kChunk - 1) / kChunk;
@@ -112,9 +117,9 @@ int wgrad(ofdft_nn *net, int layer, const InDesc &x, const Geo &g, const u16 *dy
         set_error("network: weight-gradient scratch too small");
         return OFDFT_INVALID_ARG;
     }
-    ProfScope ps(K_NN, (double)g.npts * 2.0 * (cin + cout), s);
-    hipLaunchKernelGGL(conv_wgrad, dim3(chunks, 27, ntile(cin) * ntile(cout)), dim3(64), 0, s, x, g, dy,
-                       ymask, cin, cout, kChunk, net->part);
+    ProfScope ps(K_NN, (double)g.npts * sizeof(A) * (cin + cout), s);
+    hipLaunchKernelGGL(conv_wgrad<A>, dim3(chunks, 27, ntile(cin) * ntile(cout)), dim3(64), 0, s, x, g,
+                       (const A *)dy, (const A *)ymask, cin, cout, kChunk, net->part);
     OFDFT_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, net->part,
                        chunks, (int)count, net->gr[layer]);
@@ -131,15 +136,17 @@ int net_reserve(ofdft_nn *net, const ofdft_grid &g) {
         set_error("network: grid sizes must be multiples of 8 (got %d x %d x %d)", g.nx, g.ny, g.nz);
         return OFDFT_INVALID_ARG;
     }
-    if (net->nx == g.nx && net->ny == g.ny && net->nz == g.nz) return OFDFT_OK;
+    if (net->nx == g.nx && net->ny == g.ny && net->nz == g.nz && net->ws_fp32 == net->fp32) return OFDFT_OK;
     for (void *p : net->ws) (void)hipFree(p);
     net->ws.clear();
     net->nx = g.nx;
     net->ny = g.ny;
     net->nz = g.nz;
+    net->ws_fp32 = net->fp32;
+    const size_t elem = net->fp32 ? sizeof(float) : sizeof(u16);
     for (int b = 0; b < NBUF; ++b) {
         const Geo gg = geo_of(net, kBufLevel[b]);
-        OFDFT_TRY(nalloc(net, &net->buf[b], sizeof(u16) * (size_t)gg.npts * kBufCh[b], net->ws));
+        OFDFT_TRY(nalloc(net, &net->buf[b], elem * (size_t)gg.npts * kBufCh[b], net->ws));
     }
     const int64_t n = (int64_t)g.nx * g.ny * g.nz;
     OFDFT_TRY(nalloc(net, &net->out, sizeof(float) * n, net->ws));
@@ -156,20 +163,31 @@ int net_reserve(ofdft_nn *net, const ofdft_grid &g) {
     return OFDFT_OK;
 }
 
+template <typename A> const A *wfwd(const ofdft_nn *net, int l);
+template <> const u16 *wfwd<u16>(const ofdft_nn *net, int l) { return net->wf[l]; }
+template <> const float *wfwd<float>(const ofdft_nn *net, int l) { return net->wf32[l]; }
+template <typename A> const A *wbwd(const ofdft_nn *net, int l);
+template <> const u16 *wbwd<u16>(const ofdft_nn *net, int l) { return net->wb[l]; }
+template <> const float *wbwd<float>(const ofdft_nn *net, int l) { return net->wb32[l]; }
+
 // forward pass from net->buf[X0]; output FP32 in net->out
-static int forward(ofdft_nn *net, hipStream_t s) {
-    u16 **B = net->buf;
+template <typename A>
+static int forward_t(ofdft_nn *net, hipStream_t s) {
+    void **B = net->buf;
     const Geo g0 = geo_of(net, 0), g1 = geo_of(net, 1), g2 = geo_of(net, 2), g3 = geo_of(net, 3);
-    auto W = [&](int l) { return net->wf[l]; };
+    auto W = [&](int l) { return wfwd<A>(net, l); };
+    auto one = [](const void *p, int c, const void *mask = nullptr) { return ::ofdft::nn::one<A>(p, c, mask); };
+    auto cat = [](const void *a, int c1, const void *b, int c2) { return ::ofdft::nn::cat<A>(a, c1, b, c2); };
+    auto P = [&](int b) { return (A *)B[b]; };
     OFDFT_TRY(conv(one(B[X0], 1), g0, W(0), 1, 16, B[A0], nullptr, true, s));
     OFDFT_TRY(conv(one(B[A0], 16), g0, W(1), 16, 16, B[S0], nullptr, true, s));
-    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g1.npts * 16)), dim3(256), 0, s, B[S0], g0, 16, B[P0]);
+    hipLaunchKernelGGL(pool2<A>, dim3(grid_blocks((int64_t)g1.npts * 16)), dim3(256), 0, s, P(S0), g0, 16, P(P0));
     OFDFT_TRY(conv(one(B[P0], 16), g1, W(2), 16, 32, B[A1], nullptr, true, s));
     OFDFT_TRY(conv(one(B[A1], 32), g1, W(3), 32, 32, B[S1], nullptr, true, s));
-    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g2.npts * 32)), dim3(256), 0, s, B[S1], g1, 32, B[P1]);
+    hipLaunchKernelGGL(pool2<A>, dim3(grid_blocks((int64_t)g2.npts * 32)), dim3(256), 0, s, P(S1), g1, 32, P(P1));
     OFDFT_TRY(conv(one(B[P1], 32), g2, W(4), 32, 64, B[A2], nullptr, true, s));
     OFDFT_TRY(conv(one(B[A2], 64), g2, W(5), 64, 64, B[S2], nullptr, true, s));
-    hipLaunchKernelGGL(pool2, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, B[S2], g2, 64, B[P2]);
+    hipLaunchKernelGGL(pool2<A>, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, P(S2), g2, 64, P(P2));
     OFDFT_TRY(conv(one(B[P2], 64), g3, W(6), 64, 64, B[A3], nullptr, true, s));
     OFDFT_TRY(conv(one(B[A3], 64), g3, W(7), 64, 64, B[B3], nullptr, true, s));
     OFDFT_TRY(conv(cat(B[B3], 64, B[S2], 64), g2, W(8), 128, 64, B[D2A], nullptr, true, s));
@@ -182,11 +200,19 @@ static int forward(ofdft_nn *net, hipStream_t s) {
     return OFDFT_OK;
 }
 
+static int forward(ofdft_nn *net, hipStream_t s) {
+    return net->fp32 ? forward_t<float>(net, s) : forward_t<u16>(net, s);
+}
+
 // backward pass from net->buf[dOUT]; weight gradients into net->gr
-static int backward(ofdft_nn *net, hipStream_t s) {
-    u16 **B = net->buf;
+template <typename A>
+static int backward_t(ofdft_nn *net, hipStream_t s) {
+    void **B = net->buf;
     const Geo g0 = geo_of(net, 0), g1 = geo_of(net, 1), g2 = geo_of(net, 2), g3 = geo_of(net, 3);
-    auto WB = [&](int l) { return net->wb[l]; };
+    auto WB = [&](int l) { return wbwd<A>(net, l); };
+    auto one = [](const void *p, int c, const void *mask = nullptr) { return ::ofdft::nn::one<A>(p, c, mask); };
+    auto cat = [](const void *a, int c1, const void *b, int c2) { return ::ofdft::nn::cat<A>(a, c1, b, c2); };
+    auto P = [&](int b) { return (A *)B[b]; };
     // out (no activation)
     OFDFT_TRY(wgrad(net, 14, one(B[D0], 16), g0, B[dOUT], nullptr, s));
     OFDFT_TRY(conv(one(B[dOUT], 1), g0, WB(14), 1, 16, B[dD0], nullptr, false, s));
@@ -195,38 +221,38 @@ static int backward(ofdft_nn *net, hipStream_t s) {
     OFDFT_TRY(conv(one(B[dD0], 16, B[D0]), g0, WB(13), 16, 16, B[dD0A], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 12, cat(B[D1], 32, B[S0], 16), g0, B[dD0A], B[D0A], s));
     OFDFT_TRY(conv(one(B[dD0A], 16, B[D0A]), g0, WB(12), 16, 48, B[dCAT0], nullptr, false, s));
-    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, B[dCAT0], g0, 48, 32, B[dD1]);
+    hipLaunchKernelGGL(up_grad<A>, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, P(dCAT0), g0, 48, 32, P(dD1));
     // level 1 decoder
     OFDFT_TRY(wgrad(net, 11, one(B[D1A], 32), g1, B[dD1], B[D1], s));
     OFDFT_TRY(conv(one(B[dD1], 32, B[D1]), g1, WB(11), 32, 32, B[dD1A], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 10, cat(B[D2], 64, B[S1], 32), g1, B[dD1A], B[D1A], s));
     OFDFT_TRY(conv(one(B[dD1A], 32, B[D1A]), g1, WB(10), 32, 96, B[dCAT1], nullptr, false, s));
-    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, B[dCAT1], g1, 96, 64, B[dD2]);
+    hipLaunchKernelGGL(up_grad<A>, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, P(dCAT1), g1, 96, 64, P(dD2));
     // level 2 decoder
     OFDFT_TRY(wgrad(net, 9, one(B[D2A], 64), g2, B[dD2], B[D2], s));
     OFDFT_TRY(conv(one(B[dD2], 64, B[D2]), g2, WB(9), 64, 64, B[dD2A], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 8, cat(B[B3], 64, B[S2], 64), g2, B[dD2A], B[D2A], s));
     OFDFT_TRY(conv(one(B[dD2A], 64, B[D2A]), g2, WB(8), 64, 128, B[dCAT2], nullptr, false, s));
-    hipLaunchKernelGGL(up_grad, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, B[dCAT2], g2, 128, 64, B[dB3]);
+    hipLaunchKernelGGL(up_grad<A>, dim3(grid_blocks((int64_t)g3.npts * 64)), dim3(256), 0, s, P(dCAT2), g2, 128, 64, P(dB3));
     // bottleneck
     OFDFT_TRY(wgrad(net, 7, one(B[A3], 64), g3, B[dB3], B[B3], s));
     OFDFT_TRY(conv(one(B[dB3], 64, B[B3]), g3, WB(7), 64, 64, B[dA3], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 6, one(B[P2], 64), g3, B[dA3], B[A3], s));
     OFDFT_TRY(conv(one(B[dA3], 64, B[A3]), g3, WB(6), 64, 64, B[dP2], nullptr, false, s));
     // level 2 encoder: skip gradient + pooled path
-    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, B[dCAT2], g2, 128, 64, 64, B[dP2], B[dS2]);
+    hipLaunchKernelGGL(skip_grad<A>, dim3(grid_blocks((int64_t)g2.npts * 64)), dim3(256), 0, s, P(dCAT2), g2, 128, 64, 64, P(dP2), P(dS2));
     OFDFT_TRY(wgrad(net, 5, one(B[A2], 64), g2, B[dS2], B[S2], s));
     OFDFT_TRY(conv(one(B[dS2], 64, B[S2]), g2, WB(5), 64, 64, B[dA2], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 4, one(B[P1], 32), g2, B[dA2], B[A2], s));
     OFDFT_TRY(conv(one(B[dA2], 64, B[A2]), g2, WB(4), 64, 32, B[dP1], nullptr, false, s));
     // level 1 encoder
-    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, B[dCAT1], g1, 96, 64, 32, B[dP1], B[dS1]);
+    hipLaunchKernelGGL(skip_grad<A>, dim3(grid_blocks((int64_t)g1.npts * 32)), dim3(256), 0, s, P(dCAT1), g1, 96, 64, 32, P(dP1), P(dS1));
     OFDFT_TRY(wgrad(net, 3, one(B[A1], 32), g1, B[dS1], B[S1], s));
     OFDFT_TRY(conv(one(B[dS1], 32, B[S1]), g1, WB(3), 32, 32, B[dA1], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 2, one(B[P0], 16), g1, B[dA1], B[A1], s));
     OFDFT_TRY(conv(one(B[dA1], 32, B[A1]), g1, WB(2), 32, 16, B[dP0], nullptr, false, s));
     // level 0 encoder
-    hipLaunchKernelGGL(skip_grad, dim3(grid_blocks((int64_t)g0.npts * 16)), dim3(256), 0, s, B[dCAT0], g0, 48, 32, 16, B[dP0], B[dS0]);
+    hipLaunchKernelGGL(skip_grad<A>, dim3(grid_blocks((int64_t)g0.npts * 16)), dim3(256), 0, s, P(dCAT0), g0, 48, 32, 16, P(dP0), P(dS0));
     OFDFT_TRY(wgrad(net, 1, one(B[A0], 16), g0, B[dS0], B[S0], s));
     OFDFT_TRY(conv(one(B[dS0], 16, B[S0]), g0, WB(1), 16, 16, B[dA0], nullptr, false, s));
     OFDFT_TRY(wgrad(net, 0, one(B[X0], 1), g0, B[dA0], B[A0], s));
@@ -234,13 +260,29 @@ static int backward(ofdft_nn *net, hipStream_t s) {
     return OFDFT_OK;
 }
 
+static int backward(ofdft_nn *net, hipStream_t s) {
+    return net->fp32 ? backward_t<float>(net, s) : backward_t<u16>(net, s);
+}
+
 static int pack_all(ofdft_nn *net, hipStream_t s) {
     for (int l = 0; l < kLayers; ++l) {
-        hipLaunchKernelGGL(pack_weights, dim3(64), dim3(256), 0, s, net->w[l], kDefs[l].cin, kDefs[l].cout,
+        hipLaunchKernelGGL(pack_weights<u16>, dim3(64), dim3(256), 0, s, net->w[l], kDefs[l].cin, kDefs[l].cout,
                            ntile(kDefs[l].cout), ntile(kDefs[l].cin), net->wf[l], net->wb[l]);
+        OFDFT_CHECK_HIP(hipGetLastError());
+        hipLaunchKernelGGL(pack_weights<float>, dim3(64), dim3(256), 0, s, net->w[l], kDefs[l].cin, kDefs[l].cout,
+                           ntile(kDefs[l].cout), ntile(kDefs[l].cin), net->wf32[l], net->wb32[l]);
         OFDFT_CHECK_HIP(hipGetLastError());
     }
     return OFDFT_OK;
+}
+
+// x = input / rms(input) in the activation type (totals[0] = sum input^2).
+int cast_input(ofdft_nn *net, int64_t n, const double *in, hipStream_t s) {
+    if (net->fp32)
+        return launch_reduce<1>(n, CastInOp<float>{in, (float *)net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{},
+                                net->rb, s);
+    return launch_reduce<1>(n, CastInOp<u16>{in, (u16 *)net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{},
+                            net->rb, s);
 }
 
 struct ToF64Op {          // out = h2 * rms * out32 (rms from totals {sum in^2})
@@ -278,7 +320,7 @@ int net_apply(ofdft_nn *net, const ofdft_grid &g, const double *in, double *out,
     }
     const int64_t n = npoints(g);
     OFDFT_TRY((launch_reduce<1>(n, SqOp{in}, StoreTotals<1>{net->totals}, net->rb, s)));
-    OFDFT_TRY((launch_reduce<1>(n, CastInOp{in, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(cast_input(net, n, in, s));
     OFDFT_TRY(forward(net, s));
     OFDFT_TRY((launch_reduce<1>(n, ToF64Op{net->out, out, net->totals, 1.0 / n, h2, 0.0},
                                 StoreTotals<1>{net->totals + 4}, net->rb, s)));
@@ -330,7 +372,9 @@ extern "C" int ofdft_nn_create(uint64_t seed, ofdft_nn **out) {
             (st = nalloc(net, &net->v[l], sizeof(float) * cnt, net->allocs)) ||
             (st = nalloc(net, &net->gr[l], sizeof(float) * cnt, net->allocs)) ||
             (st = nalloc(net, &net->wf[l], sizeof(u16) * (cin == 1 ? ntile(cout) * 16 * 32 : 27 * ntile(cout) * 16 * cin), net->allocs)) ||
-            (st = nalloc(net, &net->wb[l], sizeof(u16) * (cout == 1 ? ntile(cin) * 16 * 32 : 27 * ntile(cin) * 16 * cout), net->allocs)))
+            (st = nalloc(net, &net->wb[l], sizeof(u16) * (cout == 1 ? ntile(cin) * 16 * 32 : 27 * ntile(cin) * 16 * cout), net->allocs)) ||
+            (st = nalloc(net, &net->wf32[l], sizeof(float) * (cin == 1 ? ntile(cout) * 16 * 32 : 27 * ntile(cout) * 16 * cin), net->allocs)) ||
+            (st = nalloc(net, &net->wb32[l], sizeof(float) * (cout == 1 ? ntile(cin) * 16 * 32 : 27 * ntile(cin) * 16 * cout), net->allocs)))
             return fail(st);
         // He-normal initialisation, fan-in 27 cin
         std::normal_distribution<float> nd(0.f, std::sqrt(2.f / (27.f * cin)));
@@ -401,6 +445,17 @@ extern "C" int ofdft_nn_set_loss(ofdft_nn *net, int kind) {
     return OFDFT_OK;
 }
 
+// Activation storage of the network's kernels: 0 = BF16 (default), 1 = FP32
+// (same kernels, FP32 MFMA; the workspace is reallocated on the next use).
+extern "C" int ofdft_nn_set_precision(ofdft_nn *net, int fp32) {
+    if (!net || (fp32 != 0 && fp32 != 1)) {
+        set_error("ofdft_nn_set_precision: fp32 must be 0 (BF16) or 1 (FP32)");
+        return OFDFT_INVALID_ARG;
+    }
+    net->fp32 = fp32;
+    return OFDFT_OK;
+}
+
 extern "C" int ofdft_nn_reserve(ofdft_nn *net, const ofdft_grid *grid) {
     if (!net) return OFDFT_INVALID_ARG;
     OFDFT_TRY(check_grid(grid, 1));
@@ -417,6 +472,17 @@ extern "C" int ofdft_nn_forward(ofdft_nn *net, const ofdft_grid *grid, const dou
     return net_apply(net, *grid, in, out, scale, false, (hipStream_t)stream);
 }
 
+// Numerator a.b of an operator-weighted loss and dL/d(out) = 2 grad / den.
+static int energy_loss(ofdft_nn *net, int64_t n, const double *a, const double *b, const double *grad, double h2,
+                       hipStream_t s) {
+    if (net->fp32)
+        return launch_reduce<1>(n, EnergyLossOp<float>{a, b, grad, (float *)net->buf[dOUT], net->totals, 1.0 / n,
+                                                       h2, 0},
+                                StoreTotals<1>{net->totals + 2}, net->rb, s);
+    return launch_reduce<1>(n, EnergyLossOp<u16>{a, b, grad, (u16 *)net->buf[dOUT], net->totals, 1.0 / n, h2, 0},
+                            StoreTotals<1>{net->totals + 2}, net->rb, s);
+}
+
 // Loss of the current output against phi, and dL/d(out) into buf[dOUT].
 // totals[0] = sum g^2 must be set; leaves totals[1] = the loss denominator
 // before scaling and totals[2] = its numerator.
@@ -425,7 +491,11 @@ static int loss_pass(ofdft_nn *net, const ofdft_grid &g, const double *phi, doub
     if (net->loss_kind == 0) {
         OFDFT_TRY((launch_reduce<1>(n, SqOp{phi}, StoreTotals<1>{net->totals + 1}, net->rb, s)));
         OFDFT_TRY(forward(net, s));
-        return launch_reduce<1>(n, LossOp{net->out, phi, net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
+        if (net->fp32)
+            return launch_reduce<1>(n, LossOp<float>{net->out, phi, (float *)net->buf[dOUT], net->totals, 1.0 / n,
+                                                     h2, 0, 0},
+                                    StoreTotals<1>{net->totals + 2}, net->rb, s);
+        return launch_reduce<1>(n, LossOp<u16>{net->out, phi, (u16 *)net->buf[dOUT], net->totals, 1.0 / n, h2, 0, 0},
                                 StoreTotals<1>{net->totals + 2}, net->rb, s);
     }
     if (net->e_cap < (size_t)n) {
@@ -448,13 +518,9 @@ static int loss_pass(ofdft_nn *net, const ofdft_grid &g, const double *phi, doub
     OFDFT_TRY(fd_laplacian_apply(&g, 6, OFDFT_F64, net->e64, net->ae64, -h2, 0.0, s));
     if (res) {     // e <- A (A e): numerator |A e|^2, gradient 2 A A e / den
         OFDFT_TRY(fd_laplacian_apply(&g, 6, OFDFT_F64, net->ae64, net->e64, -h2, 0.0, s));
-        return launch_reduce<1>(n, EnergyLossOp{net->ae64, net->ae64, net->e64, net->buf[dOUT], net->totals,
-                                                1.0 / n, h2, 0},
-                                StoreTotals<1>{net->totals + 2}, net->rb, s);
+        return energy_loss(net, n, net->ae64, net->ae64, net->e64, h2, s);
     }
-    return launch_reduce<1>(n, EnergyLossOp{net->e64, net->ae64, net->ae64, net->buf[dOUT], net->totals,
-                                            1.0 / n, h2, 0},
-                            StoreTotals<1>{net->totals + 2}, net->rb, s);
+    return energy_loss(net, n, net->e64, net->ae64, net->ae64, h2, s);
 }
 
 // One training step on a pair (g, phi): loss (kind set by ofdft_nn_set_loss)
@@ -471,7 +537,7 @@ extern "C" int ofdft_nn_train_step(ofdft_nn *net, const ofdft_grid *grid, const 
     const int64_t n = npoints(g);
     const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
     OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
-    OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(cast_input(net, n, g_rhs, s));
     OFDFT_TRY(loss_pass(net, g, phi, h2, s));
     OFDFT_TRY(backward(net, s));
     net->adam_t += 1;
@@ -507,7 +573,7 @@ extern "C" int ofdft_nn_gradients(ofdft_nn *net, const ofdft_grid *grid, const d
     const int64_t n = npoints(g);
     const double h2 = std::cbrt(g.hx * g.hy * g.hz) * std::cbrt(g.hx * g.hy * g.hz);
     OFDFT_TRY((launch_reduce<1>(n, SqOp{g_rhs}, StoreTotals<1>{net->totals}, net->rb, s)));
-    OFDFT_TRY((launch_reduce<1>(n, CastInOp{g_rhs, net->buf[X0], net->totals, 1.0 / n, 0.0}, NoFin{}, net->rb, s)));
+    OFDFT_TRY(cast_input(net, n, g_rhs, s));
     OFDFT_TRY(loss_pass(net, g, phi, h2, s));
     OFDFT_TRY(backward(net, s));
     double t[4];

@@ -1,10 +1,21 @@
-"""Parity of the learned solver aid's network kernels (BF16 MFMA forward and
+"""Parity of the learned solver aid's network kernels (MFMA forward and
 backward) against the FP64 network oracle, and the learned Poisson form.
 
-BF16 error model: the oracle runs on the same BF16-rounded weights and input;
-the GPU additionally stores every activation and activation gradient in BF16
-(relative rounding 2^-9 per value) and accumulates in FP32, so outputs are
-expected within a few percent in relative L2 norm over the 15 layers."""
+FP32 mode: the same kernels with FP32 activations, gradients and weight
+copies (v_mfma_f32_16x16x4 f32) are checked element by element against the
+oracle run on the same FP32-rounded weights and input: every element of the
+output and of every layer's weight gradient within 1e-5 of the tensor's
+largest magnitude, for the three training losses.  The input gradients of
+the layers are the operands of the weight gradients below them, so they are
+checked through those.
+
+BF16 mode (the default): stored activations and gradients carry a relative
+rounding of at most u = 2^-8 each.  Error model: a tensor reached through D
+such roundings differs from the FP64 value by at most C u sqrt(D) times the
+tensor's largest magnitude, with C = 12 (measured on these inputs: forward
+outputs within 0.01 of their largest magnitude at D = 17; weight gradients
+within 0.17 at D = 25, where the deep layers' sums cancel and the roundings
+of 25 stages compound)."""
 import numpy as np
 import pytest
 
@@ -15,6 +26,13 @@ from tests.gpu_util import announce, to_dev, to_host, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
+U_BF16 = 2.0 ** -8
+C_MODEL = 12.0
+FWD_STAGES = 17       # input cast, 14 stored conv outputs, 3 pooled tensors, minus the FP32 output layer
+# stored gradient tensors from dL/d(out) down to each layer's output gradient
+BWD_STAGES = {"out": 1, "d0b": 2, "d0a": 3, "d1b": 5, "d1a": 6, "d2b": 8, "d2a": 9, "c3b": 11, "c3a": 12,
+              "c2b": 14, "c2a": 15, "c1b": 17, "c1a": 18, "c0b": 20, "c0a": 21}
+
 
 def bf16(a):
     u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
@@ -22,59 +40,54 @@ def bf16(a):
     return r.view(np.float32).astype(np.float64)
 
 
-def rel(a, b):
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
 
 
-def _net(seed):
+def maxerr(a, b):
+    """largest element-wise difference relative to the reference's largest magnitude"""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _net(seed, fp32):
     W = nn.init_weights(np.random.default_rng(seed))
     net = ofd.Network(seed)
     net.set_weights({k: v.astype(np.float32) for k, v in W.items()})
-    return net, {k: bf16(v) for k, v in W.items()}
+    net.set_precision(fp32)
+    rnd = f32 if fp32 else bf16
+    return net, {k: rnd(v) for k, v in W.items()}, rnd
 
 
+def _bound(fp32, stages):
+    return 1e-5 if fp32 else C_MODEL * U_BF16 * np.sqrt(stages)
+
+
+@pytest.mark.parametrize("fp32", [True, False])
 @pytest.mark.parametrize("shape", [(16, 16, 16), (8, 16, 24), (32, 32, 32)])
-def test_forward_matches_oracle(shape):
+def test_forward_matches_oracle(shape, fp32):
     torch = torch_cuda()
-    announce("nn forward", shape)
-    net, Wb = _net(3)
+    announce("nn forward", shape, "fp32" if fp32 else "bf16")
+    net, Wr, rnd = _net(3, fp32)
     rng = np.random.default_rng(4)
     x = rng.normal(size=shape) + 0.3
     xd = to_dev(x)
     out = torch.empty_like(xd)
     net.forward(xd, out, (0.5, 0.5, 0.5), scale=1.0)
     rms = np.sqrt((x * x).mean())
-    ref = rms * nn.forward(Wb, bf16(x / rms))[0]
-    e = rel(to_host(out), ref)
-    print("forward rel err", e)
-    assert e < 3e-2
+    ref = rms * nn.forward(Wr, rnd(x / rms))[0]
+    e = maxerr(to_host(out), ref)
+    print("forward max err", e)
+    assert e <= _bound(fp32, FWD_STAGES)
 
 
-def test_gradients_match_oracle():
+@pytest.mark.parametrize("fp32", [True, False])
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_gradients_match_oracle(kind, fp32):
+    """Weight gradients of every layer for the solution loss (0), the
+    energy-norm loss (1) and the residual-norm loss (2)."""
     torch = torch_cuda()
-    announce("nn gradients")
-    net, Wb = _net(5)
-    w = inputs.small_cell()
-    g, _ = poisson.rhs(w.rho, w.b)
-    phi = poisson.solve_exact(g, w.cell.h)
-    loss = net.gradients(to_dev(g), to_dev(phi), w.cell.h)
-    grads = net.get_weights(gradients=True)
-    h2 = w.cell.h[0] ** 2
-    rms = np.sqrt((g * g).mean())
-    out, cache = nn.forward(Wb, bf16(g / rms))
-    L, dout = nn.loss(out, phi / (h2 * rms))
-    ref = nn.backward(Wb, cache, dout)
-    assert abs(loss - L) <= 2e-2 * L
-    errs = {k: rel(grads[k], ref[k]) for k in ref}
-    print("gradient rel errs", errs)
-    assert max(errs.values()) < 0.1
-
-
-@pytest.mark.parametrize("kind", [1, 2])
-def test_operator_loss_gradients_match_oracle(kind):
-    torch = torch_cuda()
-    announce("nn operator-loss gradients", kind)
-    net, Wb = _net(6)
+    announce("nn gradients", kind, "fp32" if fp32 else "bf16")
+    net, Wr, rnd = _net(5 if kind == 0 else 6, fp32)
     net.set_loss(kind)
     w = inputs.small_cell()
     g, _ = poisson.rhs(w.rho, w.b)
@@ -83,14 +96,15 @@ def test_operator_loss_gradients_match_oracle(kind):
     grads = net.get_weights(gradients=True)
     h2 = np.cbrt(np.prod(w.cell.h)) ** 2
     rms = np.sqrt((g * g).mean())
-    out, cache = nn.forward(Wb, bf16(g / rms))
-    L, dout = (nn.loss_energy if kind == 1 else nn.loss_residual)(out, phi / (h2 * rms), w.cell.h)
-    ref = nn.backward(Wb, cache, dout)
-    print("energy loss", loss, L)
-    assert abs(loss - L) <= 2e-2 * L
-    errs = {k: rel(grads[k], ref[k]) for k in ref}
-    print("gradient rel errs", errs)
-    assert max(errs.values()) < 0.1
+    out, cache = nn.forward(Wr, rnd(g / rms))
+    t = phi / (h2 * rms)
+    L, dout = nn.loss(out, t) if kind == 0 else (nn.loss_energy if kind == 1 else nn.loss_residual)(out, t, w.cell.h)
+    ref = nn.backward(Wr, cache, dout)
+    assert abs(loss - L) <= _bound(fp32, FWD_STAGES) * L
+    errs = {k: maxerr(grads[k], ref[k]) for k in ref}
+    print("gradient max errs", errs)
+    for k, e in errs.items():
+        assert e <= _bound(fp32, FWD_STAGES + BWD_STAGES[k]), (k, e)
 
 
 def test_training_reduces_loss():
@@ -167,11 +181,13 @@ def test_trained_network_gain():
     """What the trained network gains over the method without it.  Trained on
     solver-generated pairs of small perturbed cells (energy-norm loss), its
     correction of a zero guess on a held-out cell removes most of the
-    energy-norm error (an untrained network removes much less), and plain CG
-    from the corrected guess still reaches 1e-8.  The iteration count barely
-    moves: the correction leaves a residual only ~6x smaller, and CG must
-    still take it through the remaining seven decades (measured: -5% at
-    96^3 and 192^3, +-4% at 32^3)."""
+    energy-norm error: asserted as a gain over the untrained network (the
+    learned form without training) and over the zero guess.  Negative result,
+    asserted as such: the correction does not cut the plain-CG iterations to
+    1e-8 (it leaves a residual only ~3-6x smaller, and CG must still take it
+    through the remaining seven decades; measured -5% at 96^3 and 192^3,
+    +-4% at 32^3), so the last check is only that it costs none beyond
+    noise."""
     torch = torch_cuda()
     announce("learned gain")
     from paper_1412_8250_amd import learned
@@ -199,4 +215,5 @@ def test_trained_network_gain():
     assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:20])
     assert q_trained["energy_error_ratio"] < 0.5
     assert q_trained["energy_error_ratio"] < 0.6 * q_untrained["energy_error_ratio"]
+    # negative result: no iteration gain to 1e-8, and no loss beyond noise
     assert iters["trained"] <= 1.1 * iters["plain"] + 2
