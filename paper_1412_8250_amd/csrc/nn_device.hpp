@@ -137,63 +137,133 @@ conv_c1(InDescT<A> in, Geo g, const A *__restrict__ W1, int cout, A *out_a, floa
     }
 }
 
-// Weight gradient partials: part[chunk][t][ci][co] = sum over the chunk's
-// points p of X[p + off_t][ci] * dYm[p][co], dYm = dY * (Y > 0) if ymask.
-// Grid: (chunks, 27, ci_tiles * co_tiles); one wave per block.  K = 16
-// points per step: one bf16 16x16x16 instruction (lane kq supplies points
-// 4 kq .. 4 kq + 3) or four f32 16x16x4 ones (step j: point 4 kq + j).
+// Weight gradient on bricks: one block (4 waves) owns a (16 ci x 16 co) tile
+// pair and a column of kWbZg bricks of 16 x 4 x 4 points along z.  Per brick
+// the input tile with its one-point halo (18 x 6 x 6 points, the ci tile)
+// and the masked output gradient (256 points, the co tile) are staged in LDS
+// once; every wave then runs its taps (t = wave + 4u) over the brick's 16
+// rows of 16 points, one MFMA K step per row (bf16 16x16x16, or four f32
+// 16x16x4 steps): lane (m, kq) supplies X[row point 4 kq + j + shift][ci m]
+// and dY[row point 4 kq + j][co m] (zero outside the grid), so each input
+// value is read from memory once per brick instead of once per tap.
+// part[chunk][t][ci][co], chunk = block column; summed by wgrad_reduce.
+constexpr int kWbX = 16, kWbY = 4, kWbZ = 4, kWbZg = 4;
+constexpr int kWbTX = kWbX + 2, kWbTY = kWbY + 2, kWbTZ = kWbZ + 2;
+constexpr int kWbHalo = kWbTX * kWbTY * kWbTZ;      // 648 points
+constexpr int kWbPts = kWbX * kWbY * kWbZ;          // 256 points
+constexpr int kWbStride = 20;                       // LDS elements per point (16 + pad: no bank conflicts)
+
+__device__ inline int wrap_any(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+inline int wb_chunks(const Geo &g, int &nbx, int &nby, int &ngz) {
+    nbx = (g.nx + kWbX - 1) / kWbX;
+    nby = (g.ny + kWbY - 1) / kWbY;
+    const int nbz = (g.nz + kWbZ - 1) / kWbZ;
+    ngz = (nbz + kWbZg - 1) / kWbZg;
+    return nbx * nby * ngz;
+}
+
 template <typename A>
-__global__ void __launch_bounds__(64)
-conv_wgrad(InDescT<A> x_in, Geo g, const A *__restrict__ dy, const A *__restrict__ ymask, int cin,
-           int cout, int chunk_pts, float *__restrict__ part) {
-    const int lane = threadIdx.x;
-    const int chunk = blockIdx.x, t = blockIdx.y;
+__global__ void __launch_bounds__(256)
+conv_wgrad_brick(InDescT<A> x_in, Geo g, const A *__restrict__ dy, const A *__restrict__ ymask, int cin,
+                 int cout, int nbx, int nby, float *__restrict__ part) {
+    __shared__ A xs[kWbHalo * kWbStride];
+    __shared__ A ys[kWbPts * kWbStride];
     const int cot = (cout + 15) / 16;
-    const int cit = blockIdx.z / cot, co_t = blockIdx.z % cot;
-    const int m = lane & 15, kq = lane >> 4;
-    const int ci = cit * 16 + m, co = co_t * 16 + m;
-    const int dx = t % 3 - 1, dyo = (t / 3) % 3 - 1, dz = t / 9 - 1;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int pb = chunk * chunk_pts;
-    const int pe = min(pb + chunk_pts, g.npts);
-    for (int k0 = pb; k0 < pe; k0 += 16) {
-        A av[4], bv[4];
+    const int cit = blockIdx.y / cot, co_t = blockIdx.y % cot;
+    int b = blockIdx.x;
+    const int bxi = b % nbx;
+    b /= nbx;
+    const int byi = b % nby;
+    const int gz = b / nby;
+    const int x0 = bxi * kWbX, y0 = byi * kWbY;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, kq = lane >> 4;
+    const int ci0 = cit * 16, co0 = co_t * 16;
+    const int nbz = (g.nz + kWbZ - 1) / kWbZ;
+    f32x4 acc[7];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int p = k0 + 4 * kq + j;
-            A xa = A(0), db = A(0);
-            if (p < pe) {
-                const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-                if (ci < cin)
-                    xa = fetch1<A>(x_in, wrapc(x + dx, g.nx), wrapc(y + dyo, g.ny), wrapc(z + dz, g.nz), ci, g);
-                if (co < cout) {
-                    A d = dy[(size_t)p * cout + co];
-                    if (ymask && !Act<A>::pos(ymask[(size_t)p * cout + co])) d = A(0);
-                    db = d;
+    for (int u = 0; u < 7; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int bz = gz * kWbZg; bz < min((gz + 1) * kWbZg, nbz); ++bz) {
+        const int z0 = bz * kWbZ;
+        __syncthreads();                      // the previous brick's readers are done
+        // input tile with halo, channels [ci0, ci0 + 16), periodic images
+        if (cin >= 16) {
+            for (int e = tid; e < kWbHalo * 4; e += 256) {
+                const int q = e >> 2, c4 = e & 3;
+                const int lx = q % kWbTX, ly = (q / kWbTX) % kWbTY, lz = q / (kWbTX * kWbTY);
+                const typename Vec4<A>::type v =
+                    fetch4<A>(x_in, wrap_any(x0 - 1 + lx, g.nx), wrap_any(y0 - 1 + ly, g.ny),
+                              wrap_any(z0 - 1 + lz, g.nz), ci0 + 4 * c4, g);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xs[q * kWbStride + 4 * c4 + j] = static_cast<A>(v[j]);   // same bits: short -> u16, float -> float
+            }
+        } else {                              // one input channel
+            for (int q = tid; q < kWbHalo; q += 256) {
+                const int lx = q % kWbTX, ly = (q / kWbTX) % kWbTY, lz = q / (kWbTX * kWbTY);
+                xs[q * kWbStride] = fetch1<A>(x_in, wrap_any(x0 - 1 + lx, g.nx), wrap_any(y0 - 1 + ly, g.ny),
+                                              wrap_any(z0 - 1 + lz, g.nz), 0, g);
+#pragma unroll
+                for (int c = 1; c < 16; ++c) xs[q * kWbStride + c] = A(0);
+            }
+        }
+        // masked output gradient of the brick's points, channels [co0, co0 + 16)
+        for (int e = tid; e < kWbPts * 16; e += 256) {
+            const int q = e >> 4, c = e & 15;
+            const int lx = q % kWbX, ly = (q / kWbX) % kWbY, lz = q / (kWbX * kWbY);
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz, co = co0 + c;
+            A d = A(0);
+            if (x < g.nx && y < g.ny && z < g.nz && co < cout) {
+                const size_t i = (size_t)pidx(x, y, z, g) * cout + co;
+                d = dy[i];
+                if (ymask && !Act<A>::pos(ymask[i])) d = A(0);
+            }
+            ys[q * kWbStride + c] = d;
+        }
+        __syncthreads();
+        for (int r = 0; r < kWbY * kWbZ; ++r) {
+            const int ly = r % kWbY, lz = r / kWbY;
+            A bv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = ys[((lz * kWbY + ly) * kWbX + 4 * kq + j) * kWbStride + m];
+#pragma unroll
+            for (int u = 0; u < 7; ++u) {
+                const int t = wave + 4 * u;
+                if (t >= 27) break;
+                const int dx = t % 3, dyo = (t / 3) % 3, dz = t / 9;      // shift + 1
+                const A *xr = xs + (((lz + dz) * kWbTY + (ly + dyo)) * kWbTX + 4 * kq + dx) * kWbStride + m;
+                A av[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) av[j] = xr[j * kWbStride];
+                if constexpr (sizeof(A) == 2) {
+                    s16x4 a, bb;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        a[j] = (short)av[j];
+                        bb[j] = (short)bv[j];
+                    }
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bb, acc[u], 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc[u], 0, 0, 0);
                 }
             }
-            av[j] = xa;
-            bv[j] = db;
-        }
-        if constexpr (sizeof(A) == 2) {
-            s16x4 a, b;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                a[j] = (short)av[j];
-                b[j] = (short)bv[j];
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[j], bv[j], acc, 0, 0, 0);
         }
     }
-    // lane holds D[ci = cit*16 + 4*kq + i][co = co_t*16 + m]
+    // lane holds D[ci = ci0 + 4 kq + i][co = co0 + m] of each of its taps
+    const int co = co0 + m;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int cii = cit * 16 + 4 * kq + i;
-        if (cii < cin && co < cout)
-            part[(((size_t)chunk * 27 + t) * cin + cii) * cout + co] = acc[i];
+    for (int u = 0; u < 7; ++u) {
+        const int t = wave + 4 * u;
+        if (t >= 27) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ci = ci0 + 4 * kq + i;
+            if (ci < cin && co < cout)
+                part[(((size_t)blockIdx.x * 27 + t) * cin + ci) * cout + co] = acc[u][i];
+        }
     }
 }
 

@@ -31,7 +31,6 @@ const int kBufLevel[NBUF] = {0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 3, 3, 
 const int kBufCh[NBUF] = {1, 16, 16, 16, 16, 16, 32, 32, 32, 32, 32, 64, 64, 64, 64, 64, 64, 64,
                           1, 16, 16, 48, 16, 16, 32, 32, 96, 16, 32, 32, 64, 64, 128, 32, 64, 64,
                           64, 64, 64};
-constexpr int kChunk = 4096;
 
 int ntile(int c) { return (c + 15) / 16; }
 
@@ -111,15 +110,16 @@ template <typename A>
 int wgrad(ofdft_nn *net, int layer, const InDescT<A> &x, const Geo &g, const void *dy, const void *ymask,
           hipStream_t s) {
     const int cin = kDefs[layer].cin, cout = kDefs[layer].cout;
-    const int chunks = (g.npts + kChunk - 1) / kChunk;
+    int nbx, nby, ngz;
+    const int chunks = wb_chunks(g, nbx, nby, ngz);
     const size_t count = (size_t)27 * cin * cout;
     if ((size_t)chunks * count > net->part_cap) {
         set_error("network: weight-gradient scratch too small");
         return OFDFT_INVALID_ARG;
     }
     ProfScope ps(K_NN, (double)g.npts * sizeof(A) * (cin + cout), s);
-    hipLaunchKernelGGL(conv_wgrad<A>, dim3(chunks, 27, ntile(cin) * ntile(cout)), dim3(64), 0, s, x, g,
-                       (const A *)dy, (const A *)ymask, cin, cout, kChunk, net->part);
+    hipLaunchKernelGGL(conv_wgrad_brick<A>, dim3(chunks, ntile(cin) * ntile(cout)), dim3(256), 0, s, x, g,
+                       (const A *)dy, (const A *)ymask, cin, cout, nbx, nby, net->part);
     OFDFT_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, net->part,
                        chunks, (int)count, net->gr[layer]);
@@ -155,7 +155,8 @@ int net_reserve(ofdft_nn *net, const ofdft_grid &g) {
         // layer l runs on the level of its output
         static const int lvl[kLayers] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0};
         const Geo gg = geo_of(net, lvl[l]);
-        const size_t chunks = (gg.npts + kChunk - 1) / kChunk;
+        int nbx, nby, ngz;
+        const size_t chunks = (size_t)wb_chunks(gg, nbx, nby, ngz);
         cap = std::max(cap, chunks * 27 * kDefs[l].cin * kDefs[l].cout);
     }
     OFDFT_TRY(nalloc(net, &net->part, sizeof(float) * cap, net->ws));
