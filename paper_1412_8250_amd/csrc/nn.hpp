@@ -39,7 +39,7 @@ struct ofdft_nn {
     std::vector<void *> ws;
     void *buf[64] = {};
     float *out = nullptr;
-    float *part = nullptr;
+    float *part = nullptr, *part2 = nullptr;   // weight-gradient chunk partials, slice sums
     size_t part_cap = 0;
     double *totals = nullptr;
     ofdft::RedBuf rb{};

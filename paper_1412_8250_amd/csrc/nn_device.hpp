@@ -15,6 +15,19 @@
 namespace ofdft {
 namespace nn {
 
+// Bricks of the convolution and weight-gradient kernels: 16 x 4 x 4 points,
+// staged in LDS with a one-point halo.
+constexpr int kWbX = 16, kWbY = 4, kWbZ = 4, kWbZg = 4;
+constexpr int kWbTX = kWbX + 2, kWbTY = kWbY + 2, kWbTZ = kWbZ + 2;
+constexpr int kWbHalo = kWbTX * kWbTY * kWbTZ;      // 648 points
+constexpr int kWbPts = kWbX * kWbY * kWbZ;          // 256 points
+constexpr int kWbStride = 20;                       // LDS elements per point (16 + pad: no bank conflicts)
+
+__device__ inline int wrap_any(int i, int n) {
+    const int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
 // ---------------------------------------------------------------------------
 // Convolution, C_in a multiple of 16.  Block = 4 waves, each 16 points.
 // Weights Wt: [27][NTILE*16][Cin] (BF16, or FP32 in the FP32 mode; zero rows
@@ -78,6 +91,94 @@ conv_k16(InDescT<A> in, Geo g, const A *__restrict__ Wt, int cin, int cout, A *o
             if (relu) v = fmaxf(v, 0.f);
             if (out_f32) out_f32[(size_t)q * cout + co] = v;
             else out_a[(size_t)q * cout + co] = Act<A>::from(v);
+        }
+    }
+}
+
+// Convolution on bricks, C_in a multiple of 16: one block (4 waves) owns a
+// brick of 16 x 4 x 4 points and NTB output tiles of 16 channels (tile group
+// blockIdx.y).  Per 16-channel input chunk the brick's input with its
+// one-point halo (18 x 6 x 6 points) is staged in LDS once (periodic images,
+// upsampled / concatenated / masked sources as in fetch4); then wave w runs
+// the 27 taps over the 4 rows of brick plane z0 + w: per tap it loads the
+// weights of its NTB tiles once (lane (m, kq): ci 4 kq .. 4 kq + 3 of output
+// channel m) and, per row, the 16 points' shifted input (lane (m, kq): point
+// m, channels 4 kq .. 4 kq + 3, one 8-byte LDS read) -- one MFMA K step per
+// (tap, chunk, row, tile).  Each input value is read from memory once per
+// brick and chunk instead of once per tap.  wgt layout as for conv_k16.
+template <int NTB, typename A>
+__global__ void __launch_bounds__(256)
+conv_brick(InDescT<A> in, Geo g, const A *__restrict__ Wt, int cin, int cout, A *out_a, float *out_f32,
+           int relu, int nbx, int nby) {
+    using V = typename Vec4<A>::type;
+    using Raw = typename Vec4<A>::raw;
+    __shared__ __align__(16) A xs[kWbHalo * kWbStride];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, m = lane & 15, kq = lane >> 4;
+    int b = blockIdx.x;
+    const int bxi = b % nbx;
+    b /= nbx;
+    const int byi = b % nby;
+    const int bzi = b / nby;
+    const int x0 = bxi * kWbX, y0 = byi * kWbY, z0 = bzi * kWbZ;
+    const int cop = ((cout + 15) / 16) * 16;          // padded rows of the weight layout
+    const int cob = blockIdx.y * NTB * 16;            // first output channel of the block
+    f32x4 acc[kWbY][NTB];
+#pragma unroll
+    for (int r = 0; r < kWbY; ++r)
+#pragma unroll
+        for (int nt = 0; nt < NTB; ++nt) acc[r][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+        __syncthreads();
+        for (int e = tid; e < kWbHalo * 4; e += 256) {
+            const int q = e >> 2, c4 = e & 3;
+            const int lx = q % kWbTX, ly = (q / kWbTX) % kWbTY, lz = q / (kWbTX * kWbTY);
+            const V v = fetch4<A>(in, wrap_any(x0 - 1 + lx, g.nx), wrap_any(y0 - 1 + ly, g.ny),
+                                  wrap_any(z0 - 1 + lz, g.nz), c0 + 4 * c4, g);
+            *reinterpret_cast<Raw *>(xs + q * kWbStride + 4 * c4) = __builtin_bit_cast(Raw, v);
+        }
+        __syncthreads();
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t % 3, dyo = (t / 3) % 3, dz = t / 9;      // shift + 1
+            const A *wt = Wt + ((size_t)t * cop + cob + m) * cin + c0 + 4 * kq;
+            V bw[NTB];
+#pragma unroll
+            for (int nt = 0; nt < NTB; ++nt)
+                bw[nt] = __builtin_bit_cast(V, *reinterpret_cast<const Raw *>(wt + (size_t)nt * 16 * cin));
+#pragma unroll
+            for (int r = 0; r < kWbY; ++r) {
+                const A *xr = xs + (((wave + dz) * kWbTY + (r + dyo)) * kWbTX + m + dx) * kWbStride + 4 * kq;
+                const V a = __builtin_bit_cast(V, *reinterpret_cast<const Raw *>(xr));
+#pragma unroll
+                for (int nt = 0; nt < NTB; ++nt) {
+                    if constexpr (sizeof(A) == 2) {
+                        acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[nt], acc[r][nt], 0, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[j], bw[nt][j], acc[r][nt], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // lane holds D[point 4 kq + i][channel m] of each row and tile
+    const int z = z0 + wave;
+#pragma unroll
+    for (int r = 0; r < kWbY; ++r) {
+        const int y = y0 + r;
+#pragma unroll
+        for (int nt = 0; nt < NTB; ++nt) {
+            const int co = cob + nt * 16 + m;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + 4 * kq + i;
+                if (x >= g.nx || y >= g.ny || z >= g.nz || co >= cout) continue;
+                const size_t q = (size_t)pidx(x, y, z, g);
+                float v = acc[r][nt][i];
+                if (relu) v = fmaxf(v, 0.f);
+                if (out_f32) out_f32[q * cout + co] = v;
+                else out_a[q * cout + co] = Act<A>::from(v);
+            }
         }
     }
 }
@@ -147,16 +248,6 @@ conv_c1(InDescT<A> in, Geo g, const A *__restrict__ W1, int cout, A *out_a, floa
 // and dY[row point 4 kq + j][co m] (zero outside the grid), so each input
 // value is read from memory once per brick instead of once per tap.
 // part[chunk][t][ci][co], chunk = block column; summed by wgrad_reduce.
-constexpr int kWbX = 16, kWbY = 4, kWbZ = 4, kWbZg = 4;
-constexpr int kWbTX = kWbX + 2, kWbTY = kWbY + 2, kWbTZ = kWbZ + 2;
-constexpr int kWbHalo = kWbTX * kWbTY * kWbTZ;      // 648 points
-constexpr int kWbPts = kWbX * kWbY * kWbZ;          // 256 points
-constexpr int kWbStride = 20;                       // LDS elements per point (16 + pad: no bank conflicts)
-
-__device__ inline int wrap_any(int i, int n) {
-    const int r = i % n;
-    return r < 0 ? r + n : r;
-}
 
 inline int wb_chunks(const Geo &g, int &nbx, int &nby, int &ngz) {
     nbx = (g.nx + kWbX - 1) / kWbX;
@@ -265,6 +356,22 @@ conv_wgrad_brick(InDescT<A> x_in, Geo g, const A *__restrict__ dy, const A *__re
                 part[(((size_t)blockIdx.x * 27 + t) * cin + ci) * cout + co] = acc[u][i];
         }
     }
+}
+
+// First stage of the chunk sum: slice s of `slices` sums chunks
+// [s * per, (s + 1) * per) in order into tmp[s][i] (per = ceil(chunks /
+// slices)), so that many blocks share the work; wgrad_reduce then sums the
+// slices in order.  The result does not depend on timing.
+__global__ void wgrad_reduce_slices(const float *__restrict__ part, int chunks, int count, int slices,
+                                    float *__restrict__ tmp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (i >= count) return;
+    const int per = (chunks + slices - 1) / slices;
+    const int c0 = sl * per, c1 = min(c0 + per, chunks);
+    float s = 0.f;
+    for (int c = c0; c < c1; ++c) s += part[(size_t)c * count + i];
+    tmp[(size_t)sl * count + i] = s;
 }
 
 // dW[i] = sum over chunks (fixed order) of part[chunk][i]

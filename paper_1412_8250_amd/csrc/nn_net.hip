@@ -33,6 +33,7 @@ const int kBufCh[NBUF] = {1, 16, 16, 16, 16, 16, 32, 32, 32, 32, 32, 64, 64, 64,
                           64, 64, 64};
 
 int ntile(int c) { return (c + 15) / 16; }
+constexpr int kWgradSlices = 32;    // first-stage slices of the weight-gradient chunk sum
 
 Geo geo_of(const ofdft_nn *net, int level) {
     Geo g;
@@ -90,16 +91,20 @@ int conv(const InDescT<A> &in, const Geo &g, const A *w, int cin, int cout, void
             default: hipLaunchKernelGGL((conv_c1<4, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cout, oa, out_f32, r); break;
         }
     } else {
-        switch (ntile(cout)) {
-            case 1: hipLaunchKernelGGL((conv_k16<1, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            case 2: hipLaunchKernelGGL((conv_k16<2, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            case 3: hipLaunchKernelGGL((conv_k16<3, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            case 4: hipLaunchKernelGGL((conv_k16<4, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            case 6: hipLaunchKernelGGL((conv_k16<6, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            case 8: hipLaunchKernelGGL((conv_k16<8, A>), dim3(blocks), dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r); break;
-            default:
-                set_error("network: unsupported channel count %d", cout);
-                return OFDFT_INVALID_ARG;
+        // bricks of 16 x 4 x 4 points; at most 4 output tiles per block
+        const int nbx = (g.nx + kWbX - 1) / kWbX, nby = (g.ny + kWbY - 1) / kWbY, nbz = (g.nz + kWbZ - 1) / kWbZ;
+        const int nt = ntile(cout);
+        const int ntb = nt <= 4 ? nt : (nt % 4 == 0 ? 4 : 3);
+        if (nt % ntb) {
+            set_error("network: unsupported channel count %d", cout);
+            return OFDFT_INVALID_ARG;
+        }
+        const dim3 grid(nbx * nby * nbz, nt / ntb);
+        switch (ntb) {
+            case 1: hipLaunchKernelGGL((conv_brick<1, A>), grid, dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r, nbx, nby); break;
+            case 2: hipLaunchKernelGGL((conv_brick<2, A>), grid, dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r, nbx, nby); break;
+            case 3: hipLaunchKernelGGL((conv_brick<3, A>), grid, dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r, nbx, nby); break;
+            default: hipLaunchKernelGGL((conv_brick<4, A>), grid, dim3(256), 0, s, in, g, w, cin, cout, oa, out_f32, r, nbx, nby); break;
         }
     }
     OFDFT_CHECK_HIP(hipGetLastError());
@@ -121,8 +126,13 @@ int wgrad(ofdft_nn *net, int layer, const InDescT<A> &x, const Geo &g, const voi
     hipLaunchKernelGGL(conv_wgrad_brick<A>, dim3(chunks, ntile(cin) * ntile(cout)), dim3(256), 0, s, x, g,
                        (const A *)dy, (const A *)ymask, cin, cout, nbx, nby, net->part);
     OFDFT_CHECK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, net->part,
-                       chunks, (int)count, net->gr[layer]);
+    // the chunk sum in two fixed-order stages (slices of chunks, then the slices)
+    const int slices = std::min(kWgradSlices, chunks);
+    hipLaunchKernelGGL(wgrad_reduce_slices, dim3((unsigned)((count + 255) / 256), slices), dim3(256), 0, s,
+                       net->part, chunks, (int)count, slices, net->part2);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(wgrad_reduce, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, net->part2,
+                       slices, (int)count, net->gr[layer]);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
@@ -161,6 +171,9 @@ int net_reserve(ofdft_nn *net, const ofdft_grid &g) {
     }
     OFDFT_TRY(nalloc(net, &net->part, sizeof(float) * cap, net->ws));
     net->part_cap = cap;
+    size_t cmax = 0;
+    for (int l = 0; l < kLayers; ++l) cmax = std::max(cmax, (size_t)27 * kDefs[l].cin * kDefs[l].cout);
+    OFDFT_TRY(nalloc(net, &net->part2, sizeof(float) * cmax * kWgradSlices, net->ws));
     return OFDFT_OK;
 }
 
