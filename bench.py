@@ -18,10 +18,13 @@ value  = algorithmic HBM bytes of every kernel launched in the timed steps
          library per launch) / wall time of those steps, in GB/s.
 roofline = the dominant kernel class in the timed steps, its algorithmic
          bytes / its summed launch durations (HIP events on its stream).
-Extras: stand-alone stencil GB/s at 320^3 (f64, f32, c128); Poisson
-time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined, the
-multigrid-preconditioned and the learned forms (the network trained here
-first, on 16 small perturbed cells, about 20 s); the uneven batch of 256
+Extras: the autotuner's choices; stand-alone stencil GB/s at 320^3 (f64,
+f32, c128); the learned aid as configured (learned_c5: 20k solver-generated
+pairs of perturbed 4^3-6^3 cells on 64^3-112^3 grids produced into a device
+ring and trained on, then the held-out 96^3 and 192^3 cells solved to 1e-8
+by plain FP64 CG, multigrid-preconditioned CG and the learned forms);
+Poisson time-to-1e-8 at 320^3 for the plain FP64, the FP32-in-FP64 refined,
+the multigrid-preconditioned and the learned forms; the uneven batch of 256
 shifted systems to 1e-8; the four K_00 shifts of one right-hand side at
 320^3 by multi-shift COCG against the batched COCG (plain and multigrid-
 preconditioned); energy terms and forces of the large cell; one SCF step
@@ -48,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip training/evaluating the learned aid")
+    ap.add_argument("--c5-pairs", type=int, default=20000,
+                    help="solver-generated training pairs of the learned aid (the configured 20k)")
     ap.add_argument("--plain-poisson", action="store_true",
                     help="SCF Poisson solve by plain FP64 CG instead of multigrid-preconditioned CG")
     ap.add_argument("--plain-helmholtz", action="store_true",
@@ -472,24 +477,24 @@ def main():
             t = e0.elapsed_time(e1) / 20 * 1e-3
             extras[f"stencil_{str(dt).split('.')[-1]}_GBps"] = 2 * x.numel() * eb / t / 1e9
             del x, y
-        g = torch.from_numpy(4 * np.pi * (w.rho + w.b)).to(dev)
+        g = torch.empty_like(b)
+        ofd.PoissonSolver(shape, h, 6, ofd.PLAIN_F64).rhs(torch.from_numpy(w.rho).to(dev), b, g)
         net = None
         if not args.no_learned:
-            # the learned aid, trained here on solver-generated pairs of small
-            # perturbed cells (the same recipe as the library's training module)
+            # the learned aid as configured: trained on the configured number of
+            # solver-generated pairs of perturbed 4^3-6^3 cells (64^3-112^3),
+            # produced on the fly into a device ring; evaluated on the held-out
+            # 96^3 and 192^3 cells against plain FP64 CG and multigrid-
+            # preconditioned CG
             from paper_1412_8250_amd import learned
             t0 = time.perf_counter()
-            cells = [inputs.training_workload(i) for i in range(16)]
-            pairs = learned.solve_pairs(cells, snapshots=(0, 10, 40, 120))
-            net = ofd.Network(0)
-            net.set_loss(ofd.Network.ENERGY)
-            losses = learned.train(net, pairs, 1000, lr=1e-3, lr_final=1e-4, seed=0)
-            extras["learned_training"] = {"cells": 16, "pairs": len(pairs), "steps": 1000,
-                                          "seconds": time.perf_counter() - t0,
-                                          "loss_first": float(np.mean(losses[:50])),
-                                          "loss_last": float(np.mean(losses[-50:]))}
-            gp = g - g.mean()
-            extras["learned_correction_320"] = learned.correction_quality(net, gp, h)
+            rep_c5, net = learned.c5(n_pairs=args.c5_pairs, log=log)
+            rep_c5["seconds"] = time.perf_counter() - t0
+            for which, name in ((0, "heldout_96"), (1, "heldout_192")):
+                rep_c5[name] = learned.c5_heldout(net, which)
+            extras["learned_c5"] = rep_c5
+            log("learned_c5", rep_c5)
+            extras["learned_correction_320"] = learned.correction_quality(net, g, h)
         forms = [("plain_f64", ofd.PLAIN_F64, None), ("refined_f32", ofd.REFINED_F32, None),
                  ("multigrid", ofd.MULTIGRID, None)]
         if net is not None:

@@ -133,6 +133,14 @@ int ofdft_poisson_create(const ofdft_grid *grid, int radius, int mode, ofdft_poi
 int ofdft_poisson_destroy(ofdft_poisson *s);
 int cg_poisson_solve(ofdft_poisson *s, const double *rhs, double *x, double rel_tol,
                      int max_iter, ofdft_solve_stats *stats, void *stream);
+/* ofdft_poisson_rhs: the right-hand side of the solver's grid from a density
+ * and the nuclear charge density (Section 3.3, Poisson equation, whose
+ * continuum form is -(1/4 pi) Lap phi = rho + b): g = 4 pi (rho + b) with its
+ * mean removed (the net-charge projection, FP64 sums).  rho, b, g: device
+ * FP64 arrays of the grid (g may alias rho or b).  removed_mean (host,
+ * optional) receives the mean removed.  Synchronises the stream. */
+int ofdft_poisson_rhs(ofdft_poisson *s, const double *rho, const double *b, double *g, double *removed_mean,
+                      void *stream);
 /* cg_poisson_solve_noalloc -- for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the OFDFT_PLAIN_F64 form of cg_poisson_solve with the same

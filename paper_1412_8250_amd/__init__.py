@@ -85,6 +85,7 @@ def _declare(l):
         "ofdft_poisson_destroy": (_I, [_V]),
         "cg_poisson_solve": (_I, [_V, _V, _V, _D, _I, _SP, _V]),
         "cg_poisson_solve_noalloc": (_I, [_GP, _I, _V, _V, _D, _I, _SP, _V]),
+        "ofdft_poisson_rhs": (_I, [_V, _V, _V, _V, ctypes.POINTER(_D), _V]),
         "ofdft_batch_create": (_I, [_I, _GP, _I, _I, ctypes.POINTER(_V)]),
         "ofdft_batch_destroy": (_I, [_V]),
         "cg_helmholtz_solve_batched": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_V),
@@ -290,6 +291,14 @@ class PoissonSolver:
         self._h = ctypes.c_void_p()
         _check(lib().ofdft_poisson_create(ctypes.byref(self.grid), int(radius), int(mode),
                                           ctypes.byref(self._h)))
+
+    def rhs(self, rho, b, g, stream=None) -> float:
+        """g = 4 pi (rho + b) projected to zero mean (FP64 arrays of the grid);
+        returns the removed mean."""
+        m = ctypes.c_double()
+        _check(lib().ofdft_poisson_rhs(self._h, _dev(rho, self.shape), _dev(b, self.shape), _dev(g, self.shape),
+                                       ctypes.byref(m), _stream(stream)))
+        return m.value
 
     def set_refinement(self, inner_min: float, inner_max: float):
         _check(lib().ofdft_poisson_set_refinement(self._h, float(inner_min), float(inner_max)))

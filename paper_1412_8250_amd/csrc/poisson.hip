@@ -108,6 +108,22 @@ struct AddScaledOp {     // x += ||r|| d32   (||r|| from the residual totals)
     __device__ void operator()(int64_t i, double (&)[1]) const { x[i] = ::fma(nrm, (double)d32[i], x[i]); }
 };
 
+// Poisson right-hand side from a density and the nuclear charge (Section 3.3,
+// Poisson equation: -(1/4 pi) Lap phi = rho + b): g = 4 pi (rho + b); totals {sum g}.
+struct RhsSumOp {
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *rho, *b;
+    double *g;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double v = 4.0 * 3.14159265358979323846 * (rho[i] + b[i]);
+        g[i] = v;
+        acc[0] += v;
+    }
+};
+
 struct InitCgFin {       // set rr, tol2 from totals and arm the solver
     CgState *st;
     double tol_rel2;
@@ -467,6 +483,26 @@ extern "C" int ofdft_poisson_set_refinement(ofdft_poisson *s, double inner_min, 
     s->inner_min = inner_min;
     s->inner_max = inner_max;
     return OFDFT_OK;
+}
+
+// g = 4 pi (rho + b) with its mean removed (net-charge projection, FP64
+// sums); the removed mean is returned.  Synchronises the stream.
+extern "C" int ofdft_poisson_rhs(ofdft_poisson *s, const double *rho, const double *b, double *g,
+                                 double *removed_mean, void *stream) {
+    if (!s || !rho || !b || !g) {
+        set_error("ofdft_poisson_rhs: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = npoints(s->g);
+    OFDFT_TRY((launch_reduce<1>(n, RhsSumOp{rho, b, g}, StoreTotals<1>{s->totals + 8}, s->rb, st)));
+    ShiftOp sh{g, g, s->totals + 8, 1.0 / (double)n, 0.0};
+    OFDFT_TRY((launch_reduce<2>(n, sh, NoFin{}, s->rb, st)));
+    double t = 0.0;
+    OFDFT_CHECK_HIP(hipMemcpyAsync(&t, s->totals + 8, sizeof(double), hipMemcpyDeviceToHost, st));
+    OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+    if (removed_mean) *removed_mean = t / (double)n;
+    return std::isfinite(t) ? OFDFT_OK : OFDFT_NONFINITE;
 }
 
 // Enable (1, default) or disable (0) captured iteration blocks for a solver.

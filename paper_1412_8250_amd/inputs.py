@@ -259,3 +259,89 @@ def jellium(cells: int, n: int, a: float = A_AL) -> Workload:
     cell = Cell((n, n, n), (cells * a,) * 3, atoms)
     rho_bar = cell.n_electrons / cell.volume
     return Workload(cell, np.full(cell.shape, -rho_bar), np.full(cell.shape, rho_bar))
+
+
+# ----------------------------------------------------------------------------
+# The same recipes evaluated with torch on a device, for workloads that need
+# thousands of cells (the learned aid's training pairs).  Every random draw is
+# the numpy recipe's own (same generator, same order), so a cell equals its
+# numpy counterpart up to rounding; only the evaluation of the Gaussians and
+# of the smooth field runs on the device.  Still no arithmetic of the method.
+# ----------------------------------------------------------------------------
+
+def _axis_factors_torch(r, n: int, L: float, sigma: float, cut: float, torch, device):
+    """[M, n] periodic 1D Gaussian factors, the numpy recipe's window: the
+    unwrapped points floor((r - cut)/h) .. ceil((r + cut)/h), folded mod n."""
+    h = L / n
+    r = torch.as_tensor(r, dtype=torch.float64, device=device)
+    i0 = torch.floor((r - cut) / h).to(torch.int64)
+    i1 = torch.ceil((r + cut) / h).to(torch.int64)
+    width = int(math.ceil(2.0 * cut / h)) + 3
+    idx = i0[:, None] + torch.arange(width, device=device)[None, :]
+    vals = torch.exp(-((idx.to(torch.float64) * h - r[:, None]) ** 2) / (2.0 * sigma * sigma))
+    vals = torch.where(idx <= i1[:, None], vals, torch.zeros_like(vals))
+    out = torch.zeros((r.shape[0], n), dtype=torch.float64, device=device)
+    return out.scatter_add_(1, torch.remainder(idx, n), vals)
+
+
+def pseudocharge_torch(cell: Cell, device, sigma: float = 0.8, charge: float = -Z_AL,
+                       cutoff_sigmas: float = 8.5):
+    """pseudocharge() on a device: the per-axis image sums as [M, n] factors,
+    b[z, y, x] = norm sum_J Fz[J, z] Fy[J, y] Fx[J, x] as one matrix product."""
+    import torch
+    nx, ny, nz = cell.n
+    Lx, Ly, Lz = cell.L
+    cut = cutoff_sigmas * sigma
+    at = cell.atoms
+    fx = _axis_factors_torch(at[:, 0], nx, Lx, sigma, cut, torch, device)
+    fy = _axis_factors_torch(at[:, 1], ny, Ly, sigma, cut, torch, device)
+    fz = _axis_factors_torch(at[:, 2], nz, Lz, sigma, cut, torch, device)
+    norm = charge * (2.0 * math.pi * sigma * sigma) ** -1.5
+    gyx = (fy[:, :, None] * fx[:, None, :]).reshape(len(at), ny * nx)
+    return (norm * (fz.t() @ gyx)).reshape(nz, ny, nx)
+
+
+def smooth_field_torch(n: Sequence[int], rng: np.random.Generator, device, kmax: int = 3):
+    """smooth_field() on a device (same draws, same modes)."""
+    import torch
+    nx, ny, nz = n
+    m = kmax + 1
+    amp = rng.normal(0.0, 1.0, size=(m, m, m))
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=(m, m, m))
+    coef = amp * np.exp(1j * phase)
+    coef[0, 0, 0] = 0.0
+    k = np.arange(m)
+    c = torch.from_numpy(coef).to(device)
+    ex = torch.from_numpy(np.exp(2j * math.pi * np.outer(k, np.arange(nx)) / nx)).to(device)
+    ey = torch.from_numpy(np.exp(2j * math.pi * np.outer(k, np.arange(ny)) / ny)).to(device)
+    ez = torch.from_numpy(np.exp(2j * math.pi * np.outer(k, np.arange(nz)) / nz)).to(device)
+    t1 = (c.reshape(m * m, m) @ ex).reshape(m, m, nx)                   # [kz, ky, i]
+    t2 = torch.einsum("zyi,yj->zji", t1, ey).reshape(m, ny * nx)        # [kz, (j, i)]
+    g = (ez.t() @ t2).real.reshape(nz, ny, nx)
+    return g / g.abs().max()
+
+
+def electron_density_torch(cell: Cell, b, rng: np.random.Generator, device, amplitude: float = 0.05):
+    rho_bar = cell.n_electrons / cell.volume
+    rho = rho_bar * (1.0 + amplitude * smooth_field_torch(cell.n, rng, device))
+    return rho * (-b.sum() / rho.sum())
+
+
+def training_cell_torch(i: int, device):
+    """training_workload(i) on a device: (cell, b, rho) with b, rho tensors."""
+    rng = np.random.default_rng(1000 + i)
+    m, n = TRAIN_SHAPES[int(rng.integers(len(TRAIN_SHAPES)))]
+    atoms = fcc_atoms((m, m, m), A_AL, 0.1, rng)
+    cell = Cell((n, n, n), (m * A_AL,) * 3, atoms)
+    b = pseudocharge_torch(cell, device)
+    return cell, b, electron_density_torch(cell, b, rng, device)
+
+
+def heldout_cell_torch(which: int, device):
+    """heldout_workload(which) on a device: (cell, b, rho)."""
+    m, n, seed = ((5, 96, 9001), (10, 192, 9002))[which]
+    rng = np.random.default_rng(seed)
+    atoms = fcc_atoms((m, m, m), A_AL, 0.1, rng)
+    cell = Cell((n, n, n), (m * A_AL,) * 3, atoms)
+    b = pseudocharge_torch(cell, device)
+    return cell, b, electron_density_torch(cell, b, rng, device)

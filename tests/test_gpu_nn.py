@@ -217,3 +217,31 @@ def test_trained_network_gain():
     assert q_trained["energy_error_ratio"] < 0.6 * q_untrained["energy_error_ratio"]
     # negative result: no iteration gain to 1e-8, and no loss beyond noise
     assert iters["trained"] <= 1.1 * iters["plain"] + 2
+
+
+def test_c5_pairs_are_exact_solver_pairs():
+    """The learned aid's training pairs (right-hand side, correction) of one
+    training cell, generated on the device: the first is the library's
+    4 pi (rho + b) with its multigrid-CG solution, the others the residuals
+    of plain-CG iterates with their exact corrections; the oracle's stencil
+    checks every pair's residual, and the right-hand side against the
+    oracle's assembly of the same (numpy-generated) cell."""
+    torch = torch_cuda()
+    announce("c5 pairs")
+    from oracle import fd
+    from paper_1412_8250_amd import learned
+    cell, b, rho = inputs.training_cell_torch(0, torch.device("cuda"))
+    mg = ofd.PoissonSolver(cell.shape, cell.h, 6, ofd.MULTIGRID)
+    plain = ofd.PoissonSolver(cell.shape, cell.h, 6, ofd.PLAIN_F64)
+    pairs = learned.cell_pairs(mg, plain, rho, b, cell.h, (0, 5, 20))
+    assert len(pairs) == 3
+    w = inputs.training_workload(0)
+    ref, _ = poisson.rhs(w.rho, w.b)
+    g0 = to_host(pairs[0][0])
+    assert np.abs(g0 - ref).max() <= 1e-12 * np.abs(ref).max()
+    for k, (r, t) in enumerate(pairs):
+        rh, th = to_host(r), to_host(t)
+        res = np.linalg.norm(rh + fd.laplacian(th, cell.h)) / np.linalg.norm(rh)
+        assert res <= (1e-10 if k == 0 else 1e-7), (k, res)
+    mg.close()
+    plain.close()

@@ -228,3 +228,21 @@ def test_multigrid_iterations_do_not_grow_with_the_grid():
 def test_multigrid_rejects_grids_it_cannot_coarsen():
     with pytest.raises(ofd.OfdftError):
         ofd.PoissonSolver((24, 24, 50), (0.4,) * 3, 6, ofd.MULTIGRID)
+
+
+@pytest.mark.parametrize("which", ["small", "supercell"])
+def test_rhs_assembly_matches_oracle(which):
+    """g = 4 pi (rho + b) with its mean removed, by the library, against the
+    oracle's assembly, and the removed mean."""
+    torch_cuda()
+    announce("poisson rhs", which)
+    w = inputs.small_cell() if which == "small" else inputs.supercell_500()
+    ref, mean = poisson.rhs(w.rho, w.b)
+    s = ofd.PoissonSolver(w.rho.shape, w.cell.h)
+    gd = to_dev(np.zeros_like(w.rho))
+    m = s.rhs(to_dev(w.rho), to_dev(w.b), gd)
+    g = to_host(gd)
+    assert np.abs(g - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert abs(m - mean) <= 1e-12 * np.abs(4 * np.pi * (w.rho + w.b)).max()
+    assert abs(g.mean()) <= 1e-14 * np.abs(g).max()
+    s.close()

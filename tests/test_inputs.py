@@ -52,3 +52,22 @@ def test_batched_cell_sizes_and_shifts():
     assert (kappa.real > 0).all()
     assert (np.abs(kappa) >= 0.1 - 1e-12).all() and (np.abs(kappa) <= 5 + 1e-12).all()
     assert np.allclose(np.abs(c), 1.0)
+
+
+def test_device_generator_equals_numpy_recipe():
+    """The torch evaluation of the training and held-out cells (run here on
+    the CPU) reproduces the numpy recipes: same atoms, same draws, the same
+    Gaussians and field up to rounding."""
+    import torch
+    from paper_1412_8250_amd import inputs
+    for i in (0, 3):
+        w = inputs.training_workload(i)
+        cell, b, rho = inputs.training_cell_torch(i, "cpu")
+        assert np.array_equal(cell.atoms, w.cell.atoms)
+        assert np.abs(b.numpy() - w.b).max() <= 1e-13 * np.abs(w.b).max()
+        assert np.abs(rho.numpy() - w.rho).max() <= 1e-13 * np.abs(w.rho).max()
+    w = inputs.heldout_workload(0)
+    cell, b, rho = inputs.heldout_cell_torch(0, "cpu")
+    assert np.abs(b.numpy() - w.b).max() <= 1e-13 * np.abs(w.b).max()
+    assert np.abs(rho.numpy() - w.rho).max() <= 1e-13 * np.abs(w.rho).max()
+    del torch
