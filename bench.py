@@ -76,19 +76,73 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, iters=40):
-    """Oracle textbook CG on the same Poisson problem, `iters` iterations."""
-    from oracle import fd, poisson
+    """The oracle (C, OpenMP; test infrastructure) on the host cores, a
+    bounded sample (~30 s): textbook CG iterations of the same 320^3 Poisson
+    problem (the value, on all cores; a few iterations on one core), the
+    stencil apply at 320^3 and at the 500-atom cell's 96^3 (all cores and one
+    core), plain CG of the 96^3 cell to 1e-8, and the small cell's 20 TFW
+    fixed-point steps.  Bytes counted as on the GPU: 80 B/point per CG
+    iteration, 16 B/point per apply."""
+    import os
+    from oracle import fd, poisson, scf as oscf
+    from paper_1412_8250_amd import inputs
+    allc = fd.threads()
     g, _ = poisson.rhs(w.rho, w.b)
+    n = g.size
     t0 = time.perf_counter()
     x, it, rel = poisson.solve_cg(g, w.cell.h, tol=1e-30, maxit=iters)
     dt = time.perf_counter() - t0
-    n = g.size
-    # same accounting as the GPU CG: 32 B/pt stencil pass + 48 B/pt vector pass
     gbps = 80.0 * n * it / dt / 1e9
-    return {"value": gbps, "unit": "GB/s", "cores": fd.threads(), "kind": "oracle",
-            "sample": f"{it} textbook CG iterations of the 320^3 FP64 Poisson solve "
-                      f"({dt:.1f} s), bytes counted as 80 B/point/iteration like the GPU path"}
+    items = {}
+
+    def apply_rate(a, h, threads, reps, warm=True):
+        fd.set_threads(threads)
+        if warm:
+            fd.laplacian(a, h)
+        t = time.perf_counter()
+        for _ in range(reps):
+            fd.laplacian(a, h)
+        sec = (time.perf_counter() - t) / reps
+        return {"seconds": sec, "GBps": 16.0 * a.size / sec / 1e9, "points_per_s": a.size / sec}
+
+    sc = inputs.supercell_500()
+    g96, _ = poisson.rhs(sc.rho, sc.b)
+    for threads, tag in ((allc, "all_cores"), (1, "one_core")):
+        items[f"stencil_320_{tag}"] = apply_rate(w.rho, w.cell.h, threads, 3 if threads > 1 else 1, threads > 1)
+        items[f"stencil_96_{tag}"] = apply_rate(sc.rho, sc.cell.h, threads, 10 if threads > 1 else 3)
+    fd.set_threads(1)
+    t0 = time.perf_counter()
+    _, it1, _ = poisson.solve_cg(g, w.cell.h, tol=1e-30, maxit=2)
+    d1 = time.perf_counter() - t0
+    items["cg_320_one_core"] = {"iterations": it1, "seconds": d1, "GBps": 80.0 * n * it1 / d1 / 1e9}
+    fd.set_threads(allc)
+    t0 = time.perf_counter()
+    _, it96, rel96 = poisson.solve_cg(g96, sc.cell.h, tol=1e-8)
+    items["cg_96_to_1e-8_all_cores"] = {"iterations": it96, "seconds": time.perf_counter() - t0, "rel_res": rel96}
+    sm = inputs.small_cell()
+    o = oscf.SCF(sm.rho, sm.b, sm.cell.h, sm.cell.n_electrons, sm.cell.volume, oscf.Params(lam=0.2, mu=0))
+    t0 = time.perf_counter()
+    for _ in range(20):
+        o.step()
+    items["scf_16_20_tfw_steps_all_cores"] = {"seconds": time.perf_counter() - t0}
+    return {"value": gbps, "unit": "GB/s", "cores": allc, "kind": "oracle",
+            "sample": f"{it} textbook CG iterations of the 320^3 FP64 Poisson solve on {allc} threads "
+                      f"({dt:.1f} s), bytes counted as 80 B/point/iteration like the GPU path; "
+                      f"items: stencil apply and CG on one core and all, CG of the 96^3 cell to 1e-8, "
+                      f"20 TFW steps of the 16^3 cell",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "items": items}
 
 
 def source_sha():

@@ -27,6 +27,7 @@ def lib():
         l.orc_cocg.argtypes = [_I, _I, _I, _D, _D, _D, _I, _D, _D, _P, _P, _D, _I, _P]
         l.orc_cocg.restype = _I
         l.orc_threads.restype = _I
+        l.orc_set_threads.argtypes = [_I]
         _lib = l
     return _lib
 

@@ -82,3 +82,8 @@ def laplacian_at(x: np.ndarray, h_xyz, N: int, points) -> np.ndarray:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of later oracle calls (timing on one core or all)."""
+    lib().orc_set_threads(int(n))

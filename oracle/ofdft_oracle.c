@@ -231,3 +231,14 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of later calls (n >= 1), for timing the
+ * oracle on one core and on all of them. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
