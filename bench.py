@@ -589,6 +589,29 @@ def main():
         extras["batched_256_systems"] = batch_extra(dev, autotune=not args.no_autotune)
         # the K_00 shifts of one right-hand side at 320^3: multi-shift against batched COCG
         extras["multishift_320_4_shifts"] = multishift_extra(dev, w.rho, h, scf.kernel_shifts()[0])
+        # the same first step with the precision forms of the solves: FP32
+        # stencil + FP32 CG in FP64 refinement for the Poisson solve and
+        # complex64 COCG in complex128 refinement for the shifted solves
+        # (the multigrid preconditioner needs complex128), and with every solver
+        # plain FP64 / complex128 and unpreconditioned
+        for key, kw in (("scf_step_refined_f32", dict(poisson_mode=ofd.REFINED_F32, helmholtz_dtype=ofd.C64,
+                                                      helmholtz_precond=ofd.PRECOND_NONE,
+                                                      u_precond=ofd.PRECOND_MULTIGRID)),
+                        ("scf_step_plain_f64", dict(poisson_mode=ofd.PLAIN_F64, helmholtz_dtype=ofd.C128,
+                                                    helmholtz_precond=ofd.PRECOND_NONE,
+                                                    u_precond=ofd.PRECOND_NONE))):
+            t0 = time.perf_counter()
+            sv = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, lam=1.0, mu=1, history=7, zeta=0.3, u_tol=1e-8,
+                         poisson_tol=1e-8, helmholtz_tol=1e-8, line_slope_tol=LINE_SLOPE_TOL, **kw)
+            torch.cuda.synchronize()
+            create_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            sv.step()
+            torch.cuda.synchronize()
+            extras[key] = {"seconds": time.perf_counter() - t0, "context_and_v0_seconds": create_s,
+                           "stats": sv.stats()}
+            sv.close()
+            del sv
         # the order-2 kernel terms (K_00, K_10, K_20, K_11: 32 solved systems)
         # on the same cell: one step from the initial state, every system by the
         # batched multigrid-preconditioned COCG (warm-started), then with the

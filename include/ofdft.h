@@ -380,6 +380,17 @@ int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream);
  * one, each (kernel, power) once.  INVALID_ARG for other values. */
 int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream);
 int ofdft_scf_set(ofdft_scf *s, int which, const double *src, void *stream);
+/* Checkpoint of the whole iteration state to a file and back: every state
+ * array of ofdft_scf_get (v, u, phi, V_LR, the shifted systems' warm
+ * starts), the Anderson history (S, Y, the previous v and f, ring position)
+ * and the line-search step memory, so that a loaded context continues the
+ * saved one's trajectory exactly.  load requires a context created with the
+ * same grid, spacings, radius, N_e, kernel settings and history length
+ * (INVALID_ARG otherwise, or for an unreadable / short file).  Both
+ * synchronise the stream; the file holds (4 + warm starts) grid arrays plus
+ * 2 m + 2 for Anderson. */
+int ofdft_scf_save(ofdft_scf *s, const char *path, void *stream);
+int ofdft_scf_load(ofdft_scf *s, const char *path, void *stream);
 /* Forget the Anderson history and the line-search step memory, so that the
  * next step behaves like the first step from the current state. */
 int ofdft_scf_reset_history(ofdft_scf *s);
@@ -471,6 +482,12 @@ size_t ofdft_nn_param_count(void);
 int ofdft_nn_set_weights(ofdft_nn *net, const float *w, size_t count);
 int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int gradients);
 int ofdft_nn_set_loss(ofdft_nn *net, int kind);
+/* ofdft_nn_save / ofdft_nn_load: the network's training state in a file (FP32
+ * weights, Adam moments and step count, loss kind, activation storage);
+ * load repacks the kernels' weight copies, so training resumes exactly.
+ * INVALID_ARG for an unreadable file or one of another network. */
+int ofdft_nn_save(ofdft_nn *net, const char *path);
+int ofdft_nn_load(ofdft_nn *net, const char *path);
 /* ofdft_nn_set_precision: activation storage of the same kernels: 0 = BF16
  *   (default: BF16 activations, gradients and weight copies, FP32
  *   accumulation on v_mfma_f32_16x16x16 bf16), 1 = FP32 (FP32 activations,

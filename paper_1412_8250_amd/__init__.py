@@ -130,6 +130,10 @@ def _declare(l):
         "ofdft_poisson_apply_preconditioner": (_I, [_V, _V, _V, _V]),
         "ofdft_nn_set_loss": (_I, [_V, _I]),
         "ofdft_nn_set_precision": (_I, [_V, _I]),
+        "ofdft_nn_save": (_I, [_V, ctypes.c_char_p]),
+        "ofdft_nn_load": (_I, [_V, ctypes.c_char_p]),
+        "ofdft_scf_save": (_I, [_V, ctypes.c_char_p, _V]),
+        "ofdft_scf_load": (_I, [_V, ctypes.c_char_p, _V]),
         "ofdft_profile_reset": (_I, [ctypes.c_uint]),
         "ofdft_tune_stencil": (_I, [_GP, _I, _I, _I, _I, ctypes.POINTER(TuneResult), _V]),
         "ofdft_batch_tune": (_I, [_V, ctypes.POINTER(_D), ctypes.POINTER(_V), ctypes.POINTER(_V), _I,
@@ -551,6 +555,14 @@ class SCF:
     def reset_history(self):
         _check(lib().ofdft_scf_reset_history(self._h))
 
+    def save(self, path: str, stream=None):
+        """Checkpoint the iteration state (arrays, Anderson history, line-search memory) to a file."""
+        _check(lib().ofdft_scf_save(self._h, str(path).encode(), _stream(stream)))
+
+    def load(self, path: str, stream=None):
+        """Resume from a checkpoint written by save() of a context with the same settings."""
+        _check(lib().ofdft_scf_load(self._h, str(path).encode(), _stream(stream)))
+
     def snapshot(self):
         """Device copies of every state vector (restorable with restore())."""
         import torch
@@ -678,6 +690,14 @@ class Network:
         """Training loss: Network.L2 (solution error), Network.ENERGY (A-norm
         error) or Network.RESIDUAL (norm of the residual the output leaves)."""
         _check(lib().ofdft_nn_set_loss(self._h, int(kind)))
+
+    def save(self, path: str):
+        """Checkpoint weights, Adam moments and step count to a file."""
+        _check(lib().ofdft_nn_save(self._h, str(path).encode()))
+
+    def load(self, path: str):
+        """Resume from a checkpoint written by save()."""
+        _check(lib().ofdft_nn_load(self._h, str(path).encode()))
 
     def set_precision(self, fp32: bool):
         """Activation storage of the kernels: BF16 (default) or FP32 (the FP32

@@ -304,6 +304,47 @@ extern "C" int ofdft_anderson_reset(ofdft_anderson *a) {
     return OFDFT_OK;
 }
 
+namespace ofdft {
+
+// History of an Anderson context in a checkpoint: the host call count, the
+// device state (ring head, column count, ...), S and Y (m columns) and the
+// previous v and f.
+int anderson_write(ofdft_anderson *a, std::FILE *f) {
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
+    const int64_t hdr[3] = {a->n, a->m, a->calls};
+    OFDFT_TRY(ck_write(f, hdr, sizeof hdr));
+    AndState h{};
+    OFDFT_CHECK_HIP(hipMemcpy(&h, a->st, sizeof h, hipMemcpyDeviceToHost));
+    OFDFT_TRY(ck_write(f, &h, sizeof h));
+    const size_t col = sizeof(double) * (size_t)a->n * (size_t)std::max(a->m, 1);
+    OFDFT_TRY(ck_write_dev(f, a->S, col));
+    OFDFT_TRY(ck_write_dev(f, a->Y, col));
+    OFDFT_TRY(ck_write_dev(f, a->v_prev, sizeof(double) * a->n));
+    return ck_write_dev(f, a->f_prev, sizeof(double) * a->n);
+}
+
+int anderson_read(ofdft_anderson *a, std::FILE *f) {
+    int64_t hdr[3];
+    OFDFT_TRY(ck_read(f, hdr, sizeof hdr));
+    if (hdr[0] != a->n || hdr[1] != a->m || hdr[2] < 0) {
+        set_error("checkpoint: Anderson history of %lld values x %lld columns, the context has %lld x %d",
+                  (long long)hdr[0], (long long)hdr[1], (long long)a->n, a->m);
+        return OFDFT_INVALID_ARG;
+    }
+    AndState h{};
+    OFDFT_TRY(ck_read(f, &h, sizeof h));
+    const size_t col = sizeof(double) * (size_t)a->n * (size_t)std::max(a->m, 1);
+    OFDFT_TRY(ck_read_dev(f, a->S, col));
+    OFDFT_TRY(ck_read_dev(f, a->Y, col));
+    OFDFT_TRY(ck_read_dev(f, a->v_prev, sizeof(double) * a->n));
+    OFDFT_TRY(ck_read_dev(f, a->f_prev, sizeof(double) * a->n));
+    OFDFT_CHECK_HIP(hipMemcpy(a->st, &h, sizeof h, hipMemcpyHostToDevice));
+    a->calls = (int)hdr[2];
+    return OFDFT_OK;
+}
+
+}  // namespace ofdft
+
 extern "C" int ofdft_anderson_destroy(ofdft_anderson *a) {
     if (!a) return OFDFT_OK;
     and_free(a);

@@ -1,6 +1,8 @@
 // Status strings, FD coefficients and argument checks.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "common.hpp"
 #include "vec.hpp"
@@ -106,4 +108,48 @@ extern "C" int ofdft_last_error(char *buf, size_t len) {
     return (int)e.size();
 }
 
-extern "C" const char *ofdft_version(void) { return "ofdft-gfx950 0.2"; }
+extern "C" const char *ofdft_version(void) { return "ofdft-gfx950 0.3"; }
+
+namespace ofdft {
+
+int ck_write(std::FILE *f, const void *host, size_t bytes) {
+    if (std::fwrite(host, 1, bytes, f) != bytes) {
+        set_error("checkpoint: writing %zu bytes failed", bytes);
+        return OFDFT_INVALID_ARG;
+    }
+    return OFDFT_OK;
+}
+
+int ck_read(std::FILE *f, void *host, size_t bytes) {
+    if (std::fread(host, 1, bytes, f) != bytes) {
+        set_error("checkpoint: the file ends before %zu more bytes", bytes);
+        return OFDFT_INVALID_ARG;
+    }
+    return OFDFT_OK;
+}
+
+namespace {
+constexpr size_t kCkChunk = (size_t)64 << 20;
+}
+
+int ck_write_dev(std::FILE *f, const void *dev, size_t bytes) {
+    std::vector<char> buf(std::min(bytes, kCkChunk));
+    for (size_t off = 0; off < bytes; off += kCkChunk) {
+        const size_t b = std::min(kCkChunk, bytes - off);
+        OFDFT_CHECK_HIP(hipMemcpy(buf.data(), (const char *)dev + off, b, hipMemcpyDeviceToHost));
+        OFDFT_TRY(ck_write(f, buf.data(), b));
+    }
+    return OFDFT_OK;
+}
+
+int ck_read_dev(std::FILE *f, void *dev, size_t bytes) {
+    std::vector<char> buf(std::min(bytes, kCkChunk));
+    for (size_t off = 0; off < bytes; off += kCkChunk) {
+        const size_t b = std::min(kCkChunk, bytes - off);
+        OFDFT_TRY(ck_read(f, buf.data(), b));
+        OFDFT_CHECK_HIP(hipMemcpy((char *)dev + off, buf.data(), b, hipMemcpyHostToDevice));
+    }
+    return OFDFT_OK;
+}
+
+}  // namespace ofdft

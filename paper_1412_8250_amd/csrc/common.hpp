@@ -52,6 +52,14 @@ Coef<double> make_coef(const ofdft_grid &g, int radius);
 Coef<float> to_float(const Coef<double> &c);
 
 int check_grid(const ofdft_grid *g, int radius);
+
+// Checkpoint files: device arrays written and read through a host staging
+// buffer (blocking copies).  Each returns OFDFT_OK, or an error with the
+// message set (INVALID_ARG for a short or failed file operation).
+int ck_write_dev(std::FILE *f, const void *dev, size_t bytes);
+int ck_read_dev(std::FILE *f, void *dev, size_t bytes);
+int ck_write(std::FILE *f, const void *host, size_t bytes);
+int ck_read(std::FILE *f, void *host, size_t bytes);
 inline int64_t npoints(const ofdft_grid &g) { return (int64_t)g.nx * g.ny * g.nz; }
 
 // ---------------------------------------------------------------------------

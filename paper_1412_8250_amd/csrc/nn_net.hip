@@ -2,6 +2,8 @@
 // orchestration, Adam, and the C entry points of the learned solver aid.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <new>
 #include <random>
 
@@ -447,6 +449,79 @@ extern "C" int ofdft_nn_get_weights(ofdft_nn *net, float *w, size_t count, int g
                                   hipMemcpyDeviceToHost));
         off += cnt;
     }
+    return OFDFT_OK;
+}
+
+// Network checkpoint: a header (magic, parameter count, Adam step, loss
+// kind, activation storage), then every layer's FP32 weights and Adam
+// moments; load repacks the BF16 / FP32 copies.
+namespace {
+constexpr char kNnMagic[8] = {'O', 'F', 'D', 'F', 'T', 'N', 'N', '1'};
+struct NnHeader {
+    char magic[8];
+    int64_t params, adam_t, loss_kind, fp32;
+};
+}  // namespace
+
+extern "C" int ofdft_nn_save(ofdft_nn *net, const char *path) {
+    if (!net || !path) {
+        set_error("ofdft_nn_save: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
+    std::FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error("ofdft_nn_save: cannot open %s", path);
+        return OFDFT_INVALID_ARG;
+    }
+    NnHeader h{};
+    std::memcpy(h.magic, kNnMagic, 8);
+    h.params = (int64_t)ofdft_nn_param_count();
+    h.adam_t = net->adam_t;
+    h.loss_kind = net->loss_kind;
+    h.fp32 = net->fp32;
+    int rc = ck_write(f, &h, sizeof h);
+    for (int l = 0; rc == OFDFT_OK && l < kLayers; ++l) {
+        const size_t b = sizeof(float) * 27 * kDefs[l].cin * kDefs[l].cout;
+        if ((rc = ck_write_dev(f, net->w[l], b)) == OFDFT_OK && (rc = ck_write_dev(f, net->m[l], b)) == OFDFT_OK)
+            rc = ck_write_dev(f, net->v[l], b);
+    }
+    if (std::fclose(f) != 0 && rc == OFDFT_OK) {
+        set_error("ofdft_nn_save: closing %s failed", path);
+        rc = OFDFT_INVALID_ARG;
+    }
+    return rc;
+}
+
+extern "C" int ofdft_nn_load(ofdft_nn *net, const char *path) {
+    if (!net || !path) {
+        set_error("ofdft_nn_load: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    std::FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error("ofdft_nn_load: cannot open %s", path);
+        return OFDFT_INVALID_ARG;
+    }
+    NnHeader h{};
+    int rc = ck_read(f, &h, sizeof h);
+    if (rc == OFDFT_OK && (std::memcmp(h.magic, kNnMagic, 8) != 0 || h.params != (int64_t)ofdft_nn_param_count() ||
+                           h.loss_kind < 0 || h.loss_kind > 2 || (h.fp32 != 0 && h.fp32 != 1) || h.adam_t < 0)) {
+        set_error("ofdft_nn_load: %s is not a checkpoint of this network", path);
+        rc = OFDFT_INVALID_ARG;
+    }
+    for (int l = 0; rc == OFDFT_OK && l < kLayers; ++l) {
+        const size_t b = sizeof(float) * 27 * kDefs[l].cin * kDefs[l].cout;
+        if ((rc = ck_read_dev(f, net->w[l], b)) == OFDFT_OK && (rc = ck_read_dev(f, net->m[l], b)) == OFDFT_OK)
+            rc = ck_read_dev(f, net->v[l], b);
+    }
+    std::fclose(f);
+    if (rc != OFDFT_OK) return rc;
+    net->adam_t = (int)h.adam_t;
+    net->loss_kind = (int)h.loss_kind;
+    net->fp32 = (int)h.fp32;
+    OFDFT_TRY(pack_all(net, nullptr));
+    OFDFT_CHECK_HIP(hipDeviceSynchronize());
     return OFDFT_OK;
 }
 

@@ -10,6 +10,8 @@
 // kappa_r = (2 kF)^2 Q_r.  V_{beta,r} (solution for rho^beta) multiplies
 // alpha rho^{alpha-1} in V_LR and V_{alpha,r} multiplies beta rho^{beta-1}.
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <new>
 
 #include "physics.hpp"
@@ -818,6 +820,102 @@ static double *state_ptr(ofdft_scf *s, int which, size_t &count) {
             }
             return nullptr;
     }
+}
+
+// Checkpoint file: a header (magic, version, grid, spacings, radius, kernel
+// settings, history length, number of state arrays, the line-search memory,
+// whether the kernel solutions are warm), every state array of
+// ofdft_scf_get in order, then the Anderson history.
+namespace {
+constexpr char kCkMagic[8] = {'O', 'F', 'D', 'F', 'T', 'C', 'K', '1'};
+struct CkHeader {
+    char magic[8];
+    int64_t nx, ny, nz, radius, mu, lr_order, history, nstate, kernel_warm;
+    double hx, hy, hz, n_electrons, s_prev;
+};
+
+int64_t state_count(ofdft_scf *s) {
+    int64_t k = 0;
+    size_t c = 0;
+    while (state_ptr(s, (int)k, c)) ++k;
+    return k;
+}
+}  // namespace
+
+extern "C" int ofdft_scf_save(ofdft_scf *s, const char *path, void *stream) {
+    if (!s || !path) {
+        set_error("ofdft_scf_save: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    std::FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error("ofdft_scf_save: cannot open %s", path);
+        return OFDFT_INVALID_ARG;
+    }
+    CkHeader h{};
+    std::memcpy(h.magic, kCkMagic, 8);
+    h.nx = s->g.nx;
+    h.ny = s->g.ny;
+    h.nz = s->g.nz;
+    h.radius = s->p.radius;
+    h.mu = s->p.mu;
+    h.lr_order = s->p.lr_order;
+    h.history = s->p.history;
+    h.nstate = state_count(s);
+    h.kernel_warm = s->kernel_warm ? 1 : 0;
+    h.hx = s->g.hx;
+    h.hy = s->g.hy;
+    h.hz = s->g.hz;
+    h.n_electrons = s->p.n_electrons;
+    h.s_prev = s->s_prev;
+    int rc = ck_write(f, &h, sizeof h);
+    for (int64_t k = 0; rc == OFDFT_OK && k < h.nstate; ++k) {
+        size_t c = 0;
+        const double *p = state_ptr(s, (int)k, c);
+        rc = ck_write_dev(f, p, sizeof(double) * c);
+    }
+    if (rc == OFDFT_OK) rc = anderson_write(s->mix, f);
+    if (std::fclose(f) != 0 && rc == OFDFT_OK) {
+        set_error("ofdft_scf_save: closing %s failed", path);
+        rc = OFDFT_INVALID_ARG;
+    }
+    return rc;
+}
+
+extern "C" int ofdft_scf_load(ofdft_scf *s, const char *path, void *stream) {
+    if (!s || !path) {
+        set_error("ofdft_scf_load: NULL argument");
+        return OFDFT_INVALID_ARG;
+    }
+    OFDFT_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+    std::FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error("ofdft_scf_load: cannot open %s", path);
+        return OFDFT_INVALID_ARG;
+    }
+    CkHeader h{};
+    int rc = ck_read(f, &h, sizeof h);
+    if (rc == OFDFT_OK &&
+        (std::memcmp(h.magic, kCkMagic, 8) != 0 || h.nx != s->g.nx || h.ny != s->g.ny || h.nz != s->g.nz ||
+         h.hx != s->g.hx || h.hy != s->g.hy || h.hz != s->g.hz || h.radius != s->p.radius || h.mu != s->p.mu ||
+         h.lr_order != s->p.lr_order || h.history != s->p.history || h.n_electrons != s->p.n_electrons ||
+         h.nstate != state_count(s))) {
+        set_error("ofdft_scf_load: %s is not a checkpoint of a context with these grid and kernel settings", path);
+        rc = OFDFT_INVALID_ARG;
+    }
+    for (int64_t k = 0; rc == OFDFT_OK && k < h.nstate; ++k) {
+        size_t c = 0;
+        double *p = state_ptr(s, (int)k, c);
+        rc = ck_read_dev(f, p, sizeof(double) * c);
+    }
+    if (rc == OFDFT_OK) rc = anderson_read(s->mix, f);
+    std::fclose(f);
+    if (rc == OFDFT_OK) {
+        s->kernel_warm = h.kernel_warm != 0;
+        s->s_prev = h.s_prev;
+    }
+    return rc;
 }
 
 extern "C" int ofdft_scf_get(ofdft_scf *s, int which, double *dst, void *stream) {

@@ -78,6 +78,10 @@ struct ofdft_scf {
 
 namespace ofdft {
 
+// Anderson history in checkpoint files (anderson.hip).
+int anderson_write(ofdft_anderson *a, std::FILE *f);
+int anderson_read(ofdft_anderson *a, std::FILE *f);
+
 // U(v): Algorithm 1 from the current s->u; v is a device array.
 int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
                    hipStream_t st);

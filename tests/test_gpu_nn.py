@@ -245,3 +245,32 @@ def test_c5_pairs_are_exact_solver_pairs():
         assert res <= (1e-10 if k == 0 else 1e-7), (k, res)
     mg.close()
     plain.close()
+
+
+def test_network_checkpoint_resumes_training_exactly(tmp_path):
+    """A network saved after a few Adam steps and loaded into a fresh one
+    trains on bitwise as the saved one does (weights, Adam moments, step
+    count, loss kind)."""
+    torch_cuda()
+    announce("nn checkpoint")
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    gd, pd = to_dev(g), to_dev(phi)
+    a = ofd.Network(31)
+    a.set_loss(ofd.Network.ENERGY)
+    for _ in range(3):
+        a.train_step(gd, pd, w.cell.h, 1e-3)
+    path = str(tmp_path / "net.ck")
+    a.save(path)
+    la = [a.train_step(gd, pd, w.cell.h, 1e-3) for _ in range(3)]
+    b = ofd.Network(32)
+    b.load(path)
+    lb = [b.train_step(gd, pd, w.cell.h, 1e-3) for _ in range(3)]
+    assert la == lb
+    wa, wb = a.get_weights(), b.get_weights()
+    assert all(np.array_equal(wa[k], wb[k]) for k in wa)
+    bad = tmp_path / "bad.ck"
+    bad.write_bytes(b"not a checkpoint")
+    with pytest.raises(ofd.OfdftError):
+        b.load(str(bad))

@@ -105,15 +105,28 @@ def test_bitwise_repeatable():
 
 def test_large_cell_320():
     """16x16x16 FCC cells (16384 atoms) on 320^3: true FP64 residual from the
-    oracle's stencil, plain FP64, refined FP32 and multigrid forms."""
+    oracle's stencil, plain FP64, refined FP32 and multigrid forms, and the
+    solution against the oracle's exact DFT-diagonalised solve: the error is
+    within ||A^-1|| ||r|| (A = -L_h on the zero-mean space, ||A^-1|| the
+    inverse of its smallest non-zero eigenvalue), element by element."""
+    from oracle import fd
     announce("poisson 320^3")
     w = inputs.large_cell()
     g, _ = poisson.rhs(w.rho, w.b)
+    exact = poisson.solve_exact(g, w.cell.h)
+    lam1 = -fd.symbol_1d(w.rho.shape[0], w.cell.h[0], 6)
+    inv_norm = 1.0 / lam1[lam1 > 1e-12].min()
+    gn = np.linalg.norm(g)
     for mode in (ofd.PLAIN_F64, ofd.REFINED_F32, ofd.MULTIGRID):
         announce("poisson 320^3 mode", mode)
         x, st = _solve(g, w.cell.h, mode, 1e-8)
-        assert poisson.residual(x, g, w.cell.h) <= 1e-8
+        res = poisson.residual(x, g, w.cell.h)
+        assert res <= 1e-8
         assert abs(x.mean()) <= 1e-12 * np.abs(x).max()
+        err = x - exact
+        assert np.abs(err).max() <= np.linalg.norm(err) <= 1.01 * inv_norm * res * gn
+        announce("max error / max |phi|", float(np.abs(err).max() / np.abs(exact).max()))
+        del x, err
 
 
 @pytest.mark.parametrize("mode", [ofd.PLAIN_F64, ofd.REFINED_F32])

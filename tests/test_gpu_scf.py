@@ -265,3 +265,38 @@ def test_step_reports_not_converged(case):
     ctx.get(ofd.SCF.V, vd)
     assert np.all(np.isfinite(to_host(vd)))
     ctx.close()
+
+
+@pytest.mark.parametrize("mu", [0, 1])
+def test_checkpoint_resumes_trajectory_exactly(mu, tmp_path):
+    """A context saved after three steps and loaded into a fresh context of
+    the same settings continues bitwise as the saved one does (state arrays,
+    Anderson history, line-search memory); a context of other settings
+    refuses the file, and so does a context given a truncated file."""
+    torch = torch_cuda()
+    announce("scf checkpoint", mu)
+    w = inputs.small_cell()
+    kw = dict(lam=1.0 if mu else 0.2, mu=mu, history=7, zeta=0.3)
+    a = _ctx(w, **kw)
+    for _ in range(3):
+        a.step()
+    path = str(tmp_path / "scf.ck")
+    a.save(path)
+    ra = [a.step() for _ in range(3)]
+    b = _ctx(w, **kw)
+    b.load(path)
+    rb = [b.step() for _ in range(3)]
+    assert ra == rb
+    va, vb = (torch.empty(w.rho.shape, dtype=torch.float64, device="cuda") for _ in range(2))
+    a.get(ofd.SCF.V, va)
+    b.get(ofd.SCF.V, vb)
+    assert torch.equal(va, vb)
+    other = _ctx(w, **dict(kw, history=5))
+    with pytest.raises(ofd.OfdftError):
+        other.load(path)
+    short = tmp_path / "short.ck"
+    short.write_bytes(open(path, "rb").read()[:1000])
+    with pytest.raises(ofd.OfdftError):
+        b.load(str(short))
+    for c in (a, b, other):
+        c.close()
