@@ -518,7 +518,7 @@ int ofdft_poisson_set_network(ofdft_poisson *s, ofdft_nn *net);
  *   replaces the grid's tuned entries): shape 0 = 64x16 tile of 256 threads
  *   (4 rows per thread), 1 = 64x8 tile of 256, 2 = 32x16 tile of 256, 3 =
  *   64x16 tile of 512, 4 = 64x8 tile of 512, 5 = 64x32 tile of 512 (the plain
- *   FP64 apply; 3 elsewhere); zlen = planes per z chunk (0 = automatic).
+ *   FP64 and FP32 applies; 3 elsewhere); zlen = planes per z chunk (0 = automatic).
  *   shape < 0 removes the grid's entries.  INVALID_ARG for unknown shapes.
  * ofdft_batch_set_config: schedule of the shifted-system solver.  group 0
  *   (default) = stepped schedule: one launch per COCG phase over all systems,

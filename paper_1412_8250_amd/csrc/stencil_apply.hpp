@@ -17,7 +17,7 @@ int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x
     LoadPlain<T> ld{(const T *)x};
     ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
     auto go = [&](const auto &ep) {
-        if constexpr (std::is_same_v<T, double>) {
+        if constexpr (std::is_same_v<T, double> || std::is_same_v<T, float>) {
             const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T), FAMILY_APPLY);
             if (cfg.shape == SHAPE_64x8x4) return launch_stencil_shape<T, 64, 8, 4>(g, cfg.zlen, c, ld, ep, s);
         }

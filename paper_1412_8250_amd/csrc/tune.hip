@@ -34,10 +34,11 @@ struct Candidate {
 };
 
 // Shapes whose launch differs for the element type and family (the 64 x 32
-// tile exists only for the plain FP64 apply; elsewhere it runs 64 x 16).
+// tile exists only for the plain FP64 and FP32 applies; elsewhere it runs
+// 64 x 16).
 std::vector<int> legal_shapes(int elem_bytes, int family) {
     std::vector<int> s = {SHAPE_64x4x4, SHAPE_64x4x2, SHAPE_32x8x2, SHAPE_64x8x2, SHAPE_64x8x1};
-    if (family == FAMILY_APPLY && elem_bytes == 8) s.push_back(SHAPE_64x8x4);
+    if (family == FAMILY_APPLY && elem_bytes <= 8) s.push_back(SHAPE_64x8x4);
     return s;
 }
 

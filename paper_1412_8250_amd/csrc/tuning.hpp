@@ -17,7 +17,7 @@ enum StencilShape {
     SHAPE_32x8x2 = 2,    // 32 x 16 tile, 256 threads
     SHAPE_64x8x2 = 3,    // 64 x 16 tile, 512 threads
     SHAPE_64x8x1 = 4,    // 64 x 8 tile, 512 threads
-    SHAPE_64x8x4 = 5,    // 64 x 32 tile, 512 threads: the plain FP64 apply only
+    SHAPE_64x8x4 = 5,    // 64 x 32 tile, 512 threads: the plain FP64 and FP32 applies only
                          // (fused kernels given this id run 64 x 8 x 2)
     SHAPE_COUNT = 6
 };
