@@ -898,10 +898,11 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
             for (int j : which) {
                 iters[j] += it_pass[j];
                 done[j] = done_pass[j];
-                // init: read x, f, write r; stencil phase: read r, p_old, write
-                // p, Ap; vector phase: read x, p, r, Ap, write x, r
+                // init: read x, f, write r; stencil phase: read r (z), p_old,
+                // Ap_old, write p, Ap (the first one reads r only); vector
+                // phase: read x, p, r, Ap, write x, r
                 const double n = (double)npoints(b->grids[j]);
-                bs += n * e * (3.0 + 4.0 * it_pass[j]);
+                bs += n * e * (3.0 + (it_pass[j] > 0 ? 5.0 * it_pass[j] - 2.0 : 0.0));
                 bu += n * e * 6.0 * it_pass[j];
                 if (b->precond) {
                     // one cycle and one dot phase (read r, z) after the init

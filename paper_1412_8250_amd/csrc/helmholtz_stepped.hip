@@ -4,10 +4,13 @@
 // symmetric).
 //
 // Each COCG phase is ONE launch over all running systems of the batch:
-//  * stencil phase: p = r + beta p_old formed on the fly, p and Ap = -L p +
-//    kappa p written, p^T Ap reduced;  the grid holds the stencil tiles of
-//    every system (block -> system by a prefix table, XCD-aware order), so
-//    eight 320^3 systems give thousands of workgroups per launch;
+//  * stencil phase: the stencil runs on r alone (A r = -L r + kappa r); the
+//    new direction and its image follow point by point from the previous
+//    ones, p = r + beta p_old and Ap = A r + beta Ap_old (A is linear), so
+//    only one array is read with a halo; p^T Ap is reduced;  the grid holds
+//    the stencil tiles of every system (block -> system by a prefix table,
+//    XCD-aware order), so eight 320^3 systems give thousands of workgroups
+//    per launch;
 //  * vector phase: x += alpha p, r -= alpha Ap, r^T r and |r|^2 reduced.
 // The scalars of every system (alpha, beta, r^T r, status) live on the
 // device: the last workgroup of a system to finish a phase combines that
@@ -20,8 +23,8 @@
 // With a preconditioner M (one multigrid cycle per system, complex
 // symmetric) the iteration is preconditioned COCG: after the vector phase
 // z = M r is formed by the cycle's own launches, a dot phase reduces
-// rho = r^T z and sets beta = rho_new / rho, and the stencil phase builds
-// p = z + beta p_old.
+// rho = r^T z and sets beta = rho_new / rho, and the stencil phase runs on z:
+// p = z + beta p_old, Ap = A z + beta Ap_old.
 #include <algorithm>
 #include <cmath>
 
@@ -60,12 +63,6 @@ struct StepLoadX {
     __device__ T operator()(int64_t i) const { return x[i]; }
 };
 
-template <typename T>
-struct StepLoadP {       // r + beta p_old (first iteration: p_old = r, beta = 0); z for r when preconditioned
-    GPtr<T> r, p_old;
-    T beta;
-    __device__ T operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
-};
 
 template <typename T>
 struct StepEpiInit {     // r = f - (-L x + kappa x); acc {r^T r re, im, |r|^2, |f|^2}
@@ -87,18 +84,34 @@ struct StepEpiInit {     // r = f - (-L x + kappa x); acc {r^T r re, im, |r|^2, 
     }
 };
 
+// Centre = r (z when preconditioned), s = L r.  p = r + beta p_old and
+// Ap = (-L r + kappa r) + beta Ap_old, Ap updated in place (each point is read
+// and written by the same thread); the first iteration (beta = 0) reads
+// neither p_old nor Ap_old.  acc {p^T Ap re, im}.
 template <typename T>
-struct StepEpiPAp {      // p_new = centre, Ap = -L p + kappa p; acc {p^T Ap re, im}
-    GPtr<T> p_out, Ap;
-    T kappa;
+struct StepEpiPAp {
+    GPtr<T> p_old, p_out, Ap;
+    T kappa, beta;
+    bool first;
     double acc[2];
-    __device__ void pre(int, int64_t) {}
-    __device__ void point(int, int64_t i, T c, T s) {
-        const T a = cfma(kappa, c, T{-s.x, -s.y});
-        p_out.st(i, c);
+    T po[4], ao[4];
+    __device__ void pre(int q, int64_t i) {
+        if (!first) {
+            po[q] = p_old[i];
+            ao[q] = Ap[i];
+        }
+    }
+    __device__ void point(int q, int64_t i, T c, T s) {
+        T a = cfma(kappa, c, T{-s.x, -s.y});
+        T p = c;
+        if (!first) {
+            p = cfma(beta, po[q], c);
+            a = cfma(beta, ao[q], a);
+        }
+        p_out.st(i, p);
         Ap.st(i, a);
-        acc[0] += (double)c.x * a.x - (double)c.y * a.y;
-        acc[1] += (double)c.x * a.y + (double)c.y * a.x;
+        acc[0] += (double)p.x * a.x - (double)p.y * a.y;
+        acc[1] += (double)p.x * a.y + (double)p.y * a.x;
     }
 };
 
@@ -147,16 +160,10 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int tota
         const void *p_old = sj->parity ? h.pB : h.pA;
         const void *p_new = sj->parity ? h.pA : h.pB;
         const void *base = h.z ? h.z : h.r;
-        StepLoadP<T> ld{GPtr<T>(base), GPtr<T>(first ? base : p_old),
-                        first ? CT::mk(0.0, 0.0) : CT::mk(sj->be_re, sj->be_im)};
-        StepEpiPAp<T> ep{GPtr<T>(p_new), GPtr<T>(h.Ap), kappa, {0, 0}};
-        // The two-array loader doubles the registers of in-flight ring fetches:
-        // with 512 threads (at most 256 registers per lane) complex128 keeps
-        // two ring buffers, deeper staging would spill.
-        using SLd = StencilLds<T, TX, TYT, RY>;
-        constexpr int PR = (sizeof(T) == 16 && TX * TYT >= 512) ? 2 : SLd::kRingDepth;
-        stencil_tile<T, TX, TYT, RY, StepLoadP<T>, StepEpiPAp<T>, SLd::kLead, PR>(h.tg, coef_of<T>(h), ld,
-                                                                                 ep, unit, lds);
+        StepLoadX<T> ld{GPtr<T>(base)};
+        StepEpiPAp<T> ep{GPtr<T>(p_old), GPtr<T>(p_new), GPtr<T>(h.Ap), kappa,
+                         CT::mk(sj->be_re, sj->be_im), first, {0, 0}, {}, {}};
+        stencil_tile<T, TX, TYT, RY>(h.tg, coef_of<T>(h), ld, ep, unit, lds);
         double acc[2] = {ep.acc[0], ep.acc[1]};
         block_sum<2>(acc, scratch);
         double t[2];
