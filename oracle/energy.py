@@ -23,6 +23,23 @@ which for Gaussians is the absolutely convergent pair sum
 and f^c_J = -dE_c/dR_J.
 Forces (Section 3.3):
   f_J = sum_images int grad b_J (phi - V_J) + f^c_J.
+
+Paper forms (Section 3.3 energy expression as printed; Section 4 FD
+gradient; Appendix B):
+  * vw_gradient_form: (lambda/2) h^3 sum |grad_h u|^2 with the FD gradient;
+  * overlap_appendix_b: reference charges b~_J (Gaussians of width s_ref,
+    charge q), V_c the zero-mean solution of -L_h V_c = 4 pi (b~ - b) plus
+    the constant that makes its mean the mean of sum_J (V~_J - V_J), which
+    for Gaussians is -2 pi q M (s_ref^2 - s^2) / |Omega| (the k = 0 limit of
+    the pair's potential: its integral is -(2 pi / 3) times the second
+    moment of b~_J - b_J);
+      E_c = 1/2 h^3 sum (b~ + b) V_c + 1/2 sum_J h^3 sum b_J V_J
+            - 1/2 sum_J h^3 sum b~_J V~_J,
+      f^c_J = 1/2 sum_images h^3 sum [grad b~_J (V_c - V~_J)
+              + grad b_J (V_c + V_J) + (grad V~_J - grad V_J)(b~ + b)
+              + b_J grad V_J - b~_J grad V~_J],
+    every per-atom sum over the atom's grid points within `cut` (which must
+    cover both Gaussians).
 """
 import math
 
@@ -124,3 +141,58 @@ def forces(phi, atoms, q, s, h, cut):
     box = [n * hh for n, hh in zip(phi.shape[::-1], h)]
     _, f = self_and_forces(phi, atoms, q, s, h, cut)
     return f + overlap(atoms, q, s, box)[1]
+
+
+def gauss_dv(r, q, s):
+    """dV/dr of V = q erf(r / (sqrt 2 s)) / r (0 at r = 0)."""
+    small = r < 1e-12
+    rr = np.where(small, 1.0, r)
+    d = q * (math.sqrt(2.0 / math.pi) * np.exp(-rr * rr / (2.0 * s * s)) / (s * rr)
+             - erf(rr / (math.sqrt(2.0) * s)) / (rr * rr))
+    return np.where(small, 0.0, d)
+
+
+def vw_gradient_form(u, h, lam, N=6):
+    """(lambda/2) h^3 sum |grad_h u|^2 (Section 4 FD gradient)."""
+    dv = float(np.prod(h))
+    gx, gy, gz = fd.gradient(u, h, N)
+    return 0.5 * lam * dv * float(np.sum(gx * gx + gy * gy + gz * gz))
+
+
+def reference_charge(atoms, shape, h, q, s_ref, cut):
+    """b~ on the grid: the Gaussians of width s_ref over each atom's points within cut."""
+    bt = np.zeros(int(np.prod(shape)))
+    for R in atoms:
+        idx, _, r = _atom_points(R, shape, h, cut)
+        np.add.at(bt, idx, gauss_b(r, q, s_ref))
+    return bt.reshape(shape)
+
+
+def overlap_appendix_b(b, atoms, q, s, s_ref, h, cut, N=6):
+    """(E_c, f^c [M x 3], V_c) by the grid form of Appendix B."""
+    shape = b.shape
+    dv = float(np.prod(h))
+    volume = dv * b.size
+    atoms = np.asarray(atoms, dtype=float)
+    bt = reference_charge(atoms, shape, h, q, s_ref, cut)
+    g, _ = poisson.rhs(bt, -b)
+    vc = poisson.solve_exact(g, h, N) - 2.0 * math.pi * q * len(atoms) * (s_ref ** 2 - s ** 2) / volume
+    e = 0.5 * dv * float(np.sum((bt + b) * vc))
+    f = np.zeros_like(atoms)
+    vcf, btf, bf = vc.reshape(-1), bt.reshape(-1), b.reshape(-1)
+    for J, R in enumerate(atoms):
+        idx, d, r = _atom_points(R, shape, h, cut)
+        bj, vj = gauss_b(r, q, s), gauss_v(r, q, s)
+        btj, vtj = gauss_b(r, q, s_ref), gauss_v(r, q, s_ref)
+        e += 0.5 * dv * float(np.sum(bj * vj)) - 0.5 * dv * float(np.sum(btj * vtj))
+        rr = np.where(r < 1e-12, 1.0, r)[:, None]
+        unit = d / rr
+        grad_b = -bj[:, None] * d / (s * s)
+        grad_bt = -btj[:, None] * d / (s_ref * s_ref)
+        grad_v = gauss_dv(r, q, s)[:, None] * unit
+        grad_vt = gauss_dv(r, q, s_ref)[:, None] * unit
+        tot = (btf[idx] + bf[idx])[:, None]
+        integrand = (grad_bt * (vcf[idx] - vtj)[:, None] + grad_b * (vcf[idx] + vj)[:, None]
+                     + (grad_vt - grad_v) * tot + bj[:, None] * grad_v - btj[:, None] * grad_vt)
+        f[J] = 0.5 * dv * np.sum(integrand, axis=0)
+    return e, f, vc

@@ -1,9 +1,12 @@
-"""Finite-difference Laplacian of order 2N on a periodic uniform grid.
+"""Finite-difference Laplacian and gradient of order 2N on a periodic uniform
+grid.
 
 Section 4, FD Laplacian equation: the Laplacian at (i,j,k) is the sum over
 p = 0..N of w_p times the six values at offsets +-p along each axis, with the
 weight formulas given there; indices outside the grid map to their periodic
-images.
+images.  Section 4, FD gradient equation: each component is the sum over
+p = 1..N of w~_p times the difference of the values at offsets +p and -p
+along its axis.
 """
 from fractions import Fraction
 from math import factorial
@@ -21,6 +24,27 @@ def weights_exact(N: int):
         ws.append(Fraction(2 * (-1) ** (p + 1) * factorial(N) ** 2,
                            p * p * factorial(N - p) * factorial(N + p)))
     return ws
+
+
+def gradient_weights_exact(N: int):
+    """Exact rational first-derivative weights w~_1 .. w~_N for h = 1
+    (Section 4, the weights of the FD gradient equation)."""
+    return [Fraction((-1) ** (p + 1) * factorial(N) ** 2, p * factorial(N - p) * factorial(N + p))
+            for p in range(1, N + 1)]
+
+
+def gradient(x: np.ndarray, h_xyz, N: int = 6):
+    """(d/dx, d/dy, d/dz) of a real [nz][ny][nx] array by the periodic FD
+    gradient: sum_p w~_p / h (f(i + p) - f(i - p)) along each axis."""
+    x = np.asarray(x, dtype=np.float64)
+    out = []
+    for axis, hh in zip((2, 1, 0), h_xyz):
+        w = [float(c) / hh for c in gradient_weights_exact(N)]
+        g = np.zeros_like(x)
+        for p in range(1, N + 1):
+            g += w[p - 1] * (np.roll(x, -p, axis=axis) - np.roll(x, p, axis=axis))
+        out.append(g)
+    return tuple(out)
 
 
 def weights(N: int, h: float) -> np.ndarray:
