@@ -99,6 +99,21 @@ int fd_laplacian_apply(const ofdft_grid *grid, int radius, ofdft_dtype dtype,
                        const void *x, void *y, double alpha, double beta, void *stream);
 
 /* ------------------------------------------------------------------------
+ * fd_gradient_apply -- (gx, gy, gz) = grad_h x
+ *
+ * The order-2N central-difference gradient of Section 4 (FD gradient
+ * equation): component a is sum over p = 1..N of w~_p (x(+p) - x(-p)) along
+ * axis a, w~_p = (-1)^{p+1} (N!)^2 / (h_a p (N-p)!(N+p)!), periodic images.
+ *   grid    grid descriptor (host); radius N in 1..6
+ *   x       device FP64 array of nx*ny*nz elements
+ *   gx, gy, gz  device FP64 outputs of the same size; x and the outputs must
+ *           be four distinct arrays
+ * Errors: INVALID_ARG for bad sizes/radius, null or repeated pointers.
+ * ------------------------------------------------------------------------ */
+int fd_gradient_apply(const ofdft_grid *grid, int radius, const double *x, double *gx, double *gy,
+                      double *gz, void *stream);
+
+/* ------------------------------------------------------------------------
  * Periodic Poisson solve (Section 3.3, Poisson equation; Section 4 solver
  * notes): finds phi with -L_h phi = P g and sum(phi) = 0, where
  * P = I - (1/n) 1 1^T removes the mean of the right-hand side.  The paper
@@ -432,6 +447,29 @@ typedef struct {
 } ofdft_gauss_atoms;
 int ofdft_scf_energy(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double *terms, void *stream);
 int ofdft_scf_forces(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double *forces, void *stream);
+
+/* The same terms and forces in the forms the paper prints:
+ *   - von Weizsacker term (lambda/2) h^3 sum |grad_h u|^2 with the FD gradient
+ *     of Section 4 (fd_gradient_apply);
+ *   - overlap correction by the grid form of Appendix B: reference charges
+ *     b~_J = Gaussians of width sigma_ref (same charge), V_c from one Poisson
+ *     solve of -L_h V_c = 4 pi (b~ - b) with the context's solver and
+ *     poisson_tol, its constant set so that V_c has the mean of
+ *     sum_J (V~_J - V_J), i.e. -2 pi charge M (sigma_ref^2 - sigma^2) / |Omega|;
+ *       E_c = 1/2 h^3 sum (b~ + b) V_c + 1/2 sum_J h^3 sum b_J V_J
+ *             - 1/2 sum_J h^3 sum b~_J V~_J
+ *     and the Appendix B force correction f^c_J (per-atom sums).  With
+ *     non-overlapping reference charges both tend to the closed forms of
+ *     ofdft_scf_energy / ofdft_scf_forces as h -> 0.
+ * `cutoff` must cover both Gaussians (e.g. 8.5 max(sigma, sigma_ref)).
+ * terms: the 8 doubles of ofdft_scf_energy with [1], [5] and [7] in these
+ * forms.  They use the density-update workspace (not during a step).
+ * Returns NOT_CONVERGED (results written) if the Poisson solve missed its
+ * tolerance; INVALID_ARG for a bad context, atoms or sigma_ref <= 0. */
+int ofdft_scf_energy_paper_form(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double sigma_ref,
+                                double *terms, void *stream);
+int ofdft_scf_forces_paper_form(ofdft_scf *s, const ofdft_gauss_atoms *atoms, double sigma_ref,
+                                double *forces, void *stream);
 
 /* The density update U(v) alone (Algorithm 1), using the context's parameters:
  * v, u device FP64; u holds the starting guess on entry and U(v) on exit.

@@ -81,6 +81,7 @@ def _declare(l):
         "ofdft_last_error": (_I, [ctypes.c_char_p, ctypes.c_size_t]),
         "ofdft_version": (ctypes.c_char_p, []),
         "fd_laplacian_apply": (_I, [_GP, _I, _I, _V, _V, _D, _D, _V]),
+        "fd_gradient_apply": (_I, [_GP, _I, _V, _V, _V, _V, _V]),
         "ofdft_poisson_create": (_I, [_GP, _I, _I, ctypes.POINTER(_V)]),
         "ofdft_poisson_destroy": (_I, [_V]),
         "cg_poisson_solve": (_I, [_V, _V, _V, _D, _I, _SP, _V]),
@@ -108,6 +109,8 @@ def _declare(l):
         "ofdft_batch_set_config": (_I, [_V, _I, _I]),
         "ofdft_batch_set_preconditioner": (_I, [_V, _I]),
         "ofdft_scf_energy": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
+        "ofdft_scf_energy_paper_form": (_I, [_V, ctypes.POINTER(GaussAtoms), _D, ctypes.POINTER(_D), _V]),
+        "ofdft_scf_forces_paper_form": (_I, [_V, ctypes.POINTER(GaussAtoms), _D, ctypes.POINTER(_D), _V]),
         "ofdft_scf_forces": (_I, [_V, ctypes.POINTER(GaussAtoms), ctypes.POINTER(_D), _V]),
         "ofdft_batch_apply_preconditioner": (_I, [_V, _I, ctypes.POINTER(_D), _V, _V, _V]),
         "ofdft_multishift_create": (_I, [ctypes.POINTER(Grid), _I, _I, ctypes.POINTER(_V)]),
@@ -215,6 +218,17 @@ def fd_laplacian_apply(x, y, h_xyz, radius: int = 6, alpha: float = 1.0, beta: f
     _check(lib().fd_laplacian_apply(ctypes.byref(g), int(radius), _dtype_code(x), _dev(x), _dev(y),
                                     float(alpha), float(beta), _stream(stream)))
     return y
+
+
+def fd_gradient_apply(x, gx, gy, gz, h_xyz, radius: int = 6, stream=None):
+    """(gx, gy, gz) = FD gradient of x (FP64, periodic, order 2*radius)."""
+    for t in (gx, gy, gz):
+        if t.dtype != x.dtype or t.shape != x.shape:
+            raise ValueError("gradient outputs must match x in dtype and shape")
+    g = grid_of(x.shape, h_xyz)
+    _check(lib().fd_gradient_apply(ctypes.byref(g), int(radius), _dev(x), _dev(gx), _dev(gy), _dev(gz),
+                                   _stream(stream)))
+    return gx, gy, gz
 
 
 KERNEL_CLASSES = ("apply", "cg_stencil", "cg_update", "residual", "cocg", "u_stencil", "u_vector",
@@ -610,6 +624,27 @@ class SCF:
         out = (ctypes.c_double * 8)()
         _check(lib().ofdft_scf_energy(self._h, ctypes.byref(a), out, _stream(stream)))
         return dict(zip(self.ENERGY_TERMS, list(out)))
+
+    def energy_paper_form(self, pos, sigma_ref: float, charge: float = -3.0, sigma: float = 0.8, cutoff=None,
+                          stream=None, allow_not_converged: bool = False) -> dict:
+        """Energy terms with the FD-gradient von Weizsacker term and the Appendix B
+        grid-form overlap correction (reference Gaussians of width sigma_ref)."""
+        a, keep = self._atoms(pos, charge, sigma, 8.5 * max(sigma, sigma_ref) if cutoff is None else cutoff)
+        out = (ctypes.c_double * 8)()
+        st = lib().ofdft_scf_energy_paper_form(self._h, ctypes.byref(a), float(sigma_ref), out, _stream(stream))
+        _check(st, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        return dict(zip(self.ENERGY_TERMS, list(out)))
+
+    def forces_paper_form(self, pos, sigma_ref: float, charge: float = -3.0, sigma: float = 0.8, cutoff=None,
+                          stream=None, allow_not_converged: bool = False):
+        """Forces with the Appendix B grid-form correction (M x 3, hartree/bohr)."""
+        import numpy as _np
+        a, keep = self._atoms(pos, charge, sigma, 8.5 * max(sigma, sigma_ref) if cutoff is None else cutoff)
+        out = _np.zeros((a.count, 3))
+        st = lib().ofdft_scf_forces_paper_form(self._h, ctypes.byref(a), float(sigma_ref),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream))
+        _check(st, (OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        return out
 
     def forces(self, pos, charge: float = -3.0, sigma: float = 0.8, cutoff=None, stream=None):
         """Forces on the nuclei (M x 3, hartree/bohr) from the current state."""
