@@ -21,6 +21,15 @@ The search runs along d_q (the printed listing shows r_q, which would leave
 the Polak-Ribiere direction unused); all norms are h^3-weighted.
 Stops when ||H u - eta u|| / ||u|| <= tol.
 
+Hartree inside (the paper's own map U(V_LR), Section 3.3 fixed point in the
+kernel potential): with pseudocharges b given, the functional also holds the
+electrostatic energy 1/2 h^3 sum (rho + b) phi[rho], phi[rho] the zero-mean
+solution of -L_h phi = 4 pi (rho + b) (exact, spectral), and v is only the
+external part (mu V_LR).  Its gradient is the same 2 (H u - eta u) with phi
+added to the potential, because the electrostatic energy is quadratic and
+symmetric in rho + b; every evaluation of H (residual, line-search slope)
+re-solves phi for the u it is evaluated at.
+
 Line search: Brent's method is applied to the root of the directional
 derivative dE/ds (Brent-Dekker root finding after bracketing), which is where
 the minimum along the line sits.  A derivative-free search on E(s) itself
@@ -32,7 +41,7 @@ is flat there, and the outer iteration then stalls near 1e-8.
 import numpy as np
 from scipy.optimize import brentq
 
-from . import fd, xc
+from . import fd, poisson, xc
 
 
 def _dv(h_xyz):
@@ -58,10 +67,21 @@ def el_residual(u, v, h_xyz, lam, n_electrons, N=6):
     return float(np.linalg.norm(hu - eta * u) / np.linalg.norm(u)), eta
 
 
-def update(u0, v, h_xyz, lam, n_electrons, N=6, tol=1e-10, n_restart=50, maxit=20000):
-    """Algorithm 1; returns (u, iterations, final residual, eta)."""
+def hartree(u, b, h_xyz, N=6):
+    """phi[rho]: zero-mean solution of -L_h phi = 4 pi (u^2 + b)."""
+    g, _ = poisson.rhs(u * u, b)
+    return poisson.solve_exact(g, h_xyz, N)
+
+
+def update(u0, v, h_xyz, lam, n_electrons, N=6, tol=1e-10, n_restart=50, maxit=20000, b=None):
+    """Algorithm 1; returns (u, iterations, final residual, eta).  With b the
+    electrostatic energy is part of the functional (phi re-solved for every u)."""
     dv = _dv(h_xyz)
     sqn = np.sqrt(n_electrons)
+
+    def ham(uu):
+        vt = v if b is None else v + hartree(uu, b, h_xyz, N)
+        return hamiltonian(uu, vt, h_xyz, lam, N)
 
     def inner(a, b):
         return dv * float((a * b).sum())
@@ -76,7 +96,7 @@ def update(u0, v, h_xyz, lam, n_electrons, N=6, tol=1e-10, n_restart=50, maxit=2
     eta = 0.0
     q = 0
     while q < maxit:
-        hu = hamiltonian(u, v, h_xyz, lam, N)
+        hu = ham(u)
         eta = inner(u, hu) / n_electrons
         r = -2.0 * (hu - eta * u)
         res = float(np.linalg.norm(hu - eta * u) / np.linalg.norm(u))
@@ -93,7 +113,7 @@ def update(u0, v, h_xyz, lam, n_electrons, N=6, tol=1e-10, n_restart=50, maxit=2
             ww = inner(w, w)
             us = sqn * w / np.sqrt(ww)
             dus = (sqn / np.sqrt(ww)) * (d - w * (inner(w, d) / ww))
-            return 2.0 * inner(hamiltonian(us, v, h_xyz, lam, N), dus)
+            return 2.0 * inner(ham(us), dus)
 
         if slope(0.0) >= 0.0:          # not a descent direction: restart along r
             d = r

@@ -60,3 +60,40 @@ class SCF:
         err = float(np.linalg.norm(f)) / nv if nv > 0 else float(np.linalg.norm(f))
         self.v = self.mixer.step(self.v, f).reshape(self.v.shape)
         return err
+
+
+def kernel_potential(u, h_xyz, n_electrons, volume, N=6):
+    """V_LR[u] from the shifted solves (K_00, Appendix A)."""
+    rho = u * u
+    V = kernel.solve_all(rho, h_xyz, n_electrons, volume, N)
+    return kernel.potential(rho, V, 1e-12 * n_electrons / volume)
+
+
+class KernelPotentialSCF:
+    """The paper's own fixed point (Section 3.3, the map V_LR -> V[U(V_LR)] and
+    the flowchart): the mixing variable is the kernel potential V_LR alone and
+    U minimises the functional with the electrostatics inside (phi re-solved
+    for every u, density.update with b), with mu V_LR as the external
+    potential.  Start: u_0 = sqrt(rho_0), V_0 = V_LR[u_0].  Error:
+    ||Vhat_k - V_k|| / ||V_k||.  For mu = 0 one step gives the TFW ground
+    state and the error is 0."""
+
+    def __init__(self, rho0, b, h_xyz, n_electrons, volume, p: Params):
+        self.b, self.h, self.ne, self.vol, self.p = b, h_xyz, n_electrons, volume, p
+        self.u = np.sqrt(rho0)
+        self.V = (kernel_potential(self.u, h_xyz, n_electrons, volume, p.N) if p.mu
+                  else np.zeros_like(self.u))
+        self.mixer = Anderson(p.history, p.zeta)
+
+    def step(self):
+        p = self.p
+        self.u, it, res, eta = density.update(self.u, p.mu * self.V, self.h, p.lam, self.ne, p.N,
+                                              tol=p.u_tol, n_restart=p.n_restart, b=self.b)
+        if not p.mu:
+            return 0.0
+        vhat = kernel_potential(self.u, self.h, self.ne, self.vol, p.N)
+        f = vhat - self.V
+        nv = float(np.linalg.norm(self.V))
+        err = float(np.linalg.norm(f)) / nv if nv > 0 else float(np.linalg.norm(f))
+        self.V = self.mixer.step(self.V, f).reshape(self.V.shape)
+        return err
