@@ -312,6 +312,20 @@ int anderson_mix(ofdft_anderson *a, const double *v, const double *f, double *v_
  *            (Section 3.1 with m = n = 0; Appendix A table)      (mu = 1 only)
  *   vhat   = phi + mu V_LR,  f = vhat - v,  v <- Anderson(v, f)
  * and reports ||f|| / ||v||.
+ * fixed_point = 1 takes the paper's own form instead: the mixing variable is
+ * the kernel potential V_LR alone and U keeps the electrostatics inside its
+ * functional (the map U(V_LR) of Section 3.3), so a step is
+ *   u      = U(mu V_LR) -- minimiser of the functional above with
+ *            v = mu V_LR + phi[u] and the electrostatic energy
+ *            1/2 h^3 sum (rho + b) phi[rho] added, phi re-solved for every u
+ *   phi    = Poisson(4 pi (u^2 + b));  Vhat = V_LR[u] (8 shifted solves)
+ *   f = Vhat - V_LR,  V_LR <- Anderson(V_LR, f),  reports ||f|| / ||V_LR||
+ * (0 for mu = 0, where one step gives the TFW ground state).  U solves two
+ * Poisson equations per iteration, for the fields of u d and d^2 (d the
+ * search direction); phi along the line u + s d follows from them exactly,
+ * and each line-search probe is a pointwise pass.  The potential form mixes
+ * the electrostatic response too, which the paper reports (and large cells
+ * show) to become unstable as the cell grows.
  * ------------------------------------------------------------------------ */
 typedef struct {
     ofdft_grid grid;
@@ -367,11 +381,16 @@ typedef struct {
                                   (ofdft_tune_stencil) and, for mu = 1, the shifted-
                                   system batch on the first batched kernel solve
                                   (ofdft_batch_tune, 8 iterations); 0 = untuned      */
+    int fixed_point;           /* 0 = potential mixing (v = phi + mu V_LR, U local);
+                                  1 = the kernel-potential fixed point with the
+                                  electrostatics inside U (see above); state vector 0
+                                  then holds V_LR                                      */
 } ofdft_scf_params;
 
 typedef struct ofdft_scf ofdft_scf;
 /* b: device FP64 nuclear charge density; u0: device FP64 initial sqrt-density.
- * Both are copied.  Computes v_0 = phi[u0] + mu V_LR[u0].
+ * Both are copied.  Computes v_0 = phi[u0] + mu V_LR[u0] (fixed_point 1:
+ * V_LR[u0], and the field of b alone for the electrostatics inside U).
  * Status of create and step: the worst of their parts.  NOT_CONVERGED (the
  * context is still created, the step still taken and *fp_residual written)
  * when U(v) stopped above u_tol (u_max_iter reached, or no descent direction

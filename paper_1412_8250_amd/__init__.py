@@ -52,7 +52,8 @@ class ScfParams(ctypes.Structure):
                 ("helmholtz_dtype", ctypes.c_int), ("max_iter", ctypes.c_int), ("line_tol", ctypes.c_double),
                 ("helmholtz_precond", ctypes.c_int), ("u_precond", ctypes.c_int), ("lr_order", ctypes.c_int),
                 ("u_precond_sigma", ctypes.c_double), ("line_slope_tol", ctypes.c_double),
-                ("helmholtz_multishift", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("helmholtz_multishift", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("fixed_point", ctypes.c_int)]
 
 
 class TuneResult(ctypes.Structure):
@@ -513,7 +514,11 @@ class Anderson:
 
 
 class SCF:
-    """Fixed-point iteration context (mixing variable v = phi + mu V_LR)."""
+    """Fixed-point iteration context: mixing variable v = phi + mu V_LR
+    (fixed_point 0) or the kernel potential V_LR with the electrostatics
+    inside U (fixed_point 1, the paper's form)."""
+
+    POTENTIAL, KERNEL_POTENTIAL = 0, 1
 
     V, U, PHI, VLR = 0, 1, 2, 3
 
@@ -524,7 +529,7 @@ class SCF:
                  radius: int = 6, line_tol: float = 0.0, helmholtz_precond: int = PRECOND_NONE,
                  u_precond: int = PRECOND_NONE, lr_order: int = 0, u_precond_sigma: float = 0.0,
                  line_slope_tol: float = 0.0, helmholtz_multishift: bool = False, stream=None,
-                 allow_not_converged: bool = False, autotune: bool = False):
+                 allow_not_converged: bool = False, autotune: bool = False, fixed_point: int = 0):
         self.shape = tuple(shape_zyx)
         p = ScfParams()
         p.grid = grid_of(shape_zyx, h_xyz)
@@ -540,6 +545,7 @@ class SCF:
         p.line_slope_tol = float(line_slope_tol)
         p.helmholtz_multishift = int(bool(helmholtz_multishift))
         p.autotune = int(bool(autotune))
+        p.fixed_point = int(fixed_point)
         self.params = p
         self._h = ctypes.c_void_p()
         st = lib().ofdft_scf_create(ctypes.byref(p), _dev(b, self.shape), _dev(u0, self.shape),

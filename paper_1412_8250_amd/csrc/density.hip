@@ -15,6 +15,16 @@
 // Weizsacker part of dE/ds is a quadratic in s built from the Kd/Ka totals, so
 // each probe reads only u, d and v.
 //
+// Electrostatics inside (fixed_point 1, the paper's map U(V_LR)): v is the
+// external potential and the functional also holds 1/2 h^3 sum (rho + b)
+// phi[rho].  Its gradient keeps the form 2 (H u - eta u) with phi[rho] added
+// to the potential.  Along the line, rho_s = c_s^2 (u + s d)^2 with
+// c_s^2 = N_e / (h^3 ||u + s d||^2), so by linearity
+//   phi_s = phi[b] + c_s^2 (Q0 + 2 s Q1 + s^2 Q2),
+// Q0, Q1, Q2 the zero-mean fields of u^2, u d and d^2: two Poisson solves per
+// iteration (Q1, Q2) make every probe a pointwise pass, and the accepted
+// step updates Q0 by the same formula.  Q0 is solved afresh at entry.
+//
 // Optional preconditioning (not in the paper; its conclusion calls for
 // real-space preconditioners, Section 5.5): the steepest-descent direction r
 // is replaced by z = M r projected onto the tangent space of the constraint,
@@ -190,6 +200,72 @@ struct StepOp {         // u <- c (u + s d)
     __device__ void operator()(int64_t i, double (&)[1]) const { u[i] = c * ::fma(s, d[i], u[i]); }
 };
 
+// electrostatics inside U ------------------------------------------------
+struct SrcOp {          // g = 4 pi a b (the source of the field of a b)
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 24;
+    const double *a, *b;
+    double *g;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { g[i] = 4.0 * kPi * a[i] * b[i]; }
+};
+
+struct ZeroVecOp {
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 8;
+    double *x;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { x[i] = 0.0; }
+};
+
+struct PotPrepOp {      // P = v + phi[b], V = P + Q0
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 40;
+    const double *v, *pb, *q0;
+    double *P, *V;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        const double p = v[i] + pb[i];
+        P[i] = p;
+        V[i] = p + q0[i];
+    }
+};
+
+struct EvalHOp {        // EvalOp with the potential of the probe: P + c2 (Q0 + 2 s Q1 + s^2 Q2)
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 48;
+    const double *u, *d, *P, *q0, *q1, *q2;
+    double s, c2, t;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double w = ::fma(s, d[i], u[i]);
+        const double rho = c2 * w * w;
+        const double vl = rho > 0.0 ? v_local(rho) : 0.0;
+        const double vs = ::fma(c2, ::fma(s, ::fma(s, q2[i], 2.0 * q1[i]), q0[i]), P[i]);
+        acc[0] = ::fma((vl + vs) * w, ::fma(-t, w, d[i]), acc[0]);
+    }
+};
+
+struct StepHOp {        // u <- c (u + s d); Q0 <- c^2 (Q0 + 2 s Q1 + s^2 Q2); V = P + Q0
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 72;
+    double *u, *q0, *V;
+    const double *d, *q1, *q2, *P;
+    double s, c;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        u[i] = c * ::fma(s, d[i], u[i]);
+        const double q = c * c * ::fma(s, ::fma(s, q2[i], 2.0 * q1[i]), q0[i]);
+        q0[i] = q;
+        V[i] = P[i] + q;
+    }
+};
+
 template <class Load, class Epi>
 int stencil_pass(const ofdft_grid &g, const Coef<double> &c, const Load &ld, const Epi &ep, hipStream_t s,
                  int bytes_per_point) {
@@ -281,10 +357,29 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     double f0_prev = 0.0;                        // slope at s = 0 of the previous iteration
     const int maxit = s->p.u_max_iter > 0 ? s->p.u_max_iter : 20000;
     const int nres = s->p.n_restart > 0 ? s->p.n_restart : 50;
+    // electrostatics inside: the field of a b into x by the context's Poisson solver
+    const bool hart = s->p.fixed_point == 1;
+    int worst = OFDFT_OK;
+    s->u_pois_it = 0;
+    auto field = [&](const double *a, const double *b, double *x, bool zero) -> int {
+        OFDFT_TRY((launch_reduce<1>(n, SrcOp{a, b, s->g4}, NoFin{}, s->rb, st)));
+        if (zero) OFDFT_TRY((launch_reduce<1>(n, ZeroVecOp{x}, NoFin{}, s->rb, st)));
+        ofdft_solve_stats ps{};
+        const int pst = poisson_solve(s->pois, s->g4, x, s->p.poisson_tol, s->p.max_iter, ps, st);
+        if (pst < 0) return pst;
+        s->u_pois_it += ps.iters;
+        worst = std::max(worst, pst);
+        return OFDFT_OK;
+    };
+    if (hart) {
+        OFDFT_TRY(field(u, u, s->hQ0, false));          // warm start: the previous field
+        OFDFT_TRY((launch_reduce<1>(n, PotPrepOp{v, s->hPb, s->hQ0, s->hP, s->hV}, NoFin{}, s->rb, st)));
+    }
+    const double *vtot = hart ? s->hV : v;
     for (;;) {
         // Ka: H u
         OFDFT_TRY(stencil_pass(g, s->coef, LoadPlain<double>{u},
-                               EpiHu{v, s->Hu, s->dsc, s->rb.partials, s->rb.counter, 0.5 * lam,
+                               EpiHu{vtot, s->Hu, s->dsc, s->rb.partials, s->rb.counter, 0.5 * lam,
                                      dv / ne, 0, 0, 0},
                                st, 24));
         // Kb: r
@@ -345,8 +440,13 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
             const double ww = uu + sv * (2.0 * ud + sv * dd);
             const double t = (ud + sv * dd) / ww;
             const double c2 = ne / (dv * ww);
-            EvalOp ev{u, d_cur, v, sv, c2, t};
-            OFDFT_TRY((launch_reduce<1>(n, ev, StoreTotals<1>{s->dsc + S_EVAL}, s->rb, st)));
+            if (hart) {
+                EvalHOp ev{u, d_cur, s->hP, s->hQ0, s->hQ1, s->hQ2, sv, c2, t};
+                OFDFT_TRY((launch_reduce<1>(n, ev, StoreTotals<1>{s->dsc + S_EVAL}, s->rb, st)));
+            } else {
+                EvalOp ev{u, d_cur, v, sv, c2, t};
+                OFDFT_TRY((launch_reduce<1>(n, ev, StoreTotals<1>{s->dsc + S_EVAL}, s->rb, st)));
+            }
             OFDFT_TRY(fetch(s, S_EVAL, 1, st));
             const double vw = uLd + sv * dLd - t * (uLu + sv * (2.0 * uLd + sv * dLd));
             out = c2 * (s->hsc[S_EVAL] - 0.5 * lam * vw);
@@ -360,6 +460,10 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
             f0 = slope0();
         }
         if (!(f0 < 0.0)) break;                  // no descent possible at this precision
+        if (hart) {                              // the fields of u d and d^2 along this direction
+            OFDFT_TRY(field(u, d_cur, s->hQ1, true));
+            OFDFT_TRY(field(d_cur, d_cur, s->hQ2, true));
+        }
         double lo = 0.0, flo = f0;
         // first probe: the previous step scaled by the ratio of the slopes at
         // s = 0 (the first-order decrease of the last step, repeated), kept
@@ -398,8 +502,13 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
             OFDFT_TRY(brent_root(slope, lo, hi, flo, fhi, ltol * hi, ftol, 200, sstar));
         const double ww = uu + sstar * (2.0 * ud + sstar * dd);
         const double c = sqn / std::sqrt(dv * ww);
-        StepOp so{u, d_cur, sstar, c};
-        OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+        if (hart) {
+            StepHOp so{u, s->hQ0, s->hV, d_cur, s->hQ1, s->hQ2, s->hP, sstar, c};
+            OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+        } else {
+            StepOp so{u, d_cur, sstar, c};
+            OFDFT_TRY((launch_reduce<1>(n, so, NoFin{}, s->rb, st)));
+        }
         s_prev = std::fabs(sstar);
         f0_prev = f0;
         rr_prev = rr;
@@ -411,8 +520,9 @@ int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double 
     s->s_prev = s_prev;
     iters = q;
     // stopped by the iteration cap or by the lack of a descent direction
-    // before the tolerance: the result is written, the status says so
-    return res <= s->p.u_tol ? OFDFT_OK : OFDFT_NOT_CONVERGED;
+    // before the tolerance (or a Poisson solve inside missed its own): the
+    // result is written, the status says so
+    return std::max(res <= s->p.u_tol ? OFDFT_OK : OFDFT_NOT_CONVERGED, worst);
 }
 
 }  // namespace ofdft

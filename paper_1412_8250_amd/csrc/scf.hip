@@ -436,16 +436,17 @@ int lr2_potential(ofdft_scf *s, hipStream_t st, int &helm_it, double &helm_res) 
     return worst;
 }
 
-struct MixResidOp {     // vhat = phi + mu vlr; f = vhat - v; totals {|f|^2, |v|^2}
+struct MixResidOp {     // vhat = phi + mu vlr (kernel_only: mu vlr); f = vhat - v; totals {|f|^2, |v|^2}
     static constexpr int kClass = K_POINTWISE;
     static constexpr int kBytes = 32;
     const double *phi, *vlr, *v;
     double *f;
     double mu;
+    int kernel_only;
     __device__ bool skip() const { return false; }
     __device__ void prepare() {}
     __device__ void operator()(int64_t i, double (&acc)[2]) const {
-        const double vh = mu != 0.0 ? ::fma(mu, vlr[i], phi[i]) : phi[i];
+        const double vh = kernel_only ? mu * vlr[i] : (mu != 0.0 ? ::fma(mu, vlr[i], phi[i]) : phi[i]);
         const double vi = v[i];
         const double fi = vh - vi;
         f[i] = fi;
@@ -462,6 +463,29 @@ struct CopyOp {
     __device__ bool skip() const { return false; }
     __device__ void prepare() {}
     __device__ void operator()(int64_t i, double (&)[1]) const { b[i] = a[i]; }
+};
+
+struct SubOp {          // y = a - b
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *a, *b;
+    double *y;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const { y[i] = a[i] - b[i]; }
+};
+
+struct BRhsOp {         // g = 4 pi b (the source of phi[b]); x = 0
+    static constexpr int kClass = K_POINTWISE;
+    static constexpr int kBytes = 24;
+    const double *b;
+    double *g, *x;
+    __device__ bool skip() const { return false; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&)[1]) const {
+        g[i] = 4.0 * kPi * b[i];
+        x[i] = 0.0;
+    }
 };
 
 template <typename P_>
@@ -600,7 +624,7 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
         !(p->u_tol > 0) || !(p->poisson_tol > 0) || (p->mu && !(p->helmholtz_tol > 0)) ||
         (p->lr_order != 0 && p->lr_order != 2) || !(p->line_slope_tol >= 0.0 && p->line_slope_tol < 1.0) ||
         (p->helmholtz_multishift != 0 && p->helmholtz_multishift != 1) ||
-        (p->autotune != 0 && p->autotune != 1)) {
+        (p->autotune != 0 && p->autotune != 1) || (p->fixed_point != 0 && p->fixed_point != 1)) {
         set_error("ofdft_scf_create: invalid parameters");
         return OFDFT_INVALID_ARG;
     }
@@ -624,6 +648,11 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
                        &s->rA, &s->rB, &s->dA, &s->dB};
     for (double **q : vecs)
         if ((rc = salloc(s, q, b8))) return fail(rc);
+    if (p->fixed_point == 1) {
+        double **hv[] = {&s->hPb, &s->hP, &s->hQ0, &s->hQ1, &s->hQ2, &s->hV};
+        for (double **q : hv)
+            if ((rc = salloc(s, q, b8))) return fail(rc);
+    }
     const bool u_mg = p->u_precond == OFDFT_PRECOND_MULTIGRID || p->u_precond == OFDFT_PRECOND_MULTIGRID_F64;
     if (u_mg && p->lambda > 0) {
         // preconditioner of the density update: -Delta + 2 sigma / lambda,
@@ -738,18 +767,29 @@ extern "C" int ofdft_scf_create(const ofdft_scf_params *p, const double *b, cons
             (rc = ofdft_tune_stencil(&p->grid, p->radius, OFDFT_F64, OFDFT_TUNE_APPLY, 5, nullptr, st)))
             return fail(rc);
     }
-    // v_0 = phi[u_0] + mu V_LR[u_0]
+    // v_0 = phi[u_0] + mu V_LR[u_0] (fixed_point 1: V_LR[u_0], and phi[b] for U)
     double pr, hr;
     int pit, hit;
-    const int mst = potential_map(s, st, pr, pit, hit, hr);
+    int bst = OFDFT_OK;
+    if (p->fixed_point == 1) {
+        if ((rc = launch_reduce<1>(s->n, BRhsOp{s->b, s->g4, s->hPb}, NoFin{}, s->rb, st)) < 0) return fail(rc);
+        ofdft_solve_stats ps{};
+        bst = poisson_solve(s->pois, s->g4, s->hPb, p->poisson_tol, s->p.max_iter, ps, st);
+        if (bst < 0) return fail(bst);
+    }
+    int mst = potential_map(s, st, pr, pit, hit, hr);
     if (mst < 0) return fail(mst);
+    mst = std::max(mst, bst);
+    if (p->fixed_point == 1 &&
+        (rc = launch_reduce<1>(s->n, SubOp{s->phi, s->hPb, s->hQ0}, NoFin{}, s->rb, st)) < 0)
+        return fail(rc);
     // the multi-shift context serves only this first kernel potential (the
     // steps warm-start the batched solver): release its vectors
     if (s->ms) {
         ofdft_multishift_destroy(s->ms);
         s->ms = nullptr;
     }
-    if ((rc = launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)p->mu},
+    if ((rc = launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)p->mu, p->fixed_point},
                                NoFin{}, s->rb, st)) < 0)
         return fail(rc);
     // v = 0 + f  (MixResidOp wrote f = vhat - 0)
@@ -780,7 +820,13 @@ extern "C" int ofdft_scf_step(ofdft_scf *s, double *fp_residual, void *stream) {
     int pit = 0, hit = 0;
     const int mst = potential_map(s, st, pr, pit, hit, hr);
     if (mst < 0) return mst;
-    OFDFT_TRY((launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)s->p.mu},
+    if (s->p.fixed_point == 1) {
+        // the field of u^2 for the next U (its warm start) and the Poisson
+        // iterations inside this one
+        OFDFT_TRY((launch_reduce<1>(s->n, SubOp{s->phi, s->hPb, s->hQ0}, NoFin{}, s->rb, st)));
+        pit += (int)s->u_pois_it;
+    }
+    OFDFT_TRY((launch_reduce<2>(s->n, MixResidOp{s->phi, s->vlr, s->v, s->fres, (double)s->p.mu, s->p.fixed_point},
                                 StoreTotals<2>{s->dsc + 40}, s->rb, st)));
     OFDFT_CHECK_HIP(hipMemcpyAsync(s->hsc + 40, s->dsc + 40, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     OFDFT_TRY(anderson_mix(s->mix, s->v, s->fres, s->v, st));
@@ -827,10 +873,10 @@ static double *state_ptr(ofdft_scf *s, int which, size_t &count) {
 // whether the kernel solutions are warm), every state array of
 // ofdft_scf_get in order, then the Anderson history.
 namespace {
-constexpr char kCkMagic[8] = {'O', 'F', 'D', 'F', 'T', 'C', 'K', '1'};
+constexpr char kCkMagic[8] = {'O', 'F', 'D', 'F', 'T', 'C', 'K', '2'};
 struct CkHeader {
     char magic[8];
-    int64_t nx, ny, nz, radius, mu, lr_order, history, nstate, kernel_warm;
+    int64_t nx, ny, nz, radius, mu, lr_order, history, nstate, kernel_warm, fixed_point;
     double hx, hy, hz, n_electrons, s_prev;
 };
 
@@ -862,6 +908,7 @@ extern "C" int ofdft_scf_save(ofdft_scf *s, const char *path, void *stream) {
     h.mu = s->p.mu;
     h.lr_order = s->p.lr_order;
     h.history = s->p.history;
+    h.fixed_point = s->p.fixed_point;
     h.nstate = state_count(s);
     h.kernel_warm = s->kernel_warm ? 1 : 0;
     h.hx = s->g.hx;
@@ -899,7 +946,8 @@ extern "C" int ofdft_scf_load(ofdft_scf *s, const char *path, void *stream) {
     if (rc == OFDFT_OK &&
         (std::memcmp(h.magic, kCkMagic, 8) != 0 || h.nx != s->g.nx || h.ny != s->g.ny || h.nz != s->g.nz ||
          h.hx != s->g.hx || h.hy != s->g.hy || h.hz != s->g.hz || h.radius != s->p.radius || h.mu != s->p.mu ||
-         h.lr_order != s->p.lr_order || h.history != s->p.history || h.n_electrons != s->p.n_electrons ||
+         h.lr_order != s->p.lr_order || h.history != s->p.history || h.fixed_point != s->p.fixed_point ||
+         h.n_electrons != s->p.n_electrons ||
          h.nstate != state_count(s))) {
         set_error("ofdft_scf_load: %s is not a checkpoint of a context with these grid and kernel settings", path);
         rc = OFDFT_INVALID_ARG;

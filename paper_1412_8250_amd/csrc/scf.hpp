@@ -65,6 +65,11 @@ struct ofdft_scf {
     ofdft::Multigrid *umg = nullptr;
     double u_kappa = 0;
     double s_prev = 0;
+    // electrostatics inside U (fixed_point 1): phi[b]; the external potential
+    // plus phi[b] (P); the fields of u^2, u d and d^2 (Q0, Q1, Q2); the total
+    // potential at the current u (V = P + Q0); Poisson iterations inside U
+    double *hPb = nullptr, *hP = nullptr, *hQ0 = nullptr, *hQ1 = nullptr, *hQ2 = nullptr, *hV = nullptr;
+    int64_t u_pois_it = 0;
     // solver contexts
     ofdft_poisson *pois = nullptr;
     ofdft_batch *batch = nullptr;

@@ -108,7 +108,8 @@ def test_scf_parameters_are_checked_before_gpu_work():
         assert st == m.INVALID_ARG, (field, bad)
         assert "invalid parameters" in m.last_error()
     # the multi-shift switch is 0 or 1
-    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": -1}, {"autotune": 2}):
+    for extra in ({"helmholtz_multishift": 2}, {"helmholtz_multishift": -1}, {"autotune": 2},
+                  {"fixed_point": 2}, {"fixed_point": -1}):
         q = m.ScfParams.from_buffer_copy(p)
         q.mu = 1
         for k, v in extra.items():
