@@ -63,9 +63,12 @@ def parse():
     ap.add_argument("--plain-density", action="store_true",
                     help="density update by Algorithm 1 as printed instead of the multigrid-preconditioned NLCG")
     ap.add_argument("--workload", choices=["large", "small"], default="large")
+    ap.add_argument("--no-trajectory", action="store_true",
+                    help="skip the ground-state runs of the large cell (kernel-potential and potential-mixing forms)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's untuned launch configuration (no autotuner run)")
-    ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy", "mgc", "mg", "density", "msc"],
+    ap.add_argument("--profile-kernel", choices=["cocg", "cg", "stencil", "copy", "mgc", "mg", "density", "msc",
+                                                 "nn", "nntrain"],
                     default=None,
                     help="only launch the named kernel(s) a few times at the workload's grid "
                          "(for rocprofv3 counter runs) and exit")
@@ -230,6 +233,18 @@ def profile_kernel(which, shape, h, reps=5):
         ms.solve(kappas, f, xs, 1e-30, max_iter=8, seed=0, allow_not_converged=True)
         counts = ofd.profile_read()
         ms.close()
+    elif which in ("nn", "nntrain"):   # the network at 96^3: 1 + reps applications or training steps
+        n96, h96 = (96, 96, 96), (0.390625,) * 3
+        g = torch.randn(n96, dtype=torch.float64, device=dev, generator=gen)
+        phi = torch.randn(n96, dtype=torch.float64, device=dev, generator=gen)
+        net = ofd.Network(0)
+        net.set_loss(ofd.Network.ENERGY)
+        z = torch.empty_like(g)
+        for _ in range(reps + 1):
+            if which == "nn":
+                net.forward(g, z, h96, scale=1.0)
+            else:
+                net.train_step(g, phi, h96, 1e-4)
     elif which == "density":   # preconditioned density update, `reps` iterations
         ne = 3.0 * 4 * 16 ** 3                      # the large cell's electrons
         vol = float(np.prod([n * hh for n, hh in zip(shape, h)]))
@@ -391,6 +406,72 @@ def multishift_extra(dev, rho_np, h, kappas):
                      "max_rel_res": max(s["rel_res"] for s in st)}
         bt.close()
         del xs
+    return out
+
+
+def ground_state_runs(dev):
+    """The large cell with sigma = 1.2 pseudocharges (as soft as a local
+    pseudopotential: rho_max / rho_bar ~ 3) run to its ground state by the
+    kernel-potential fixed point with the electrostatics inside U (the
+    paper's form, Anderson m = 3, zeta = 1), then energy and forces in both
+    forms; and the first steps of the potential-mixing form from the same
+    start (m = 7, zeta = 0.3, U capped at 2000 iterations)."""
+    import torch
+    import paper_1412_8250_amd as ofd
+    from paper_1412_8250_amd import inputs
+    w = inputs.large_cell(sigma=1.2)
+    shape, h = w.rho.shape, w.cell.h
+    b = torch.from_numpy(w.b).to(dev)
+    u0 = torch.from_numpy(np.sqrt(w.rho)).to(dev)
+    common = dict(lam=1.0, mu=1, u_tol=1e-8, poisson_tol=1e-8, helmholtz_tol=1e-8, poisson_mode=ofd.MULTIGRID,
+                  helmholtz_precond=ofd.PRECOND_MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID,
+                  line_slope_tol=LINE_SLOPE_TOL, allow_not_converged=True)
+    out = {}
+    t0 = time.perf_counter()
+    k = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, history=3, zeta=1.0, fixed_point=ofd.SCF.KERNEL_POTENTIAL,
+                **common)
+    torch.cuda.synchronize()
+    create = time.perf_counter() - t0
+    res, secs, stats = [], [], []
+    t_all = time.perf_counter()
+    for step in range(25):
+        t0 = time.perf_counter()
+        r = k.step(allow_not_converged=True)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        res.append(r)
+        stats.append(k.stats())
+        log(f"kernel-potential step {step}: residual {r:.3e} in {secs[-1]:.2f}s  {stats[-1]}")
+        if r < 1e-7 or not np.isfinite(r):
+            break
+    total = time.perf_counter() - t_all
+    atoms = np.array(w.cell.atoms, dtype=float)
+    e = k.energy(atoms, sigma=1.2)
+    ep = k.energy_paper_form(atoms, 0.55, sigma=1.2, allow_not_converged=True)
+    f = k.forces(atoms, sigma=1.2)
+    fp = k.forces_paper_form(atoms, 0.55, sigma=1.2, allow_not_converged=True)
+    out["kernel_potential"] = {
+        "history": 3, "zeta": 1.0, "steps": len(res), "residuals": res, "step_seconds": secs,
+        "seconds_to_1e-7": total, "context_and_v0_seconds": create, "converged": bool(res[-1] < 1e-7),
+        "u_iters": [s_["u_iters"] for s_ in stats], "poisson_iters": [s_["poisson_iters"] for s_ in stats],
+        "helmholtz_iters": [s_["helmholtz_iters"] for s_ in stats],
+        "atoms": len(atoms), "energy_per_atom": e["total"] / len(atoms),
+        "energy_per_atom_paper_form": ep["total"] / len(atoms), "energy_terms": e, "energy_terms_paper_form": ep,
+        "max_force": float(np.abs(f).max()), "max_force_paper_form": float(np.abs(fp).max()),
+        "max_force_difference_between_forms": float(np.abs(f - fp).max())}
+    k.close()
+    del k
+    p = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, history=7, zeta=0.3, u_max_iter=2000, **common)
+    pres, pit = [], []
+    for step in range(6):
+        r = p.step(allow_not_converged=True)
+        pres.append(r)
+        pit.append(p.stats()["u_iters"])
+        log(f"potential-mixing step {step}: residual {r:.3e}")
+        if not np.isfinite(r):
+            break
+    out["potential_mixing_first_steps"] = {"history": 7, "zeta": 0.3, "residuals": pres, "u_iters": pit}
+    p.close()
     return out
 
 
@@ -636,6 +717,10 @@ def main():
                                      "imaginary part read as -0.266195 (printed -0.0266195)"}
             scf2.close()
             del scf2
+        if not args.no_trajectory:
+            del scf
+            torch.cuda.empty_cache()
+            extras["ground_state_320_sigma_1.2"] = ground_state_runs(dev)
         log("extras", extras)
 
     cpu = None

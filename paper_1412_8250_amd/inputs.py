@@ -181,9 +181,9 @@ def supercell_500(vacancy: bool = False) -> Workload:
     return cubic_workload(5, 96, 3 if vacancy else 2, jitter=0.05, vacancy=vacancy)
 
 
-def large_cell() -> Workload:
+def large_cell(sigma: float = 0.8) -> Workload:
     """16x16x16 FCC cells (16384 atoms), 120 bohr box, 320^3 grid, jitter 0.05."""
-    return cubic_workload(16, 320, 5, jitter=0.05)
+    return cubic_workload(16, 320, 5, jitter=0.05, sigma=sigma)
 
 
 def batched_cell_sizes(count: int = 32, seed: int = 4) -> List[Tuple[int, int]]:
