@@ -25,6 +25,18 @@
 // iteration (Q1, Q2) make every probe a pointwise pass, and the accepted
 // step updates Q0 by the same formula.  Q0 is solved afresh at entry.
 //
+// Device-driven form (the potential-mixing map, fixed_point 0): the same
+// iteration with every scalar decision on the device (struct UDev): the
+// residual test, the Polak-Ribiere coefficient and restarts, the slope at
+// s = 0 and the line search, which brackets the root of dE/ds by the same
+// secant growth and then refines it by false position with the Illinois
+// modification, within a budget of kProbes evaluations per iteration
+// (Brent's method needs host decisions).  Every kernel returns at once when
+// the update is over (or, for the line-search passes, when the step is
+// chosen), so blocks of kBlockIters iterations are captured once in a HIP
+// graph and replayed; the host reads the state once per block.  Profiled
+// runs of the classes launch the same kernels one by one.
+//
 // Optional preconditioning (not in the paper; its conclusion calls for
 // real-space preconditioners, Section 5.5): the steepest-descent direction r
 // is replaced by z = M r projected onto the tangent space of the constraint,
@@ -338,10 +350,531 @@ int brent_root(F &&f, double a, double b, double fa, double fb, double tol, doub
     return OFDFT_OK;
 }
 
+// ---- device-driven iteration ---------------------------------------------
+constexpr int kProbes = 10;        // line-search evaluations per iteration
+constexpr int kBlockIters = 4;     // iterations per captured block (even: r, d in A; odd: in B)
+
+enum { U_RUN = 0, U_CONVERGED = 1, U_STOPPED = 2, U_NONFINITE = 3 };
+
+struct UDev {
+    double uhu, ulu, uu, eta, rr, rrp;          // Ka, Kb totals
+    double dots[5], kd[5], eval;                // preconditioner dots, direction totals, probe total
+    double res, xi, cu, rz, rz_prev, rr_prev;
+    double ud, dd, uLd, dLd, dHu, f0, f0_prev, s_prev;
+    double lo, flo, hi, fhi, s, ftol, sstar, c; // line search
+    int q, done, skipit, ls_done, phase, probes, restart, side;
+    int n_ka, n_kb, n_dots, n_kd, n_eval, n_step;   // passes that did work
+};
+
+struct UPar {
+    double ne, dv, lam, tol, sqn, ltol, stol;
+    int maxit, nres, pre;
+};
+
+struct EpiHuD {          // EpiHu with the totals into UDev
+    const double *__restrict__ v;
+    double *__restrict__ Hu;
+    UDev *U;
+    double *partials;
+    unsigned int *counter;
+    double half_lam, inv_ne_dv;
+    double a0, a1, a2;
+    double vv[4];
+    __device__ bool skip() const { return U->done != U_RUN; }
+    __device__ void pre(int q, int64_t i) { vv[q] = v[i]; }
+    __device__ void point(int q, int64_t i, double c, double s) {
+        const double rho = c * c;
+        const double vl = rho > 0.0 ? v_local(rho) : 0.0;
+        const double hu = ::fma(-half_lam, s, (vl + vv[q]) * c);
+        Hu[i] = hu;
+        a0 = ::fma(c, hu, a0);
+        a1 = ::fma(c, s, a1);
+        a2 = ::fma(c, c, a2);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[3] = {a0, a1, a2};
+        block_sum<3>(x, scratch);
+        double t[3];
+        if (reduce_grid<3>(x, partials, nblocks, block, counter, scratch, t)) {
+            U->uhu = t[0];
+            U->ulu = t[1];
+            U->uu = t[2];
+            U->eta = t[0] * inv_ne_dv;
+            U->n_ka += 1;
+        }
+    }
+};
+
+struct ResidOpD {        // r = -2 (Hu - eta u); {<r,r>, <r,r_prev>}
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 0;     // counted from the passes that did work
+    const double *Hu, *u, *r_prev;
+    double *r;
+    UDev *U;
+    double eta;
+    int have_prev;
+    __device__ bool skip() const { return U->done != U_RUN; }
+    __device__ void prepare() {
+        eta = U->eta;
+        have_prev = U->q > 0;
+    }
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double ri = -2.0 * (Hu[i] - eta * u[i]);
+        r[i] = ri;
+        acc[0] = ::fma(ri, ri, acc[0]);
+        if (have_prev) acc[1] = ::fma(ri, r_prev[i], acc[1]);
+    }
+};
+struct FinRR {
+    UDev *U;
+    __device__ void operator()(const double (&t)[2]) const {
+        U->rr = t[0];
+        U->rrp = t[1];
+        U->n_kb += 1;
+    }
+};
+
+struct DotsOpD {         // {<u,z>, <r,z>, <r_prev,z>, <u,r>, <u,r_prev>}
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 0;     // counted from the passes that did work
+    const double *u, *z, *r, *r_prev;
+    UDev *U;
+    int have_prev;
+    __device__ bool skip() const { return U->done != U_RUN; }
+    __device__ void prepare() { have_prev = U->q > 0; }
+    __device__ void operator()(int64_t i, double (&acc)[5]) const {
+        const double ui = u[i], zi = z[i], ri = r[i];
+        acc[0] = ::fma(ui, zi, acc[0]);
+        acc[1] = ::fma(ri, zi, acc[1]);
+        acc[3] = ::fma(ui, ri, acc[3]);
+        if (have_prev) {
+            const double pi = r_prev[i];
+            acc[2] = ::fma(pi, zi, acc[2]);
+            acc[4] = ::fma(ui, pi, acc[4]);
+        }
+    }
+};
+struct FinDots {
+    UDev *U;
+    __device__ void operator()(const double (&t)[5]) const {
+        for (int k = 0; k < 5; ++k) U->dots[k] = t[k];
+        U->n_dots += 1;
+    }
+};
+
+struct LoadDirD {        // d' = r + xi d_prev, xi from the device state
+    const double *__restrict__ r;
+    const double *__restrict__ d_prev;
+    const UDev *U;
+    double xi;
+    __device__ void prepare() {
+        xi = U->xi;
+        if (xi == 0.0) d_prev = r;
+    }
+    __device__ double operator()(int64_t i) const { return ::fma(xi, d_prev[i], r[i]); }
+};
+
+struct EpiLdD {          // EpiLd with cu and the totals in UDev
+    const double *__restrict__ u;
+    const double *__restrict__ Hu;
+    double *__restrict__ d;
+    UDev *U;
+    double *partials;
+    unsigned int *counter;
+    double cu;
+    double a0, a1, a2, a3, a4;
+    double uv[4], hv[4];
+    __device__ bool skip() const { return U->done != U_RUN; }
+    __device__ void prepare() { cu = U->cu; }
+    __device__ void pre(int q, int64_t i) {
+        uv[q] = u[i];
+        hv[q] = Hu[i];
+    }
+    __device__ void point(int q, int64_t i, double c, double s) {
+        const double ui = uv[q];
+        d[i] = ::fma(-cu, ui, c);
+        a0 = ::fma(ui, c, a0);
+        a1 = ::fma(c, c, a1);
+        a2 = ::fma(ui, s, a2);
+        a3 = ::fma(c, s, a3);
+        a4 = ::fma(hv[q], c, a4);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[5] = {a0, a1, a2, a3, a4};
+        block_sum<5>(x, scratch);
+        double t[5];
+        if (reduce_grid<5>(x, partials, nblocks, block, counter, scratch, t)) {
+            for (int k = 0; k < 5; ++k) U->kd[k] = t[k];
+            U->n_kd += 1;
+        }
+    }
+};
+
+struct EvalOpD {         // EvalOp at the probe point U->s
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 0;     // counted from the passes that did work
+    const double *u, *d, *v;
+    UDev *U;
+    double ne_dv;
+    double s, c2, t;
+    __device__ bool skip() const { return U->done != U_RUN || U->skipit || U->ls_done; }
+    __device__ void prepare() {
+        s = U->s;
+        const double ww = U->uu + s * (2.0 * U->ud + s * U->dd);
+        t = (U->ud + s * U->dd) / ww;
+        c2 = ne_dv / ww;
+    }
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        const double w = ::fma(s, d[i], u[i]);
+        const double rho = c2 * w * w;
+        const double vl = rho > 0.0 ? v_local(rho) : 0.0;
+        acc[0] = ::fma((vl + v[i]) * w, ::fma(-t, w, d[i]), acc[0]);
+    }
+};
+struct FinEval {
+    UDev *U;
+    __device__ void operator()(const double (&t)[1]) const {
+        U->eval = t[0];
+        U->n_eval += 1;
+    }
+};
+
+struct StepOpD {         // u <- c (u + s* d)
+    static constexpr int kClass = K_U_VECTOR;
+    static constexpr int kBytes = 0;     // counted from the passes that did work
+    double *u;
+    const double *d;
+    UDev *U;
+    double s, c;
+    __device__ bool skip() const { return U->done != U_RUN || U->skipit; }
+    __device__ void prepare() {
+        s = U->sstar;
+        c = U->c;
+    }
+    __device__ void operator()(int64_t i, double (&)[1]) const { u[i] = c * ::fma(s, d[i], u[i]); }
+};
+struct FinStep {
+    UDev *U;
+    __device__ void operator()(const double (&)[1]) const { U->n_step += 1; }
+};
+
+// residual test (after Ka, Kb)
+__global__ void u_check(UDev *U, UPar P) {
+    if (U->done != U_RUN) return;
+    const double res = 0.5 * sqrt(U->rr / U->uu);
+    U->res = res;
+    if (!isfinite(res)) U->done = U_NONFINITE;
+    else if (res <= P.tol) U->done = U_CONVERGED;
+    else if (U->q >= P.maxit) U->done = U_STOPPED;
+}
+
+// Polak-Ribiere coefficient and the projection coefficient (after the dots)
+__global__ void u_direction(UDev *U, UPar P) {
+    if (U->done != U_RUN) return;
+    double xi = 0.0, cu = 0.0, rz = 0.0;
+    if (P.pre) {
+        cu = U->dots[0] / U->uu;
+        rz = U->dots[1] - cu * U->dots[3];
+        if (U->q > 0) xi = (rz - (U->dots[2] - cu * U->dots[4])) / U->rz_prev;
+        if (!isfinite(rz) || !(rz > 0.0)) {
+            U->done = U_NONFINITE;
+            return;
+        }
+    } else if (U->q > 0) {
+        xi = (U->rr - U->rrp) / U->rr_prev;
+    }
+    if (U->q % P.nres == 0 || !(xi > 0.0) || U->restart) xi = 0.0;
+    U->restart = 0;
+    U->xi = xi;
+    U->cu = cu;
+    U->rz = rz;
+}
+
+__device__ inline void u_accept(UDev *U, const UPar &P, double x) {
+    U->sstar = x;
+    U->ls_done = 1;
+    const double ww = U->uu + x * (2.0 * U->ud + x * U->dd);
+    U->c = P.sqn / sqrt(P.dv * ww);
+}
+
+// slope at s = 0 from the direction totals; line-search start (after Kd)
+__global__ void u_slope0(UDev *U, UPar P) {
+    if (U->done != U_RUN) return;
+    const double cu = U->cu, uu = U->uu, ulu = U->ulu, uhu = U->uhu;
+    const double *t = U->kd;
+    const double ud = t[0] - cu * uu, dd = t[1] - 2.0 * cu * t[0] + cu * cu * uu;
+    const double uLd = t[2] - cu * ulu, dLd = t[3] - 2.0 * cu * t[2] + cu * cu * ulu;
+    const double dHu = t[4] - cu * uhu;
+    U->ud = ud;
+    U->dd = dd;
+    U->uLd = uLd;
+    U->dLd = dLd;
+    U->dHu = dHu;
+    U->skipit = 0;
+    U->ls_done = 0;
+    if (!(dd > 0.0)) {
+        U->done = U_STOPPED;
+        return;
+    }
+    const double f0 = P.ne / (P.dv * uu) * (dHu - ud / uu * uhu);
+    U->f0 = f0;
+    if (!(f0 < 0.0)) {
+        if (U->xi != 0.0) {          // not a descent direction: restart along r next iteration
+            U->restart = 1;
+            U->skipit = 1;
+        } else {
+            U->done = U_STOPPED;     // no descent possible at this precision
+        }
+        return;
+    }
+    const double sp = U->s_prev;
+    double hi = sp > 0.0 ? sp : 1.0 / sqrt(fmax(dd * P.dv / P.ne, 1e-300));
+    if (sp > 0.0 && U->f0_prev < 0.0) hi = sp * fmin(fmax(U->f0_prev / f0, 0.1), 10.0);
+    U->lo = 0.0;
+    U->flo = f0;
+    U->hi = hi;
+    U->s = hi;
+    U->ftol = P.stol * fabs(f0);
+    U->phase = 0;
+    U->probes = 0;
+    U->side = 0;
+}
+
+// one line-search decision after a probe: grow the bracket (secant past the
+// estimated root, 1.1x to 8x) while the slope stays negative, then false
+// position with the Illinois modification inside it
+__global__ void u_linesearch(UDev *U, UPar P) {
+    if (U->done != U_RUN || U->skipit || U->ls_done) return;
+    const double sv = U->s;
+    const double ww = U->uu + sv * (2.0 * U->ud + sv * U->dd);
+    const double t = (U->ud + sv * U->dd) / ww;
+    const double c2 = P.ne / (P.dv * ww);
+    const double vw = U->uLd + sv * U->dLd - t * (U->ulu + sv * (2.0 * U->uLd + sv * U->dLd));
+    const double f = c2 * (U->eval - 0.5 * P.lam * vw);
+    U->probes += 1;
+    if (!isfinite(f)) {
+        U->done = U_NONFINITE;
+        return;
+    }
+    if (fabs(f) <= U->ftol) {
+        u_accept(U, P, sv);
+        return;
+    }
+    double lo = U->lo, flo = U->flo, hi = U->hi, fhi = U->fhi;
+    if (U->phase == 0) {
+        fhi = f;
+        if (f < 0.0) {
+            double next = 2.0 * hi;
+            if (fhi > flo) {
+                const double sec = hi + (hi - lo) * (-fhi) / (fhi - flo);
+                next = fmin(fmax(1.1 * sec, 1.1 * hi), 8.0 * hi);
+            }
+            lo = hi;
+            flo = fhi;
+            hi = next;
+            U->s = hi;
+        } else {
+            U->phase = 1;
+            U->side = 0;
+            U->s = lo - flo * (hi - lo) / (fhi - flo);
+        }
+    } else {
+        if (f < 0.0) {
+            lo = sv;
+            flo = f;
+            if (U->side == -1) fhi *= 0.5;
+            U->side = -1;
+        } else {
+            hi = sv;
+            fhi = f;
+            if (U->side == 1) flo *= 0.5;
+            U->side = 1;
+        }
+        if (hi - lo <= P.ltol * hi) {
+            u_accept(U, P, sv);
+            return;
+        }
+        U->s = lo - flo * (hi - lo) / (fhi - flo);
+    }
+    U->lo = lo;
+    U->flo = flo;
+    U->hi = hi;
+    U->fhi = fhi;
+}
+
+// budget spent without acceptance: the last point of negative slope while
+// still growing, else the current false-position point inside the bracket
+__global__ void u_linesearch_end(UDev *U, UPar P) {
+    if (U->done != U_RUN || U->skipit || U->ls_done) return;
+    u_accept(U, P, U->phase == 0 ? U->lo : U->s);
+}
+
+// end of an iteration
+__global__ void u_end(UDev *U) {
+    if (U->done != U_RUN) return;
+    if (!U->skipit) {
+        U->s_prev = fabs(U->sstar);
+        U->f0_prev = U->f0;
+        U->rr_prev = U->rr;
+        U->rz_prev = U->rz;
+        U->q += 1;
+    }
+    U->skipit = 0;
+}
+
+// one iteration; parity 0 keeps r and d in rA/dA (previous in rB/dB), 1 the reverse
+int u_iteration(ofdft_scf *s, const double *v, double *u, int parity, const UPar &P, hipStream_t st) {
+    const ofdft_grid &g = s->g;
+    const int64_t n = s->n;
+    UDev *U = (UDev *)s->udev;
+    double *r_cur = parity ? s->rB : s->rA, *r_prev = parity ? s->rA : s->rB;
+    double *d_cur = parity ? s->dB : s->dA, *d_prev = parity ? s->dA : s->dB;
+    {
+        ProfScope ps(K_U_STENCIL, 0.0, st);
+        OFDFT_TRY(launch_stencil<double>(g, s->coef, LoadPlain<double>{u},
+                                         EpiHuD{v, s->Hu, U, s->rb.partials, s->rb.counter, 0.5 * P.lam,
+                                                P.dv / P.ne, 0, 0, 0, {}},
+                                         st));
+    }
+    OFDFT_TRY((launch_reduce<2>(n, ResidOpD{s->Hu, u, r_prev, r_cur, U, 0.0, 0}, FinRR{U}, s->rb, st)));
+    hipLaunchKernelGGL(u_check, dim3(1), dim3(1), 0, st, U, P);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    const double *base = r_cur;
+    if (P.pre) {
+        OFDFT_TRY(mg_apply_run(*s->umg, r_cur, s->z, st, s->u_kappa, &U->done));
+        OFDFT_TRY((launch_reduce<5>(n, DotsOpD{u, s->z, r_cur, r_prev, U, 0}, FinDots{U}, s->rb, st)));
+        base = s->z;
+    }
+    hipLaunchKernelGGL(u_direction, dim3(1), dim3(1), 0, st, U, P);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    {
+        ProfScope ps(K_U_STENCIL, 0.0, st);
+        OFDFT_TRY(launch_stencil<double>(g, s->coef, LoadDirD{base, d_prev, U, 0.0},
+                                         EpiLdD{u, s->Hu, d_cur, U, s->rb.partials, s->rb.counter, 0.0, 0, 0, 0, 0,
+                                                0, {}, {}},
+                                         st));
+    }
+    hipLaunchKernelGGL(u_slope0, dim3(1), dim3(1), 0, st, U, P);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    for (int k = 0; k < kProbes; ++k) {
+        OFDFT_TRY((launch_reduce<1>(n, EvalOpD{u, d_cur, v, U, P.ne / P.dv, 0.0, 0.0, 0.0}, FinEval{U}, s->rb, st)));
+        hipLaunchKernelGGL(u_linesearch, dim3(1), dim3(1), 0, st, U, P);
+        OFDFT_CHECK_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(u_linesearch_end, dim3(1), dim3(1), 0, st, U, P);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    OFDFT_TRY((launch_reduce<1>(n, StepOpD{u, d_cur, U, 0.0, 0.0}, FinStep{U}, s->rb, st)));
+    hipLaunchKernelGGL(u_end, dim3(1), dim3(1), 0, st, U);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    return OFDFT_OK;
+}
+
+int u_graph_get(ofdft_scf *s, const double *v, double *u, const UPar &P) {
+    const void *key[3] = {v, u, s->udev};
+    if (s->ugraph && std::equal(key, key + 3, s->ugraph_key)) return OFDFT_OK;
+    if (s->ugraph) {
+        (void)hipGraphExecDestroy(s->ugraph);
+        s->ugraph = nullptr;
+    }
+    if (!s->ucap) OFDFT_CHECK_HIP(hipStreamCreateWithFlags(&s->ucap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    OFDFT_CHECK_HIP(hipStreamBeginCapture(s->ucap, hipStreamCaptureModeThreadLocal));
+    prof_suspend(true);
+    int rc = OFDFT_OK;
+    for (int k = 0; k < kBlockIters && rc == OFDFT_OK; ++k) rc = u_iteration(s, v, u, k & 1, P, s->ucap);
+    prof_suspend(false);
+    const hipError_t e = hipStreamEndCapture(s->ucap, &graph);
+    if (rc != OFDFT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    OFDFT_CHECK_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&s->ugraph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    OFDFT_CHECK_HIP(ei);
+    for (int i = 0; i < 3; ++i) s->ugraph_key[i] = key[i];
+    return OFDFT_OK;
+}
+
+int density_update_dev(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
+                       hipStream_t st) {
+    if (!s->udev) {
+        OFDFT_CHECK_HIP(hipMalloc(&s->udev, sizeof(UDev)));
+        OFDFT_CHECK_HIP(hipHostMalloc(&s->udev_h, sizeof(UDev), hipHostMallocDefault));
+    }
+    UDev *Uh = (UDev *)s->udev_h;
+    UPar P{};
+    P.ne = s->p.n_electrons;
+    P.dv = s->dv;
+    P.lam = s->p.lambda;
+    P.tol = s->p.u_tol;
+    P.sqn = std::sqrt(P.ne);
+    P.ltol = s->p.line_tol > 0.0 ? s->p.line_tol : 1e-8;
+    P.stol = s->p.line_slope_tol > 0.0 ? s->p.line_slope_tol : 1e-6;
+    P.maxit = s->p.u_max_iter > 0 ? s->p.u_max_iter : 20000;
+    P.nres = s->p.n_restart > 0 ? s->p.n_restart : 50;
+    P.pre = s->umg != nullptr;
+    *Uh = UDev{};
+    Uh->s_prev = s->s_prev;
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->udev, Uh, sizeof(UDev), hipMemcpyHostToDevice, st));
+    const bool eager = prof_timed(K_U_STENCIL) || prof_timed(K_U_VECTOR) || (P.pre && prof_timed(K_MULTIGRID));
+    auto read_state = [&]() -> int {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(Uh, s->udev, sizeof(UDev), hipMemcpyDeviceToHost, st));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+        return OFDFT_OK;
+    };
+    // every iteration either steps (q grows) or restarts once; the cap is a guard
+    const int64_t cap = 2 * (int64_t)P.maxit + 8;
+    if (eager) {
+        for (int64_t k = 0; k < cap; ++k) {
+            OFDFT_TRY(u_iteration(s, v, u, (int)(k & 1), P, st));
+            OFDFT_TRY(read_state());
+            if (Uh->done != U_RUN) break;
+        }
+    } else {
+        OFDFT_TRY(u_graph_get(s, v, u, P));
+        for (int64_t k = 0; k < cap; k += kBlockIters) {
+            OFDFT_CHECK_HIP(hipGraphLaunch(s->ugraph, st));
+            OFDFT_TRY(read_state());
+            if (Uh->done != U_RUN) break;
+        }
+    }
+    if (Uh->done == U_RUN) {
+        set_error("ofdft_density_update: iteration guard reached");
+        return OFDFT_HIP_ERROR;
+    }
+    // algorithmic bytes of the passes that did work (the early exits move none)
+    const double nd = (double)s->n;
+    const int64_t nst = Uh->n_ka + Uh->n_kd, nvec = Uh->n_kb + Uh->n_dots + Uh->n_eval + Uh->n_step;
+    prof_add(K_U_STENCIL, nd * (24.0 * Uh->n_ka + 40.0 * Uh->n_kd), eager ? 0 : nst);
+    prof_add(K_U_VECTOR, nd * (32.0 * Uh->n_kb + 32.0 * Uh->n_dots + 24.0 * Uh->n_eval + 24.0 * Uh->n_step),
+             eager ? 0 : nvec);
+    if (P.pre) prof_add(K_MULTIGRID, mg_cycle_bytes(*s->umg) * Uh->n_dots, eager ? 0 : Uh->n_dots);
+    s->s_prev = Uh->s_prev;
+    iters = Uh->q;
+    res = Uh->res;
+    eta = Uh->eta;
+    if (Uh->done == U_NONFINITE) return OFDFT_NONFINITE;
+    return Uh->done == U_CONVERGED ? OFDFT_OK : OFDFT_NOT_CONVERGED;
+}
+
 }  // namespace
+
+void density_free(ofdft_scf *s) {
+    if (s->ugraph) (void)hipGraphExecDestroy(s->ugraph);
+    if (s->ucap) (void)hipStreamDestroy(s->ucap);
+    if (s->udev) (void)hipFree(s->udev);
+    if (s->udev_h) (void)hipHostFree(s->udev_h);
+    s->ugraph = nullptr;
+    s->ucap = nullptr;
+    s->udev = s->udev_h = nullptr;
+}
 
 int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
                    hipStream_t st) {
+    // the potential-mixing map runs device-driven; with the electrostatics
+    // inside (Poisson solves between the passes) the host drives the loop
+    if (s->p.fixed_point == 0) return density_update_dev(s, v, u, iters, res, eta, st);
     const ofdft_grid &g = s->g;
     const int64_t n = s->n;
     const double ne = s->p.n_electrons, dv = s->dv, lam = s->p.lambda;

@@ -671,6 +671,17 @@ int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double ka
                    : vcycle<double, double>(mg, 0, 1, f, o, k, sh, s);
 }
 
+int mg_apply_run(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa, const int *run) {
+    if (mg.lv.empty() || mg.elem != 8) return OFDFT_INVALID_ARG;
+    ProfScope ps(K_MULTIGRID, 0.0, s);      // bytes: the caller counts the cycles that ran
+    const double2 k = make_double2(kappa, 0.0);
+    const MgShift sh{nullptr, run, 0, 0};
+    const MgArr<const double> f{r, 0, nullptr};
+    const MgArr<double> o{z, 0, nullptr};
+    return mg.fp32 ? vcycle<double, float>(mg, 0, 1, f, o, k, sh, s)
+                   : vcycle<double, double>(mg, 0, 1, f, o, k, sh, s);
+}
+
 int mg_apply_shifted(Multigrid &mg, int q, const double2 *r, double2 *z, const double *kappa, const int *run,
                      hipStream_t s) {
     if (mg.lv.empty() || mg.elem != 16 || !kappa || q < 0 || q >= mg.groups) return OFDFT_INVALID_ARG;

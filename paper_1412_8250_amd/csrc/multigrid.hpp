@@ -52,6 +52,9 @@ void mg_free(Multigrid &mg);
 // z = M r for -Delta + kappa, kappa >= 0 real (device FP64 arrays of the fine
 // grid; z must not alias r).
 int mg_apply(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa = 0.0);
+// The same cycle, every kernel returning at once while *run != 0 (device
+// flag, for cycles inside captured blocks of an iteration that may be over).
+int mg_apply_run(Multigrid &mg, const double *r, double *z, hipStream_t s, double kappa, const int *run);
 // z = M r for -Delta + kappa (complex128 arrays).  kappa points to device
 // memory holding {Re, Im} and is read by every launch, so a captured launch
 // sequence follows later changes of the shift; if `run` is given, every

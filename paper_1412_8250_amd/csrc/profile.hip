@@ -37,7 +37,15 @@ void drain_locked() {
 }
 }  // namespace
 
+namespace {
+thread_local int t_suspend = 0;
+}
+
+void prof_suspend(bool on) { t_suspend += on ? 1 : -1; }
+bool prof_suspended() { return t_suspend > 0; }
+
 void prof_add(int cls, double bytes, int64_t launches) {
+    if (t_suspend > 0) return;
     std::lock_guard<std::mutex> lk(g_mu);
     g_bytes[cls] += bytes;
     g_launches[cls] += launches;

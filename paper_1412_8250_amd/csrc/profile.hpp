@@ -31,6 +31,10 @@ enum KClass {
 
 void prof_add(int cls, double bytes, int64_t launches = 1);
 bool prof_timed(int cls);
+// While suspended (this thread), launches are neither accounted nor timed:
+// launches captured into a graph are accounted per replay by their caller.
+void prof_suspend(bool on);
+bool prof_suspended();
 void prof_record(int cls, hipEvent_t a, hipEvent_t b);
 hipEvent_t prof_event();
 
@@ -42,7 +46,7 @@ struct ProfScope {
     // active = false: nothing is accounted or recorded (launches captured
     // into a graph, accounted per replay by the caller)
     ProfScope(int c, double bytes, hipStream_t st, bool active = true) : cls(c), s(st) {
-        if (!active) return;
+        if (!active || prof_suspended()) return;
         prof_add(c, bytes);
         if (prof_timed(c)) {
             a = prof_event();

@@ -501,6 +501,7 @@ int salloc(ofdft_scf *s, P_ **p, size_t bytes) {
 }
 
 void scf_free(ofdft_scf *s) {
+    density_free(s);
     if (s->pois) ofdft_poisson_destroy(s->pois);
     if (s->batch) ofdft_batch_destroy(s->batch);
     if (s->ms) ofdft_multishift_destroy(s->ms);

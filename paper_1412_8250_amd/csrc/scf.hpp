@@ -70,6 +70,13 @@ struct ofdft_scf {
     // potential at the current u (V = P + Q0); Poisson iterations inside U
     double *hPb = nullptr, *hP = nullptr, *hQ0 = nullptr, *hQ1 = nullptr, *hQ2 = nullptr, *hV = nullptr;
     int64_t u_pois_it = 0;
+    // device-driven density update: iteration state (device and pinned host
+    // copies), the captured block of iterations and the pointers it was
+    // captured with
+    void *udev = nullptr, *udev_h = nullptr;
+    hipGraphExec_t ugraph = nullptr;
+    hipStream_t ucap = nullptr;
+    const void *ugraph_key[3] = {};
     // solver contexts
     ofdft_poisson *pois = nullptr;
     ofdft_batch *batch = nullptr;
@@ -90,5 +97,7 @@ int anderson_read(ofdft_anderson *a, std::FILE *f);
 // U(v): Algorithm 1 from the current s->u; v is a device array.
 int density_update(ofdft_scf *s, const double *v, double *u, int &iters, double &res, double &eta,
                    hipStream_t st);
+// Releases the density update's device-driven state (graph, stream, buffers).
+void density_free(ofdft_scf *s);
 
 }  // namespace ofdft

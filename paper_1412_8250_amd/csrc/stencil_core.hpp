@@ -319,6 +319,14 @@ __device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>
     __syncthreads();
 }
 
+// Epilogues may read per-launch scalars from device memory in prepare().
+template <class E>
+__device__ inline auto epi_prepare(E &e, int) -> decltype(e.prepare(), void()) {
+    e.prepare();
+}
+template <class E>
+__device__ inline void epi_prepare(E &, long) {}
+
 // Plain kernel wrapper: one tile per workgroup, XCD-aware tile order, then the
 // epilogue's block-level finish (reductions).
 template <typename T, int TX, int TYT, int RY, class Load, class Epi>
@@ -328,6 +336,7 @@ stencil_kernel(TileGeom g, Coef<typename VT<T>::S> w, Load ld, Epi ep) {
     __shared__ double red_scratch[64];
     if (ep.skip()) return;
     ld.prepare();
+    epi_prepare(ep, 0);
     const int lb = xcd_remap(blockIdx.x, g.nblocks);
     stencil_tile<T, TX, TYT, RY>(g, w, ld, ep, lb, lds);
     ep.finish(blockIdx.x, g.nblocks, red_scratch);

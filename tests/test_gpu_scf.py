@@ -300,3 +300,59 @@ def test_checkpoint_resumes_trajectory_exactly(mu, tmp_path):
         b.load(str(short))
     for c in (a, b, other):
         c.close()
+
+
+@pytest.mark.parametrize("precond", [ofd.PRECOND_NONE, ofd.PRECOND_MULTIGRID])
+def test_density_update_graph_replay_equals_eager(precond):
+    """The potential-mixing update is device-driven: blocks of iterations are
+    captured once and replayed.  The same kernels launched one by one (the
+    path a profiled run takes) give the same u, bit for bit, in the same
+    number of iterations (fresh contexts: the line-search memory starts
+    equal)."""
+    torch = torch_cuda()
+    announce("density update graph vs eager", precond)
+    w = inputs.supercell_500()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    outs = []
+    try:
+        for timed in ((), ("u_stencil", "u_vector", "multigrid")):
+            ofd.profile_reset(timed=timed)
+            ctx = _ctx(w, lam=1.0, u_precond=precond)
+            ud = to_dev(np.sqrt(w.rho))
+            it, res, eta = ctx.density_update(to_dev(phi), ud)
+            prof = ofd.profile_read()
+            outs.append((to_host(ud), it, res, eta, prof["u_stencil"]["bytes"], prof["u_vector"]["bytes"]))
+            ctx.close()
+    finally:
+        ofd.profile_reset()
+    (u0, it0, r0, e0, bs0, bv0), (u1, it1, r1, e1, bs1, bv1) = outs
+    announce("iterations", it0, it1, "residual", r0, r1)
+    assert it0 == it1 and r0 == r1 and e0 == e1 and r0 <= 1e-10
+    assert np.array_equal(u0, u1)
+    # both account the same algorithmic bytes (the passes that did work)
+    assert bs0 == bs1 and bv0 == bv1
+
+
+def test_scf_steps_graph_replay_equal_eager():
+    """Two steps of the K_00 iteration with every class profiled (eager
+    launches throughout) and without (captured blocks): the same residuals
+    and the same state, bit for bit."""
+    torch = torch_cuda()
+    announce("scf graph vs eager")
+    w = inputs.small_cell()
+    outs = []
+    try:
+        for timed in ((), ofd.KERNEL_CLASSES):
+            ofd.profile_reset(timed=timed)
+            ctx = _ctx(w, lam=1.0, mu=1, u_precond=ofd.PRECOND_MULTIGRID, helmholtz_precond=ofd.PRECOND_MULTIGRID,
+                       poisson_mode=ofd.MULTIGRID)
+            res = [ctx.step() for _ in range(2)]
+            vd = torch.empty(w.rho.shape, dtype=torch.float64, device="cuda")
+            ctx.get(ofd.SCF.V, vd)
+            outs.append((res, to_host(vd)))
+            ctx.close()
+    finally:
+        ofd.profile_reset()
+    assert outs[0][0] == outs[1][0], (outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
