@@ -598,6 +598,14 @@ def main():
                     r["shape_name"] = ofd.SHAPE_NAMES[r["shape"]]
                     at[f"{fam}_f64_{n}"] = r
             extras["autotune_grids"] = at
+        if not args.no_autotune:
+            # back-to-back launches between two HIP events (the tuner's timing
+            # of the configuration it keeps); per-launch events below add the
+            # launch gap to each 0.07-0.3 ms kernel
+            for key, eb, ms in (("float64", 8, tuned["apply_f64"]["best_ms"]),
+                                ("float32", 4, extras["autotune_grids"]["apply_f32_320"]["best_ms"]),
+                                ("complex128", 16, extras["autotune_grids"]["apply_c128_320"]["best_ms"])):
+                extras[f"stencil_{key}_GBps_back_to_back"] = 2 * int(np.prod(shape)) * eb / (ms * 1e-3) / 1e9
         for dt, eb in ((torch.float64, 8), (torch.float32, 4), (torch.complex128, 16)):
             x = torch.randn(shape, dtype=dt, device=dev)
             y = torch.empty_like(x)

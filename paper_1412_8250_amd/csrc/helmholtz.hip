@@ -859,7 +859,10 @@ extern "C" int ofdft_batch_apply_preconditioner(ofdft_batch *b, int j, const dou
     }
     hipStream_t s = (hipStream_t)stream;
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_kap, kappa, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-    OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], b->mg_q[j], (const double2 *)r, (double2 *)z, b->d_kap, nullptr, s));
+    {
+        ProfScope ps(K_MULTIGRID_C, mg_cycle_bytes(*b->mg_of[j]), s);
+        OFDFT_TRY(mg_apply_shifted(*b->mg_of[j], b->mg_q[j], (const double2 *)r, (double2 *)z, b->d_kap, nullptr, s));
+    }
     OFDFT_CHECK_HIP(hipStreamSynchronize(s));
     return OFDFT_OK;
 }
