@@ -724,11 +724,173 @@ double mg_cycle_bytes(const Multigrid &mg) {
 
 // CG on the projected Poisson system preconditioned by the V-cycle (flexible
 // CG form, which equals preconditioned CG for this fixed SPD operator).
+// The start (residual, first cycle, rho = r^T z) runs with host reads; the
+// iterations are driven from the device: alpha, the convergence test and
+// beta are one-thread kernels on a device state (PDev), every pass returns
+// at once when the solve is over, and blocks of kPcgBlock iterations are
+// captured once in a HIP graph (x is read from the state, so one graph
+// serves every solution array) and replayed with one host read per block.
+// Profiled runs of the classes launch the same kernels one by one.
+namespace {
+
+constexpr int kPcgBlock = 4;
+enum { P_RUN = 0, P_OK = 1, P_NONFINITE = 2, P_BREAKDOWN = 3, P_MAXIT = 4 };
+
+struct PDev {
+    double *x;
+    double rz, pAp, r2, tol2, a, b;
+    int iters, maxit, done;
+    int n_ap, n_step, n_dots;
+};
+
+struct EpiApD {          // Ap = -L p, <p, Ap> into the state
+    double *__restrict__ Ap;
+    PDev *D;
+    double *partials;
+    unsigned int *counter;
+    double acc;
+    __device__ bool skip() const { return D->done != P_RUN; }
+    __device__ void pre(int, int64_t) {}
+    __device__ void point(int, int64_t i, double c, double s) {
+        Ap[i] = -s;
+        acc = ::fma(c, -s, acc);
+    }
+    __device__ void finish(int block, int nblocks, double *scratch) {
+        double x[1] = {acc};
+        block_sum<1>(x, scratch);
+        double t[1];
+        if (reduce_grid<1>(x, partials, nblocks, block, counter, scratch, t)) {
+            D->pAp = t[0];
+            D->n_ap += 1;
+        }
+    }
+};
+
+__global__ void pcg_alpha(PDev *D) {
+    if (D->done != P_RUN) return;
+    const double pAp = D->pAp, rz = D->rz;
+    if (!isfinite(pAp) || !isfinite(rz)) D->done = P_NONFINITE;
+    else if (!(pAp > 0.0) || !(rz > 0.0)) D->done = P_BREAKDOWN;
+    else D->a = rz / pAp;
+}
+
+struct FcgStepOpD {      // x += a p; r_old = r; r -= a Ap; {<r,r>}
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 0;     // counted from the passes that did work
+    double *r, *r_old;
+    const double *p, *Ap;
+    PDev *D;
+    double *x;
+    double a;
+    __device__ bool skip() const { return D->done != P_RUN; }
+    __device__ void prepare() {
+        x = D->x;
+        a = D->a;
+    }
+    __device__ void operator()(int64_t i, double (&acc)[1]) const {
+        x[i] = ::fma(a, p[i], x[i]);
+        const double ro = r[i];
+        r_old[i] = ro;
+        const double rn = ::fma(-a, Ap[i], ro);
+        r[i] = rn;
+        acc[0] = ::fma(rn, rn, acc[0]);
+    }
+};
+struct FinStepP {
+    PDev *D;
+    __device__ void operator()(const double (&t)[1]) const {
+        const double r2 = t[0];
+        D->r2 = r2;
+        D->iters += 1;
+        D->n_step += 1;
+        if (!isfinite(r2)) D->done = P_NONFINITE;
+        else if (r2 <= D->tol2) D->done = P_OK;
+        else if (D->iters >= D->maxit) D->done = P_MAXIT;
+    }
+};
+
+struct FcgDotsOpD {      // {<z, r - r_old>, <r, z>}: beta and the next rho
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 0;
+    const double *z, *r, *r_old;
+    PDev *D;
+    __device__ bool skip() const { return D->done != P_RUN; }
+    __device__ void prepare() {}
+    __device__ void operator()(int64_t i, double (&acc)[2]) const {
+        const double zi = z[i], ri = r[i];
+        acc[0] = ::fma(zi, ri - r_old[i], acc[0]);
+        acc[1] = ::fma(ri, zi, acc[1]);
+    }
+};
+struct FinDotsP {
+    PDev *D;
+    __device__ void operator()(const double (&t)[2]) const {
+        const double b = t[0] / D->rz;
+        D->b = isfinite(b) ? b : 0.0;
+        D->rz = t[1];
+        D->n_dots += 1;
+    }
+};
+
+struct DirOpD {          // p = z + b p
+    static constexpr int kClass = K_CG_UPDATE;
+    static constexpr int kBytes = 0;
+    double *p;
+    const double *z;
+    PDev *D;
+    double b;
+    __device__ bool skip() const { return D->done != P_RUN; }
+    __device__ void prepare() { b = D->b; }
+    __device__ void operator()(int64_t i, double (&)[1]) const { p[i] = ::fma(b, p[i], z[i]); }
+};
+
+int pcg_iteration(ofdft_poisson *s, hipStream_t st) {
+    const ofdft_grid &g = s->g;
+    const int64_t n = npoints(g);
+    PDev *D = (PDev *)s->pdev;
+    double *r = s->r, *p = s->pA, *r_old = s->pB, *Ap = s->Ap, *z = s->z;
+    {
+        ProfScope ps(K_CG_STENCIL, 0.0, st);
+        OFDFT_TRY(launch_stencil<double>(g, s->coef, LoadPlain<double>{p},
+                                         EpiApD{Ap, D, s->rb.partials, s->rb.counter, 0.0}, st));
+    }
+    hipLaunchKernelGGL(pcg_alpha, dim3(1), dim3(1), 0, st, D);
+    OFDFT_CHECK_HIP(hipGetLastError());
+    OFDFT_TRY((launch_reduce<1>(n, FcgStepOpD{r, r_old, p, Ap, D, nullptr, 0.0}, FinStepP{D}, s->rb, st)));
+    OFDFT_TRY(mg_apply_run(*s->mg, r, z, st, 0.0, &D->done));
+    OFDFT_TRY((launch_reduce<2>(n, FcgDotsOpD{z, r, r_old, D}, FinDotsP{D}, s->rb, st)));
+    OFDFT_TRY((launch_reduce<1>(n, DirOpD{p, z, D, 0.0}, NoFin{}, s->rb, st)));
+    return OFDFT_OK;
+}
+
+int pcg_graph(ofdft_poisson *s) {
+    if (s->mggraph) return OFDFT_OK;
+    if (!s->mgcap) OFDFT_CHECK_HIP(hipStreamCreateWithFlags(&s->mgcap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    OFDFT_CHECK_HIP(hipStreamBeginCapture(s->mgcap, hipStreamCaptureModeThreadLocal));
+    prof_suspend(true);
+    int rc = OFDFT_OK;
+    for (int k = 0; k < kPcgBlock && rc == OFDFT_OK; ++k) rc = pcg_iteration(s, s->mgcap);
+    prof_suspend(false);
+    const hipError_t e = hipStreamEndCapture(s->mgcap, &graph);
+    if (rc != OFDFT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    OFDFT_CHECK_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&s->mggraph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    OFDFT_CHECK_HIP(ei);
+    return OFDFT_OK;
+}
+
+}  // namespace
+
 int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter, ofdft_solve_stats &stats,
                      hipStream_t st) {
     const ofdft_grid &g = s->g;
     const int64_t n = npoints(g);
-    double *r = s->r, *p = s->pA, *r_old = s->pB, *Ap = s->Ap, *z = s->z;
+    double *r = s->r, *p = s->pA, *z = s->z;
     double *tot = s->totals + 8, *th = s->totals_host + 8;
     auto sync_tot = [&](int count) -> int {
         OFDFT_CHECK_HIP(hipMemcpyAsync(th, tot, sizeof(double) * count, hipMemcpyDeviceToHost, st));
@@ -741,8 +903,7 @@ int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter, 
     const double tol2 = rel_tol * rel_tol * g2;
     OFDFT_TRY(residual_pass<double>(g, s->coef, x, s->gp, r, tot, s->rb, st));
     OFDFT_TRY(sync_tot(2));
-    double r2 = th[1];
-    int iters = 0;
+    const double r2 = th[1];
     stats.iters = 0;
     if (!std::isfinite(r2)) return OFDFT_NONFINITE;
     if (r2 <= tol2) return OFDFT_OK;
@@ -750,44 +911,50 @@ int poisson_solve_mg(ofdft_poisson *s, double *x, double rel_tol, int max_iter, 
     OFDFT_TRY(mg_apply(*s->mg, r, z, st));
     OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r}, StoreTotals<2>{tot}, s->rb, st)));
     OFDFT_TRY(sync_tot(2));
-    double rz = th[1];
     OFDFT_TRY((launch_reduce<1>(n, CopyOp2{p, z}, NoFin{}, s->rb, st)));
-    int status = OFDFT_NOT_CONVERGED;
-    while (iters < max_iter) {
-        OFDFT_TRY(pass64(g, s->coef, LoadPlain<double>{p}, EpiAp{Ap, tot, s->rb.partials, s->rb.counter, 0.0},
-                         st, 16.0, K_CG_STENCIL));
-        OFDFT_TRY(sync_tot(1));
-        const double pAp = th[0];
-        if (!std::isfinite(pAp) || !std::isfinite(rz)) {
-            status = OFDFT_NONFINITE;
-            break;
-        }
-        if (!(pAp > 0.0) || !(rz > 0.0)) {
-            status = OFDFT_BREAKDOWN;
-            break;
-        }
-        const double a = rz / pAp;
-        OFDFT_TRY((launch_reduce<1>(n, FcgStepOp{x, r, r_old, p, Ap, a}, StoreTotals<1>{tot}, s->rb, st)));
-        OFDFT_TRY(sync_tot(1));
-        r2 = th[0];
-        ++iters;
-        if (!std::isfinite(r2)) {
-            status = OFDFT_NONFINITE;
-            break;
-        }
-        if (r2 <= tol2) {
-            status = OFDFT_OK;
-            break;
-        }
-        OFDFT_TRY(mg_apply(*s->mg, r, z, st));
-        OFDFT_TRY((launch_reduce<2>(n, FcgDotsOp{z, r, r_old}, StoreTotals<2>{tot}, s->rb, st)));
-        OFDFT_TRY(sync_tot(2));
-        const double b = th[0] / rz;
-        rz = th[1];
-        OFDFT_TRY((launch_reduce<1>(n, DirOp{p, z, std::isfinite(b) ? b : 0.0}, NoFin{}, s->rb, st)));
+    if (!s->pdev) {
+        OFDFT_CHECK_HIP(hipMalloc(&s->pdev, sizeof(PDev)));
+        OFDFT_CHECK_HIP(hipHostMalloc(&s->pdev_h, sizeof(PDev), hipHostMallocDefault));
     }
-    stats.iters = iters;
-    return status;
+    PDev *Dh = (PDev *)s->pdev_h;
+    *Dh = PDev{};
+    Dh->x = x;
+    Dh->rz = th[1];
+    Dh->tol2 = tol2;
+    Dh->maxit = max_iter;
+    OFDFT_CHECK_HIP(hipMemcpyAsync(s->pdev, Dh, sizeof(PDev), hipMemcpyHostToDevice, st));
+    auto read_state = [&]() -> int {
+        OFDFT_CHECK_HIP(hipMemcpyAsync(Dh, s->pdev, sizeof(PDev), hipMemcpyDeviceToHost, st));
+        OFDFT_CHECK_HIP(hipStreamSynchronize(st));
+        return OFDFT_OK;
+    };
+    const bool eager = !s->use_graphs || prof_timed(K_CG_STENCIL) || prof_timed(K_CG_UPDATE) ||
+                       prof_timed(K_MULTIGRID);
+    if (eager) {
+        for (int k = 0; k <= max_iter; ++k) {
+            OFDFT_TRY(pcg_iteration(s, st));
+            OFDFT_TRY(read_state());
+            if (Dh->done != P_RUN) break;
+        }
+    } else {
+        OFDFT_TRY(pcg_graph(s));
+        for (int k = 0; k <= max_iter; k += kPcgBlock) {
+            OFDFT_CHECK_HIP(hipGraphLaunch(s->mggraph, st));
+            OFDFT_TRY(read_state());
+            if (Dh->done != P_RUN) break;
+        }
+    }
+    const double nd = (double)n;
+    prof_add(K_CG_STENCIL, nd * 16.0 * Dh->n_ap, eager ? 0 : Dh->n_ap);
+    prof_add(K_CG_UPDATE, nd * (56.0 * Dh->n_step + 48.0 * Dh->n_dots), eager ? 0 : Dh->n_step + 2 * Dh->n_dots);
+    prof_add(K_MULTIGRID, mg_cycle_bytes(*s->mg) * Dh->n_dots, eager ? 0 : Dh->n_dots);
+    stats.iters = Dh->iters;
+    switch (Dh->done) {
+        case P_OK: return OFDFT_OK;
+        case P_NONFINITE: return OFDFT_NONFINITE;
+        case P_BREAKDOWN: return OFDFT_BREAKDOWN;
+        default: return OFDFT_NOT_CONVERGED;
+    }
 }
 
 }  // namespace ofdft

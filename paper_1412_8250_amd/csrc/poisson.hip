@@ -277,6 +277,13 @@ int poisson_alloc(ofdft_poisson *s) {
 }
 
 void poisson_free(ofdft_poisson *s) {
+    if (s->mggraph) (void)hipGraphExecDestroy(s->mggraph);
+    if (s->mgcap) (void)hipStreamDestroy(s->mgcap);
+    if (s->pdev) (void)hipFree(s->pdev);
+    if (s->pdev_h) (void)hipHostFree(s->pdev_h);
+    s->mggraph = nullptr;
+    s->mgcap = nullptr;
+    s->pdev = s->pdev_h = nullptr;
     if (s->graph64) {
         graph_release(*s->graph64);
         delete s->graph64;

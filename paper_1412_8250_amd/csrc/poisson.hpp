@@ -29,8 +29,12 @@ struct ofdft_poisson {
     ofdft_nn *net = nullptr;
     double *z = nullptr, *zprev = nullptr, *xbest = nullptr;
     int learned_fcg = 0;     // 0: network correction + plain CG; 1: + network-preconditioned FCG
-    // multigrid form
+    // multigrid form; its iteration state on the device (and a pinned host
+    // copy) and the captured block of iterations
     ofdft::Multigrid *mg = nullptr;
+    void *pdev = nullptr, *pdev_h = nullptr;
+    hipGraphExec_t mggraph = nullptr;
+    hipStream_t mgcap = nullptr;
 };
 
 namespace ofdft {

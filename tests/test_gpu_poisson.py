@@ -129,10 +129,12 @@ def test_large_cell_320():
         del x, err
 
 
-@pytest.mark.parametrize("mode", [ofd.PLAIN_F64, ofd.REFINED_F32])
+@pytest.mark.parametrize("mode", [ofd.PLAIN_F64, ofd.REFINED_F32, ofd.MULTIGRID, ofd.MULTIGRID_F64])
 def test_graph_replays_equal_eager(mode):
-    """Captured 16-iteration blocks replayed with host synchronisations in
-    between give bitwise the eager result, on every repeat."""
+    """Captured iteration blocks (16 CG iterations; 4 multigrid-preconditioned
+    ones, which read the solution array from the device state) replayed with
+    host synchronisations in between give bitwise the eager result, on every
+    repeat and for every solution array."""
     torch = torch_cuda()
     announce("poisson graphs", mode)
     w = inputs.supercell_500()
