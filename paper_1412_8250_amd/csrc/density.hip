@@ -28,10 +28,9 @@
 // Device-driven form (the potential-mixing map, fixed_point 0): the same
 // iteration with every scalar decision on the device (struct UDev): the
 // residual test, the Polak-Ribiere coefficient and restarts, the slope at
-// s = 0 and the line search, which brackets the root of dE/ds by the same
-// secant growth and then refines it by false position with the Illinois
-// modification, within a budget of kProbes evaluations per iteration
-// (Brent's method needs host decisions).  Every kernel returns at once when
+// s = 0 and the line search (the same secant growth and Brent's method as
+// the host form, one decision kernel per evaluation), within a budget of
+// kProbes evaluations per iteration.  Every kernel returns at once when
 // the update is over (or, for the line-search passes, when the step is
 // chosen), so blocks of kBlockIters iterations are captured once in a HIP
 // graph and replayed; the host reads the state once per block.  Profiled
@@ -362,6 +361,7 @@ struct UDev {
     double res, xi, cu, rz, rz_prev, rr_prev;
     double ud, dd, uLd, dLd, dHu, f0, f0_prev, s_prev;
     double lo, flo, hi, fhi, s, ftol, sstar, c; // line search
+    double ba, bb, bc, bfa, bfb, bfc, bd, be, btol;   // Brent's method inside the bracket
     int q, done, skipit, ls_done, phase, probes, restart, side;
     int n_ka, n_kb, n_dots, n_kd, n_eval, n_step;   // passes that did work
 };
@@ -640,9 +640,65 @@ __global__ void u_slope0(UDev *U, UPar P) {
     U->side = 0;
 }
 
+// One step of Brent's method (Brent 1973: bisection safeguarding secant and
+// inverse quadratic interpolation steps) on the state after f(b) is known,
+// the same arithmetic as brent_root; true when b is accepted, else b is the
+// next point to evaluate.
+__device__ bool brent_decide(UDev *U) {
+    double a = U->ba, b = U->bb, c = U->bc, fa = U->bfa, fb = U->bfb, fc = U->bfc, d = U->bd, e = U->be;
+    if ((fb > 0) == (fc > 0)) {
+        c = a;
+        fc = fa;
+        d = e = b - a;
+    }
+    if (fabs(fc) < fabs(fb)) {
+        a = b; b = c; c = a;
+        fa = fb; fb = fc; fc = fa;
+    }
+    const double tol1 = 2.0 * 2.220446049250313e-16 * fabs(b) + 0.5 * U->btol;
+    const double xm = 0.5 * (c - b);
+    bool accepted = false;
+    if (fabs(xm) <= tol1 || fabs(fb) <= U->ftol) {
+        accepted = true;
+    } else {
+        if (fabs(e) >= tol1 && fabs(fa) > fabs(fb)) {
+            double p, q, r;
+            const double sr = fb / fa;
+            if (a == c) {
+                p = 2.0 * xm * sr;
+                q = 1.0 - sr;
+            } else {
+                q = fa / fc;
+                r = fb / fc;
+                p = sr * (2.0 * xm * q * (q - r) - (b - a) * (r - 1.0));
+                q = (q - 1.0) * (r - 1.0) * (sr - 1.0);
+            }
+            if (p > 0) q = -q;
+            p = fabs(p);
+            if (2.0 * p < fmin(3.0 * xm * q - fabs(tol1 * q), fabs(e * q))) {
+                e = d;
+                d = p / q;
+            } else {
+                d = xm;
+                e = d;
+            }
+        } else {
+            d = xm;
+            e = d;
+        }
+        a = b;
+        fa = fb;
+        b += fabs(d) > tol1 ? d : (xm > 0 ? tol1 : -tol1);
+    }
+    U->ba = a; U->bb = b; U->bc = c;
+    U->bfa = fa; U->bfb = fb; U->bfc = fc;
+    U->bd = d; U->be = e;
+    return accepted;
+}
+
 // one line-search decision after a probe: grow the bracket (secant past the
-// estimated root, 1.1x to 8x) while the slope stays negative, then false
-// position with the Illinois modification inside it
+// estimated root, 1.1x to 8x) while the slope stays negative, then Brent's
+// method inside it (the host form's search, one evaluation per probe)
 __global__ void u_linesearch(UDev *U, UPar P) {
     if (U->done != U_RUN || U->skipit || U->ls_done) return;
     const double sv = U->s;
@@ -656,57 +712,46 @@ __global__ void u_linesearch(UDev *U, UPar P) {
         U->done = U_NONFINITE;
         return;
     }
-    if (fabs(f) <= U->ftol) {
-        u_accept(U, P, sv);
-        return;
-    }
-    double lo = U->lo, flo = U->flo, hi = U->hi, fhi = U->fhi;
     if (U->phase == 0) {
-        fhi = f;
-        if (f < 0.0) {
+        if (fabs(f) <= U->ftol) {
+            u_accept(U, P, sv);
+            return;
+        }
+        const double lo = U->lo, flo = U->flo, hi = U->hi, fhi = f;
+        if (fhi < 0.0) {
             double next = 2.0 * hi;
             if (fhi > flo) {
                 const double sec = hi + (hi - lo) * (-fhi) / (fhi - flo);
                 next = fmin(fmax(1.1 * sec, 1.1 * hi), 8.0 * hi);
             }
-            lo = hi;
-            flo = fhi;
-            hi = next;
-            U->s = hi;
-        } else {
-            U->phase = 1;
-            U->side = 0;
-            U->s = lo - flo * (hi - lo) / (fhi - flo);
-        }
-    } else {
-        if (f < 0.0) {
-            lo = sv;
-            flo = f;
-            if (U->side == -1) fhi *= 0.5;
-            U->side = -1;
-        } else {
-            hi = sv;
-            fhi = f;
-            if (U->side == 1) flo *= 0.5;
-            U->side = 1;
-        }
-        if (hi - lo <= P.ltol * hi) {
-            u_accept(U, P, sv);
+            U->lo = hi;
+            U->flo = fhi;
+            U->hi = next;
+            U->s = next;
             return;
         }
-        U->s = lo - flo * (hi - lo) / (fhi - flo);
+        // bracketed: Brent from (lo, hi)
+        U->phase = 1;
+        U->ba = lo;
+        U->bfa = flo;
+        U->bb = hi;
+        U->bfb = fhi;
+        U->bc = lo;
+        U->bfc = flo;
+        U->bd = U->be = hi - lo;
+        U->btol = P.ltol * hi;
+    } else {
+        U->bfb = f;
     }
-    U->lo = lo;
-    U->flo = flo;
-    U->hi = hi;
-    U->fhi = fhi;
+    if (brent_decide(U)) u_accept(U, P, U->bb);
+    else U->s = U->bb;
 }
 
 // budget spent without acceptance: the last point of negative slope while
-// still growing, else the current false-position point inside the bracket
+// still growing, else Brent's current point inside the bracket
 __global__ void u_linesearch_end(UDev *U, UPar P) {
     if (U->done != U_RUN || U->skipit || U->ls_done) return;
-    u_accept(U, P, U->phase == 0 ? U->lo : U->s);
+    u_accept(U, P, U->phase == 0 ? U->lo : U->bb);
 }
 
 // end of an iteration
