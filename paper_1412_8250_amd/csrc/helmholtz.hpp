@@ -114,6 +114,8 @@ struct ofdft_batch {
     // stepped schedule
     ofdft::StepState *d_step = nullptr, *h_step = nullptr;   // per system (host copy pinned)
     int *d_ublk = nullptr, *d_vblk = nullptr;                 // block prefix sums (nsys + 1)
+    int *d_xpre = nullptr;       // per XCD: prefix sums of its share of every system's tiles (8 x (nsys + 1))
+    int step_grid = 0;           // stencil-phase workgroups: 8 x the longest XCD share
     unsigned int *d_ctr = nullptr;                           // per-system arrival counters
     double *d_spart = nullptr;                               // per-system partial slots
     int step_shape = -1, step_units = 0, step_vblocks = 0;

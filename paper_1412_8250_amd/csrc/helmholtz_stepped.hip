@@ -8,9 +8,11 @@
 //    new direction and its image follow point by point from the previous
 //    ones, p = r + beta p_old and Ap = A r + beta Ap_old (A is linear), so
 //    only one array is read with a halo; p^T Ap is reduced;  the grid holds
-//    the stencil tiles of every system (block -> system by a prefix table,
-//    XCD-aware order), so eight 320^3 systems give thousands of workgroups
-//    per launch;
+//    the stencil tiles of every system, so eight 320^3 systems give
+//    thousands of workgroups per launch.  Each XCD takes one contiguous
+//    eighth of every system's tiles (neighbouring tiles share their halos
+//    in that XCD's L2, and the systems still running keep every XCD busy
+//    when the others have converged);
 //  * vector phase: x += alpha p, r -= alpha Ap, r^T r and |r|^2 reduced.
 // The scalars of every system (alpha, beta, r^T r, status) live on the
 // device: the last workgroup of a system to finish a phase combines that
@@ -121,19 +123,24 @@ enum StepPhase { PH_INIT = 0, PH_PAP = 1 };
 // 4 * ublk[j] and is laid out [k][unit].
 template <typename T, int TX, int TYT, int RY, int Phase>
 __global__ void __launch_bounds__(TX * TYT)
-step_stencil(const HSys *sys, StepState *st, const int *ublk, int nsys, int total,
+step_stencil(const HSys *sys, StepState *st, const int *ublk, const int *xpre, int nsys,
              unsigned int *ctr, double *part, double tol) {
     using CT = CX<T>;
     __shared__ T lds[StencilLds<T, TX, TYT, RY>::kElems];
     __shared__ double scratch[4 * (TX * TYT / 64)];
-    const int lb = xcd_remap(blockIdx.x, total);
-    const int j = find_sys(ublk, nsys, lb);
+    // workgroup b runs on XCD b % 8; that XCD's list holds, system after
+    // system, the tiles [n x / 8, n (x + 1) / 8) of each system of n tiles
+    constexpr int kXcd = 8;
+    const int x = blockIdx.x % kXcd, l = blockIdx.x / kXcd;
+    const int *xp = xpre + x * (nsys + 1);
+    if (l >= xp[nsys]) return;
+    const int j = find_sys(xp, nsys, l);
     StepState *sj = st + j;
     const int done = sj->done;
     if (done != H_RUNNING) return;
     const HSys &h = sys[j];
-    const int unit = lb - ublk[j];
     const int nunits = ublk[j + 1] - ublk[j];
+    const int unit = (int)(((int64_t)nunits * x) / kXcd) + (l - xp[j]);
     double *pj = part + 4 * (size_t)ublk[j];
     const T kappa = CT::mk(h.kre, h.kim);
     if constexpr (Phase == PH_INIT) {
@@ -277,13 +284,13 @@ step_dot(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned int
 
 template <typename T, int TX, int TYT, int RY>
 int launch_phase(ofdft_batch *b, int phase, double tol, hipStream_t s) {
-    const int total = b->step_units;
+    const int grid = b->step_grid;
     if (phase == PH_INIT)
-        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_INIT>), dim3(total), dim3(TX, TYT), 0, s,
-                           b->d_sys, b->d_step, b->d_ublk, b->nsys, total, b->d_ctr, b->d_spart, tol);
+        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_INIT>), dim3(grid), dim3(TX, TYT), 0, s,
+                           b->d_sys, b->d_step, b->d_ublk, b->d_xpre, b->nsys, b->d_ctr, b->d_spart, tol);
     else
-        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_PAP>), dim3(total), dim3(TX, TYT), 0, s,
-                           b->d_sys, b->d_step, b->d_ublk, b->nsys, total, b->d_ctr, b->d_spart, tol);
+        hipLaunchKernelGGL((step_stencil<T, TX, TYT, RY, PH_PAP>), dim3(grid), dim3(TX, TYT), 0, s,
+                           b->d_sys, b->d_step, b->d_ublk, b->d_xpre, b->nsys, b->d_ctr, b->d_spart, tol);
     OFDFT_CHECK_HIP(hipGetLastError());
     return OFDFT_OK;
 }
@@ -412,7 +419,19 @@ int prepare_layout(ofdft_batch *b, const std::vector<HSys> &hs, hipStream_t s) {
         (void)hipGraphExecDestroy(b->step_graph);
         b->step_graph = nullptr;
     }
+    // per-XCD shares of every system's tiles (see step_stencil)
+    std::vector<int> xpre(8 * (size_t)(nsys + 1), 0);
+    int longest = 0;
+    for (int x = 0; x < 8; ++x) {
+        int *xp = xpre.data() + x * (nsys + 1);
+        for (int j = 0; j < nsys; ++j) {
+            const int64_t nu = ublk[j + 1] - ublk[j];
+            xp[j + 1] = xp[j] + (int)(nu * (x + 1) / 8 - nu * x / 8);
+        }
+        longest = std::max(longest, xp[nsys]);
+    }
     if (!b->d_ublk) {
+        OFDFT_CHECK_HIP(hipMalloc(&b->d_xpre, sizeof(int) * 8 * (nsys + 1)));
         OFDFT_CHECK_HIP(hipMalloc(&b->d_ublk, sizeof(int) * (nsys + 1)));
         OFDFT_CHECK_HIP(hipMalloc(&b->d_vblk, sizeof(int) * (nsys + 1)));
         OFDFT_CHECK_HIP(hipMalloc(&b->d_ctr, sizeof(unsigned int) * nsys));
@@ -429,11 +448,13 @@ int prepare_layout(ofdft_batch *b, const std::vector<HSys> &hs, hipStream_t s) {
         OFDFT_CHECK_HIP(hipMalloc(&b->d_spart, sizeof(double) * slots));
     }
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_ublk, ublk.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
+    OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_xpre, xpre.data(), sizeof(int) * xpre.size(), hipMemcpyHostToDevice, s));
     OFDFT_CHECK_HIP(hipMemcpyAsync(b->d_vblk, vblk.data(), sizeof(int) * (nsys + 1), hipMemcpyHostToDevice, s));
     OFDFT_CHECK_HIP(hipStreamSynchronize(s));
     b->h_ublk = ublk;
     b->h_vblk = vblk;
     b->step_units = ublk[nsys];
+    b->step_grid = 8 * std::max(longest, 1);
     b->step_vblocks = vblk[nsys];
     return OFDFT_OK;
 }
@@ -538,6 +559,7 @@ int stepped_run(ofdft_batch *b, bool c64, int shape, const std::vector<HSys> &hs
 void stepped_free(ofdft_batch *b) {
     if (b->step_graph) (void)hipGraphExecDestroy(b->step_graph);
     if (b->step_cap) (void)hipStreamDestroy(b->step_cap);
+    if (b->d_xpre) (void)hipFree(b->d_xpre);
     if (b->d_ublk) (void)hipFree(b->d_ublk);
     if (b->d_vblk) (void)hipFree(b->d_vblk);
     if (b->d_ctr) (void)hipFree(b->d_ctr);
@@ -546,7 +568,7 @@ void stepped_free(ofdft_batch *b) {
     if (b->d_spart) (void)hipFree(b->d_spart);
     b->step_graph = nullptr;
     b->step_cap = nullptr;
-    b->d_ublk = b->d_vblk = nullptr;
+    b->d_ublk = b->d_vblk = b->d_xpre = nullptr;
     b->d_ctr = nullptr;
     b->d_step = b->h_step = nullptr;
     b->d_spart = nullptr;
