@@ -140,11 +140,25 @@ def cpu_baseline(w, iters=40):
     for _ in range(20):
         o.step()
     items["scf_16_20_tfw_steps_all_cores"] = {"seconds": time.perf_counter() - t0}
+    # the uneven batch, sampled: the 8 shifted systems of its first cell
+    # (5^3 cells on 80^3), textbook COCG to 1e-8 from zero
+    from oracle import helmholtz as oh
+    cw, kap, cf = inputs.batched_workloads(count=1)[0]
+    al, be = 5.0 / 6.0 + 5.0 ** 0.5 / 6.0, 5.0 / 6.0 - 5.0 ** 0.5 / 6.0
+    lap = {a: -fd.laplacian(cw.rho ** a, cw.cell.h) for a in (al, be)}
+    t0 = time.perf_counter()
+    its = []
+    for j in range(8):
+        _, itj, _ = oh.solve_cocg(cf[j] * lap[al if j < 4 else be], complex(kap[j]), cw.cell.h, tol=1e-8)
+        its.append(itj)
+    items["batch_cell0_8_systems_cocg_to_1e-8_all_cores"] = {"seconds": time.perf_counter() - t0,
+                                                             "grid": list(cw.rho.shape), "iterations": its}
     return {"value": gbps, "unit": "GB/s", "cores": allc, "kind": "oracle",
             "sample": f"{it} textbook CG iterations of the 320^3 FP64 Poisson solve on {allc} threads "
                       f"({dt:.1f} s), bytes counted as 80 B/point/iteration like the GPU path; "
                       f"items: stencil apply and CG on one core and all, CG of the 96^3 cell to 1e-8, "
-                      f"20 TFW steps of the 16^3 cell",
+                      f"20 TFW steps of the 16^3 cell, the 8 shifted systems of the uneven batch's "
+                      f"first cell (80^3) by COCG to 1e-8",
             "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "items": items}
 
 
@@ -578,6 +592,21 @@ def main():
     # the extras run untimed: per-launch events would force the eager paths
     # (the batched solver's per-system cycles, no graph replays)
     ofd.profile_reset(timed=())
+    # the measured streaming ceiling: a plain device copy of one 320^3 FP64
+    # vector (read + write), 20 back-to-back copies between two events
+    ca = torch.empty(shape, dtype=torch.float64, device=dev).fill_(1.0)
+    cb = torch.empty_like(ca)
+    cb.copy_(ca)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        cb.copy_(ca)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * ca.numel() * 8 / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+    del ca, cb
+    roofline["copy_GBps_measured"] = copy_gbps
+    roofline["frac_of_measured_copy"] = (achieved / copy_gbps) if achieved else None
 
     extras = {}
     if tuned is not None:
