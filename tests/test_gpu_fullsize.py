@@ -99,3 +99,44 @@ def test_anderson_320():
         assert np.abs(got - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), k
         v = ref
         vd = to_dev(v)
+
+
+def test_fd_gradient_320(large):
+    """The FD gradient of the large cell's density against the oracle's, element
+    by element over the whole 320^3 grid."""
+    torch = torch_cuda()
+    announce("fd gradient 320^3")
+    w = large
+    xd = to_dev(w.rho)
+    g = [torch.empty_like(xd) for _ in range(3)]
+    ofd.fd_gradient_apply(xd, *g, w.cell.h, 6)
+    torch.cuda.synchronize()
+    ref = fd.gradient(w.rho, w.cell.h, 6)
+    for a in range(3):
+        assert np.abs(to_host(g[a]) - ref[a]).max() <= 1e-13 * np.abs(ref[a]).max(), a
+    del g, xd
+
+
+def test_density_update_with_electrostatics_supercell():
+    """U with the electrostatics inside (the paper's map, fixed_point 1) on the
+    500-atom cell at 96^3 (multigrid-preconditioned direction and Poisson
+    solves): the oracle's Euler-Lagrange residual of the GPU answer with phi
+    re-solved spectrally for that answer (the minimiser is unique; the
+    oracle's own NLCG to the same point takes minutes on the host, so the
+    element-wise comparison is the 16^3 test's)."""
+    torch = torch_cuda()
+    announce("density update with electrostatics 96^3")
+    w = inputs.supercell_500()
+    c = w.cell
+    ctx = ofd.SCF(w.rho.shape, c.h, to_dev(w.b), to_dev(np.sqrt(w.rho)), c.n_electrons, lam=0.2, u_tol=1e-10,
+                  poisson_tol=1e-12, poisson_mode=ofd.MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID,
+                  fixed_point=ofd.SCF.KERNEL_POTENTIAL)
+    ud = to_dev(np.sqrt(w.rho))
+    it, res, eta = ctx.density_update(torch.zeros_like(ud), ud)
+    u = to_host(ud)
+    announce("iterations", it, "residual", res)
+    assert res <= 1e-10
+    r_orc, eta_orc = density.el_residual(u, density.hartree(u, w.b, c.h), c.h, 0.2, c.n_electrons)
+    assert r_orc <= 5e-10 and abs(eta - eta_orc) <= 1e-9
+    assert abs(float(np.prod(c.h)) * float(np.sum(u * u)) - c.n_electrons) <= 1e-9 * c.n_electrons
+    ctx.close()
