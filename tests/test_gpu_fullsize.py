@@ -128,8 +128,9 @@ def test_density_update_with_electrostatics_supercell():
     announce("density update with electrostatics 96^3")
     w = inputs.supercell_500()
     c = w.cell
+    # the fields' true residuals bottom out near 1e-12 at this size: 1e-11
     ctx = ofd.SCF(w.rho.shape, c.h, to_dev(w.b), to_dev(np.sqrt(w.rho)), c.n_electrons, lam=0.2, u_tol=1e-10,
-                  poisson_tol=1e-12, poisson_mode=ofd.MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID,
+                  poisson_tol=1e-11, poisson_mode=ofd.MULTIGRID, u_precond=ofd.PRECOND_MULTIGRID,
                   fixed_point=ofd.SCF.KERNEL_POTENTIAL)
     ud = to_dev(np.sqrt(w.rho))
     it, res, eta = ctx.density_update(torch.zeros_like(ud), ud)
