@@ -475,6 +475,30 @@ def ground_state_runs(dev):
         "max_force_difference_between_forms": float(np.abs(f - fp).max())}
     k.close()
     del k
+    # the same run at the tolerances of the paper's scaling study (density
+    # update 1e-3, kernel and Poisson solves 1e-6, fixed point 1e-2)
+    loose = dict(common, u_tol=1e-3, poisson_tol=1e-6, helmholtz_tol=1e-6)
+    t0 = time.perf_counter()
+    k = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, history=3, zeta=1.0, fixed_point=ofd.SCF.KERNEL_POTENTIAL,
+                **loose)
+    lres, lsecs = [], []
+    for step in range(25):
+        t1 = time.perf_counter()
+        r = k.step(allow_not_converged=True)
+        torch.cuda.synchronize()
+        lsecs.append(time.perf_counter() - t1)
+        lres.append(r)
+        log(f"kernel-potential (paper tolerances) step {step}: residual {r:.3e} in {lsecs[-1]:.2f}s")
+        if r < 1e-2 or not np.isfinite(r):
+            break
+    le = k.energy(atoms, sigma=1.2)
+    out["kernel_potential_paper_tolerances"] = {
+        "u_tol": 1e-3, "solve_tol": 1e-6, "fixed_point_tol": 1e-2, "steps": len(lres), "residuals": lres,
+        "step_seconds": lsecs, "seconds_including_context": time.perf_counter() - t0,
+        "energy_per_atom": le["total"] / len(atoms),
+        "energy_per_atom_difference_to_tight_run": le["total"] / len(atoms) - e["total"] / len(atoms)}
+    k.close()
+    del k
     p = ofd.SCF(shape, h, b, u0, w.cell.n_electrons, history=7, zeta=0.3, u_max_iter=2000, **common)
     pres, pit = [], []
     for step in range(6):
