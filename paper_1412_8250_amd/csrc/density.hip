@@ -362,7 +362,7 @@ struct UDev {
     double ud, dd, uLd, dLd, dHu, f0, f0_prev, s_prev;
     double lo, flo, hi, fhi, s, ftol, sstar, c; // line search
     double ba, bb, bc, bfa, bfb, bfc, bd, be, btol;   // Brent's method inside the bracket
-    int q, done, skipit, ls_done, phase, probes, restart, side;
+    int q, done, skipit, ls_done, phase, probes, restart;
     int n_ka, n_kb, n_dots, n_kd, n_eval, n_step;   // passes that did work
 };
 
@@ -637,7 +637,6 @@ __global__ void u_slope0(UDev *U, UPar P) {
     U->ftol = P.stol * fabs(f0);
     U->phase = 0;
     U->probes = 0;
-    U->side = 0;
 }
 
 // One step of Brent's method (Brent 1973: bisection safeguarding secant and

@@ -356,3 +356,29 @@ def test_scf_steps_graph_replay_equal_eager():
         ofd.profile_reset()
     assert outs[0][0] == outs[1][0], (outs[0][0], outs[1][0])
     assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("cap", [1, 3, 6])
+def test_density_update_iteration_cap(cap):
+    """The device-driven update stops after exactly u_max_iter steps (the
+    cap falls inside a captured block of four) with NOT_CONVERGED, and the
+    iterate it leaves is the eager path's, bit for bit."""
+    torch = torch_cuda()
+    announce("density update cap", cap)
+    w = inputs.small_cell()
+    g, _ = poisson.rhs(w.rho, w.b)
+    phi = poisson.solve_exact(g, w.cell.h)
+    outs = []
+    try:
+        for timed in ((), ("u_stencil",)):
+            ofd.profile_reset(timed=timed)
+            ctx = _ctx(w, lam=1.0, u_max_iter=cap, u_precond=ofd.PRECOND_MULTIGRID)
+            ud = to_dev(np.sqrt(w.rho))
+            it, res, eta = ctx.density_update(to_dev(phi), ud, allow_not_converged=True)
+            outs.append((to_host(ud), it, res))
+            ctx.close()
+    finally:
+        ofd.profile_reset()
+    for u, it, res in outs:
+        assert it == cap and res > 1e-10 and np.isfinite(u).all()
+    assert np.array_equal(outs[0][0], outs[1][0])
