@@ -297,10 +297,11 @@ struct MsEpiRes {        // acc |f - (-L x + kappa x)|^2
     GPtr<double2> f;
     double2 kappa;
     double acc[1];
-    __device__ void pre(int, int64_t) {}
-    __device__ void point(int, int64_t i, double2 c, double2 s) {
+    double2 fo[2];
+    __device__ void pre(int r, int64_t i) { fo[r] = f[i]; }
+    __device__ void point(int r, int64_t, double2 c, double2 s) {
         const double2 a = cfma(kappa, c, c2(-s.x, -s.y));
-        const double2 d = csub(f[i], a);
+        const double2 d = csub(fo[r], a);
         acc[0] += d.x * d.x + d.y * d.y;
     }
 };
@@ -315,7 +316,7 @@ ms_residual(TileGeom tg, Coef<double> coef, double kre, double kim, const double
     const int total = tg.nblocks;
     const int lb = xcd_remap(blockIdx.x, total);
     MsLoadX ld{GPtr<double2>(x)};
-    MsEpiRes ep{GPtr<double2>(f), c2(kre, kim), {0.0}};
+    MsEpiRes ep{GPtr<double2>(f), c2(kre, kim), {0.0}, {}};
     stencil_tile<double2, TX, TYT, RY>(tg, coef, ld, ep, lb, lds);
     double acc[1] = {ep.acc[0]};
     block_sum<1>(acc, scratch);
@@ -327,10 +328,11 @@ struct MsEpiResVec {     // d = f - (-L x + kappa x) written; acc |d|^2
     GPtr<double2> f, d;
     double2 kappa;
     double acc[1];
-    __device__ void pre(int, int64_t) {}
-    __device__ void point(int, int64_t i, double2 c, double2 s) {
+    double2 fo[2];
+    __device__ void pre(int r, int64_t i) { fo[r] = f[i]; }
+    __device__ void point(int r, int64_t i, double2 c, double2 s) {
         const double2 a = cfma(kappa, c, c2(-s.x, -s.y));
-        const double2 dv = csub(f[i], a);
+        const double2 dv = csub(fo[r], a);
         d.st(i, dv);
         acc[0] += dv.x * dv.x + dv.y * dv.y;
     }
@@ -346,7 +348,7 @@ ms_resvec(TileGeom tg, Coef<double> coef, double kre, double kim, const double2 
     const int total = tg.nblocks;
     const int lb = xcd_remap(blockIdx.x, total);
     MsLoadX ld{GPtr<double2>(x)};
-    MsEpiResVec ep{GPtr<double2>(f), GPtr<double2>(d), c2(kre, kim), {0.0}};
+    MsEpiResVec ep{GPtr<double2>(f), GPtr<double2>(d), c2(kre, kim), {0.0}, {}};
     stencil_tile<double2, TX, TYT, RY>(tg, coef, ld, ep, lb, lds);
     double acc[1] = {ep.acc[0]};
     block_sum<1>(acc, scratch);

@@ -16,8 +16,14 @@ int apply_t(const ofdft_grid &g, const Coef<typename VT<T>::S> &c, const void *x
     using S = typename VT<T>::S;
     LoadPlain<T> ld{(const T *)x};
     ProfScope ps(K_APPLY, (double)npoints(g) * sizeof(T) * (beta != 0.0 ? 3 : 2), s);
+    // 64 x 32 tiles for the real types; with beta != 0 the FP64 form would
+    // need more than 256 registers (the four y values per thread), so it
+    // takes the 64 x 16 tile of the generic dispatch instead of spilling
     auto go = [&](const auto &ep) {
-        if constexpr (std::is_same_v<T, double> || std::is_same_v<T, float>) {
+        using E = std::decay_t<decltype(ep)>;
+        constexpr bool wide = std::is_same_v<T, float> ||
+                              (std::is_same_v<T, double> && std::is_same_v<E, EpiAxpby<T, false>>);
+        if constexpr (wide) {
             const StencilCfg cfg = pick_stencil_cfg(g, sizeof(T), FAMILY_APPLY);
             if (cfg.shape == SHAPE_64x8x4) return launch_stencil_shape<T, 64, 8, 4>(g, cfg.zlen, c, ld, ep, s);
         }

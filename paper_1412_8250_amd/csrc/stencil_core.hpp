@@ -228,12 +228,19 @@ struct StencilLds {
 // front is first used A - R planes after its fetch, a halo ring PR planes
 // after.  Halo fetches past the chunk end are clamped to its last plane
 // (never used, an L2 hit).
+//
+// The geometry and the weights are taken by value, so they live in scalar
+// registers for the whole march.  A reference into device memory (a field of
+// a per-system descriptor) would be re-read after every store of the
+// epilogue, since the stores may alias it; that re-read is a vector load, and
+// waiting for it means waiting for every prefetch issued before it, which
+// empties the z queue once per plane.
 constexpr int gcd_i(int a, int b) { return b == 0 ? a : gcd_i(b, a % b); }
 
 template <typename T, int TX, int TYT, int RY, class Load, class Epi,
           int L = StencilLds<T, TX, TYT, RY>::kLead, int PR = StencilLds<T, TX, TYT, RY>::kRingDepth,
           int A = kMaxRadius + 3>
-__device__ inline void stencil_tile(const TileGeom &g, const Coef<typename VT<T>::S> &w,
+__device__ inline void stencil_tile(const TileGeom g, const Coef<typename VT<T>::S> w,
                                     const Load &ld, Epi &ep, int logical_block, T *lds) {
     using TS = TileShape<TX, TYT, RY>;
     constexpr int R = TS::R, W = TS::W, H = TS::H;
