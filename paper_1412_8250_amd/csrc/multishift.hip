@@ -18,17 +18,18 @@
 // zero, x_r += e, until the true residual meets the tolerance.
 //
 // Two launches per iteration:
-//  * stencil phase: the seed direction p = r + beta p_old is formed on the
-//    fly, p and q = A p are written and p^T q reduced; the last workgroup
+//  * stencil phase: the stencil runs on r alone; the seed direction and its
+//    image follow point by point, p = r + beta p_old and q = A r + beta q_old
+//    (A linear; q updated in place), p^T q is reduced; the last workgroup
 //    sets alpha_k and every running shift's pi_{k+1} and alpha_k^(r);
 //  * vector phase: every running shift forms p^(r) = r / pi^(r) + beta^(r)
 //    p^(r) (the seed's was written by the stencil phase) and x^(r) +=
 //    alpha^(r) p^(r); r -= alpha q; r^T r and |r|^2 are reduced and the last
 //    workgroup sets beta_k, the next beta^(r), advances pi and freezes the
 //    converged shifts.
-// Per point and iteration this moves 4 complex128 vectors in the stencil
+// Per point and iteration this moves 5 complex128 vectors in the stencil
 // phase and 3 + 3 (seed) + 4 per other running shift in the vector phase,
-// against 10 per system for separate COCG solves.  The scalars live on the
+// against 11 per system for separate COCG solves.  The scalars live on the
 // device; the host reads the status every few iterations, and launches made
 // after the end exit at once.
 #include <algorithm>
@@ -108,27 +109,43 @@ ms_init(MsState *st, const MsShift *sh, const double2 *f, double2 *r, int64_t n,
     }
 }
 
-struct MsLoadP {         // seed direction r + beta p_old (first iteration: r)
-    GPtr<double2> r, p_old;
-    double2 beta;
-    __device__ double2 operator()(int64_t i) const { return cfma(beta, p_old[i], r[i]); }
+struct MsLoadR {
+    GPtr<double2> r;
+    __device__ double2 operator()(int64_t i) const { return r[i]; }
 };
 
-struct MsEpiQ {          // p written, q = -L p + kappa_s p; acc {p^T q re, im}
-    GPtr<double2> p_out, q;
-    double2 kappa;
+// Centre c = r, s = L r: p = r + beta p_old and q = (-L r + kappa_s r) +
+// beta q_old written (q in place: each point is read and written by the same
+// thread); the first iteration (beta = 0, its own kernel) reads neither.
+// acc {p^T q re, im}.
+template <bool First>
+struct MsEpiQ {
+    GPtr<double2> p_old, p_out, q;
+    double2 kappa, beta;
     double acc[2];
-    __device__ void pre(int, int64_t) {}
-    __device__ void point(int, int64_t i, double2 c, double2 s) {
-        const double2 a = cfma(kappa, c, c2(-s.x, -s.y));
-        p_out.st(i, c);
+    double2 po[2], qo[2];
+    __device__ void pre(int r, int64_t i) {
+        if constexpr (!First) {
+            po[r] = p_old[i];
+            qo[r] = q[i];
+        }
+    }
+    __device__ void point(int r, int64_t i, double2 c, double2 s) {
+        double2 a = cfma(kappa, c, c2(-s.x, -s.y));
+        double2 p = c;
+        if constexpr (!First) {
+            p = cfma(beta, po[r], c);
+            a = cfma(beta, qo[r], a);
+        }
+        p_out.st(i, p);
         q.st(i, a);
-        acc[0] += c.x * a.x - c.y * a.y;
-        acc[1] += c.x * a.y + c.y * a.x;
+        acc[0] += p.x * a.x - p.y * a.y;
+        acc[1] += p.x * a.y + p.y * a.x;
     }
 };
 
-template <int TX, int TYT, int RY>
+// First: iteration 0 (launched as the first stencil phase after ms_init).
+template <int TX, int TYT, int RY, bool First>
 __global__ void __launch_bounds__(TX * TYT)
 ms_stencil(TileGeom tg, Coef<double> coef, double kre, double kim, MsState *st, MsShift *sh,
            const double2 *r, double2 *pA, double2 *pB, double2 *q, double *part, unsigned int *ctr) {
@@ -138,15 +155,13 @@ ms_stencil(TileGeom tg, Coef<double> coef, double kre, double kim, MsState *st, 
     if (st->done != H_RUNNING) return;
     const int total = tg.nblocks;
     const int lb = xcd_remap(blockIdx.x, total);
-    const bool first = st->iter == 0;
+    constexpr bool first = First;
     const double2 *p_old = st->parity ? pB : pA;
     double2 *p_new = st->parity ? pA : pB;
-    MsLoadP ld{GPtr<double2>(r), GPtr<double2>(first ? r : p_old),
-               first ? c2(0.0, 0.0) : c2(st->be_re, st->be_im)};
-    MsEpiQ ep{GPtr<double2>(p_new), GPtr<double2>(q), c2(kre, kim), {0.0, 0.0}};
-    // two-array loader with 512 threads: two halo ring buffers fit the register budget
-    constexpr int PR = TX * TYT >= 512 ? 2 : SLd::kRingDepth;
-    stencil_tile<double2, TX, TYT, RY, MsLoadP, MsEpiQ, SLd::kLead, PR>(tg, coef, ld, ep, lb, lds);
+    MsLoadR ld{GPtr<double2>(r)};
+    MsEpiQ<First> ep{GPtr<double2>(p_old), GPtr<double2>(p_new), GPtr<double2>(q), c2(kre, kim),
+                     c2(st->be_re, st->be_im), {0.0, 0.0}, {}, {}};
+    stencil_tile<double2, TX, TYT, RY>(tg, coef, ld, ep, lb, lds);
     double acc[2] = {ep.acc[0], ep.acc[1]};
     block_sum<2>(acc, scratch);
     double t[2];
@@ -535,9 +550,11 @@ int ms_iterate(ofdft_multishift *m, int S, const double *kappa, int seed, const 
             int st = ms_dispatch(m->shape, [&](auto sh) {
                 using Sh = decltype(sh);
                 ProfScope ps(K_MS_STENCIL, 0.0, s);
-                hipLaunchKernelGGL((ms_stencil<Sh::TX, Sh::TYT, Sh::RY>), dim3(m->tg.nblocks),
-                                   dim3(Sh::TX, Sh::TYT), 0, s, m->tg, m->coef, kre, kim, m->d_state,
-                                   m->d_shift, m->r, m->pA, m->pB, m->q, m->d_part, m->d_ctr);
+                // the first launch after ms_init is iteration 0
+                auto kern = round == 0 && c == 0 ? ms_stencil<Sh::TX, Sh::TYT, Sh::RY, true>
+                                                 : ms_stencil<Sh::TX, Sh::TYT, Sh::RY, false>;
+                hipLaunchKernelGGL(kern, dim3(m->tg.nblocks), dim3(Sh::TX, Sh::TYT), 0, s, m->tg, m->coef, kre,
+                                   kim, m->d_state, m->d_shift, m->r, m->pA, m->pB, m->q, m->d_part, m->d_ctr);
                 OFDFT_CHECK_HIP(hipGetLastError());
                 return OFDFT_OK;
             });
@@ -555,14 +572,14 @@ int ms_iterate(ofdft_multishift *m, int S, const double *kappa, int seed, const 
         set_error("cocg_multishift_solve: iteration did not finish");
         return OFDFT_HIP_ERROR;
     }
-    // Algorithmic bytes of the iterations taken: the stencil phase reads r and
-    // p_old (r only in the first iteration) and writes p and q; the vector
+    // Algorithmic bytes of the iterations taken: the stencil phase reads r,
+    // p_old and q_old (r only in the first iteration) and writes p and q; the vector
     // phase reads r, q and writes r, plus 3 vectors for the seed (p, x read,
     // x written) and 4 for every other shift (p, x read and written; 3 in the
     // first iteration) while the shift runs.
     const int steps = hst.iter;
     if (steps > 0) {
-        prof_add(K_MS_STENCIL, n * e * (4.0 * steps - 1.0), 0);
+        prof_add(K_MS_STENCIL, n * e * (5.0 * steps - 2.0), 0);
         double upd = 3.0 * steps;
         for (int j = 0; j < S; ++j) {
             const int it = hsh[j].stat == H_RUNNING ? steps : hsh[j].iters;
