@@ -105,6 +105,29 @@ def test_max_iter_cap_reports_not_converged():
     assert all(s["status"] == ofd.NOT_CONVERGED for s in st)
 
 
+@pytest.mark.parametrize("cap", [1, 2, 5])
+@pytest.mark.parametrize("config", [None, (2, 0)])
+def test_capped_iterates_match_textbook_cocg(cap, config):
+    """The first iterations one by one: the batched solve stopped after `cap`
+    iterations equals the oracle's textbook COCG after as many, element by
+    element (iteration 0 and the later ones run different stencil-phase
+    kernels; both tile shapes)."""
+    announce("helmholtz capped iterates", cap, config)
+    torch = torch_cuda()
+    cells = _random_cells(4, 31)
+    b = ofd.HelmholtzBatch([c[0] for c in cells], [c[1] for c in cells], 6, ofd.C128)
+    if config is not None:
+        b.set_config(*config)
+    rhs = [to_dev(c[3].astype(np.complex128)) for c in cells]
+    xs = [to_dev(np.zeros(c[0], np.complex128)) for c in cells]
+    status, st = b.solve([c[2] for c in cells], rhs, xs, 1e-14, max_iter=cap, allow_not_converged=True)
+    for (shape, h, kap, f), x, s in zip(cells, xs, st):
+        ref, it, _ = helmholtz.solve_cocg(f, kap, h, tol=1e-14, maxit=cap)
+        assert s["iters"] == cap and it == cap
+        got = to_host(x)
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
 def test_warm_start_converged_guess():
     cells = _random_cells(3, 13)
     xs, st = _batch(cells, ofd.C128, 1e-9)
