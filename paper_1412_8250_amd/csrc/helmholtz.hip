@@ -902,11 +902,12 @@ static int batch_solve(ofdft_batch *b, const double *kappa, const void *const *r
                 iters[j] += it_pass[j];
                 done[j] = done_pass[j];
                 // init: read x, f, write r; stencil phase: read r (z), p_old,
-                // Ap_old, write p, Ap (the first one reads r only); vector
-                // phase: read x, p, r, Ap, write x, r
+                // Ap_old, x, write p, Ap, x (the first one reads r only and
+                // writes p, Ap); vector phase: read r, Ap, write r (the last
+                // direction's x update is accounted by the run itself)
                 const double n = (double)npoints(b->grids[j]);
-                bs += n * e * (3.0 + (it_pass[j] > 0 ? 5.0 * it_pass[j] - 2.0 : 0.0));
-                bu += n * e * 6.0 * it_pass[j];
+                bs += n * e * (3.0 + (it_pass[j] > 0 ? 7.0 * it_pass[j] - 4.0 : 0.0));
+                bu += n * e * 3.0 * it_pass[j];
                 if (b->precond) {
                     // one cycle and one dot phase (read r, z) after the init
                     // phase and after each iteration but the last

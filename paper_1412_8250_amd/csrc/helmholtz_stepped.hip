@@ -40,6 +40,7 @@ struct StepState {
     double be_re, be_im;     // beta of the next direction
     double rn2, fn2, tol2;   // |r|^2, |f|^2, tol^2 |f|^2
     int iter, done, maxit, parity;   // parity: 0 -> p_old in pA, 1 -> p_old in pB
+    int xpend, pad;          // x += alpha p of the last direction still to apply
 };
 
 namespace {
@@ -88,27 +89,32 @@ struct StepEpiInit {     // r = f - (-L x + kappa x); acc {r^T r re, im, |r|^2, 
 
 // Centre = r (z when preconditioned), s = L r.  p = r + beta p_old and
 // Ap = (-L r + kappa r) + beta Ap_old, Ap updated in place (each point is read
-// and written by the same thread); the first iteration (beta = 0) reads
-// neither p_old nor Ap_old.  acc {p^T Ap re, im}.  The first iteration is
+// and written by the same thread); the previous iteration's x += alpha p_old
+// is applied here too, where p_old is read anyway (the vector phase then
+// moves r and Ap only; the last direction's update is left to step_finish).
+// The first iteration (beta = 0, no previous direction) reads neither p_old,
+// Ap_old nor x.  acc {p^T Ap re, im}.  The first iteration is
 // a kernel of its own: with a run-time flag the loads and their use sit in
 // branches, and the compiler then waits for the halo fetches of the previous
 // plane before it reuses the registers of these loads.
 template <typename T, bool First>
 struct StepEpiPAp {
-    GPtr<T> p_old, p_out, Ap;
-    T kappa, beta;
+    GPtr<T> p_old, p_out, Ap, x;
+    T kappa, beta, alpha;
     double acc[2];
-    T po[4], ao[4];
+    T po[4], ao[4], xo[4];
     __device__ void pre(int q, int64_t i) {
         if constexpr (!First) {
             po[q] = p_old[i];
             ao[q] = Ap[i];
+            xo[q] = x[i];
         }
     }
     __device__ void point(int q, int64_t i, T c, T s) {
         T a = cfma(kappa, c, T{-s.x, -s.y});
         T p = c;
         if constexpr (!First) {
+            x.st(i, cfma(alpha, po[q], xo[q]));
             p = cfma(beta, po[q], c);
             a = cfma(beta, ao[q], a);
         }
@@ -171,14 +177,19 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, const int *xpre, i
         const void *p_new = sj->parity ? h.pA : h.pB;
         const void *base = h.z ? h.z : h.r;
         StepLoadX<T> ld{GPtr<T>(base)};
-        StepEpiPAp<T, Phase == PH_PAP_FIRST> ep{GPtr<T>(p_old), GPtr<T>(p_new), GPtr<T>(h.Ap), kappa,
-                                                CT::mk(sj->be_re, sj->be_im), {0, 0}, {}, {}};
+        // alpha of the previous iteration: the last workgroup below sets this
+        // iteration's only after every workgroup has arrived
+        StepEpiPAp<T, Phase == PH_PAP_FIRST> ep{GPtr<T>(p_old), GPtr<T>(p_new), GPtr<T>(h.Ap), GPtr<T>(h.x),
+                                                kappa, CT::mk(sj->be_re, sj->be_im),
+                                                CT::mk(sj->al_re, sj->al_im), {0, 0}, {}, {}, {}};
         stencil_tile<T, TX, TYT, RY>(h.tg, coef_of<T>(h), ld, ep, unit, lds);
         double acc[2] = {ep.acc[0], ep.acc[1]};
         block_sum<2>(acc, scratch);
         double t[2];
         if (reduce_grid<2>(acc, pj, nunits, unit, ctr + j, scratch, t)) {
             const double den = t[0] * t[0] + t[1] * t[1];
+            // the previous direction's x update is applied by now
+            sj->xpend = 0;
             if (!isfinite(den)) {
                 sj->done = H_NONFINITE;
             } else if (den == 0.0) {
@@ -186,13 +197,14 @@ step_stencil(const HSys *sys, StepState *st, const int *ublk, const int *xpre, i
             } else {
                 sj->al_re = (sj->rr_re * t[0] + sj->rr_im * t[1]) / den;
                 sj->al_im = (sj->rr_im * t[0] - sj->rr_re * t[1]) / den;
+                sj->xpend = 1;
             }
         }
     }
 }
 
-// Vector phase: x += alpha p, r -= alpha Ap; then beta (unpreconditioned)
-// and status.  part region of system j starts at 4 * vblk[j] (the caller
+// Vector phase: r -= alpha Ap (x follows in the next stencil phase or in
+// step_finish); then beta (unpreconditioned) and status.  part region of system j starts at 4 * vblk[j] (the caller
 // offsets part past the stencil slots).
 template <typename T>
 __global__ void __launch_bounds__(kVecThreadsStep)
@@ -206,12 +218,11 @@ step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned 
     if (sj->done != H_RUNNING) return;
     const HSys &h = sys[j];
     const int lb = b - vblk[j], nb = vblk[j + 1] - vblk[j];
-    const GPtr<T> x(h.x), r(h.r), Ap(h.Ap), p(sj->parity ? h.pA : h.pB);
-    const T al = CT::mk(sj->al_re, sj->al_im), nal = CT::mk(-sj->al_re, -sj->al_im);
+    const GPtr<T> r(h.r), Ap(h.Ap);
+    const T nal = CT::mk(-sj->al_re, -sj->al_im);
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t stride = (int64_t)nb * kVecThreadsStep;
     for (int64_t i = (int64_t)lb * kVecThreadsStep + threadIdx.x; i < h.n; i += stride) {
-        x.st(i, cfma(al, p[i], x[i]));
         const T rv = cfma(nal, Ap[i], r[i]);
         r.st(i, rv);
         const double a = rv.x, c = rv.y;
@@ -242,6 +253,27 @@ step_update(const HSys *sys, StepState *st, const int *vblk, int nsys, unsigned 
         else if (iter >= sj->maxit) d = H_MAXIT;
         sj->done = d;
     }
+}
+
+// x += alpha p of the last direction of every system whose update is still
+// pending (the stencil phase applies each direction's update one iteration
+// late, so a converged, capped or stopped system owes its last one).
+template <typename T>
+__global__ void __launch_bounds__(kVecThreadsStep)
+step_finish(const HSys *sys, const StepState *st, const int *vblk, int nsys) {
+    using CT = CX<T>;
+    const int b = blockIdx.x;
+    const int j = find_sys(vblk, nsys, b);
+    const StepState *sj = st + j;
+    if (!sj->xpend) return;
+    const HSys &h = sys[j];
+    const int lb = b - vblk[j], nb = vblk[j + 1] - vblk[j];
+    // the direction written by the last stencil phase (parity has flipped since)
+    const GPtr<T> x(h.x), p(sj->parity ? h.pB : h.pA);
+    const T al = CT::mk(sj->al_re, sj->al_im);
+    const int64_t stride = (int64_t)nb * kVecThreadsStep;
+    for (int64_t i = (int64_t)lb * kVecThreadsStep + threadIdx.x; i < h.n; i += stride)
+        x.st(i, cfma(al, p[i], x[i]));
 }
 
 // Dot phase of the preconditioned iteration: rho = r^T z, |z|^2; first call
@@ -484,7 +516,7 @@ int prepare_layout(ofdft_batch *b, const std::vector<HSys> &hs, hipStream_t s) {
 }
 
 template <typename T>
-int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::vector<int> &maxit,
+int run_t(ofdft_batch *b, int shape, const std::vector<HSys> &hs, const std::vector<int> &which, const std::vector<int> &maxit,
           double tol, std::vector<int> &iters, std::vector<int> &done, hipStream_t s) {
     const int nsys = b->nsys;
     for (int j = 0; j < nsys; ++j) {
@@ -548,6 +580,16 @@ int run_t(ofdft_batch *b, int shape, const std::vector<int> &which, const std::v
             if (b->precond) prof_add(K_MULTIGRID_C, 0.0, (int64_t)reps * kStepIters * nsys);
         }
     }
+    // the last directions' x updates (read x, p; write x)
+    double fin = 0.0;
+    for (int j : which)
+        if (b->h_step[j].xpend) fin += 3.0 * sizeof(T) * (double)hs[j].n;
+    if (fin > 0.0) {
+        ProfScope ps(K_COCG_UPDATE, fin, s);
+        hipLaunchKernelGGL(step_finish<T>, dim3(b->step_vblocks), dim3(kVecThreadsStep), 0, s, b->d_sys, b->d_step,
+                           b->d_vblk, b->nsys);
+        OFDFT_CHECK_HIP(hipGetLastError());
+    }
     for (int j = 0; j < nsys; ++j) {
         iters[j] = b->h_step[j].iter;
         done[j] = b->h_step[j].done;
@@ -577,8 +619,8 @@ int stepped_run(ofdft_batch *b, bool c64, int shape, const std::vector<HSys> &hs
                 std::vector<int> &iters, std::vector<int> &done, hipStream_t s) {
     if (b->precond && c64) return OFDFT_INVALID_ARG;
     OFDFT_TRY(prepare_layout(b, hs, s));
-    if (c64) return run_t<float2>(b, shape, which, maxit, tol, iters, done, s);
-    return run_t<double2>(b, shape, which, maxit, tol, iters, done, s);
+    if (c64) return run_t<float2>(b, shape, hs, which, maxit, tol, iters, done, s);
+    return run_t<double2>(b, shape, hs, which, maxit, tol, iters, done, s);
 }
 
 void stepped_free(ofdft_batch *b) {
